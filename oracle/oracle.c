@@ -1,0 +1,471 @@
+/*
+ * FP64 CPU oracle for the simplified string method on an atomistic spin
+ * lattice (Heistracher et al., "GPU Accelerated Atomistic Energy Barrier
+ * Calculations of Skyrmion Annihilations", arXiv:1804.07135).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is compiled into liboracle.so, which
+ * only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * load.  The product library never links, loads or calls it, and it shares
+ * no source with the HIP path.
+ *
+ * Plain, slow, obviously correct: every quantity is FP64, the dipolar field
+ * and energy are direct O(N^2) sums over all site pairs (no FFT), and every
+ * sum over sites is a fixed-order pairwise sum so results do not depend on
+ * the OpenMP thread count.
+ *
+ * Units and conventions (reduced units; lattice constant 1, unit spins):
+ *   - spins of one image are stored SoA: s[c*N + (z*ny + y)*nx + x],
+ *     c = 0,1,2 for the x,y,z components, N = nx*ny*nz; images follow each
+ *     other with stride 3N.
+ *   - the field is h = mu0*|S|*H_eff = -dE/ds (Sec. II.A, eq. (2)), so the
+ *     paper's prefactors 1/(mu0 |S|) disappear.
+ *   - D = mu0 |S|^2 / (4 pi a^3) is the reduced dipolar strength, so one
+ *     unordered pair contributes -D [3(s_i.r)(s_j.r) - s_i.s_j]/r^3
+ *     (last term of eq. (1); the 1/(8 pi) over ordered pairs is 1/(4 pi)
+ *     over unordered ones).
+ *   - nearest-neighbour bonds <i,j> are counted once each; open boundaries,
+ *     missing neighbours contribute nothing (Sec. II: free boundaries).
+ *
+ * Every function below names the passage of the paper it follows.
+ * Parity pins for each function live in tests/test_oracle_pins.py.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_VERSION 1
+
+int oracle_version(void) { return ORACLE_VERSION; }
+
+/* ------------------------------------------------------------------ */
+/* fixed-order pairwise summation                                       */
+/* ------------------------------------------------------------------ */
+static double psum(const double* a, int64_t n)
+{
+    if (n <= 0) return 0.0;
+    if (n <= 16) {
+        double t = 0.0;
+        for (int64_t i = 0; i < n; ++i) t += a[i];
+        return t;
+    }
+    int64_t h = n / 2;
+    return psum(a, h) + psum(a + h, n - h);
+}
+
+static inline int64_t site(int nx, int ny, int x, int y, int z)
+{
+    return ((int64_t)z * ny + y) * nx + x;
+}
+
+/* ------------------------------------------------------------------ */
+/* Term energies, written as the bond and pair sums of eq. (1).         */
+/* T[0] = -sum_bonds s_i.s_j                       (exchange, per unit J)
+ * T[1] =  sum_bonds (r_ij x z).(s_i x s_j)        (DMI, per unit d)
+ * T[2] = -sum_i (s_i.z)^2                         (anisotropy, per unit k)
+ * T[3] = -sum_{i<j} [3(s_i.r)(s_j.r) - s_i.s_j]/r^3 (dipolar, per unit D)
+ * E = J*T[0] + d*T[1] + k*T[2] + D*T[3].
+ * These never touch the field code, so they pin it by finite differences. */
+/* ------------------------------------------------------------------ */
+void oracle_energy_terms(int nx, int ny, int nz, const double* s, double* T)
+{
+    const int64_t N = (int64_t)nx * ny * nz;
+    const double* sx = s;
+    const double* sy = s + N;
+    const double* sz = s + 2 * N;
+    double* ex = (double*)calloc((size_t)N, sizeof(double));
+    double* dm = (double*)calloc((size_t)N, sizeof(double));
+    double* an = (double*)calloc((size_t)N, sizeof(double));
+    double* dd = (double*)calloc((size_t)N, sizeof(double));
+
+    /* local terms: each site owns the bonds to its +x, +y, +z neighbour */
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        int x = (int)(i % nx);
+        int y = (int)((i / nx) % ny);
+        int z = (int)(i / ((int64_t)nx * ny));
+        double e_ex = 0.0, e_dm = 0.0;
+        const int dx[3] = {1, 0, 0}, dy[3] = {0, 1, 0}, dz[3] = {0, 0, 1};
+        for (int b = 0; b < 3; ++b) {
+            int xj = x + dx[b], yj = y + dy[b], zj = z + dz[b];
+            if (xj >= nx || yj >= ny || zj >= nz) continue;
+            int64_t j = site(nx, ny, xj, yj, zj);
+            e_ex -= sx[i] * sx[j] + sy[i] * sy[j] + sz[i] * sz[j];
+            /* DMI vector r_ij x z: x-bond -> (0,-1,0), y-bond -> (1,0,0),
+             * z-bond -> 0.  (s_i x s_j) written out component by component. */
+            double cx = sy[i] * sz[j] - sz[i] * sy[j];
+            double cy = sz[i] * sx[j] - sx[i] * sz[j];
+            double rx = (double)dx[b], ry = (double)dy[b];
+            /* (r x z) = (ry, -rx, 0) */
+            e_dm += ry * cx - rx * cy;
+        }
+        ex[i] = e_ex;
+        dm[i] = e_dm;
+        an[i] = -sz[i] * sz[i];
+    }
+
+    /* dipolar: unordered pairs i<j, charged to the lower site */
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < N; ++i) {
+        int xi = (int)(i % nx);
+        int yi = (int)((i / nx) % ny);
+        int zi = (int)(i / ((int64_t)nx * ny));
+        double acc = 0.0;
+        for (int64_t j = i + 1; j < N; ++j) {
+            int xj = (int)(j % nx);
+            int yj = (int)((j / nx) % ny);
+            int zj = (int)(j / ((int64_t)nx * ny));
+            double rx = xj - xi, ry = yj - yi, rz = zj - zi;
+            double r2 = rx * rx + ry * ry + rz * rz;
+            double r = sqrt(r2);
+            double ux = rx / r, uy = ry / r, uz = rz / r;
+            double si_u = sx[i] * ux + sy[i] * uy + sz[i] * uz;
+            double sj_u = sx[j] * ux + sy[j] * uy + sz[j] * uz;
+            double si_sj = sx[i] * sx[j] + sy[i] * sy[j] + sz[i] * sz[j];
+            acc -= (3.0 * si_u * sj_u - si_sj) / (r2 * r);
+        }
+        dd[i] = acc;
+    }
+
+    T[0] = psum(ex, N);
+    T[1] = psum(dm, N);
+    T[2] = psum(an, N);
+    T[3] = psum(dd, N);
+    free(ex); free(dm); free(an); free(dd);
+}
+
+double oracle_energy(int nx, int ny, int nz, double J, double d, double k,
+                     double D, const double* s)
+{
+    double T[4];
+    oracle_energy_terms(nx, ny, nz, s, T);
+    return J * T[0] + d * T[1] + k * T[2] + D * T[3];
+}
+
+/* ------------------------------------------------------------------ */
+/* Effective field h_i = -dE/ds_i at one site.                          */
+/*   exchange   eq. (3):  J * sum over nearest neighbours of s_j
+ *   DMI        eq. (4):  -d (s^z_{+x}-s^z_{-x}, s^z_{+y}-s^z_{-y},
+ *                            -s^x_{+x}+s^x_{-x}-s^y_{+y}+s^y_{-y})
+ *   anisotropy eq. (5):  2k s^z z
+ *   dipolar    eqs. (6)-(7): D sum_{j != i} (3 r r^T/r^5 - I/r^3) s_j
+ * Missing neighbours (open boundary) contribute 0.                     */
+/* ------------------------------------------------------------------ */
+static void field_at(int nx, int ny, int nz, double J, double d, double k,
+                     double D, const double* s, int64_t i, double* hout)
+{
+    const int64_t N = (int64_t)nx * ny * nz;
+    const double* sx = s;
+    const double* sy = s + N;
+    const double* sz = s + 2 * N;
+    int x = (int)(i % nx);
+    int y = (int)((i / nx) % ny);
+    int z = (int)(i / ((int64_t)nx * ny));
+
+    /* neighbour values, 0 where the neighbour is outside the sample */
+    double px[3] = {0, 0, 0}, mx[3] = {0, 0, 0};
+    double py[3] = {0, 0, 0}, my[3] = {0, 0, 0};
+    double pz[3] = {0, 0, 0}, mz[3] = {0, 0, 0};
+    int64_t j;
+    if (x + 1 < nx) { j = site(nx, ny, x + 1, y, z); px[0] = sx[j]; px[1] = sy[j]; px[2] = sz[j]; }
+    if (x - 1 >= 0) { j = site(nx, ny, x - 1, y, z); mx[0] = sx[j]; mx[1] = sy[j]; mx[2] = sz[j]; }
+    if (y + 1 < ny) { j = site(nx, ny, x, y + 1, z); py[0] = sx[j]; py[1] = sy[j]; py[2] = sz[j]; }
+    if (y - 1 >= 0) { j = site(nx, ny, x, y - 1, z); my[0] = sx[j]; my[1] = sy[j]; my[2] = sz[j]; }
+    if (z + 1 < nz) { j = site(nx, ny, x, y, z + 1); pz[0] = sx[j]; pz[1] = sy[j]; pz[2] = sz[j]; }
+    if (z - 1 >= 0) { j = site(nx, ny, x, y, z - 1); mz[0] = sx[j]; mz[1] = sy[j]; mz[2] = sz[j]; }
+
+    double h[3];
+    for (int c = 0; c < 3; ++c)
+        h[c] = J * (px[c] + mx[c] + py[c] + my[c] + pz[c] + mz[c]);
+
+    h[0] += -d * (px[2] - mx[2]);
+    h[1] += -d * (py[2] - my[2]);
+    h[2] += -d * (-px[0] + mx[0] - py[1] + my[1]);
+
+    h[2] += 2.0 * k * sz[i];
+
+    if (D != 0.0) {
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        for (int64_t jj = 0; jj < N; ++jj) {
+            if (jj == i) continue;
+            int xj = (int)(jj % nx);
+            int yj = (int)((jj / nx) % ny);
+            int zj = (int)(jj / ((int64_t)nx * ny));
+            double rx = xj - x, ry = yj - y, rz = zj - z;
+            double r2 = rx * rx + ry * ry + rz * rz;
+            double r = sqrt(r2);
+            double r3 = r2 * r, r5 = r3 * r2;
+            double rs = rx * sx[jj] + ry * sy[jj] + rz * sz[jj];
+            ax += 3.0 * rx * rs / r5 - sx[jj] / r3;
+            ay += 3.0 * ry * rs / r5 - sy[jj] / r3;
+            az += 3.0 * rz * rs / r5 - sz[jj] / r3;
+        }
+        h[0] += D * ax;
+        h[1] += D * ay;
+        h[2] += D * az;
+    }
+    hout[0] = h[0];
+    hout[1] = h[1];
+    hout[2] = h[2];
+}
+
+/* Field of one image, all sites; h has the spin layout. */
+void oracle_field(int nx, int ny, int nz, double J, double d, double k,
+                  double D, const double* s, double* h)
+{
+    const int64_t N = (int64_t)nx * ny * nz;
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < N; ++i) {
+        double hi[3];
+        field_at(nx, ny, nz, J, d, k, D, s, i, hi);
+        h[i] = hi[0];
+        h[N + i] = hi[1];
+        h[2 * N + i] = hi[2];
+    }
+}
+
+/* Field at a list of sites only (for sampled checks on large lattices);
+ * hout is [nsites][3]. */
+void oracle_field_at(int nx, int ny, int nz, double J, double d, double k,
+                     double D, const double* s, const int64_t* sites,
+                     int64_t nsites, double* hout)
+{
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < nsites; ++q)
+        field_at(nx, ny, nz, J, d, k, D, s, sites[q], hout + 3 * q);
+}
+
+/* E = -1/2 sum_i h_i . s_i  (eq. (8); exact for this Hamiltonian, whose
+ * terms are all homogeneous quadratic in the spins). */
+double oracle_energy_from_field(int64_t N, const double* s, const double* h)
+{
+    double* e = (double*)malloc((size_t)N * sizeof(double));
+    for (int64_t i = 0; i < N; ++i)
+        e[i] = -0.5 * (h[i] * s[i] + h[N + i] * s[N + i] + h[2 * N + i] * s[2 * N + i]);
+    double E = psum(e, N);
+    free(e);
+    return E;
+}
+
+/* ------------------------------------------------------------------ */
+/* String method step 1 (Sec. III, eq. (10); force from the Appendix):  */
+/* the potential force on a unit spin is the field's component          */
+/* perpendicular to the spin, h - (s.h)s = -s x (s x h).  One explicit  */
+/* Euler step of length tau followed by renormalisation to |s| = 1.     */
+/* ------------------------------------------------------------------ */
+void oracle_step(int64_t N, int K, const double* s, const double* h,
+                 double tau, double* s_star)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < (int64_t)K * N; ++q) {
+        int64_t kk = q / N, i = q % N;
+        const double* sk = s + kk * 3 * N;
+        const double* hk = h + kk * 3 * N;
+        double* ok = s_star + kk * 3 * N;
+        double v[3] = {sk[i], sk[N + i], sk[2 * N + i]};
+        double f[3] = {hk[i], hk[N + i], hk[2 * N + i]};
+        double sh = v[0] * f[0] + v[1] * f[1] + v[2] * f[2];
+        double w[3];
+        for (int c = 0; c < 3; ++c) w[c] = v[c] + tau * (f[c] - sh * v[c]);
+        double nrm = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        for (int c = 0; c < 3; ++c) ok[c * N + i] = w[c] / nrm;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* String method step 2 (Sec. III, eqs. (11)-(12)): arc length,         */
+/* normalised parameters, interpolation onto the uniform grid.          */
+/* Readings where the text is garbled or silent:                        */
+/*   - eq. (12) divides by the last arc length S_{K-1};                 */
+/*   - the uniform grid is alpha_k = k/(K-1), so both endpoints stay;   */
+/*   - interpolation is piecewise linear in alpha, component by         */
+/*     component, followed by per-spin renormalisation; a spin whose    */
+/*     interpolated norm is below 1e-12 takes the nearer source spin;   */
+/*   - a zero-width interval gives weight 0; S_{K-1} = 0 skips the      */
+/*     reparametrisation (s_out = s_star).                              */
+/* alpha_star[K], jidx[K], wts[K] receive the parameters used.          */
+/* Returns 1 if the reparametrisation was applied, 0 if skipped.        */
+/* ------------------------------------------------------------------ */
+int oracle_reparam(int K, int64_t N, const double* s_star, double* s_out,
+                   double* alpha_star, int32_t* jidx, double* wts)
+{
+    const int64_t M = 3 * N;
+    double* seg = (double*)malloc((size_t)K * sizeof(double));
+    double* sq = (double*)malloc((size_t)M * sizeof(double));
+    seg[0] = 0.0;
+    for (int kk = 1; kk < K; ++kk) {
+        const double* a = s_star + (int64_t)kk * M;
+        const double* b = s_star + (int64_t)(kk - 1) * M;
+        for (int64_t q = 0; q < M; ++q) {
+            double t = a[q] - b[q];
+            sq[q] = t * t;
+        }
+        seg[kk] = sqrt(psum(sq, M));
+    }
+    double* S = (double*)malloc((size_t)K * sizeof(double));
+    S[0] = 0.0;
+    for (int kk = 1; kk < K; ++kk) S[kk] = S[kk - 1] + seg[kk];
+    double L = S[K - 1];
+    if (!(L > 0.0)) {
+        for (int kk = 0; kk < K; ++kk) {
+            alpha_star[kk] = 0.0;
+            jidx[kk] = kk;
+            wts[kk] = 0.0;
+        }
+        memcpy(s_out, s_star, (size_t)K * M * sizeof(double));
+        free(seg); free(sq); free(S);
+        return 0;
+    }
+    for (int kk = 0; kk < K; ++kk) alpha_star[kk] = S[kk] / L;
+
+    for (int kk = 0; kk < K; ++kk) {
+        if (kk == 0 || kk == K - 1) {
+            jidx[kk] = kk;
+            wts[kk] = 0.0;
+            memcpy(s_out + (int64_t)kk * M, s_star + (int64_t)kk * M, (size_t)M * sizeof(double));
+            continue;
+        }
+        double t = (double)kk / (double)(K - 1);
+        int j = 0;
+        for (int jj = 0; jj <= K - 2; ++jj)
+            if (alpha_star[jj] <= t) j = jj;
+        double width = alpha_star[j + 1] - alpha_star[j];
+        double w = (width > 0.0) ? (t - alpha_star[j]) / width : 0.0;
+        jidx[kk] = j;
+        wts[kk] = w;
+        const double* a = s_star + (int64_t)j * M;
+        const double* b = s_star + (int64_t)(j + 1) * M;
+        double* o = s_out + (int64_t)kk * M;
+        #pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < N; ++i) {
+            double v[3];
+            for (int c = 0; c < 3; ++c) v[c] = (1.0 - w) * a[c * N + i] + w * b[c * N + i];
+            double nrm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            if (nrm < 1e-12) {
+                const double* src = (w < 0.5) ? a : b;
+                for (int c = 0; c < 3; ++c) o[c * N + i] = src[c * N + i];
+            } else {
+                for (int c = 0; c < 3; ++c) o[c * N + i] = v[c] / nrm;
+            }
+        }
+    }
+    free(seg); free(sq); free(S);
+    return 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* Path tangents and the perpendicular-force norm.  An MEP is a path    */
+/* along which the potential force is parallel to the path (Sec. III),  */
+/* so convergence is measured by the force component perpendicular to   */
+/* it:                                                                  */
+/*   h_perp = h - (s.h)s per spin (Appendix, force equation);           */
+/*   tangent t_k: phi_{k+1}-phi_{k-1} (one-sided at the ends), each     */
+/*     spin's part projected onto that spin's tangent plane, then       */
+/*     normalised in R^{3N} (t = 0 if its norm is 0);                   */
+/*   F_perp = h_perp - (h_perp . t) t for interior images, h_perp at    */
+/*     the endpoints;                                                   */
+/*   norm = max over images and sites of |F_perp| per spin.             */
+/* s, h: [K][3N]; tangents_or_null: [K][3N].                            */
+/* ------------------------------------------------------------------ */
+double oracle_force_norm(int K, int64_t N, const double* s, const double* h,
+                         double* tangents_or_null)
+{
+    const int64_t M = 3 * N;
+    double* tt = (double*)malloc((size_t)M * sizeof(double));
+    double* hp = (double*)malloc((size_t)M * sizeof(double));
+    double* buf = (double*)malloc((size_t)N * sizeof(double));
+    double worst = 0.0;
+    for (int kk = 0; kk < K; ++kk) {
+        const double* sk = s + (int64_t)kk * M;
+        const double* hk = h + (int64_t)kk * M;
+        int kp = (kk + 1 < K) ? kk + 1 : kk;
+        int km = (kk - 1 >= 0) ? kk - 1 : kk;
+        const double* sp = s + (int64_t)kp * M;
+        const double* sm = s + (int64_t)km * M;
+        for (int64_t i = 0; i < N; ++i) {
+            double v[3] = {sk[i], sk[N + i], sk[2 * N + i]};
+            double f[3] = {hk[i], hk[N + i], hk[2 * N + i]};
+            double dlt[3];
+            for (int c = 0; c < 3; ++c) dlt[c] = sp[c * N + i] - sm[c * N + i];
+            double sh = v[0] * f[0] + v[1] * f[1] + v[2] * f[2];
+            double sd = v[0] * dlt[0] + v[1] * dlt[1] + v[2] * dlt[2];
+            for (int c = 0; c < 3; ++c) {
+                hp[c * N + i] = f[c] - sh * v[c];
+                tt[c * N + i] = dlt[c] - sd * v[c];
+            }
+        }
+        for (int64_t i = 0; i < N; ++i)
+            buf[i] = tt[i] * tt[i] + tt[N + i] * tt[N + i] + tt[2 * N + i] * tt[2 * N + i];
+        double tn = sqrt(psum(buf, N));
+        double inv = (tn > 0.0) ? 1.0 / tn : 0.0;
+        for (int64_t q = 0; q < M; ++q) tt[q] *= inv;
+        int interior = (kk > 0 && kk < K - 1);
+        double proj = 0.0;
+        if (interior) {
+            for (int64_t i = 0; i < N; ++i)
+                buf[i] = hp[i] * tt[i] + hp[N + i] * tt[N + i] + hp[2 * N + i] * tt[2 * N + i];
+            proj = psum(buf, N);
+        }
+        for (int64_t i = 0; i < N; ++i) {
+            double fx = hp[i] - proj * tt[i];
+            double fy = hp[N + i] - proj * tt[N + i];
+            double fz = hp[2 * N + i] - proj * tt[2 * N + i];
+            double n = sqrt(fx * fx + fy * fy + fz * fz);
+            if (n > worst) worst = n;
+        }
+        if (tangents_or_null)
+            memcpy(tangents_or_null + (int64_t)kk * M, tt, (size_t)M * sizeof(double));
+    }
+    free(tt); free(hp); free(buf);
+    return worst;
+}
+
+/* ------------------------------------------------------------------ */
+/* The two-step string iteration of Sec. III, repeated.                 */
+/*   for each iteration: field and energy of every image (eqs. (2)-(8)),*/
+/*   descent step of every image including the endpoints (eq. (10)),    */
+/*   reparametrisation (eqs. (11)-(12)).                                */
+/* Convergence (tol > 0): before iterations 0, every, 2*every, ... the  */
+/* perpendicular-force norm of the current string is computed; the run  */
+/* stops when it is below tol.  After the loop the final string is      */
+/* evaluated once more: E[K] and (optionally) h[K][3N] are its energies */
+/* and fields.  s[K][3N] is updated in place.  Returns iterations done. */
+/* ------------------------------------------------------------------ */
+int oracle_iterate(int nx, int ny, int nz, double J, double d, double k,
+                   double D, int K, int max_iter, double tau, double tol,
+                   int every, double* s, double* E, double* h_or_null,
+                   double* force_norm_out)
+{
+    const int64_t N = (int64_t)nx * ny * nz;
+    const int64_t M = 3 * N;
+    double* h = (double*)malloc((size_t)K * M * sizeof(double));
+    double* ss = (double*)malloc((size_t)K * M * sizeof(double));
+    double* al = (double*)malloc((size_t)K * sizeof(double));
+    double* wt = (double*)malloc((size_t)K * sizeof(double));
+    int32_t* jj = (int32_t*)malloc((size_t)K * sizeof(int32_t));
+    int it = 0;
+    double fn = -1.0;
+    if (every < 1) every = 1;
+    for (;;) {
+        if (tol > 0.0 && it % every == 0) {
+            for (int kk = 0; kk < K; ++kk)
+                oracle_field(nx, ny, nz, J, d, k, D, s + kk * M, h + kk * M);
+            fn = oracle_force_norm(K, N, s, h, NULL);
+            if (fn < tol) break;
+        }
+        if (it >= max_iter) break;
+        for (int kk = 0; kk < K; ++kk)
+            oracle_field(nx, ny, nz, J, d, k, D, s + kk * M, h + kk * M);
+        oracle_step(N, K, s, h, tau, ss);
+        oracle_reparam(K, N, ss, s, al, jj, wt);
+        ++it;
+    }
+    for (int kk = 0; kk < K; ++kk) {
+        oracle_field(nx, ny, nz, J, d, k, D, s + kk * M, h + kk * M);
+        E[kk] = oracle_energy_from_field(N, s + kk * M, h + kk * M);
+    }
+    if (h_or_null) memcpy(h_or_null, h, (size_t)K * M * sizeof(double));
+    if (force_norm_out) *force_norm_out = oracle_force_norm(K, N, s, h, NULL);
+    free(h); free(ss); free(al); free(wt); free(jj);
+    return it;
+}

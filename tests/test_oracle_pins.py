@@ -1,0 +1,446 @@
+"""Pins for the FP64 CPU oracle, against facts the paper and mathematics fix.
+
+None of these re-types the oracle's own formulas: each compares it with a
+closed form, an invariant, finite differences, a brute-force evaluation of
+eq. (1) in its vector form, or a hand-derived tiny case.  The barrier value
+itself is "parity unpinned" by the paper (its figures carry no numbers).
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from paper_1804_07135_amd import inputs
+
+P = dict(J=1.0, d=0.3, k=0.1, D=0.01)
+
+
+def rand_spins(nx, ny, nz, seed):
+    return inputs.random_unit_spins((3, nz, ny, nx), seed)
+
+
+# ---------------------------------------------------------------------------
+# small closed cases (eq. (1) evaluated by hand)
+# ---------------------------------------------------------------------------
+def test_single_site(oracle):
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        v = rng.standard_normal(3)
+        v /= np.linalg.norm(v)
+        s = v.reshape(3, 1, 1, 1)
+        E = oracle.energy(s, 1.0, 0.3, 0.17, 0.05)
+        assert E == pytest.approx(-0.17 * v[2] ** 2, abs=1e-15)
+        h = oracle.field(s, 1.0, 0.3, 0.17, 0.05).ravel()
+        np.testing.assert_allclose(h, [0.0, 0.0, 2 * 0.17 * v[2]], atol=1e-15)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_two_spins(oracle, axis):
+    """Two parallel spins on one bond: -J, anisotropy, and the pair dipole
+    energy -D[3 cos^2 - 1] (cos = angle between spin and bond)."""
+    shape = [1, 1, 1]  # nx, ny, nz
+    shape[axis] = 2
+    nx, ny, nz = shape
+    J, d, k, D = 1.3, 0.4, 0.11, 0.07
+    for sdir in range(3):
+        s = np.zeros((3, nz, ny, nx))
+        s[sdir] = 1.0
+        cos = 1.0 if sdir == axis else 0.0
+        expect = -J - 2 * k * (sdir == 2) - D * (3 * cos * cos - 1)
+        assert oracle.energy(s, J, d, k, D) == pytest.approx(expect, abs=1e-14)
+
+
+def test_two_spins_survey_values(oracle):
+    # two +z spins at distance 1 along x: -J - 2k + D; two +x: -J - 2D
+    s = np.zeros((3, 1, 1, 2)); s[2] = 1
+    assert oracle.energy(s, 1, 0.3, 0.1, 0.01) == pytest.approx(-1 - 0.2 + 0.01, abs=1e-15)
+    s = np.zeros((3, 1, 1, 2)); s[0] = 1
+    assert oracle.energy(s, 1, 0.3, 0.1, 0.01) == pytest.approx(-1 - 0.02, abs=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# uniform states: O(N) multiplicity closed form of the finite-lattice sums
+# ---------------------------------------------------------------------------
+def uniform_closed_form(nx, ny, nz, m, J, k, D):
+    m = np.asarray(m, dtype=np.float64)
+    nb = (nx - 1) * ny * nz + nx * (ny - 1) * nz + nx * ny * (nz - 1)
+    e_ex = -J * nb
+    e_an = -k * nx * ny * nz * m[2] ** 2
+    e_dd = 0.0
+    for dx in range(-(nx - 1), nx):
+        for dy in range(-(ny - 1), ny):
+            for dz in range(-(nz - 1), nz):
+                if dx == dy == dz == 0:
+                    continue
+                mult = (nx - abs(dx)) * (ny - abs(dy)) * (nz - abs(dz))
+                r = math.sqrt(dx * dx + dy * dy + dz * dz)
+                c = (m[0] * dx + m[1] * dy + m[2] * dz) / r
+                e_dd += mult * (3 * c * c - 1) / r ** 3
+    e_dd *= -D / 2.0
+    return e_ex, e_an, e_dd
+
+
+@pytest.mark.parametrize("dims", [(5, 4, 3), (7, 3, 2), (6, 6, 1), (32, 32, 1), (64, 64, 1)])
+@pytest.mark.parametrize("mdir", [(0, 0, 1), (1, 0, 0), (0.6, 0, 0.8)])
+def test_uniform_state_closed_form(oracle, dims, mdir):
+    nx, ny, nz = dims
+    m = np.array(mdir, dtype=np.float64)
+    m /= np.linalg.norm(m)
+    s = np.broadcast_to(m.reshape(3, 1, 1, 1), (3, nz, ny, nx)).copy()
+    J, k, D = 1.0, 0.1, 0.01
+    e_ex, e_an, e_dd = uniform_closed_form(nx, ny, nz, m, J, k, D)
+    T = oracle.energy_terms(s)
+    assert J * T[0] == pytest.approx(e_ex, rel=1e-13, abs=1e-12)
+    assert T[1] == pytest.approx(0.0, abs=1e-12)  # DMI of a uniform state
+    assert k * T[2] == pytest.approx(e_an, rel=1e-13)
+    assert D * T[3] == pytest.approx(e_dd, rel=1e-12)
+    # the energy from the field (eq. (8)) agrees with the pair sums
+    h = oracle.field(s, J, 0.3, k, D)
+    assert oracle.energy_from_field(s, h) == pytest.approx(e_ex + e_an + e_dd, rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# DMI: 1D Neel spiral and the edge field of the uniform state
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("q", [0.1, 0.37, -0.8, 2.0])
+def test_dmi_spiral(oracle, q):
+    nx = 9
+    i = np.arange(nx)
+    s = np.zeros((3, 1, 1, nx))
+    s[0, 0, 0] = np.sin(q * i)
+    s[2, 0, 0] = np.cos(q * i)
+    T = oracle.energy_terms(s)
+    assert T[1] == pytest.approx(-(nx - 1) * math.sin(q), abs=1e-13)
+    assert T[0] == pytest.approx(-(nx - 1) * math.cos(q), abs=1e-13)
+    # same spiral along y: (r x z) = x for a y-bond, spins rotate in the y-z plane
+    s2 = np.zeros((3, 1, nx, 1))
+    s2[1, 0, :, 0] = np.sin(q * i)
+    s2[2, 0, :, 0] = np.cos(q * i)
+    assert oracle.energy_terms(s2)[1] == pytest.approx(-(nx - 1) * math.sin(q), abs=1e-13)
+
+
+def test_dmi_edge_field(oracle):
+    nx, ny, nz = 6, 5, 2
+    s = inputs.ferromagnet(nx, ny, nz)
+    d = 0.3
+    h = oracle.field(s, 0.0, d, 0.0, 0.0)
+    hx, hy = h[0], h[1]
+    expect_x = np.zeros((nz, ny, nx)); expect_x[:, :, 0] = -d; expect_x[:, :, -1] = d
+    expect_y = np.zeros((nz, ny, nx)); expect_y[:, 0, :] = -d; expect_y[:, -1, :] = d
+    np.testing.assert_allclose(hx, expect_x, atol=1e-15)
+    np.testing.assert_allclose(hy, expect_y, atol=1e-15)
+    np.testing.assert_allclose(h[2], 0.0, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# h = -dE/ds: central differences are exact for a quadratic energy
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dims,seed", [((3, 2, 2), 1), ((4, 3, 1), 2), ((2, 2, 3), 3), ((5, 1, 1), 4)])
+def test_field_is_minus_gradient(oracle, dims, seed):
+    nx, ny, nz = dims
+    s = rand_spins(nx, ny, nz, seed)
+    J, d, k, D = 0.9, 0.35, 0.21, 0.13
+    h = oracle.field(s, J, d, k, D)
+    eps = 1e-3
+    g = np.zeros_like(s)
+    it = np.nditer(s, flags=["multi_index"])
+    for _ in it:
+        idx = it.multi_index
+        sp = s.copy(); sp[idx] += eps
+        sm = s.copy(); sm[idx] -= eps
+        g[idx] = (oracle.energy(sp, J, d, k, D) - oracle.energy(sm, J, d, k, D)) / (2 * eps)
+    np.testing.assert_allclose(h, -g, atol=2e-11)
+
+
+def test_euler_identity(oracle):
+    for dims, seed in [((7, 5, 3), 11), ((16, 16, 1), 12)]:
+        s = rand_spins(*dims, seed)
+        J, d, k, D = 1.0, 0.3, 0.1, 0.02
+        h = oracle.field(s, J, d, k, D)
+        assert oracle.energy_from_field(s, h) == pytest.approx(oracle.energy(s, J, d, k, D),
+                                                               rel=1e-13, abs=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# eq. (1) in its literal vector form, brute force over pairs
+# ---------------------------------------------------------------------------
+def hamiltonian_vector_form(s, J, d, k, D):
+    _, nz, ny, nx = s.shape
+    pos = [(x, y, z) for z in range(nz) for y in range(ny) for x in range(nx)]
+    spin = {p: s[:, p[2], p[1], p[0]] for p in pos}
+    zhat = np.array([0.0, 0.0, 1.0])
+    E = 0.0
+    # nearest-neighbour pairs, each unordered pair once
+    for a, b in itertools.combinations(pos, 2):
+        r = np.array(b, dtype=float) - np.array(a, dtype=float)
+        dist = np.linalg.norm(r)
+        rhat = r / dist
+        si, sj = spin[a], spin[b]
+        if abs(dist - 1.0) < 1e-12:
+            E += -J * si.dot(sj) + d * np.cross(rhat, zhat).dot(np.cross(si, sj))
+        # dipolar term: (mu0/8pi) over ordered pairs == D over unordered pairs
+        E += -D * (3 * si.dot(rhat) * sj.dot(rhat) - si.dot(sj)) / dist ** 3
+    for p in pos:
+        E += -k * spin[p][2] ** 2
+    return E
+
+
+@pytest.mark.parametrize("dims,seed", [((3, 3, 2), 21), ((4, 2, 1), 22), ((2, 3, 3), 23)])
+def test_vector_form_hamiltonian(oracle, dims, seed):
+    s = rand_spins(*dims, seed)
+    J, d, k, D = 1.1, -0.45, 0.3, 0.08
+    assert oracle.energy(s, J, d, k, D) == pytest.approx(
+        hamiltonian_vector_form(s, J, d, k, D), rel=1e-13, abs=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# symmetries
+# ---------------------------------------------------------------------------
+def rot90(s):
+    """Rotate sample and spins by +90 deg about z: site (x,y) -> (n-1-y, x),
+    spin (sx,sy,sz) -> (-sy, sx, sz).  Arrays are [3, nz, ny, nx]."""
+    sx, sy, sz = s
+    # new[yn, xn] = old[y, x] with xn = n-1-y, yn = x  =>  new = old[n-1-xn, yn]... via transpose+flip
+    def pos(a):
+        return np.flip(np.swapaxes(a, -1, -2), axis=-1)
+    return np.stack([-pos(sy), pos(sx), pos(sz)])
+
+
+def mirror_x(s):
+    sx, sy, sz = s
+    f = lambda a: np.flip(a, axis=-1)
+    return np.stack([-f(sx), f(sy), f(sz)])
+
+
+def flip_layers(s):
+    sx, sy, sz = s
+    f = lambda a: np.flip(a, axis=-3)
+    return np.stack([f(sx), f(sy), -f(sz)])
+
+
+def test_rotation_c4(oracle):
+    s = rand_spins(5, 5, 2, 31)
+    J, d, k, D = 1.0, 0.3, 0.1, 0.05
+    # check the position map on an index: site (x=1, y=0) moves to (x=4, y=1)
+    a = np.zeros((3, 1, 5, 5)); a[2, 0, 0, 1] = 1.0
+    assert rot90(a)[2, 0, 1, 4] == 1.0
+    E = oracle.energy(s, J, d, k, D)
+    r = rot90(s)
+    assert oracle.energy(r, J, d, k, D) == pytest.approx(E, rel=1e-13)
+    np.testing.assert_allclose(oracle.field(r, J, d, k, D), rot90(oracle.field(s, J, d, k, D)),
+                               atol=1e-13)
+
+
+def test_mirror(oracle):
+    s = rand_spins(6, 4, 2, 32)
+    J, d, k, D = 1.0, 0.3, 0.1, 0.05
+    E = oracle.energy(s, J, d, k, D)
+    m = mirror_x(s)
+    assert oracle.energy(m, J, d, k, D) == pytest.approx(E, rel=1e-13)
+    np.testing.assert_allclose(oracle.field(m, J, d, k, D), mirror_x(oracle.field(s, J, d, k, D)),
+                               atol=1e-13)
+
+
+def test_time_reversal(oracle):
+    s = rand_spins(4, 5, 3, 33)
+    J, d, k, D = 1.0, 0.3, 0.1, 0.05
+    assert oracle.energy(-s, J, d, k, D) == pytest.approx(oracle.energy(s, J, d, k, D), rel=1e-14)
+    np.testing.assert_allclose(oracle.field(-s, J, d, k, D), -oracle.field(s, J, d, k, D), atol=1e-14)
+
+
+def test_layer_flip_only_without_dmi(oracle):
+    s = rand_spins(4, 4, 3, 34)
+    f = flip_layers(s)
+    # invariant for d = 0
+    assert oracle.energy(f, 1.0, 0.0, 0.1, 0.05) == pytest.approx(oracle.energy(s, 1.0, 0.0, 0.1, 0.05),
+                                                                   rel=1e-13)
+    # DMI changes sign under the flip: interfacial DMI breaks z -> -z
+    Ts, Tf = oracle.energy_terms(s), oracle.energy_terms(f)
+    assert Tf[1] == pytest.approx(-Ts[1], rel=1e-13)
+    assert abs(Ts[1]) > 1e-3
+
+
+def test_spin_rotation_invariance_heisenberg(oracle):
+    s = rand_spins(4, 3, 2, 35)
+    th = 0.7
+    R = np.array([[1, 0, 0], [0, math.cos(th), -math.sin(th)], [0, math.sin(th), math.cos(th)]])
+    r = np.einsum("ab,bzyx->azyx", R, s)
+    assert oracle.energy(r, 1.0, 0, 0, 0) == pytest.approx(oracle.energy(s, 1.0, 0, 0, 0), rel=1e-14)
+    # anisotropy and dipoles break it
+    assert abs(oracle.energy(r, 1.0, 0, 0.5, 0) - oracle.energy(s, 1.0, 0, 0.5, 0)) > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# string step 1: the projected descent step
+# ---------------------------------------------------------------------------
+def test_step_descends_and_keeps_unit_norm(oracle):
+    s = np.stack([rand_spins(6, 5, 2, 40 + i) for i in range(3)])
+    J, d, k, D = 1.0, 0.3, 0.1, 0.05
+    h = np.stack([oracle.field(si, J, d, k, D) for si in s])
+    s1 = oracle.step(s, h, 0.01)
+    np.testing.assert_allclose((s1 ** 2).sum(axis=1), 1.0, atol=1e-15)
+    for i in range(3):
+        assert oracle.energy(s1[i], J, d, k, D) < oracle.energy(s[i], J, d, k, D)
+    # a field parallel to the spin produces no motion
+    s2 = oracle.step(s, 3.0 * s, 0.1)
+    np.testing.assert_allclose(s2, s, atol=1e-15)
+
+
+def test_step_single_spin_closed_form(oracle):
+    """Spin at polar angle a, field along +z: s + tau*(h - (s.h)s) stays in
+    the x-z plane and its angle becomes atan2(sin a - tau h sin a cos a ... )."""
+    a, tau, hz = 1.1, 0.3, 0.7
+    s = np.array([math.sin(a), 0.0, math.cos(a)]).reshape(1, 3, 1, 1, 1)
+    h = np.array([0.0, 0.0, hz]).reshape(1, 3, 1, 1, 1)
+    out = oracle.step(s, h, tau).ravel()
+    # h_perp = hz * sin(a) * (-cos a, 0, sin a): moves the polar angle toward 0
+    vx = math.sin(a) - tau * hz * math.sin(a) * math.cos(a)
+    vz = math.cos(a) + tau * hz * math.sin(a) ** 2
+    n = math.hypot(vx, vz)
+    np.testing.assert_allclose(out, [vx / n, 0.0, vz / n], atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# string step 2: arc-length reparametrisation
+# ---------------------------------------------------------------------------
+def rotating_string(thetas, N=3):
+    """Every spin of image k at angle theta_k in the x-z plane."""
+    K = len(thetas)
+    s = np.zeros((K, 3, 1, 1, N))
+    for kk, t in enumerate(thetas):
+        s[kk, 0] = math.sin(t)
+        s[kk, 2] = math.cos(t)
+    return s
+
+
+def test_reparam_uniform_string_is_fixed(oracle):
+    th = np.linspace(0.0, 2.5, 7)
+    s = rotating_string(th)
+    out, al, jj, w, applied = oracle.reparam(s)
+    assert applied
+    np.testing.assert_allclose(al, np.arange(7) / 6, atol=1e-15)
+    np.testing.assert_allclose(out, s, atol=1e-14)
+    assert np.array_equal(out[0], s[0]) and np.array_equal(out[-1], s[-1])
+
+
+def test_reparam_chord_closed_form(oracle):
+    """Non-uniform angles on a great circle: the chords are 2 sin(delta/2)
+    per spin; the interpolated spin on chord j at weight w, renormalised,
+    sits at angle theta_j + atan2(w sin delta_j, 1 - w + w cos delta_j)."""
+    th = np.array([0.0, 0.1, 0.5, 0.6, 1.4, 2.0, 2.05, 2.9])
+    K = len(th)
+    s = rotating_string(th, N=4)
+    out, al, jj, w, applied = oracle.reparam(s)
+    chords = 2 * np.sin(np.diff(th) / 2)
+    S = np.concatenate([[0.0], np.cumsum(chords)])
+    alpha = S / S[-1]
+    np.testing.assert_allclose(al, alpha, atol=1e-15)
+    for k in range(1, K - 1):
+        t = k / (K - 1)
+        j = max(i for i in range(K - 1) if alpha[i] <= t)
+        ww = (t - alpha[j]) / (alpha[j + 1] - alpha[j])
+        dl = th[j + 1] - th[j]
+        ang = th[j] + math.atan2(ww * math.sin(dl), 1 - ww + ww * math.cos(dl))
+        assert jj[k] == j
+        np.testing.assert_allclose(out[k, 0], math.sin(ang), atol=1e-14)
+        np.testing.assert_allclose(out[k, 2], math.cos(ang), atol=1e-14)
+    assert np.array_equal(out[0], s[0]) and np.array_equal(out[-1], s[-1])
+
+
+def test_reparam_equalises_segments(oracle):
+    """After reparametrisation of a smooth string the chord lengths are equal
+    up to O(dalpha^2)."""
+    K = 20
+    u = np.linspace(0, 1, K) ** 2  # strongly non-uniform
+    base = inputs.bloch_point_string(8, 8, 1, 200, 2.5)
+    idx = np.round(u * 199).astype(int)
+    s = base[idx]
+    out, *_ = oracle.reparam(s)
+    seg = np.sqrt(((out[1:] - out[:-1]) ** 2).reshape(K - 1, -1).sum(axis=1))
+    assert seg.std() / seg.mean() < 0.02
+    seg0 = np.sqrt(((s[1:] - s[:-1]) ** 2).reshape(K - 1, -1).sum(axis=1))
+    assert seg0.std() / seg0.mean() > 0.3
+
+
+def test_reparam_degenerate(oracle):
+    s = rotating_string([0.3] * 5)  # all images equal: zero total length
+    out, al, jj, w, applied = oracle.reparam(s)
+    assert not applied
+    assert np.array_equal(out, s)
+
+
+# ---------------------------------------------------------------------------
+# perpendicular force and tangents
+# ---------------------------------------------------------------------------
+def one_spin_string(vecs):
+    return np.array(vecs, dtype=np.float64).reshape(len(vecs), 3, 1, 1, 1)
+
+
+def test_force_norm_closed_forms(oracle):
+    k = 1.0
+    a, b = 0.7, 0.4
+    # tangent perpendicular to the (meridian) force: norm = k |sin 2a|
+    s = one_spin_string([
+        [math.sin(a) * math.cos(b), -math.sin(a) * math.sin(b), math.cos(a)],
+        [math.sin(a), 0.0, math.cos(a)],
+        [math.sin(a) * math.cos(b), math.sin(a) * math.sin(b), math.cos(a)],
+    ])
+    h = np.stack([oracle.field(si, 0.0, 0.0, k, 0.0) for si in s])
+    n, t = oracle.force_norm(s, h, want_tangents=True)
+    assert n == pytest.approx(k * abs(math.sin(2 * a)), rel=1e-14)
+    np.testing.assert_allclose(t[1].ravel(), [0.0, 1.0, 0.0], atol=1e-15)
+    # meridian string from +z to +x: force parallel to the path, endpoints stationary
+    s = one_spin_string([[0, 0, 1], [math.sin(a), 0, math.cos(a)], [1, 0, 0]])
+    h = np.stack([oracle.field(si, 0.0, 0.0, k, 0.0) for si in s])
+    assert oracle.force_norm(s, h) == pytest.approx(0.0, abs=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# whole iterations
+# ---------------------------------------------------------------------------
+def test_iterate_stationary_string(oracle):
+    """Uniform +z string with no DMI or dipoles is a fixed point."""
+    s = np.stack([inputs.ferromagnet(5, 4, 2)] * 4)
+    r = oracle.iterate(s, 1.0, 0.0, 0.1, 0.0, 5, 0.1, want_fields=True)
+    np.testing.assert_array_equal(r["s"], s)
+    e_ex, e_an, _ = uniform_closed_form(5, 4, 2, [0, 0, 1], 1.0, 0.1, 0.0)
+    np.testing.assert_allclose(r["E"], e_ex + e_an, rtol=1e-14)
+    assert r["iters"] == 5
+    assert r["force"] == 0.0
+
+
+def test_iterate_composes_documented_steps(oracle):
+    """One oracle iteration equals field -> step -> reparam, and the final
+    energies are those of the returned string."""
+    w = dict(inputs.WORKLOADS["bloch_32x32x1_k10"])
+    s0 = inputs.perturb(inputs.bloch_point_string(10, 9, 1, 5, 2.5), 7)
+    J, d, k, D = w["J"], w["d"], w["ku"], w["D"]
+    r = oracle.iterate(s0, J, d, k, D, 1, 0.1)
+    h = np.stack([oracle.field(si, J, d, k, D) for si in s0])
+    s1, *_ = oracle.reparam(oracle.step(s0, h, 0.1))
+    np.testing.assert_allclose(r["s"], s1, atol=1e-15)
+    E = [oracle.energy(si, J, d, k, D) for si in r["s"]]
+    np.testing.assert_allclose(r["E"], E, rtol=1e-12)
+
+
+def test_iterate_convergence_stops(oracle):
+    s0 = inputs.perturb(inputs.bloch_point_string(6, 6, 1, 4, 1.5), 9)
+    r = oracle.iterate(s0, 1.0, 0.3, 0.1, 0.01, 5000, 0.1, tol=2e-2, every=5)
+    assert r["iters"] % 5 == 0 and 0 < r["iters"] < 5000
+    assert r["force"] < 2e-2
+    # one check earlier the criterion was not yet met
+    r2 = oracle.iterate(s0, 1.0, 0.3, 0.1, 0.01, r["iters"] - 5, 0.1)
+    assert r2["force"] >= 2e-2
+
+
+def test_initial_string_shapes():
+    s = inputs.build_string(inputs.WORKLOADS["bloch_32x32x1_k10"])
+    assert s.shape == (10, 3, 1, 32, 32)
+    np.testing.assert_allclose((s ** 2).sum(axis=1), 1.0, atol=1e-14)
+    sk = inputs.neel_skyrmion(33, 33, 1, 5.0)
+    np.testing.assert_allclose(sk[:, 0, 16, 16], [0, 0, -1], atol=1e-15)
+    # inward in-plane component: at (x = cx + r, y = cy) the x-component is negative
+    assert sk[0, 0, 16, 20] < 0
+    b = inputs.boundary_string(64, 64, 1, 20, 5.0)
+    np.testing.assert_array_equal(b[-1], inputs.ferromagnet(64, 64, 1))
