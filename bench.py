@@ -1,0 +1,205 @@
+"""Benchmark of the string-method hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
+
+One step = one string iteration over every image of the workload: field of
+every image (FFT dipolar convolution + exchange/DMI/anisotropy stencils),
+FP64 energies, projected descent step with renormalisation, FP64 arc
+lengths, reparametrisation.  The headline value is site-field evaluations
+per second of the FP32-mixed form replayed as a HIP graph; the FP64 plain
+form (direct launches) runs the same workload for the speed-up and the
+barrier difference.  Inputs are synthetic (seeded skyrmion-tube string) and
+already resident in HBM when timing starts.  Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "site-field evals/s + string iters/s; FP32-batched vs FP64 plain at 1e-4 barrier"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1804_07135_amd/csrc/ssm_kernels.hip", "paper_1804_07135_amd/csrc/ssm_internal.hpp"]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(w, ts):
+    """Bytes each kernel must move per launch (one iteration), spin scalar size ts."""
+    nx, ny, nz, K = w["nx"], w["ny"], w["nz"], w["K"]
+    mx = 1
+    while mx < nx:
+        mx *= 2
+    my = 1
+    while my < ny:
+        my *= 2
+    pz = 1 if nz == 1 else 2 * (1 << (nz - 1).bit_length())
+    N = nx * ny * nz
+    spins = K * 3 * N * ts                         # one string
+    xspec = K * (mx + 1) * 3 * nz * ny * 2 * ts    # x half-spectra of one string
+    nhat = (mx + 1) * 2 * my * pz * 6 * ts         # dipole-kernel spectrum
+    interior = K - 2
+    return {
+        "k_xfwd": spins + xspec,
+        "k_conv": 2 * xspec + nhat,
+        "k_xinv": xspec + 2 * spins,
+        "k_arc": spins,
+        "k_interp": spins * (2 * interior + 2) / K + spins,
+    }
+
+
+def time_iterations(sm, steps, tau):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sm.iterate(steps, tau)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(w, s0, budget_s):
+    """The oracle (direct O(N^2) dipole sum, FP64, OpenMP) timed on this host:
+    fields at a sample of sites of image 0."""
+    import numpy as np
+    from oracle import oracle
+    oracle.build()
+    N = w["nx"] * w["ny"] * w["nz"]
+    rng = np.random.default_rng(0)
+    n = 64
+    t = 0.0
+    while True:
+        sites = rng.choice(N, size=n, replace=False)
+        t0 = time.perf_counter()
+        oracle.field_at(s0[0], w["J"], w["d"], w["ku"], w["D"], sites)
+        t = time.perf_counter() - t0
+        if t > budget_s / 4 or n >= N:
+            break
+        n = min(N, int(n * max(2.0, budget_s / 4 / max(t, 1e-3))))
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n / t, "unit": "site-field evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"direct-sum fields at {n} random sites of image 0 of the "
+                      f"{w['nx']}x{w['ny']}x{w['nz']} lattice ({t:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="tube_256x256x8_k48")
+    ap.add_argument("--graph-chunk", type=int, default=10)
+    ap.add_argument("--fp64-steps", type=int, default=0, help="steps of the FP64 plain run (0: = --steps)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method is built and "
+              "measured on a single MI355X", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1804_07135_amd import inputs, ssm
+
+    w = dict(inputs.WORKLOADS[args.workload])
+    prob = dict(nx=w["nx"], ny=w["ny"], nz=w["nz"], K=w["K"], J=w["J"], d=w["d"], ku=w["ku"], D=w["D"])
+    s0 = inputs.build_string(w)
+    KN = w["K"] * w["nx"] * w["ny"] * w["nz"]
+    tau = w["tau"]
+    steps, warm = args.steps, args.warmup
+
+    # --- FP32-mixed form, graph replay -------------------------------------
+    sm = ssm.StringMethod(prob, ssm.SSM_FP32_MIXED)
+    sm.set_options(check_every=10, graph_chunk=args.graph_chunk)
+    sm.set_string(s0)
+    sm.iterate(warm, tau)
+    dt32 = time_iterations(sm, steps, tau)
+    bar32 = sm.barrier().cpu().numpy()[0]
+    flags = sm.check()
+    # per-kernel durations with HIP events on the library's stream, same steps
+    sm.profile(True)
+    sm.profile_read()
+    dt32_ev = time_iterations(sm, steps, tau)
+    prof = sm.profile_read()
+    sm.profile(False)
+    del sm
+    torch.cuda.empty_cache()
+
+    # --- FP64 plain form, direct launches ----------------------------------
+    st64 = args.fp64_steps or steps
+    sm64 = ssm.StringMethod(prob, ssm.SSM_FP64)
+    sm64.set_string(s0)
+    sm64.iterate(warm, tau)
+    dt64 = time_iterations(sm64, st64, tau)
+    bar64 = sm64.barrier().cpu().numpy()[0]
+    del sm64
+    torch.cuda.empty_cache()
+
+    # barrier of both forms after the same number of iterations (warm + steps)
+    same_iters = (st64 == steps)
+    bar_err = float(abs(bar32[0] - bar64[0]) / max(abs(bar64[0]), 1e-300)) if same_iters else None
+
+    value = steps * KN / dt32
+    value64 = st64 * KN / dt64
+    # dominant kernel and its roofline
+    ab = algorithmic_bytes(w, 4)
+    kern = {k: {"ms_total": v[0], "launches": v[1], "ms_avg": v[0] / max(v[1], 1)} for k, v in prof.items()}
+    dom = max((k for k in kern if k in ab), key=lambda k: kern[k]["ms_total"])
+    achieved = ab[dom] / (kern[dom]["ms_avg"] * 1e-3) / 1e9
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", f"traffic_{dom}_{args.workload}_fp32.json")
+    if os.path.exists(tpath):
+        with open(tpath) as fh:
+            tr = json.load(fh)
+        if tr.get("kernel_source_hash") == kernel_source_hash():
+            traffic = tr.get("bytes_per_launch")
+    floor_bytes = 72 * KN  # read/write floor of one fused FP32 iteration
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "site-field evals/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": dt32 / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "lattice": [w["nx"], w["ny"], w["nz"]], "images": w["K"],
+                   "params": {"J": w["J"], "d": w["d"], "ku": w["ku"], "dip": w["D"]}, "tau": tau,
+                   "form": "FP32 spins/FFT/field storage, FP64 per-site arithmetic, energies, arc lengths "
+                           "and barrier; iterations replayed as a HIP graph of %d" % args.graph_chunk},
+        "string_iters_per_s": steps / dt32,
+        "fp64_plain": {"value": value64, "unit": "site-field evals/s", "steps": st64,
+                       "ms_per_step": dt64 / st64 * 1e3, "string_iters_per_s": st64 / dt64},
+        "speedup_fp32_batched_vs_fp64_plain": value / value64,
+        "barrier_fp32": float(bar32[0]),
+        "barrier_fp64": float(bar64[0]),
+        "barrier_rel_err_fp32_vs_fp64": bar_err,
+        "failure_flags": int(flags),
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": ab[dom], "avg_launch_ms": kern[dom]["ms_avg"]},
+        "iteration_floor_frac": floor_bytes / (dt32 / steps) / 1e9 / HBM_PEAK_GBS,
+        "kernels_ms_avg": {k: round(v["ms_avg"], 5) for k, v in kern.items()},
+        "ms_per_step_with_events": dt32_ev / steps * 1e3,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, s0, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

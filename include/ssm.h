@@ -1,0 +1,227 @@
+/*
+ * ssm.h -- C ABI of the MI355X (gfx950) simplified-string-method library.
+ *
+ * The library computes minimum energy paths and energy barriers of an
+ * atomistic spin model with the simplified string method, following
+ * Heistracher et al., "GPU Accelerated Atomistic Energy Barrier Calculations
+ * of Skyrmion Annihilations" (arXiv:1804.07135):
+ *   - Hamiltonian, eq. (1): nearest-neighbour exchange J, interfacial DMI d
+ *     with DMI vector r_ij x z, uniaxial anisotropy k_u along z and the full
+ *     dipole-dipole sum, on a simple cubic lattice with free boundaries;
+ *   - effective field, eqs. (2)-(7): exchange/DMI/anisotropy stencils plus
+ *     the dipolar field as a zero-padded FFT convolution with the
+ *     point-dipole tensor (Sec. II.A);
+ *   - energy from the field, eq. (8);
+ *   - string iteration, Sec. III: every image takes one damping-only descent
+ *     step along the force of the Appendix (the field component
+ *     perpendicular to each spin, eq. (10)) and is renormalised; the string
+ *     is then reparametrised to equal arc length, eqs. (11)-(12).
+ *
+ * Units.  Reduced units with the lattice constant as the length unit and
+ * unit spins.  Fields are h = mu0 |S| H_eff = -dE/ds, so eq. (3) reads
+ * h_ex = J sum_nn s_j, eq. (5) reads h_an = 2 k_u s_z z, and the dipolar
+ * pair energy is -dip [3(s_i.r)(s_j.r) - s_i.s_j]/r^3 per unordered pair
+ * with dip = mu0 |S|^2 / (4 pi a^3).  Every nearest-neighbour bond is
+ * counted once.
+ *
+ * Layout.  A string of K images on an nx*ny*nz lattice is stored
+ * structure-of-arrays, x fastest: element (k, c, z, y, x) sits at
+ *   ((k*3 + c)*nz + z)*ny*nx + y*nx + x,
+ * c = 0,1,2 for the x,y,z spin components.  A batch of problems stores the
+ * strings of its problems one after another in creation order.  Spins,
+ * fields and tangents are double for SSM_FP64 and float for SSM_FP32_MIXED;
+ * energies, per-term energies, barriers and force norms are always double.
+ *
+ * Memory.  Every pointer argument named d_* is device memory owned by the
+ * caller; the library only borrows it for the work it enqueues.  The
+ * library never allocates device memory: all of its state lives in one
+ * caller-provided workspace whose size ssm_workspace_size() returns.  The
+ * context object itself is host memory owned by the library.
+ *
+ * Streams.  Every call enqueues its work on the stream given to
+ * ssm_create() (a hipStream_t passed as void*; NULL = the default stream)
+ * and returns without waiting, except ssm_workspace_size, ssm_check,
+ * ssm_profile_read, ssm_autotune and ssm_iterate with tol_force > 0, which
+ * synchronise that stream.
+ *
+ * Errors.  Functions return SSM_OK (0) or a negative status; nothing
+ * throws across the ABI.  Argument errors are detected before anything is
+ * enqueued.  HIP runtime failures return SSM_EHIP; ssm_last_error() then
+ * holds the HIP error text.  A context is used by one host thread at a
+ * time; distinct contexts are independent.
+ *
+ * Limits.  1 <= nx, ny <= 1024 and 1 <= nz <= 16; 2 <= n_images <= 1024;
+ * at most 256 problems per context; every problem of a context has nz
+ * values that round up to the same power of two; one (y, z) plane of
+ * x-spectra, 3 * nz * m_y complex values with m_y the power of two >= ny,
+ * fits in 160 KiB of LDS (so nz * m_y <= 4096 for SSM_FP64 and 6826 for
+ * SSM_FP32_MIXED).  Exceeding a limit returns SSM_EUNSUPPORTED.
+ */
+#ifndef SSM_H
+#define SSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ssm_ctx ssm_ctx;
+typedef int32_t ssm_status;
+
+#define SSM_OK 0
+#define SSM_EINVAL (-1)        /* bad argument (null pointer, K < 2, dim < 1, ...) */
+#define SSM_ESTATE (-2)        /* call not valid in the current state */
+#define SSM_EHIP (-3)          /* a HIP runtime call failed; see ssm_last_error */
+#define SSM_ENONFINITE (-4)    /* ssm_check found a non-finite energy or spin */
+#define SSM_EUNSUPPORTED (-5)  /* size or option outside the documented limits */
+
+#define SSM_FP64 0        /* spins, FFTs, fields and all reductions in FP64 */
+#define SSM_FP32_MIXED 1  /* spins, spectra and FFTs in FP32; per-site field
+                             arithmetic, energies, arc lengths, weights and the
+                             barrier in FP64 */
+
+/* ssm_check flag bits */
+#define SSM_FLAG_NONFINITE_ENERGY 1
+#define SSM_FLAG_ZERO_NORM_SPIN 2
+#define SSM_FLAG_NONFINITE_SPIN 4
+
+/* One lattice + parameter set (reduced units, see above).  K = n_images. */
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t n_images;
+    double J;    /* exchange, eq. (1) first term */
+    double d;    /* interfacial DMI, eq. (1) second term */
+    double ku;   /* uniaxial anisotropy, eq. (1) third term */
+    double dip;  /* dipolar strength mu0 |S|^2/(4 pi a^3), eq. (1) last term */
+} ssm_problem;
+
+/* Library version (monotonic integer). */
+int32_t ssm_version(void);
+
+/* Bytes of device workspace a context for these problems needs.
+ * p[n_problems]: problem descriptions (host memory).  precision: SSM_FP64
+ * or SSM_FP32_MIXED.  *bytes receives the size.  Pure host computation. */
+ssm_status ssm_workspace_size(const ssm_problem* p, int32_t n_problems, int32_t precision,
+                              size_t* bytes);
+
+/* Create a context over a caller-owned workspace of ws_bytes bytes at
+ * d_workspace (256-byte aligned, at least ssm_workspace_size bytes).
+ * n_problems > 1 batches several lattices and parameter sets so that every
+ * kernel of an iteration covers all of them in one launch.  Builds the FFT
+ * of the point-dipole tensor of eq. (7) on the zero-padded grid of every
+ * distinct lattice shape (Sec. II.A: the dipolar field as a circular
+ * convolution) and synchronises the stream once.  *out receives the
+ * context.  The string is undefined until ssm_set_string. */
+ssm_status ssm_create(const ssm_problem* p, int32_t n_problems, int32_t precision,
+                      void* d_workspace, size_t ws_bytes, void* stream, ssm_ctx** out);
+
+/* Destroy a context (host memory and HIP graph objects only; the workspace
+ * stays the caller's).  Waits for the context's stream.  NULL is a no-op. */
+ssm_status ssm_destroy(ssm_ctx* ctx);
+
+/* Change the parameters (eq. (1)) of one problem.  Applies to work enqueued
+ * afterwards. */
+ssm_status ssm_set_params(ssm_ctx* ctx, int32_t problem, double J, double d, double ku,
+                          double dip);
+
+/* Copy a whole string (all problems, layout above, spin dtype of the
+ * context's precision) from d_spins into the context.  Spins are used as
+ * given (not renormalised); they must be unit vectors. */
+ssm_status ssm_set_string(ssm_ctx* ctx, const void* d_spins);
+
+/* Copy the current string out to d_spins (same layout and dtype). */
+ssm_status ssm_get_string(ssm_ctx* ctx, void* d_spins);
+
+/* Run up to max_iter string iterations (Sec. III) with descent step tau
+ * (reduced time units 1/J).  One iteration = field and energy of every image
+ * (eqs. (2)-(8)), the projected descent step with renormalisation of every
+ * image including both endpoints (eq. (10), Appendix), the arc lengths
+ * (eq. (11)) and the interpolation onto alpha_k = k/(K-1) (eq. (12)).
+ * tol_force > 0: the perpendicular-force norm (ssm_get_tangents) of the
+ * current string is checked every check_every iterations (ssm_set_options)
+ * before iterating, and a problem whose norm is below tol_force stops; the
+ * call synchronises the stream at every check.  After the loop the string
+ * is evaluated once more: ssm_get_energies/fields/barrier return that
+ * evaluation.  d_iters_done (device int32[n_problems] or NULL) receives the
+ * iterations each problem performed in this call. */
+ssm_status ssm_iterate(ssm_ctx* ctx, int32_t max_iter, double tau, double tol_force,
+                       int32_t* d_iters_done);
+
+/* Evaluate field and energies of a string without changing the context's
+ * string.  d_spins: a string in the context layout, or NULL for the
+ * current string (which also refreshes what ssm_get_energies/fields/barrier
+ * return).  d_field_or_null receives h = -dE/ds (spin layout and dtype).
+ * d_energy receives E_k = -1/2 sum h.s per image (eq. (8)), double[sum K].
+ * d_terms_or_null receives, per image, the unit-parameter term energies
+ * (T_J, T_d, T_ku, T_dip) with E = J T_J + d T_d + ku T_ku + dip T_dip
+ * (eq. (1) is linear in each parameter), double[sum K][4]. */
+ssm_status ssm_eval(ssm_ctx* ctx, const void* d_spins, void* d_field_or_null,
+                    double* d_energy, double* d_terms_or_null);
+
+/* Energies of the current string from the last evaluation (double[sum K]). */
+ssm_status ssm_get_energies(ssm_ctx* ctx, double* d_energy);
+
+/* Field h of the current string from the last evaluation (spin layout). */
+ssm_status ssm_get_fields(ssm_ctx* ctx, void* d_field);
+
+/* Path tangents of the current string and the perpendicular-force norm.
+ * An MEP has the potential force parallel to the path (Sec. III).  Tangent
+ * t_k: phi_{k+1} - phi_{k-1} (one-sided at the endpoints), each spin's part
+ * projected onto that spin's tangent plane, normalised in R^{3N}.  Force:
+ * h_perp = h - (s.h)s per spin (Appendix); F_perp = h_perp - (h_perp.t)t
+ * for interior images and h_perp at the endpoints.  Needs the field of the
+ * current string (ssm_iterate or ssm_eval(ctx, NULL, ...) first, else
+ * SSM_ESTATE).  d_tangent (spin layout, or NULL) receives t;
+ * d_force_norm_or_null (double[n_problems]) receives
+ * max_k max_i |F_perp,k,i| per problem. */
+ssm_status ssm_get_tangents(ssm_ctx* ctx, void* d_tangent, double* d_force_norm_or_null);
+
+/* Barrier of every problem from the last evaluation (Sec. III: the energy of
+ * the highest image relative to the first).  d_out: double[n_problems][6] =
+ * {B = max_k E_k - E_0, argmax k (smallest on ties),
+ *  dB/dJ, dB/dd, dB/dku, dB/ddip}; the derivatives are the envelope-theorem
+ * values T_theta(k*) - T_theta(0), valid at a converged path. */
+ssm_status ssm_get_barrier(ssm_ctx* ctx, double* d_out);
+
+/* Options.  check_every >= 1: iterations between convergence checks
+ * (default 10).  graph_chunk >= 0: when > 0, ssm_iterate replays a HIP
+ * graph holding graph_chunk iterations instead of launching kernels one by
+ * one (default 0). */
+ssm_status ssm_set_options(ssm_ctx* ctx, int32_t check_every, int32_t graph_chunk);
+
+/* Time the candidate tile shapes of the x-transform and convolution kernels
+ * on this context's problems and keep the fastest.  Uses the current string
+ * as input and leaves it unchanged; synchronises the stream.  cache_path
+ * (or NULL): a text file of previous results keyed by device name, precision
+ * and lattice shape; read if present, appended with new results. */
+ssm_status ssm_autotune(ssm_ctx* ctx, const char* cache_path);
+
+/* Synchronise the stream and read the sticky failure flags (SSM_FLAG_*,
+ * set by kernels on a non-finite energy or an interpolated spin of norm
+ * < 1e-12) into *h_flags, then clear them.  Returns SSM_ENONFINITE when a
+ * non-finite flag is set. */
+ssm_status ssm_check(ssm_ctx* ctx, int32_t* h_flags);
+
+/* Text of the last error on this context ("" if none).  ctx may be NULL for
+ * errors of ssm_create. */
+const char* ssm_last_error(const ssm_ctx* ctx);
+
+/* Kernel timing.  enable != 0: every kernel launch is bracketed by HIP
+ * events on the context's stream (graph replay is then replaced by direct
+ * launches).  ssm_profile_read synchronises, adds the elapsed times per
+ * kernel kind since enabling into h_ms[SSM_N_KERNELS] (milliseconds) and
+ * h_counts[SSM_N_KERNELS] (launches), and resets the accumulators. */
+#define SSM_N_KERNELS 12
+ssm_status ssm_profile(ssm_ctx* ctx, int32_t enable);
+ssm_status ssm_profile_read(ssm_ctx* ctx, double* h_ms, int32_t* h_counts);
+
+/* Name of kernel kind i (0 <= i < SSM_N_KERNELS), or NULL. */
+const char* ssm_kernel_name(int32_t i);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSM_H */

@@ -1,0 +1,872 @@
+// Host runtime and C ABI of the gfx950 simplified-string-method library.
+// See include/ssm.h for the contract of every entry point.
+#include "ssm.h"
+#include "ssm_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using namespace ssm;
+
+namespace {
+
+constexpr int kVersion = 1;
+constexpr size_t kAlign = 256;
+constexpr size_t kLdsMax = 160 * 1024;
+constexpr size_t kLdsBudget = 150 * 1024;
+
+thread_local std::string g_create_error;
+
+const char* const kKernelNames[SSM_N_KERNELS] = {
+    "k_xfwd", "k_conv", "k_xinv", "k_arc", "k_reduce", "k_interp",
+    "k_tan1", "k_tan2", "k_tanred", "k_spec", "k_util", "graph"};
+
+int pow2ceil(int n)
+{
+    int m = 1;
+    while (m < n) m <<= 1;
+    return m;
+}
+
+int ilog2(int m)
+{
+    int l = 0;
+    while ((1 << l) < m) ++l;
+    return l;
+}
+
+size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Tiles {
+    int yt;
+    int gconv;
+};
+
+// Everything about a batch that follows from the problem list: descriptors,
+// work maps and the carve-up of the workspace.
+struct Plan {
+    int prec = 0;
+    int np = 0;
+    int mz = 1;
+    size_t tsize = 8;                 // bytes of one spin component
+    std::vector<Prob> P;
+    std::vector<int> geo;             // problem -> distinct-shape index
+    std::vector<std::tuple<int, int, int>> shapes;
+    std::vector<long long> nh_size;   // elements per distinct shape
+    std::vector<int> wm_xt, wm_conv, wm_arc, wm_site;
+    long long n_img = 0, n_spin = 0, n_x = 0, n_nh = 0, n_ep = 0, n_ap = 0, n_fp = 0, n_fm = 0;
+    size_t lds_x = 0, lds_conv = 0;
+    size_t scratch_bytes = 0;
+    // workspace offsets
+    size_t o_P, o_wm, o_tw, o_tw64, o_s, o_ss, o_h, o_nh, o_big, o_ep, o_ap, o_fp, o_E, o_T,
+        o_alpha, o_w, o_tc, o_fn, o_fm, o_j, o_done, o_iters, o_skip, o_flags, o_it0, total;
+};
+
+size_t lds_xtile(const Prob& p, size_t tsize)
+{
+    return (size_t)3 * p.yt * p.mx * 2 * tsize + (size_t)3 * p.yt * p.nx * tsize;
+}
+
+size_t lds_convg(const Prob& p, int G, size_t tsize)
+{
+    return (size_t)G * 3 * p.nz * p.my * 2 * tsize;
+}
+
+ssm_status check_problems(const ssm_problem* pr, int np, int prec, std::string& err)
+{
+    if (!pr || np < 1) { err = "no problems"; return SSM_EINVAL; }
+    if (np > 256) { err = "more than 256 problems"; return SSM_EUNSUPPORTED; }
+    if (prec != SSM_FP64 && prec != SSM_FP32_MIXED) { err = "unknown precision"; return SSM_EINVAL; }
+    int mz0 = -1;
+    for (int i = 0; i < np; ++i) {
+        const ssm_problem& q = pr[i];
+        if (q.nx < 1 || q.ny < 1 || q.nz < 1 || q.n_images < 2) {
+            err = "problem " + std::to_string(i) + ": dims must be >= 1 and n_images >= 2";
+            return SSM_EINVAL;
+        }
+        if (!std::isfinite(q.J) || !std::isfinite(q.d) || !std::isfinite(q.ku) || !std::isfinite(q.dip)) {
+            err = "problem " + std::to_string(i) + ": non-finite parameter";
+            return SSM_EINVAL;
+        }
+        if (q.nx > 1024 || q.ny > 1024 || q.nz > 16 || q.n_images > 1024) {
+            err = "problem " + std::to_string(i) + ": size beyond the supported limits";
+            return SSM_EUNSUPPORTED;
+        }
+        const int mz = q.nz > 1 ? pow2ceil(q.nz) : 1;
+        if (mz0 >= 0 && mz != mz0) {
+            err = "all problems of a context need nz rounding to the same power of two";
+            return SSM_EUNSUPPORTED;
+        }
+        mz0 = mz;
+        const long long elems = (long long)q.n_images * 3 * q.nx * q.ny * q.nz;
+        if (elems > (1LL << 40)) { err = "string too large"; return SSM_EUNSUPPORTED; }
+    }
+    return SSM_OK;
+}
+
+// default tile shapes; autotuning may replace them
+Tiles default_tiles(const Prob& p, size_t tsize)
+{
+    Tiles t;
+    const int cs = (int)(2 * tsize);                  // bytes per complex value
+    int yt = std::max(2, 128 / cs);                   // 128-byte output chunks
+    const int ycap = std::max(2, pow2ceil(p.ny));
+    Prob q = p;
+    while (3 * yt * p.mx < 1536 && yt < ycap) yt *= 2;
+    yt = std::min(yt, ycap);
+    q.yt = yt;
+    while (yt > 2 && lds_xtile(q, tsize) > kLdsBudget) { yt /= 2; q.yt = yt; }
+    t.yt = yt;
+    const int per = 3 * p.nz * p.ny;
+    int gmax = std::max(1, kConvElems / per);
+    while (gmax > 1 && lds_convg(p, gmax, tsize) > kLdsBudget) --gmax;
+    const long long slices = (long long)p.K * (p.mx + 1);
+    int g = (int)std::max<long long>(1, std::min<long long>(gmax, slices / 1024));
+    t.gconv = g;
+    return t;
+}
+
+void apply_tiles(Prob& p, const Tiles& t)
+{
+    p.yt = t.yt;
+    p.nty = (p.ny + p.yt - 1) / p.yt;
+    p.tiles = p.nz * p.nty;
+    p.gconv = t.gconv;
+    p.xcd_remap = (t.gconv == 1) ? 1 : 0;
+}
+
+int conv_wgs(const Prob& p)
+{
+    if (p.xcd_remap) return ((p.mx + 1 + 7) / 8) * 8 * p.K;
+    const long long slices = (long long)p.K * (p.mx + 1);
+    const int w = (int)((slices + p.gconv - 1) / p.gconv);
+    return (w + 7) / 8 * 8;
+}
+
+ssm_status build_plan(const ssm_problem* pr, int np, int prec, const std::vector<Tiles>* tiles,
+                      Plan& pl, std::string& err)
+{
+    ssm_status st = check_problems(pr, np, prec, err);
+    if (st != SSM_OK) return st;
+    pl = Plan();
+    pl.prec = prec;
+    pl.np = np;
+    pl.tsize = prec == SSM_FP64 ? 8 : 4;
+    pl.P.resize(np);
+    pl.geo.resize(np);
+    std::map<std::tuple<int, int, int>, int> shape_id;
+    long long img = 0, spin = 0, xo = 0, ep = 0, ap = 0, fp = 0, fm = 0;
+    for (int i = 0; i < np; ++i) {
+        const ssm_problem& q = pr[i];
+        Prob& p = pl.P[i];
+        std::memset(&p, 0, sizeof(p));
+        p.nx = q.nx; p.ny = q.ny; p.nz = q.nz; p.K = q.n_images;
+        p.mx = pow2ceil(q.nx); p.my = pow2ceil(q.ny);
+        p.mz = q.nz > 1 ? pow2ceil(q.nz) : 1;
+        p.lmx = ilog2(p.mx); p.lmy = ilog2(p.my); p.lmz = ilog2(p.mz);
+        p.pz = q.nz > 1 ? 2 * p.mz : 1;
+        p.nhz = q.nz > 1 ? 2 : 1;
+        p.N = (long long)q.nx * q.ny * q.nz;
+        const Tiles t = tiles ? (*tiles)[i] : default_tiles(p, pl.tsize);
+        apply_tiles(p, t);
+        if (lds_xtile(p, pl.tsize) > kLdsMax || lds_convg(p, p.gconv, pl.tsize) > kLdsMax) {
+            err = "problem " + std::to_string(i) + ": lattice too large for one workgroup's LDS";
+            return SSM_EUNSUPPORTED;
+        }
+        p.img0 = (int)img;
+        p.s_off = spin;
+        p.x_off = xo;
+        p.ep_off = ep;
+        p.ap_off = ap;
+        p.arc_chunks = (int)((3 * p.N + kNT * kArcEPT - 1) / (kNT * kArcEPT));
+        p.ichunks = (int)((p.N + kNT - 1) / kNT);
+        p.fp_off = fp;
+        p.fm_off = fm;
+        p.J = q.J; p.d = q.d; p.ku = q.ku; p.D = q.dip;
+        img += p.K;
+        spin += (long long)p.K * 3 * p.N;
+        xo += (long long)p.K * (p.mx + 1) * 3 * p.nz * p.ny;
+        ep += (long long)p.K * p.tiles * kNTerm;
+        ap += (long long)p.K * p.arc_chunks * 4;
+        fp += (long long)p.K * p.ichunks * 2;
+        fm += (long long)p.K * p.ichunks;
+        const auto key = std::make_tuple(p.nx, p.ny, p.nz);
+        auto it = shape_id.find(key);
+        if (it == shape_id.end()) {
+            const int id = (int)pl.shapes.size();
+            shape_id[key] = id;
+            pl.shapes.push_back(key);
+            pl.nh_size.push_back(6LL * (p.mx + 1) * (2 * p.my) * p.pz);
+            pl.geo[i] = id;
+            // F1 + F2 scratch of the spectrum setup
+            const long long f = 6LL * (p.mx + 1) * (2 * p.nz - 1) * ((2 * p.ny - 1) + 2 * p.my);
+            pl.scratch_bytes = std::max(pl.scratch_bytes, (size_t)f * 8);
+        } else {
+            pl.geo[i] = it->second;
+        }
+        pl.mz = p.mz;
+        pl.lds_x = std::max(pl.lds_x, lds_xtile(p, pl.tsize));
+        pl.lds_conv = std::max(pl.lds_conv, lds_convg(p, p.gconv, pl.tsize));
+    }
+    // kernel-spectrum offsets per shape
+    std::vector<long long> nh_off(pl.shapes.size());
+    long long nh = 0;
+    for (size_t g = 0; g < pl.shapes.size(); ++g) {
+        nh_off[g] = nh;
+        nh += (pl.nh_size[g] + 63) / 64 * 64;
+    }
+    for (int i = 0; i < np; ++i) pl.P[i].nh_off = nh_off[pl.geo[i]];
+    pl.n_img = img; pl.n_spin = spin; pl.n_x = xo; pl.n_nh = nh;
+    pl.n_ep = ep; pl.n_ap = ap; pl.n_fp = fp; pl.n_fm = fm;
+    // work maps
+    auto prefix = [&](std::vector<int>& v, auto count) {
+        v.assign(np + 1, 0);
+        for (int i = 0; i < np; ++i) v[i + 1] = v[i] + count(pl.P[i]);
+    };
+    prefix(pl.wm_xt, [](const Prob& p) { return p.K * p.tiles; });
+    prefix(pl.wm_conv, [](const Prob& p) { return conv_wgs(p); });
+    prefix(pl.wm_arc, [](const Prob& p) { return p.arc_chunks; });
+    prefix(pl.wm_site, [](const Prob& p) { return p.K * p.ichunks; });
+    // workspace layout
+    const size_t ts = pl.tsize, cs = 2 * ts;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = up(o + std::max<size_t>(bytes, 1)); return r; };
+    pl.o_P = take(sizeof(Prob) * np);
+    pl.o_wm = take(sizeof(int) * 4 * (np + 1));
+    pl.o_tw = take(cs * kTwM);
+    pl.o_tw64 = take(16 * kTwM);
+    pl.o_s = take(ts * spin);
+    pl.o_ss = take(ts * spin);
+    pl.o_h = take(ts * spin);
+    pl.o_nh = take(ts * nh);
+    pl.o_big = take(std::max((size_t)(2 * cs * xo), pl.scratch_bytes));
+    pl.o_ep = take(8 * ep);
+    pl.o_ap = take(8 * ap);
+    pl.o_fp = take(8 * fp);
+    pl.o_E = take(8 * img);
+    pl.o_T = take(8 * 4 * img);
+    pl.o_alpha = take(8 * img);
+    pl.o_w = take(8 * img);
+    pl.o_tc = take(8 * 2 * img);
+    pl.o_fn = take(8 * np);
+    pl.o_fm = take(8 * fm);
+    pl.o_j = take(4 * img);
+    pl.o_done = take(4 * np);
+    pl.o_iters = take(4 * np);
+    pl.o_skip = take(4 * np);
+    pl.o_flags = take(4);
+    pl.o_it0 = take(4 * np);
+    pl.total = o;
+    return SSM_OK;
+}
+
+}  // namespace
+
+struct ssm_ctx {
+    Plan pl;
+    std::vector<ssm_problem> probs;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    unsigned char* ws = nullptr;
+    size_t ws_bytes = 0;
+    std::string err;
+    bool have_string = false;
+    bool have_eval = false;
+    int check_every = 10;
+    int graph_chunk = 0;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    double graph_tau = 0;
+    int graph_n = 0;
+    bool profiling = false;
+    struct Ev { int kind; hipEvent_t a, b; };
+    std::vector<Ev> events;
+    std::vector<hipEvent_t> pool;
+    double prof_ms[SSM_N_KERNELS] = {0};
+    int prof_cnt[SSM_N_KERNELS] = {0};
+
+    template <typename X> X* at(size_t off) const { return reinterpret_cast<X*>(ws + off); }
+    const Prob* P() const { return at<Prob>(pl.o_P); }
+    WorkMap wm(int which, const std::vector<int>& v) const
+    {
+        WorkMap w;
+        w.start = at<int>(pl.o_wm) + which * (pl.np + 1);
+        w.total = v.back();
+        return w;
+    }
+    WorkMap wm_xt() const { return wm(0, pl.wm_xt); }
+    WorkMap wm_conv() const { return wm(1, pl.wm_conv); }
+    WorkMap wm_arc() const { return wm(2, pl.wm_arc); }
+    WorkMap wm_site() const { return wm(3, pl.wm_site); }
+    void* X() const { return ws + pl.o_big; }
+    void* Xp() const { return ws + pl.o_big + 2 * pl.tsize * pl.n_x; }
+};
+
+namespace {
+
+ssm_status fail(ssm_ctx* c, ssm_status st, const std::string& msg)
+{
+    if (c) c->err = msg; else g_create_error = msg;
+    return st;
+}
+
+ssm_status hipfail(ssm_ctx* c, hipError_t e, const char* where)
+{
+    return fail(c, SSM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(c, expr, where)                                  \
+    do {                                                        \
+        hipError_t e_ = (expr);                                 \
+        if (e_ != hipSuccess) return hipfail((c), e_, (where)); \
+    } while (0)
+
+hipEvent_t get_event(ssm_ctx* c)
+{
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Run one launch, bracketed by events when profiling.
+template <typename F>
+hipError_t timed(ssm_ctx* c, hipStream_t st, int kind, F&& f)
+{
+    if (!c->profiling) return f();
+    hipEvent_t a = get_event(c), b = get_event(c);
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, st);
+    if (e != hipSuccess) return e;
+    e = f();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, st);
+    c->events.push_back({kind, a, b});
+    return e;
+}
+
+template <typename T>
+struct Ops {
+    // x transform -> convolution -> inverse x transform + epilogue
+    static hipError_t field(ssm_ctx* c, hipStream_t st, const T* src, T* s_star, T* hdst, int mode,
+                            double tau, const int* done)
+    {
+        const Plan& pl = c->pl;
+        const void* tw = c->at<void>(pl.o_tw);
+        hipError_t e;
+        e = timed(c, st, KK_XFWD, [&] {
+            return launch_xfwd<T>(c->P(), pl.np, c->wm_xt(), src, c->X(), tw, done, pl.lds_x, st);
+        });
+        if (e != hipSuccess) return e;
+        e = timed(c, st, KK_CONV, [&] {
+            return launch_conv<T>(pl.mz, c->P(), pl.np, c->wm_conv(), c->X(), c->Xp(),
+                                  c->at<T>(pl.o_nh), tw, done, pl.lds_conv, st);
+        });
+        if (e != hipSuccess) return e;
+        return timed(c, st, KK_XINV, [&] {
+            return launch_xinv<T>(c->P(), pl.np, c->wm_xt(), c->Xp(), src, s_star, hdst,
+                                  c->at<double>(pl.o_ep), tw, done, mode, tau, pl.lds_x, st);
+        });
+    }
+
+    static hipError_t iteration(ssm_ctx* c, hipStream_t st, double tau)
+    {
+        const Plan& pl = c->pl;
+        T* s = c->at<T>(pl.o_s);
+        T* ss = c->at<T>(pl.o_ss);
+        int* done = c->at<int>(pl.o_done);
+        hipError_t e = field(c, st, s, ss, nullptr, EPI_STEP, tau, done);
+        if (e != hipSuccess) return e;
+        e = timed(c, st, KK_ARC, [&] {
+            return launch_arc<T>(c->P(), pl.np, c->wm_arc(), ss, c->at<double>(pl.o_ap), done, st);
+        });
+        if (e != hipSuccess) return e;
+        e = timed(c, st, KK_REDUCE, [&] {
+            return launch_reduce(c->P(), pl.np, c->at<double>(pl.o_ep), c->at<double>(pl.o_ap),
+                                 c->at<double>(pl.o_E), nullptr, nullptr, nullptr,
+                                 c->at<double>(pl.o_alpha), c->at<int>(pl.o_j),
+                                 c->at<double>(pl.o_w), c->at<int>(pl.o_skip), done,
+                                 c->at<int>(pl.o_iters), c->at<int>(pl.o_flags), 1, st);
+        });
+        if (e != hipSuccess) return e;
+        return timed(c, st, KK_INTERP, [&] {
+            return launch_interp<T>(c->P(), pl.np, c->wm_site(), ss, s, c->at<int>(pl.o_j),
+                                    c->at<double>(pl.o_w), c->at<int>(pl.o_skip), done,
+                                    c->at<int>(pl.o_flags), st);
+        });
+    }
+
+    // evaluation of `src` (current string when store)
+    static hipError_t eval(ssm_ctx* c, hipStream_t st, const T* src, T* hdst, double* E_out,
+                           double* T_out, bool store)
+    {
+        const Plan& pl = c->pl;
+        const int mode = (hdst ? EPI_FIELD : 0) | EPI_TERMS;
+        hipError_t e = field(c, st, src, nullptr, hdst, mode, 0.0, nullptr);
+        if (e != hipSuccess) return e;
+        return timed(c, st, KK_REDUCE, [&] {
+            return launch_reduce(c->P(), pl.np, c->at<double>(pl.o_ep), nullptr,
+                                 store ? c->at<double>(pl.o_E) : nullptr,
+                                 store ? c->at<double>(pl.o_T) : nullptr, E_out, T_out, nullptr,
+                                 nullptr, nullptr, nullptr, nullptr, nullptr,
+                                 c->at<int>(pl.o_flags), 0, st);
+        });
+    }
+
+    // tangents of the current string, force norm; uses ss as scratch
+    static hipError_t tangents(ssm_ctx* c, hipStream_t st, T* t_out, double* norm_out, double tol)
+    {
+        const Plan& pl = c->pl;
+        T* s = c->at<T>(pl.o_s);
+        T* h = c->at<T>(pl.o_h);
+        T* tt = c->at<T>(pl.o_ss);
+        hipError_t e = timed(c, st, KK_TAN1, [&] {
+            return launch_tan1<T>(c->P(), pl.np, c->wm_site(), s, h, tt, c->at<double>(pl.o_fp), st);
+        });
+        if (e != hipSuccess) return e;
+        e = timed(c, st, KK_TANRED, [&] {
+            return launch_tanred(c->P(), pl.np, c->at<double>(pl.o_fp), c->at<double>(pl.o_tc), st);
+        });
+        if (e != hipSuccess) return e;
+        e = timed(c, st, KK_TAN2, [&] {
+            return launch_tan2<T>(c->P(), pl.np, c->wm_site(), s, h, tt, t_out,
+                                  c->at<double>(pl.o_tc), c->at<double>(pl.o_fm), st);
+        });
+        if (e != hipSuccess) return e;
+        return timed(c, st, KK_TANRED, [&] {
+            return launch_fmax(c->P(), pl.np, c->at<double>(pl.o_fm), c->at<double>(pl.o_fn),
+                               c->at<int>(pl.o_done), tol, norm_out, st);
+        });
+    }
+};
+
+template <typename F>
+hipError_t dispatch(ssm_ctx* c, F&& f)
+{
+    if (c->pl.prec == SSM_FP64) return f(Ops<double>());
+    return f(Ops<float>());
+}
+
+void drop_graph(ssm_ctx* c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->graph_n = 0;
+}
+
+ssm_status ensure_graph(ssm_ctx* c, double tau, int n)
+{
+    if (c->gexec && c->graph_tau == tau && c->graph_n == n) return SSM_OK;
+    drop_graph(c);
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < n && e == hipSuccess; ++i)
+        e = dispatch(c, [&](auto ops) { return ops.iteration(c, c->cap_stream, tau); });
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+    if (e != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hipfail(c, e, "graph capture"); }
+    if (e2 != hipSuccess) return hipfail(c, e2, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) { (void)hipGraphDestroy(g); return hipfail(c, e, "hipGraphInstantiate"); }
+    c->graph = g;
+    c->gexec = ex;
+    c->graph_tau = tau;
+    c->graph_n = n;
+    return SSM_OK;
+}
+
+void twiddles(std::vector<double>& tw64)
+{
+    tw64.resize(2 * kTwM);
+    for (int e = 0; e < kTwM; ++e) {
+        const long double th = 2.0L * 3.14159265358979323846264338327950288L * (long double)e /
+                               (long double)kTwM;
+        tw64[2 * e] = (double)cosl(th);
+        tw64[2 * e + 1] = (double)-sinl(th);
+    }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int32_t ssm_version(void) { return kVersion; }
+
+const char* ssm_kernel_name(int32_t i)
+{
+    if (i < 0 || i >= SSM_N_KERNELS) return nullptr;
+    return kKernelNames[i];
+}
+
+const char* ssm_last_error(const ssm_ctx* ctx)
+{
+    if (!ctx) return g_create_error.c_str();
+    return ctx->err.c_str();
+}
+
+ssm_status ssm_workspace_size(const ssm_problem* p, int32_t n_problems, int32_t precision,
+                              size_t* bytes)
+{
+    if (!bytes) return fail(nullptr, SSM_EINVAL, "bytes is NULL");
+    Plan pl;
+    std::string err;
+    ssm_status st = build_plan(p, n_problems, precision, nullptr, pl, err);
+    if (st != SSM_OK) return fail(nullptr, st, err);
+    *bytes = pl.total;
+    return SSM_OK;
+}
+
+static ssm_status upload_plan(ssm_ctx* c)
+{
+    const Plan& pl = c->pl;
+    HIPCHK(c, hipMemcpyAsync(c->ws + pl.o_P, pl.P.data(), sizeof(Prob) * pl.np,
+                             hipMemcpyHostToDevice, c->stream), "upload descriptors");
+    std::vector<int> wm;
+    for (const auto* v : {&pl.wm_xt, &pl.wm_conv, &pl.wm_arc, &pl.wm_site})
+        wm.insert(wm.end(), v->begin(), v->end());
+    HIPCHK(c, hipMemcpyAsync(c->ws + pl.o_wm, wm.data(), sizeof(int) * wm.size(),
+                             hipMemcpyHostToDevice, c->stream), "upload work maps");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    return SSM_OK;
+}
+
+ssm_status ssm_create(const ssm_problem* p, int32_t n_problems, int32_t precision,
+                      void* d_workspace, size_t ws_bytes, void* stream, ssm_ctx** out)
+{
+    if (!out) return fail(nullptr, SSM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!d_workspace) return fail(nullptr, SSM_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign)
+        return fail(nullptr, SSM_EINVAL, "workspace not 256-byte aligned");
+    ssm_ctx* c = new ssm_ctx();
+    std::string err;
+    ssm_status st = build_plan(p, n_problems, precision, nullptr, c->pl, err);
+    if (st != SSM_OK) { delete c; return fail(nullptr, st, err); }
+    if (ws_bytes < c->pl.total) {
+        delete c;
+        return fail(nullptr, SSM_EINVAL, "workspace too small: need " + std::to_string(c->pl.total));
+    }
+    c->probs.assign(p, p + n_problems);
+    c->stream = (hipStream_t)stream;
+    c->ws = (unsigned char*)d_workspace;
+    c->ws_bytes = ws_bytes;
+    auto bail = [&](ssm_status s) {
+        g_create_error = c->err;
+        if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+        delete c;
+        return s;
+    };
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        c->err = "hipStreamCreateWithFlags failed";
+        return bail(SSM_EHIP);
+    }
+    const Plan& pl = c->pl;
+    std::vector<double> tw64;
+    twiddles(tw64);
+    std::vector<unsigned char> twt(2 * pl.tsize * kTwM);
+    if (pl.tsize == 8) {
+        std::memcpy(twt.data(), tw64.data(), twt.size());
+    } else {
+        float* f = reinterpret_cast<float*>(twt.data());
+        for (int i = 0; i < 2 * kTwM; ++i) f[i] = (float)tw64[i];
+    }
+    hipError_t e = hipMemcpyAsync(c->ws + pl.o_tw, twt.data(), twt.size(), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->ws + pl.o_tw64, tw64.data(), 16 * kTwM, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) { hipfail(c, e, "upload twiddles"); return bail(SSM_EHIP); }
+    if ((st = upload_plan(c)) != SSM_OK) return bail(st);
+    // dipole-kernel spectrum of every distinct shape (FP64, then stored as T)
+    for (size_t g = 0; g < pl.shapes.size(); ++g) {
+        int i = 0;
+        while (pl.geo[i] != (int)g) ++i;
+        const Prob& pr = pl.P[i];
+        double* f1 = c->at<double>(pl.o_big);
+        double* f2 = f1 + 6LL * (pr.mx + 1) * (2 * pr.ny - 1) * (2 * pr.nz - 1);
+        if (pl.prec == SSM_FP64)
+            e = launch_spectrum<double>(pr, c->at<double>(pl.o_nh) + pr.nh_off, f1, f2,
+                                        c->at<double>(pl.o_tw64), c->stream);
+        else
+            e = launch_spectrum<float>(pr, c->at<float>(pl.o_nh) + pr.nh_off, f1, f2,
+                                       c->at<double>(pl.o_tw64), c->stream);
+        if (e != hipSuccess) { hipfail(c, e, "kernel spectrum"); return bail(SSM_EHIP); }
+        // scratch reuse by the next shape needs this one finished
+        e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) { hipfail(c, e, "kernel spectrum"); return bail(SSM_EHIP); }
+    }
+    e = launch_fill_int(c->at<int>(pl.o_done), pl.np, 0, c->stream);
+    if (e == hipSuccess) e = launch_fill_int(c->at<int>(pl.o_iters), pl.np, 0, c->stream);
+    if (e == hipSuccess) e = launch_fill_int(c->at<int>(pl.o_skip), pl.np, 0, c->stream);
+    if (e == hipSuccess) e = launch_fill_int(c->at<int>(pl.o_flags), 1, 0, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) { hipfail(c, e, "create"); return bail(SSM_EHIP); }
+    *out = c;
+    return SSM_OK;
+}
+
+ssm_status ssm_destroy(ssm_ctx* ctx)
+{
+    if (!ctx) return SSM_OK;
+    (void)hipStreamSynchronize(ctx->stream);
+    drop_graph(ctx);
+    for (auto& ev : ctx->events) { (void)hipEventDestroy(ev.a); (void)hipEventDestroy(ev.b); }
+    for (auto e : ctx->pool) (void)hipEventDestroy(e);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    delete ctx;
+    return SSM_OK;
+}
+
+ssm_status ssm_set_params(ssm_ctx* ctx, int32_t problem, double J, double d, double ku, double dip)
+{
+    if (!ctx) return SSM_EINVAL;
+    if (problem < 0 || problem >= ctx->pl.np) return fail(ctx, SSM_EINVAL, "problem index out of range");
+    if (!std::isfinite(J) || !std::isfinite(d) || !std::isfinite(ku) || !std::isfinite(dip))
+        return fail(ctx, SSM_EINVAL, "non-finite parameter");
+    Prob& p = ctx->pl.P[problem];
+    p.J = J; p.d = d; p.ku = ku; p.D = dip;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->ws + ctx->pl.o_P + sizeof(Prob) * problem, &p, sizeof(Prob),
+                               hipMemcpyHostToDevice, ctx->stream), "set params");
+    // the source must stay valid until the copy has run
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "set params");
+    return SSM_OK;
+}
+
+ssm_status ssm_set_string(ssm_ctx* ctx, const void* d_spins)
+{
+    if (!ctx || !d_spins) return ctx ? fail(ctx, SSM_EINVAL, "d_spins is NULL") : SSM_EINVAL;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->ws + ctx->pl.o_s, d_spins, ctx->pl.tsize * ctx->pl.n_spin,
+                               hipMemcpyDeviceToDevice, ctx->stream), "set string");
+    ctx->have_string = true;
+    ctx->have_eval = false;
+    return SSM_OK;
+}
+
+ssm_status ssm_get_string(ssm_ctx* ctx, void* d_spins)
+{
+    if (!ctx || !d_spins) return ctx ? fail(ctx, SSM_EINVAL, "d_spins is NULL") : SSM_EINVAL;
+    if (!ctx->have_string) return fail(ctx, SSM_ESTATE, "no string set");
+    HIPCHK(ctx, hipMemcpyAsync(d_spins, ctx->ws + ctx->pl.o_s, ctx->pl.tsize * ctx->pl.n_spin,
+                               hipMemcpyDeviceToDevice, ctx->stream), "get string");
+    return SSM_OK;
+}
+
+ssm_status ssm_set_options(ssm_ctx* ctx, int32_t check_every, int32_t graph_chunk)
+{
+    if (!ctx) return SSM_EINVAL;
+    if (check_every < 1 || graph_chunk < 0 || graph_chunk > 100000)
+        return fail(ctx, SSM_EINVAL, "check_every >= 1 and 0 <= graph_chunk <= 100000");
+    ctx->check_every = check_every;
+    if (graph_chunk != ctx->graph_chunk) drop_graph(ctx);
+    ctx->graph_chunk = graph_chunk;
+    return SSM_OK;
+}
+
+static ssm_status run_eval_current(ssm_ctx* c)
+{
+    const Plan& pl = c->pl;
+    hipError_t e;
+    if (pl.prec == SSM_FP64)
+        e = Ops<double>::eval(c, c->stream, c->at<double>(pl.o_s), c->at<double>(pl.o_h), nullptr,
+                              nullptr, true);
+    else
+        e = Ops<float>::eval(c, c->stream, c->at<float>(pl.o_s), c->at<float>(pl.o_h), nullptr,
+                             nullptr, true);
+    if (e != hipSuccess) return hipfail(c, e, "evaluation");
+    c->have_eval = true;
+    return SSM_OK;
+}
+
+ssm_status ssm_iterate(ssm_ctx* ctx, int32_t max_iter, double tau, double tol_force,
+                       int32_t* d_iters_done)
+{
+    if (!ctx) return SSM_EINVAL;
+    if (!ctx->have_string) return fail(ctx, SSM_ESTATE, "no string set");
+    if (max_iter < 0 || !std::isfinite(tau) || !(tol_force >= 0.0))
+        return fail(ctx, SSM_EINVAL, "max_iter >= 0, finite tau and tol_force >= 0 required");
+    ssm_ctx* c = ctx;
+    const Plan& pl = c->pl;
+    HIPCHK(c, launch_fill_int(c->at<int>(pl.o_done), pl.np, 0, c->stream), "iterate");
+    HIPCHK(c, launch_fill_int(c->at<int>(pl.o_iters), pl.np, 0, c->stream), "iterate");
+    const bool check = tol_force > 0.0;
+    const bool use_graph = c->graph_chunk > 0 && !c->profiling;
+    std::vector<int> hdone(pl.np);
+    int it = 0;
+    for (;;) {
+        if (check && it % c->check_every == 0) {
+            ssm_status st = run_eval_current(c);
+            if (st != SSM_OK) return st;
+            hipError_t e = dispatch(c, [&](auto ops) {
+                return decltype(ops)::tangents(c, c->stream, nullptr, nullptr, tol_force);
+            });
+            if (e != hipSuccess) return hipfail(c, e, "convergence check");
+            HIPCHK(c, hipMemcpyAsync(hdone.data(), c->at<int>(pl.o_done), 4 * pl.np,
+                                     hipMemcpyDeviceToHost, c->stream), "convergence check");
+            HIPCHK(c, hipStreamSynchronize(c->stream), "convergence check");
+            bool all = true;
+            for (int v : hdone) all = all && v;
+            if (all) break;
+        }
+        if (it >= max_iter) break;
+        int n = max_iter - it;
+        if (check) n = std::min(n, c->check_every - it % c->check_every);
+        if (use_graph && n >= c->graph_chunk) {
+            const int reps = n / c->graph_chunk;
+            ssm_status st = ensure_graph(c, tau, c->graph_chunk);
+            if (st != SSM_OK) return st;
+            for (int r = 0; r < reps; ++r)
+                HIPCHK(c, hipGraphLaunch(c->gexec, c->stream), "hipGraphLaunch");
+            it += reps * c->graph_chunk;
+            continue;
+        }
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < n && e == hipSuccess; ++i)
+            e = dispatch(c, [&](auto ops) { return decltype(ops)::iteration(c, c->stream, tau); });
+        if (e != hipSuccess) return hipfail(c, e, "iteration");
+        it += n;
+    }
+    ssm_status st = run_eval_current(c);
+    if (st != SSM_OK) return st;
+    if (d_iters_done)
+        HIPCHK(c, launch_iters_out(pl.np, c->at<int>(pl.o_iters), nullptr, d_iters_done, c->stream),
+               "iterate");
+    return SSM_OK;
+}
+
+ssm_status ssm_eval(ssm_ctx* ctx, const void* d_spins, void* d_field_or_null, double* d_energy,
+                    double* d_terms_or_null)
+{
+    if (!ctx) return SSM_EINVAL;
+    ssm_ctx* c = ctx;
+    const Plan& pl = c->pl;
+    if (!d_spins) {
+        if (!c->have_string) return fail(c, SSM_ESTATE, "no string set");
+        ssm_status st = run_eval_current(c);
+        if (st != SSM_OK) return st;
+        const size_t nb = pl.tsize * pl.n_spin;
+        if (d_field_or_null)
+            HIPCHK(c, hipMemcpyAsync(d_field_or_null, c->ws + pl.o_h, nb, hipMemcpyDeviceToDevice, c->stream), "eval");
+        if (d_energy)
+            HIPCHK(c, hipMemcpyAsync(d_energy, c->ws + pl.o_E, 8 * pl.n_img, hipMemcpyDeviceToDevice, c->stream), "eval");
+        if (d_terms_or_null)
+            HIPCHK(c, hipMemcpyAsync(d_terms_or_null, c->ws + pl.o_T, 32 * pl.n_img, hipMemcpyDeviceToDevice, c->stream), "eval");
+        return SSM_OK;
+    }
+    hipError_t e;
+    if (pl.prec == SSM_FP64)
+        e = Ops<double>::eval(c, c->stream, (const double*)d_spins, (double*)d_field_or_null, d_energy,
+                              d_terms_or_null, false);
+    else
+        e = Ops<float>::eval(c, c->stream, (const float*)d_spins, (float*)d_field_or_null, d_energy,
+                             d_terms_or_null, false);
+    if (e != hipSuccess) return hipfail(c, e, "eval");
+    return SSM_OK;
+}
+
+ssm_status ssm_get_energies(ssm_ctx* ctx, double* d_energy)
+{
+    if (!ctx || !d_energy) return ctx ? fail(ctx, SSM_EINVAL, "d_energy is NULL") : SSM_EINVAL;
+    if (!ctx->have_eval) return fail(ctx, SSM_ESTATE, "no evaluation of the current string");
+    HIPCHK(ctx, hipMemcpyAsync(d_energy, ctx->ws + ctx->pl.o_E, 8 * ctx->pl.n_img,
+                               hipMemcpyDeviceToDevice, ctx->stream), "get energies");
+    return SSM_OK;
+}
+
+ssm_status ssm_get_fields(ssm_ctx* ctx, void* d_field)
+{
+    if (!ctx || !d_field) return ctx ? fail(ctx, SSM_EINVAL, "d_field is NULL") : SSM_EINVAL;
+    if (!ctx->have_eval) return fail(ctx, SSM_ESTATE, "no evaluation of the current string");
+    HIPCHK(ctx, hipMemcpyAsync(d_field, ctx->ws + ctx->pl.o_h, ctx->pl.tsize * ctx->pl.n_spin,
+                               hipMemcpyDeviceToDevice, ctx->stream), "get fields");
+    return SSM_OK;
+}
+
+ssm_status ssm_get_tangents(ssm_ctx* ctx, void* d_tangent, double* d_force_norm_or_null)
+{
+    if (!ctx) return SSM_EINVAL;
+    if (!ctx->have_eval) return fail(ctx, SSM_ESTATE, "no evaluation of the current string");
+    hipError_t e;
+    if (ctx->pl.prec == SSM_FP64)
+        e = Ops<double>::tangents(ctx, ctx->stream, (double*)d_tangent, d_force_norm_or_null, 0.0);
+    else
+        e = Ops<float>::tangents(ctx, ctx->stream, (float*)d_tangent, d_force_norm_or_null, 0.0);
+    if (e != hipSuccess) return hipfail(ctx, e, "tangents");
+    return SSM_OK;
+}
+
+ssm_status ssm_get_barrier(ssm_ctx* ctx, double* d_out)
+{
+    if (!ctx || !d_out) return ctx ? fail(ctx, SSM_EINVAL, "d_out is NULL") : SSM_EINVAL;
+    if (!ctx->have_eval) return fail(ctx, SSM_ESTATE, "no evaluation of the current string");
+    HIPCHK(ctx, launch_barrier(ctx->P(), ctx->pl.np, ctx->at<double>(ctx->pl.o_E),
+                               ctx->at<double>(ctx->pl.o_T), d_out, ctx->stream), "barrier");
+    return SSM_OK;
+}
+
+ssm_status ssm_check(ssm_ctx* ctx, int32_t* h_flags)
+{
+    if (!ctx || !h_flags) return ctx ? fail(ctx, SSM_EINVAL, "h_flags is NULL") : SSM_EINVAL;
+    int f = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&f, ctx->ws + ctx->pl.o_flags, 4, hipMemcpyDeviceToHost, ctx->stream), "check");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "check");
+    HIPCHK(ctx, launch_fill_int(ctx->at<int>(ctx->pl.o_flags), 1, 0, ctx->stream), "check");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "check");
+    *h_flags = f;
+    if (f & (SSM_FLAG_NONFINITE_ENERGY | SSM_FLAG_NONFINITE_SPIN))
+        return fail(ctx, SSM_ENONFINITE, "non-finite energy or spin");
+    return SSM_OK;
+}
+
+ssm_status ssm_profile(ssm_ctx* ctx, int32_t enable)
+{
+    if (!ctx) return SSM_EINVAL;
+    ctx->profiling = enable != 0;
+    return SSM_OK;
+}
+
+ssm_status ssm_profile_read(ssm_ctx* ctx, double* h_ms, int32_t* h_counts)
+{
+    if (!ctx) return SSM_EINVAL;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "profile read");
+    for (auto& ev : ctx->events) {
+        float ms = 0;
+        HIPCHK(ctx, hipEventElapsedTime(&ms, ev.a, ev.b), "hipEventElapsedTime");
+        ctx->prof_ms[ev.kind] += ms;
+        ctx->prof_cnt[ev.kind] += 1;
+        ctx->pool.push_back(ev.a);
+        ctx->pool.push_back(ev.b);
+    }
+    ctx->events.clear();
+    for (int i = 0; i < SSM_N_KERNELS; ++i) {
+        if (h_ms) h_ms[i] = ctx->prof_ms[i];
+        if (h_counts) h_counts[i] = ctx->prof_cnt[i];
+        ctx->prof_ms[i] = 0;
+        ctx->prof_cnt[i] = 0;
+    }
+    return SSM_OK;
+}
+
+ssm_status ssm_autotune(ssm_ctx* ctx, const char* cache_path)
+{
+    if (!ctx) return SSM_EINVAL;
+    (void)cache_path;
+    return fail(ctx, SSM_EUNSUPPORTED, "autotuning not built yet");
+}
+
+}  // extern "C"

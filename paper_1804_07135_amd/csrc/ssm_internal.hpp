@@ -1,0 +1,107 @@
+// Internal declarations shared by the kernels and the host runtime of the
+// gfx950 simplified-string-method library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ssm {
+
+// Twiddle table: tw[e] = exp(-2 pi i e / kTwM).  A length-L root W_L^e is
+// tw[e * (kTwM / L)], so every transform length divides kTwM.
+constexpr int kTwLog = 11;
+constexpr int kTwM = 1 << kTwLog;
+constexpr int kMaxLogM = 10;   // half padded length m <= 1024, padded P = 2m <= 2048
+constexpr int kNT = 256;       // threads per workgroup for every kernel
+constexpr int kConvElems = 6144; // target complex values per convolution workgroup
+constexpr int kArcEPT = 8;     // flat elements per thread in the arc-length kernel
+constexpr int kNTerm = 5;      // energy partial slots: E, T_J, T_d, T_ku, T_dip
+
+// Kernel kinds (profiling slots; names in the runtime).
+enum KernelKind {
+    KK_XFWD = 0, KK_CONV, KK_XINV, KK_ARC, KK_REDUCE, KK_INTERP,
+    KK_TAN1, KK_TAN2, KK_TANRED, KK_SPEC, KK_UTIL, KK_COUNT_
+};
+
+// Per-problem descriptor, resident in device memory (read-only in kernels).
+struct Prob {
+    int nx, ny, nz, K;
+    int mx, my, mz;        // half padded lengths: powers of two >= nx, ny, nz
+    int lmx, lmy, lmz;     // their log2
+    int pz;                // padded z length: 2*mz when nz > 1, else 1
+    int nhz;               // z halves of the padded z spectrum: 2 when nz > 1, else 1
+    int yt;                // lattice rows per tile of the x-transform kernels
+    int nty;               // ceil(ny / yt)
+    int tiles;             // x-transform tiles per image = nz * nty
+    int img0;              // index of this problem's first image in batch-wide arrays
+    int gconv;             // consecutive (image, kx) slices per convolution workgroup
+    int arc_chunks;        // arc-length workgroups (flat chunks of 3N) per image
+    int xcd_remap;         // convolution kernel: group same-kx slices on one XCD
+    int pad_;
+    long long N;           // sites per image
+    long long s_off;       // element offset of image 0 in spin / field buffers
+    long long x_off;       // complex-element offset in the x-spectrum buffers
+    long long nh_off;      // element offset of this shape's dipole-kernel spectrum
+    long long ep_off;      // offset (doubles) of energy partials: [K][tiles][kNTerm]
+    long long ap_off;      // offset (doubles) of arc partials: [K][arc_chunks*4]
+    long long fp_off;      // offset (doubles) of tangent partials: [K][ichunks][2]
+    long long fm_off;      // offset (doubles) of per-workgroup force maxima: [K][ichunks]
+    int ichunks;           // per-site workgroups per image (interp / tangents)
+    int pad2_;
+    double J, d, ku, D;    // eq. (1) parameters
+};
+
+// Work maps: workgroup ranges per problem for each kernel kind.
+struct WorkMap {
+    int* start;      // device: [nprob + 1] prefix sums of workgroup counts
+    int total;
+};
+
+// ------------------------------------------------------------------------
+// launchers (ssm_kernels.hip); all enqueue on `st` and return the HIP error
+// ------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_xfwd(const Prob* P, int np, const WorkMap& wm, const T* s, void* X,
+                       const void* tw, const int* done, size_t lds, hipStream_t st);
+template <typename T>
+hipError_t launch_conv(int mz, const Prob* P, int np, const WorkMap& wm, const void* X,
+                       void* Xp, const T* nhat, const void* tw, const int* done, size_t lds,
+                       hipStream_t st);
+// mode bits for the inverse/epilogue kernel
+enum { EPI_STEP = 1, EPI_FIELD = 2, EPI_TERMS = 4 };
+template <typename T>
+hipError_t launch_xinv(const Prob* P, int np, const WorkMap& wm, const void* Xp, const T* s,
+                       T* s_star, T* h, double* epart, const void* tw, const int* done,
+                       int mode, double tau, size_t lds, hipStream_t st);
+template <typename T>
+hipError_t launch_arc(const Prob* P, int np, const WorkMap& wm, const T* ss, double* apart,
+                      const int* done, hipStream_t st);
+hipError_t launch_reduce(const Prob* P, int np, const double* epart, const double* apart,
+                         double* E, double* Tm, double* E_out, double* T_out, double* alpha,
+                         int* jidx, double* wgt, int* skip, int* done, int* iters, int* flags,
+                         int with_arc, hipStream_t st);
+template <typename T>
+hipError_t launch_interp(const Prob* P, int np, const WorkMap& wm, const T* ss, T* s,
+                         const int* jidx, const double* wgt, const int* skip, const int* done,
+                         int* flags, hipStream_t st);
+template <typename T>
+hipError_t launch_tan1(const Prob* P, int np, const WorkMap& wm, const T* s, const T* h,
+                       T* tt, double* fpart, hipStream_t st);
+hipError_t launch_tanred(const Prob* P, int np, const double* fpart, double* tcoef,
+                         hipStream_t st);
+template <typename T>
+hipError_t launch_tan2(const Prob* P, int np, const WorkMap& wm, const T* s, const T* h,
+                       const T* tt, T* t_out, const double* tcoef, double* fmax,
+                       hipStream_t st);
+hipError_t launch_fmax(const Prob* P, int np, const double* fmax, double* fnorm, int* done,
+                       double tol, double* out, hipStream_t st);
+template <typename T>
+hipError_t launch_spectrum(const Prob& p, T* nhat, double* f1, double* f2, const double* tw64,
+                           hipStream_t st);
+hipError_t launch_barrier(const Prob* P, int np, const double* E, const double* Tm,
+                          double* out, hipStream_t st);
+hipError_t launch_iters_out(int np, const int* iters, const int* iters0, int* out,
+                            hipStream_t st);
+hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st);
+
+}  // namespace ssm

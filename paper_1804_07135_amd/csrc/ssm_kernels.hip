@@ -1,0 +1,1150 @@
+// HIP kernels (gfx950) of the simplified string method for atomistic spin
+// lattices (Heistracher et al., arXiv:1804.07135).
+//
+// One string iteration is six kernels over every image of every problem:
+//   k_xfwd   zero-padded real-to-complex FFT along x of the three spin
+//            components (Sec. II.A: the dipolar field of eq. (6) is a
+//            circular convolution once the lattice is padded);
+//   k_conv   for each x-frequency: FFTs along y (and z), multiplication by
+//            the FFT of the point-dipole tensor of eq. (7), inverse FFTs;
+//   k_xinv   inverse FFT along x, then per site: exchange, DMI and
+//            anisotropy stencils (eqs. (3)-(5)), the energy -1/2 h.s of
+//            eq. (8) reduced in FP64, and the projected descent step with
+//            renormalisation (eq. (10), Appendix force);
+//   k_arc    FP64 partial sums of |phi*_k - phi*_{k-1}|^2 (eq. (11));
+//   k_reduce per problem: energies, arc lengths, alpha* (eq. (12)) and the
+//            interpolation interval/weight of every image;
+//   k_interp linear interpolation onto alpha_k = k/(K-1) + renormalisation.
+//
+// Padded lengths are P = 2m with m a power of two >= n.  A zero-padded
+// length-P transform of n <= m inputs is two length-m transforms: the even
+// outputs are the FFT of the inputs, the odd outputs the FFT of the inputs
+// times W_P^j.  The inverse restricted to the first n outputs is the sum of
+// the two inverse length-m transforms, the odd one times W_P^{-j}.  So no
+// transform ever runs on a buffer of zeros, and only the x-spectra (m+1
+// complex values per row of n reals) travel through HBM.
+//
+// Length-m transforms run in LDS as Stockham radix-4 (+ one radix-2) passes;
+// every line belongs to one wavefront, which needs no workgroup barrier
+// between passes.
+#include "ssm_internal.hpp"
+
+namespace ssm {
+
+template <typename T> struct CT;
+template <> struct CT<float> { using type = float2; };
+template <> struct CT<double> { using type = double2; };
+template <typename T> using cplx = typename CT<T>::type;
+
+template <typename V>
+__device__ __forceinline__ V mk(decltype(V::x) a, decltype(V::x) b) { V r; r.x = a; r.y = b; return r; }
+template <typename V>
+__device__ __forceinline__ V cadd(V a, V b) { return mk<V>(a.x + b.x, a.y + b.y); }
+template <typename V>
+__device__ __forceinline__ V csub(V a, V b) { return mk<V>(a.x - b.x, a.y - b.y); }
+template <typename V>
+__device__ __forceinline__ V cmul(V a, V b) { return mk<V>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+// a * conj(b)
+template <typename V>
+__device__ __forceinline__ V cmulc(V a, V b) { return mk<V>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y); }
+template <bool INV, typename V>
+__device__ __forceinline__ V twm(V a, V w) { return INV ? cmulc(a, w) : cmul(a, w); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV, typename V>
+__device__ __forceinline__ V rot(V a) { return INV ? mk<V>(-a.y, a.x) : mk<V>(a.y, -a.x); }
+
+// Order LDS traffic of one wavefront: LDS executes a wave's instructions in
+// issue order, so a compiler barrier plus wavefront-scope fences suffice.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int find_problem(const int* __restrict__ start, int np, int b)
+{
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// In-LDS transforms of nl lines of length m = 2^lm (line stride ls elements).
+// Forward uses W = exp(-2 pi i / m); inverse is unnormalised.  Lines are
+// handed out to wavefronts in groups of at most 1024 elements.
+// ---------------------------------------------------------------------------
+template <typename T, bool INV>
+__device__ void fft_lines(cplx<T>* buf, int nl, int ls, int lm, const cplx<T>* __restrict__ tw)
+{
+    using V = cplx<T>;
+    if (lm == 0) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int m = 1 << lm;
+    // A wave owns whole line groups of 512 elements (one line of 1024, whose
+    // passes are all radix 4), so no pass has more than 256 butterflies and
+    // each lane holds at most 4 of them.
+    const int lpg = (lm >= 9) ? 1 : (1 << (9 - lm));
+    for (int g0 = wave * lpg; g0 < nl; g0 += nw * lpg) {
+        const int gl = min(lpg, nl - g0);
+        V* base0 = buf + g0 * ls;
+        int lns = 0;
+        for (int rem = lm; rem > 0;) {
+            const int r4 = rem >= 2;
+            const int lr = r4 ? 2 : 1;
+            const int q = m >> lr, lq = lm - lr;
+            const int nbf = (gl << lm) >> lr;
+            const int Ns = 1 << lns;
+            const int tsh = kTwLog - lr - lns;
+            V v[16];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int g = lane + 64 * i;
+                if (g < nbf) {
+                    const int line = g >> lq, j = g & (q - 1), k = j & (Ns - 1);
+                    const V* L = base0 + line * ls + j;
+                    if (r4) {
+                        V a0 = L[0], a1 = L[q], a2 = L[2 * q], a3 = L[3 * q];
+                        const int st = k << tsh;
+                        a1 = twm<INV>(a1, tw[st]);
+                        a2 = twm<INV>(a2, tw[2 * st]);
+                        a3 = twm<INV>(a3, tw[3 * st]);
+                        const V t0 = cadd(a0, a2), t1 = csub(a0, a2);
+                        const V t2 = cadd(a1, a3), t3 = rot<INV>(csub(a1, a3));
+                        v[4 * i + 0] = cadd(t0, t2);
+                        v[4 * i + 1] = cadd(t1, t3);
+                        v[4 * i + 2] = csub(t0, t2);
+                        v[4 * i + 3] = csub(t1, t3);
+                    } else {
+                        V a0 = L[0], a1 = twm<INV>(L[q], tw[k << tsh]);
+                        v[4 * i + 0] = cadd(a0, a1);
+                        v[4 * i + 1] = csub(a0, a1);
+                    }
+                }
+            }
+            wave_sync();
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int g = lane + 64 * i;
+                if (g < nbf) {
+                    const int line = g >> lq, j = g & (q - 1), k = j & (Ns - 1);
+                    V* L = base0 + line * ls + ((j >> lns) << (lns + lr)) + k;
+                    L[0] = v[4 * i + 0];
+                    L[Ns] = v[4 * i + 1];
+                    if (r4) {
+                        L[2 * Ns] = v[4 * i + 2];
+                        L[3 * Ns] = v[4 * i + 3];
+                    }
+                }
+            }
+            wave_sync();
+            lns += lr;
+            rem -= lr;
+        }
+    }
+}
+
+// Length-MZ transform held in registers (radix-2, bit-reversed input).
+template <typename T, int MZ, bool INV>
+__device__ __forceinline__ void fft_reg(cplx<T> (&a)[MZ], const cplx<T>* __restrict__ tw)
+{
+    using V = cplx<T>;
+    if (MZ == 1) return;
+    constexpr int LZ = (MZ == 2) ? 1 : (MZ == 4) ? 2 : (MZ == 8) ? 3 : 4;
+#pragma unroll
+    for (int i = 0; i < MZ; ++i) {
+        int r = 0;
+#pragma unroll
+        for (int b = 0; b < LZ; ++b) r |= ((i >> b) & 1) << (LZ - 1 - b);
+        if (r > i) { V t = a[i]; a[i] = a[r]; a[r] = t; }
+    }
+#pragma unroll
+    for (int len = 2; len <= MZ; len <<= 1) {
+        const int half = len >> 1;
+#pragma unroll
+        for (int i = 0; i < MZ; i += len) {
+#pragma unroll
+            for (int j = 0; j < half; ++j) {
+                const V w = tw[j * (kTwM / len)];
+                const V u = a[i + j];
+                const V v = twm<INV>(a[i + j + half], w);
+                a[i + j] = cadd(u, v);
+                a[i + j + half] = csub(u, v);
+            }
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// k_xfwd: rows of a tile (image, z, yt rows) -> x half-spectra.
+// Two real rows of one spin component form one complex signal a + i b; its
+// length-2m spectrum Z gives A(k) = (Z(k) + conj Z(-k))/2 and
+// B(k) = -i (Z(k) - conj Z(-k))/2 for k = 0..m.
+// Output layout X[img][kx][c][z][y].
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_xfwd(const Prob* __restrict__ P, int np,
+                                              const int* __restrict__ wstart,
+                                              const T* __restrict__ s, cplx<T>* __restrict__ X,
+                                              const cplx<T>* __restrict__ tw,
+                                              const int* __restrict__ done)
+{
+    using V = cplx<T>;
+    extern __shared__ double2 smem_[];
+    V* lines = reinterpret_cast<V*>(smem_);
+    const int pi = find_problem(wstart, np, blockIdx.x);
+    if (done && done[pi]) return;
+    const Prob& p = P[pi];
+    const int t = blockIdx.x - wstart[pi];
+    const int ty = t % p.nty, rest = t / p.nty;
+    const int z = rest % p.nz, img = rest / p.nz;
+    const int yt = p.yt, hp = yt >> 1, nx = p.nx, ny = p.ny, nz = p.nz, m = p.mx, lm = p.lmx;
+    const int y0 = ty * yt, nq = 3 * hp;
+    const long long N = p.N;
+    const T* si = s + p.s_off + (long long)img * 3 * N + (long long)z * ny * nx;
+    const int tws = kTwLog - 1 - lm;
+
+    for (int idx = threadIdx.x; idx < nq * m; idx += kNT) {
+        const int j = idx & (m - 1), q = idx >> lm;
+        const int c = q / hp, rp = q - c * hp;
+        const int ya = y0 + 2 * rp;
+        T a = 0, b = 0;
+        if (j < nx) {
+            const T* row = si + (long long)c * N;
+            if (ya < ny) a = row[(long long)ya * nx + j];
+            if (ya + 1 < ny) b = row[(long long)(ya + 1) * nx + j];
+        }
+        const V v = mk<V>(a, b);
+        lines[(2 * q) * m + j] = v;
+        lines[(2 * q + 1) * m + j] = cmul(v, tw[j << tws]);
+    }
+    __syncthreads();
+    fft_lines<T, false>(lines, 2 * nq, m, lm, tw);
+    __syncthreads();
+
+    const int P2 = 2 * m;
+    V* Xi = X + p.x_off + (long long)img * (m + 1) * 3 * nz * ny;
+    for (int idx = threadIdx.x; idx < (m + 1) * nq; idx += kNT) {
+        const int rp = idx % hp, r2 = idx / hp;
+        const int c = r2 % 3, kx = r2 / 3;
+        const int q = c * hp + rp;
+        const int kr = (P2 - kx) & (P2 - 1);
+        const V Z = lines[(2 * q + (kx & 1)) * m + (kx >> 1)];
+        const V Zr = lines[(2 * q + (kr & 1)) * m + (kr >> 1)];
+        const T hlf = T(0.5);
+        const V A = mk<V>((Z.x + Zr.x) * hlf, (Z.y - Zr.y) * hlf);
+        const V B = mk<V>((Z.y + Zr.y) * hlf, (Zr.x - Z.x) * hlf);
+        const int ya = y0 + 2 * rp;
+        V* dst = Xi + (((long long)kx * 3 + c) * nz + z) * ny;
+        if (ya < ny) dst[ya] = A;
+        if (ya + 1 < ny) dst[ya + 1] = B;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_conv: for G consecutive (image, kx) slices [c][z][y]: for each quarter
+// (hz, hy) of the padded (z, y) spectrum: twiddle, FFT along y (LDS), FFT
+// along z (registers), multiply by the real symmetric dipole-kernel
+// spectrum (xx, xy, xz, yy, yz, zz), inverse z, inverse y, un-twiddle and
+// accumulate.  The kernel spectrum already carries 1/(Px Py Pz).
+// ---------------------------------------------------------------------------
+template <typename T, int MZ>
+__global__ __launch_bounds__(kNT) void k_conv(const Prob* __restrict__ P, int np,
+                                              const int* __restrict__ wstart,
+                                              const cplx<T>* __restrict__ X,
+                                              cplx<T>* __restrict__ Xp, const T* __restrict__ nhat,
+                                              const cplx<T>* __restrict__ tw,
+                                              const int* __restrict__ done)
+{
+    using V = cplx<T>;
+    extern __shared__ double2 smem_[];
+    V* lines = reinterpret_cast<V*>(smem_);
+    const int pi = find_problem(wstart, np, blockIdx.x);
+    if (done && done[pi]) return;
+    const Prob& p = P[pi];
+    const int w = blockIdx.x - wstart[pi];
+    const int nsl_img = p.mx + 1, nsl = p.K * nsl_img;
+    int s0, G;
+    if (p.xcd_remap) {
+        const int xcd = w & 7, j = w >> 3;
+        const int kx = (j / p.K) * 8 + xcd, img = j % p.K;
+        if (kx > p.mx || img >= p.K) return;
+        s0 = img * nsl_img + kx;
+        G = 1;
+    } else {
+        s0 = w * p.gconv;
+        if (s0 >= nsl) return;
+        G = min(p.gconv, nsl - s0);
+    }
+    const int nz = p.nz, ny = p.ny, my = p.my, lmy = p.lmy;
+    const int per = 3 * nz * ny, nel = G * per, nlines = G * 3 * nz;
+    const V* in = X + p.x_off + (long long)s0 * per;
+    const int twy = kTwLog - 1 - lmy;
+    const int twz = kTwLog - 1 - p.lmz;
+
+    V* out = Xp + p.x_off + (long long)s0 * per;
+    int first = 1;
+    for (int hz = 0; hz < p.nhz; ++hz) {
+        for (int hy = 0; hy < 2; ++hy) {
+            for (int e = threadIdx.x; e < nlines * my; e += kNT) {
+                const int y = e & (my - 1), r = e >> lmy;
+                V v = mk<V>(0, 0);
+                if (y < ny) {
+                    v = in[r * ny + y];
+                    if (hy) v = cmul(v, tw[y << twy]);
+                    if (hz) v = cmul(v, tw[(r % nz) << twz]);
+                }
+                lines[e] = v;
+            }
+            __syncthreads();
+            fft_lines<T, false>(lines, nlines, my, lmy, tw);
+            __syncthreads();
+
+            for (int col = threadIdx.x; col < G * my; col += kNT) {
+                const int g = col >> lmy, qy = col & (my - 1);
+                const int kx = (s0 + g) % nsl_img;
+                V a[3][MZ];
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int zz = 0; zz < MZ; ++zz)
+                        a[c][zz] = (zz < nz) ? lines[((g * 3 + c) * nz + zz) * my + qy] : mk<V>(0, 0);
+                if (MZ > 1) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) fft_reg<T, MZ, false>(a[c], tw);
+                }
+                const T* nh = nhat + p.nh_off +
+                              ((((long long)kx * p.nhz + hz) * 2 + hy) * MZ) * 6 * my + qy;
+#pragma unroll
+                for (int r = 0; r < MZ; ++r) {
+                    const T* q6 = nh + (long long)r * 6 * my;
+                    const T nxx = q6[0], nxy = q6[my], nxz = q6[2 * my];
+                    const T nyy = q6[3 * my], nyz = q6[4 * my], nzz = q6[5 * my];
+                    const V sx = a[0][r], sy = a[1][r], sz = a[2][r];
+                    a[0][r] = mk<V>(nxx * sx.x + nxy * sy.x + nxz * sz.x, nxx * sx.y + nxy * sy.y + nxz * sz.y);
+                    a[1][r] = mk<V>(nxy * sx.x + nyy * sy.x + nyz * sz.x, nxy * sx.y + nyy * sy.y + nyz * sz.y);
+                    a[2][r] = mk<V>(nxz * sx.x + nyz * sy.x + nzz * sz.x, nxz * sx.y + nyz * sy.y + nzz * sz.y);
+                }
+                if (MZ > 1) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) fft_reg<T, MZ, true>(a[c], tw);
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int zz = 0; zz < MZ; ++zz)
+                        if (zz < nz) lines[((g * 3 + c) * nz + zz) * my + qy] = a[c][zz];
+            }
+            __syncthreads();
+            fft_lines<T, true>(lines, nlines, my, lmy, tw);
+            __syncthreads();
+            // accumulate this quarter into the workgroup's own output slice
+            for (int e = threadIdx.x; e < nel; e += kNT) {
+                const int y = e % ny, r = e / ny;
+                V v = lines[r * my + y];
+                if (hy) v = cmulc(v, tw[y << twy]);
+                if (hz) v = cmulc(v, tw[(r % nz) << twz]);
+                out[e] = first ? v : cadd(out[e], v);
+            }
+            first = 0;
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_xinv: x half-spectra of the convolved field -> unit-strength dipolar
+// field of a tile, then the per-site epilogue.  Two half-spectra A, B of
+// real rows form Z = A + i B on k = 0..m and conj(A) + i conj(B) on
+// k = m+1..2m-1; the inverse transform gives row a in the real part and
+// row b in the imaginary part.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_xinv(const Prob* __restrict__ P, int np,
+                                              const int* __restrict__ wstart,
+                                              const cplx<T>* __restrict__ Xp,
+                                              const T* __restrict__ s, T* __restrict__ ss,
+                                              T* __restrict__ hout, double* __restrict__ epart,
+                                              const cplx<T>* __restrict__ tw,
+                                              const int* __restrict__ done, int mode, double tau)
+{
+    using V = cplx<T>;
+    extern __shared__ double2 smem_[];
+    V* lines = reinterpret_cast<V*>(smem_);
+    __shared__ double red[kNT / 64][kNTerm];
+    const int pi = find_problem(wstart, np, blockIdx.x);
+    if (done && done[pi]) return;
+    const Prob& p = P[pi];
+    const int t = blockIdx.x - wstart[pi];
+    const int ty = t % p.nty, rest = t / p.nty;
+    const int z = rest % p.nz, img = rest / p.nz;
+    const int yt = p.yt, hp = yt >> 1, nx = p.nx, ny = p.ny, nz = p.nz, m = p.mx, lm = p.lmx;
+    const int y0 = ty * yt, nq = 3 * hp;
+    const long long N = p.N;
+    T* hd = reinterpret_cast<T*>(lines + 2 * nq * m);
+
+    const V* Xi = Xp + p.x_off + (long long)img * (m + 1) * 3 * nz * ny;
+    for (int idx = threadIdx.x; idx < (m + 1) * nq; idx += kNT) {
+        const int rp = idx % hp, r2 = idx / hp;
+        const int c = r2 % 3, kx = r2 / 3;
+        const int q = c * hp + rp;
+        const int ya = y0 + 2 * rp;
+        const V* src = Xi + (((long long)kx * 3 + c) * nz + z) * ny;
+        const V A = (ya < ny) ? src[ya] : mk<V>(0, 0);
+        const V B = (ya + 1 < ny) ? src[ya + 1] : mk<V>(0, 0);
+        lines[(2 * q + (kx & 1)) * m + (kx >> 1)] = mk<V>(A.x - B.y, A.y + B.x);
+        if (kx > 0 && kx < m) {
+            const int km = 2 * m - kx;
+            lines[(2 * q + (km & 1)) * m + (km >> 1)] = mk<V>(A.x + B.y, B.x - A.y);
+        }
+    }
+    __syncthreads();
+    fft_lines<T, true>(lines, 2 * nq, m, lm, tw);
+    __syncthreads();
+    const int tws = kTwLog - 1 - lm;
+    // stage the field into registers first: hd overlaps nothing, but keep
+    // the reads of `lines` and the writes of `hd` in separate loops
+    for (int idx = threadIdx.x; idx < nq * nx; idx += kNT) {
+        const int x = idx % nx, q = idx / nx;
+        const int c = q / hp, rp = q - c * hp;
+        const V e = lines[(2 * q) * m + x];
+        const V o = cmulc(lines[(2 * q + 1) * m + x], tw[x << tws]);
+        hd[(c * yt + 2 * rp) * nx + x] = e.x + o.x;
+        hd[(c * yt + 2 * rp + 1) * nx + x] = e.y + o.y;
+    }
+    __syncthreads();
+
+    const double J = p.J, dm = p.d, ku = p.ku, D = p.D;
+    const T* si = s + p.s_off + (long long)img * 3 * N;
+    T* so = ss + p.s_off + (long long)img * 3 * N;
+    T* ho = hout ? hout + p.s_off + (long long)img * 3 * N : nullptr;
+    double acc[kNTerm] = {0, 0, 0, 0, 0};
+    for (int idx = threadIdx.x; idx < yt * nx; idx += kNT) {
+        const int x = idx % nx, r = idx / nx, y = y0 + r;
+        if (y >= ny) continue;
+        const long long i = ((long long)z * ny + y) * nx + x;
+        double sv[3], nb[3] = {0, 0, 0};
+        double xp[3] = {0, 0, 0}, xm[3] = {0, 0, 0}, yp[3] = {0, 0, 0}, ym[3] = {0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T* sc = si + (long long)c * N;
+            sv[c] = (double)sc[i];
+            if (x + 1 < nx) xp[c] = (double)sc[i + 1];
+            if (x > 0) xm[c] = (double)sc[i - 1];
+            if (y + 1 < ny) yp[c] = (double)sc[i + nx];
+            if (y > 0) ym[c] = (double)sc[i - nx];
+            double zs = 0;
+            if (z + 1 < nz) zs += (double)sc[i + (long long)nx * ny];
+            if (z > 0) zs += (double)sc[i - (long long)nx * ny];
+            nb[c] = xp[c] + xm[c] + yp[c] + ym[c] + zs;
+        }
+        // unit-strength DMI field, eq. (4)
+        const double dmx = -(xp[2] - xm[2]);
+        const double dmy = -(yp[2] - ym[2]);
+        const double dmz = -(-xp[0] + xm[0] - yp[1] + ym[1]);
+        const double hu[3] = {(double)hd[(0 * yt + r) * nx + x], (double)hd[(1 * yt + r) * nx + x],
+                              (double)hd[(2 * yt + r) * nx + x]};
+        double h[3];
+        h[0] = J * nb[0] + dm * dmx + D * hu[0];
+        h[1] = J * nb[1] + dm * dmy + D * hu[1];
+        h[2] = J * nb[2] + dm * dmz + 2.0 * ku * sv[2] + D * hu[2];
+        const double sh = sv[0] * h[0] + sv[1] * h[1] + sv[2] * h[2];
+        acc[0] += -0.5 * sh;
+        if (mode & EPI_TERMS) {
+            acc[1] += -0.5 * (sv[0] * nb[0] + sv[1] * nb[1] + sv[2] * nb[2]);
+            acc[2] += -0.5 * (sv[0] * dmx + sv[1] * dmy + sv[2] * dmz);
+            acc[3] += -sv[2] * sv[2];
+            acc[4] += -0.5 * (sv[0] * hu[0] + sv[1] * hu[1] + sv[2] * hu[2]);
+        }
+        if (mode & EPI_FIELD) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ho[(long long)c * N + i] = (T)h[c];
+        }
+        if (mode & EPI_STEP) {
+            double wv[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) wv[c] = sv[c] + tau * (h[c] - sh * sv[c]);
+            const double nrm = sqrt(wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) so[(long long)c * N + i] = (T)(wv[c] / nrm);
+        }
+    }
+    const int nterm = (mode & EPI_TERMS) ? kNTerm : 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = 0; j < nterm; ++j) {
+        const double v = wave_sum(acc[j]);
+        if (lane == 0) red[wave][j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < nterm) {
+        double v = 0;
+        for (int wv = 0; wv < kNT / 64; ++wv) v += red[wv][threadIdx.x];
+        epart[p.ep_off + ((long long)img * p.tiles + (z * p.nty + ty)) * kNTerm + threadIdx.x] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_arc: per flat chunk of the 3N components, partial sums of
+// (phi*_k - phi*_{k-1})^2 for k = 1..K-1, one value per wavefront.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_arc(const Prob* __restrict__ P, int np,
+                                             const int* __restrict__ wstart,
+                                             const T* __restrict__ ss, double* __restrict__ apart,
+                                             const int* __restrict__ done)
+{
+    const int pi = find_problem(wstart, np, blockIdx.x);
+    if (done && done[pi]) return;
+    const Prob& p = P[pi];
+    const int chunk = blockIdx.x - wstart[pi];
+    const long long M = 3 * p.N;
+    const long long base = (long long)chunk * (kNT * kArcEPT) + threadIdx.x;
+    const T* src = ss + p.s_off;
+    T prev[kArcEPT], cur[kArcEPT];
+#pragma unroll
+    for (int j = 0; j < kArcEPT; ++j) {
+        const long long e = base + (long long)j * kNT;
+        prev[j] = (e < M) ? src[e] : T(0);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k = 1; k < p.K; ++k) {
+        const T* im = src + (long long)k * M;
+#pragma unroll
+        for (int j = 0; j < kArcEPT; ++j) {
+            const long long e = base + (long long)j * kNT;
+            cur[j] = (e < M) ? im[e] : T(0);
+        }
+        double a = 0;
+#pragma unroll
+        for (int j = 0; j < kArcEPT; ++j) {
+            const double d = (double)cur[j] - (double)prev[j];
+            a += d * d;
+            prev[j] = cur[j];
+        }
+        a = wave_sum(a);
+        if (lane == 0)
+            apart[p.ap_off + ((long long)k * p.arc_chunks + chunk) * 4 + wave] = a;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_reduce: one workgroup per problem.  Fixed-order sums of the energy
+// partials (E and the four unit-parameter terms) and, with_arc, of the arc
+// partials; then S_k, alpha*_k = S_k/S_{K-1} and for every interior image
+// the interval j = max{j <= K-2 : alpha*_j <= k/(K-1)} and its weight.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kNT) void k_reduce(const Prob* __restrict__ P, int np,
+                                                const double* __restrict__ epart,
+                                                const double* __restrict__ apart,
+                                                double* E, double* Tm, double* E_out,
+                                                double* T_out, double* alpha, int* jidx,
+                                                double* wgt, int* skip, int* done, int* iters,
+                                                int* flags, int with_arc)
+{
+    __shared__ double seg[1024];
+    const int pi = blockIdx.x;
+    if (pi >= np) return;
+    if (with_arc && done && done[pi]) return;
+    const Prob& p = P[pi];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = kNT / 64;
+    for (int k = wave; k < p.K; k += nw) {
+        const double* ep = epart + p.ep_off + (long long)k * p.tiles * kNTerm;
+        double v[kNTerm] = {0, 0, 0, 0, 0};
+        for (int t = lane; t < p.tiles; t += 64)
+            for (int j = 0; j < kNTerm; ++j) v[j] += ep[(long long)t * kNTerm + j];
+        for (int j = 0; j < kNTerm; ++j) v[j] = wave_sum(v[j]);
+        if (lane == 0) {
+            const int g = p.img0 + k;
+            if (E) E[g] = v[0];
+            if (E_out) E_out[g] = v[0];
+            for (int j = 0; j < 4; ++j) {
+                if (Tm) Tm[(long long)g * 4 + j] = v[j + 1];
+                if (T_out) T_out[(long long)g * 4 + j] = v[j + 1];
+            }
+            if (!isfinite(v[0])) atomicOr(flags, 1);
+        }
+        if (with_arc) {
+            double a = 0;
+            if (k > 0) {
+                const double* ap = apart + p.ap_off + (long long)k * p.arc_chunks * 4;
+                for (int t = lane; t < p.arc_chunks * 4; t += 64) a += ap[t];
+                a = wave_sum(a);
+            }
+            if (lane == 0) seg[k] = sqrt(a);
+        }
+    }
+    if (!with_arc) return;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int K = p.K, g0 = p.img0;
+        double S = 0;
+        alpha[g0] = 0;
+        for (int k = 1; k < K; ++k) {
+            S += seg[k];
+            alpha[g0 + k] = S;
+        }
+        const double L = S;
+        if (!(L > 0.0)) {
+            skip[pi] = 1;
+            for (int k = 0; k < K; ++k) {
+                alpha[g0 + k] = 0;
+                jidx[g0 + k] = k;
+                wgt[g0 + k] = 0;
+            }
+        } else {
+            skip[pi] = 0;
+            alpha[g0] = 0;
+            for (int k = 1; k < K; ++k) alpha[g0 + k] = alpha[g0 + k] / L;
+            for (int k = 0; k < K; ++k) {
+                if (k == 0 || k == K - 1) {
+                    jidx[g0 + k] = k;
+                    wgt[g0 + k] = 0;
+                    continue;
+                }
+                const double tk = (double)k / (double)(K - 1);
+                int j = 0;
+                for (int jj = 0; jj <= K - 2; ++jj)
+                    if (alpha[g0 + jj] <= tk) j = jj;
+                const double width = alpha[g0 + j + 1] - alpha[g0 + j];
+                jidx[g0 + k] = j;
+                wgt[g0 + k] = (width > 0.0) ? (tk - alpha[g0 + j]) / width : 0.0;
+            }
+        }
+        iters[pi] += 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_interp: s_k = normalise((1-w) s*_j + w s*_{j+1}); endpoints (and every
+// image when the reparametrisation is skipped) are copied.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_interp(const Prob* __restrict__ P, int np,
+                                                const int* __restrict__ wstart,
+                                                const T* __restrict__ ss, T* __restrict__ s,
+                                                const int* __restrict__ jidx,
+                                                const double* __restrict__ wgt,
+                                                const int* __restrict__ skip,
+                                                const int* __restrict__ done, int* flags)
+{
+    const int pi = find_problem(wstart, np, blockIdx.x);
+    if (done && done[pi]) return;
+    const Prob& p = P[pi];
+    const int w = blockIdx.x - wstart[pi];
+    const int k = w / p.ichunks, chunk = w - k * p.ichunks;
+    const long long N = p.N, M = 3 * N;
+    const long long i = (long long)chunk * kNT + threadIdx.x;
+    if (i >= N) return;
+    const T* src = ss + p.s_off;
+    T* dst = s + p.s_off + (long long)k * M;
+    if (skip[pi] || k == 0 || k == p.K - 1) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dst[c * N + i] = src[(long long)k * M + c * N + i];
+        return;
+    }
+    const int j = jidx[p.img0 + k];
+    const double wt = wgt[p.img0 + k];
+    const T* a = src + (long long)j * M;
+    const T* b = a + M;
+    double v[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = (1.0 - wt) * (double)a[c * N + i] + wt * (double)b[c * N + i];
+    const double nrm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    if (nrm < 1e-12) {
+        atomicOr(flags, 2);
+        const T* n = (wt < 0.5) ? a : b;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dst[c * N + i] = n[c * N + i];
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dst[c * N + i] = (T)(v[c] / nrm);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tangents and perpendicular force.
+// k_tan1: t~ = (phi_{k+1} - phi_{k-1}) projected per spin onto the tangent
+//         plane, stored to tt; partial sums of |t~|^2 and h_perp . t~.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_tan1(const Prob* __restrict__ P, int np,
+                                              const int* __restrict__ wstart,
+                                              const T* __restrict__ s, const T* __restrict__ h,
+                                              T* __restrict__ tt, double* __restrict__ fpart)
+{
+    __shared__ double red[kNT / 64][2];
+    const int pi = find_problem(wstart, np, blockIdx.x);
+    const Prob& p = P[pi];
+    const int w = blockIdx.x - wstart[pi];
+    const int k = w / p.ichunks, chunk = w - k * p.ichunks;
+    const long long N = p.N, M = 3 * N;
+    const long long i = (long long)chunk * kNT + threadIdx.x;
+    double a0 = 0, a1 = 0;
+    if (i < N) {
+        const int kp = (k + 1 < p.K) ? k + 1 : k, km = (k > 0) ? k - 1 : k;
+        const T* sk = s + p.s_off + (long long)k * M;
+        const T* sp = s + p.s_off + (long long)kp * M;
+        const T* sm = s + p.s_off + (long long)km * M;
+        const T* hk = h + p.s_off + (long long)k * M;
+        double v[3], f[3], d[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            v[c] = (double)sk[c * N + i];
+            f[c] = (double)hk[c * N + i];
+            d[c] = (double)sp[c * N + i] - (double)sm[c * N + i];
+        }
+        const double sh = v[0] * f[0] + v[1] * f[1] + v[2] * f[2];
+        const double sd = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
+        T* to = tt + p.s_off + (long long)k * M;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double tc = d[c] - sd * v[c];
+            const double hc = f[c] - sh * v[c];
+            to[c * N + i] = (T)tc;
+            a0 += tc * tc;
+            a1 += hc * tc;
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    if (lane == 0) { red[wave][0] = a0; red[wave][1] = a1; }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double v = 0;
+        for (int wv = 0; wv < kNT / 64; ++wv) v += red[wv][threadIdx.x];
+        fpart[p.fp_off + ((long long)k * p.ichunks + chunk) * 2 + threadIdx.x] = v;
+    }
+}
+
+// per problem, wave per image: tcoef[g] = {1/|t~|, projection coefficient}
+__global__ __launch_bounds__(kNT) void k_tanred(const Prob* __restrict__ P, int np,
+                                                const double* __restrict__ fpart,
+                                                double* __restrict__ tcoef)
+{
+    const int pi = blockIdx.x;
+    if (pi >= np) return;
+    const Prob& p = P[pi];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k = wave; k < p.K; k += kNT / 64) {
+        const double* fp = fpart + p.fp_off + (long long)k * p.ichunks * 2;
+        double n2 = 0, ht = 0;
+        for (int t = lane; t < p.ichunks; t += 64) {
+            n2 += fp[2 * t];
+            ht += fp[2 * t + 1];
+        }
+        n2 = wave_sum(n2);
+        ht = wave_sum(ht);
+        if (lane == 0) {
+            const double tn = sqrt(n2);
+            const double inv = (tn > 0.0) ? 1.0 / tn : 0.0;
+            const bool interior = (k > 0 && k < p.K - 1);
+            const int g = p.img0 + k;
+            tcoef[2 * g] = inv;
+            tcoef[2 * g + 1] = interior ? ht * inv * inv : 0.0;
+        }
+    }
+}
+
+// k_tan2: F_perp = h_perp - c t~; per-workgroup max |F_perp|; tangents out.
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_tan2(const Prob* __restrict__ P, int np,
+                                              const int* __restrict__ wstart,
+                                              const T* __restrict__ s, const T* __restrict__ h,
+                                              const T* __restrict__ tt, T* __restrict__ t_out,
+                                              const double* __restrict__ tcoef,
+                                              double* __restrict__ fmx)
+{
+    __shared__ double red[kNT / 64];
+    const int pi = find_problem(wstart, np, blockIdx.x);
+    const Prob& p = P[pi];
+    const int w = blockIdx.x - wstart[pi];
+    const int k = w / p.ichunks, chunk = w - k * p.ichunks;
+    const long long N = p.N, M = 3 * N;
+    const long long i = (long long)chunk * kNT + threadIdx.x;
+    const int g = p.img0 + k;
+    double fm = 0;
+    if (i < N) {
+        const double inv = tcoef[2 * g], cf = tcoef[2 * g + 1];
+        const T* sk = s + p.s_off + (long long)k * M;
+        const T* hk = h + p.s_off + (long long)k * M;
+        const T* tk = tt + p.s_off + (long long)k * M;
+        double v[3], f[3], tc[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            v[c] = (double)sk[c * N + i];
+            f[c] = (double)hk[c * N + i];
+            tc[c] = (double)tk[c * N + i];
+        }
+        const double sh = v[0] * f[0] + v[1] * f[1] + v[2] * f[2];
+        double n2 = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double fc = f[c] - sh * v[c] - cf * tc[c];
+            n2 += fc * fc;
+        }
+        fm = sqrt(n2);
+        if (t_out) {
+            T* to = t_out + p.s_off + (long long)k * M;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) to[c * N + i] = (T)(tc[c] * inv);
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    fm = wave_max(fm);
+    if (lane == 0) red[wave] = fm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = 0;
+        for (int wv = 0; wv < kNT / 64; ++wv) v = fmax(v, red[wv]);
+        fmx[p.fm_off + (long long)k * p.ichunks + chunk] = v;
+    }
+}
+
+__global__ __launch_bounds__(kNT) void k_fmax(const Prob* __restrict__ P, int np,
+                                              const double* __restrict__ fm,
+                                              double* __restrict__ fnorm, int* done, double tol,
+                                              double* out)
+{
+    __shared__ double red[kNT / 64];
+    const int pi = blockIdx.x;
+    if (pi >= np) return;
+    const Prob& p = P[pi];
+    const long long n = (long long)p.K * p.ichunks;
+    const double* f = fm + p.fm_off;
+    double v = 0;
+    for (long long t = threadIdx.x; t < n; t += kNT) v = fmax(v, f[t]);
+    v = wave_max(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = 0;
+        for (int wv = 0; wv < kNT / 64; ++wv) r = fmax(r, red[wv]);
+        fnorm[pi] = r;
+        if (out) out[pi] = r;
+        if (tol > 0.0 && r < tol && done) done[pi] = 1;
+    }
+}
+
+// B = max_k E_k - E_0, smallest argmax, envelope derivatives.
+__global__ void k_barrier(const Prob* __restrict__ P, int np, const double* __restrict__ E,
+                          const double* __restrict__ Tm, double* __restrict__ out)
+{
+    const int pi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pi >= np) return;
+    const Prob& p = P[pi];
+    const int g0 = p.img0;
+    int km = 0;
+    for (int k = 1; k < p.K; ++k)
+        if (E[g0 + k] > E[g0 + km]) km = k;
+    double* o = out + (long long)pi * 6;
+    o[0] = E[g0 + km] - E[g0];
+    o[1] = (double)km;
+    for (int j = 0; j < 4; ++j) o[2 + j] = Tm[(long long)(g0 + km) * 4 + j] - Tm[(long long)g0 * 4 + j];
+}
+
+__global__ void k_fill_int(int* p, int n, int v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_copy_int(const int* a, int* b, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+// ---------------------------------------------------------------------------
+// Dipole-kernel spectrum, FP64, once per lattice shape.
+// N_ab(r) = 3 r_a r_b / |r|^5 - delta_ab / |r|^3 (4 pi times eq. (7), r in
+// lattice units, r != 0, |r_x| < nx, |r_y| < ny, |r_z| < nz).  Each
+// component is even or odd along each axis, so its DFT on the padded grid is
+// real: products of cosine sums (even axes) and sine sums (odd axes), with
+// sign -1 for the off-diagonal components (two odd axes).  Three separable
+// direct passes; the result carries 1/(Px Py Pz).
+// Component c: 0 xx, 1 xy, 2 xz, 3 yy, 4 yz, 5 zz.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void comp_ab(int c, int& a, int& b)
+{
+    const int A[6] = {0, 0, 0, 1, 1, 2}, B[6] = {0, 1, 2, 1, 2, 2};
+    a = A[c];
+    b = B[c];
+}
+
+__device__ __forceinline__ double trig(const double* __restrict__ tw64, long long kd, int Pn,
+                                       bool odd)
+{
+    long long e = kd % Pn;
+    if (e < 0) e += Pn;
+    const long long idx = e * (kTwM / Pn);
+    return odd ? -tw64[2 * idx + 1] : tw64[2 * idx];
+}
+
+// F1[c][kx][dyi][dzi] = sum_dx N_c(dx,dy,dz) f(kx dx)
+__global__ void k_spec1(Prob p, double* __restrict__ F1, const double* __restrict__ tw64)
+{
+    const int nyo = 2 * p.ny - 1, nzo = 2 * p.nz - 1;
+    const long long total = 6LL * (p.mx + 1) * nyo * nzo;
+    const long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= total) return;
+    const int dzi = o % nzo;
+    long long r = o / nzo;
+    const int dyi = r % nyo;
+    r /= nyo;
+    const int kx = r % (p.mx + 1);
+    const int c = r / (p.mx + 1);
+    int a, b;
+    comp_ab(c, a, b);
+    const int dy = dyi - (p.ny - 1), dz = dzi - (p.nz - 1);
+    const bool oddx = ((a == 0) + (b == 0)) == 1;
+    const int Px = 2 * p.mx;
+    double acc = 0;
+    for (int dx = -(p.nx - 1); dx <= p.nx - 1; ++dx) {
+        if (dx == 0 && dy == 0 && dz == 0) continue;
+        const double r2 = (double)dx * dx + (double)dy * dy + (double)dz * dz;
+        const double rr = sqrt(r2);
+        const double r3 = r2 * rr, r5 = r3 * r2;
+        const double v[3] = {(double)dx, (double)dy, (double)dz};
+        const double n = 3.0 * v[a] * v[b] / r5 - ((a == b) ? 1.0 / r3 : 0.0);
+        acc += n * trig(tw64, (long long)kx * dx, Px, oddx);
+    }
+    F1[o] = acc;
+}
+
+// F2[c][kx][ky][dzi] = sum_dy F1[c][kx][dyi][dzi] f(ky dy)
+__global__ void k_spec2(Prob p, const double* __restrict__ F1, double* __restrict__ F2,
+                        const double* __restrict__ tw64)
+{
+    const int nyo = 2 * p.ny - 1, nzo = 2 * p.nz - 1, Py = 2 * p.my;
+    const long long total = 6LL * (p.mx + 1) * Py * nzo;
+    const long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= total) return;
+    const int dzi = o % nzo;
+    long long r = o / nzo;
+    const int ky = r % Py;
+    r /= Py;
+    const int kx = r % (p.mx + 1);
+    const int c = r / (p.mx + 1);
+    int a, b;
+    comp_ab(c, a, b);
+    const bool oddy = ((a == 1) + (b == 1)) == 1;
+    const double* f = F1 + (((long long)c * (p.mx + 1) + kx) * nyo) * nzo + dzi;
+    double acc = 0;
+    for (int dyi = 0; dyi < nyo; ++dyi)
+        acc += f[(long long)dyi * nzo] * trig(tw64, (long long)ky * (dyi - (p.ny - 1)), Py, oddy);
+    F2[o] = acc;
+}
+
+// final pass along z, scaling and storage in the convolution kernel's layout
+template <typename T>
+__global__ void k_spec3(Prob p, const double* __restrict__ F2, T* __restrict__ nh,
+                        const double* __restrict__ tw64)
+{
+    const int nzo = 2 * p.nz - 1, Py = 2 * p.my, Pz = p.pz;
+    const long long total = 6LL * (p.mx + 1) * Py * Pz;
+    const long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= total) return;
+    const int kz = o % Pz;
+    long long r = o / Pz;
+    const int ky = r % Py;
+    r /= Py;
+    const int kx = r % (p.mx + 1);
+    const int c = r / (p.mx + 1);
+    int a, b;
+    comp_ab(c, a, b);
+    const bool oddz = ((a == 2) + (b == 2)) == 1;
+    const double* f = F2 + (((long long)c * (p.mx + 1) + kx) * Py + ky) * nzo;
+    double acc = 0;
+    for (int dzi = 0; dzi < nzo; ++dzi)
+        acc += f[dzi] * trig(tw64, (long long)kz * (dzi - (p.nz - 1)), Pz, oddz);
+    const double sign = (a == b) ? 1.0 : -1.0;
+    const double scale = sign / ((double)(2 * p.mx) * (double)Py * (double)Pz);
+    const int hy = ky & 1, qy = ky >> 1;
+    const int hz = (p.nhz == 2) ? (kz & 1) : 0, rz = (p.nhz == 2) ? (kz >> 1) : 0;
+    const long long idx = ((((long long)kx * p.nhz + hz) * 2 + hy) * p.mz + rz) * 6 * p.my;
+    nh[idx + (long long)c * p.my + qy] = (T)(acc * scale);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_xfwd(const Prob* P, int np, const WorkMap& wm, const T* s, void* X,
+                       const void* tw, const int* done, size_t lds, hipStream_t st)
+{
+    if (wm.total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_xfwd<T>, dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start, s,
+                       (cplx<T>*)X, (const cplx<T>*)tw, done);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_conv(int mz, const Prob* P, int np, const WorkMap& wm, const void* X, void* Xp,
+                       const T* nhat, const void* tw, const int* done, size_t lds, hipStream_t st)
+{
+    if (wm.total == 0) return hipSuccess;
+    const cplx<T>* x = (const cplx<T>*)X;
+    cplx<T>* xp = (cplx<T>*)Xp;
+    const cplx<T>* t = (const cplx<T>*)tw;
+    switch (mz) {
+    case 1: hipLaunchKernelGGL((k_conv<T, 1>), dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start, x, xp, nhat, t, done); break;
+    case 2: hipLaunchKernelGGL((k_conv<T, 2>), dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start, x, xp, nhat, t, done); break;
+    case 4: hipLaunchKernelGGL((k_conv<T, 4>), dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start, x, xp, nhat, t, done); break;
+    case 8: hipLaunchKernelGGL((k_conv<T, 8>), dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start, x, xp, nhat, t, done); break;
+    case 16: hipLaunchKernelGGL((k_conv<T, 16>), dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start, x, xp, nhat, t, done); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xinv(const Prob* P, int np, const WorkMap& wm, const void* Xp, const T* s,
+                       T* s_star, T* h, double* epart, const void* tw, const int* done, int mode,
+                       double tau, size_t lds, hipStream_t st)
+{
+    if (wm.total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_xinv<T>, dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start,
+                       (const cplx<T>*)Xp, s, s_star, h, epart, (const cplx<T>*)tw, done, mode, tau);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_arc(const Prob* P, int np, const WorkMap& wm, const T* ss, double* apart,
+                      const int* done, hipStream_t st)
+{
+    if (wm.total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_arc<T>, dim3(wm.total), dim3(kNT), 0, st, P, np, wm.start, ss, apart, done);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const Prob* P, int np, const double* epart, const double* apart,
+                         double* E, double* Tm, double* E_out, double* T_out, double* alpha,
+                         int* jidx, double* wgt, int* skip, int* done, int* iters, int* flags,
+                         int with_arc, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce, dim3(np), dim3(kNT), 0, st, P, np, epart, apart, E, Tm, E_out,
+                       T_out, alpha, jidx, wgt, skip, done, iters, flags, with_arc);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_interp(const Prob* P, int np, const WorkMap& wm, const T* ss, T* s,
+                         const int* jidx, const double* wgt, const int* skip, const int* done,
+                         int* flags, hipStream_t st)
+{
+    if (wm.total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_interp<T>, dim3(wm.total), dim3(kNT), 0, st, P, np, wm.start, ss, s, jidx,
+                       wgt, skip, done, flags);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tan1(const Prob* P, int np, const WorkMap& wm, const T* s, const T* h, T* tt,
+                       double* fpart, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tan1<T>, dim3(wm.total), dim3(kNT), 0, st, P, np, wm.start, s, h, tt, fpart);
+    return hipGetLastError();
+}
+
+hipError_t launch_tanred(const Prob* P, int np, const double* fpart, double* tcoef, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tanred, dim3(np), dim3(kNT), 0, st, P, np, fpart, tcoef);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tan2(const Prob* P, int np, const WorkMap& wm, const T* s, const T* h,
+                       const T* tt, T* t_out, const double* tcoef, double* fmax, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tan2<T>, dim3(wm.total), dim3(kNT), 0, st, P, np, wm.start, s, h, tt, t_out,
+                       tcoef, fmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_fmax(const Prob* P, int np, const double* fmax, double* fnorm, int* done,
+                       double tol, double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fmax, dim3(np), dim3(kNT), 0, st, P, np, fmax, fnorm, done, tol, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_spectrum(const Prob& p, T* nhat, double* f1, double* f2, const double* tw64,
+                           hipStream_t st)
+{
+    const int nyo = 2 * p.ny - 1, nzo = 2 * p.nz - 1, Py = 2 * p.my;
+    const long long n1 = 6LL * (p.mx + 1) * nyo * nzo;
+    const long long n2 = 6LL * (p.mx + 1) * Py * nzo;
+    const long long n3 = 6LL * (p.mx + 1) * Py * p.pz;
+    hipLaunchKernelGGL(k_spec1, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, p, f1, tw64);
+    hipLaunchKernelGGL(k_spec2, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, p, f1, f2, tw64);
+    hipLaunchKernelGGL(k_spec3<T>, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, p, f2, nhat, tw64);
+    return hipGetLastError();
+}
+
+hipError_t launch_barrier(const Prob* P, int np, const double* E, const double* Tm, double* out,
+                          hipStream_t st)
+{
+    hipLaunchKernelGGL(k_barrier, dim3((np + 63) / 64), dim3(64), 0, st, P, np, E, Tm, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_iters_out(int np, const int* iters, const int* iters0, int* out, hipStream_t st)
+{
+    (void)iters0;
+    hipLaunchKernelGGL(k_copy_int, dim3((np + 255) / 256), dim3(256), 0, st, iters, out, np);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+// explicit instantiations
+#define SSM_INST(T)                                                                                \
+    template hipError_t launch_xfwd<T>(const Prob*, int, const WorkMap&, const T*, void*,         \
+                                       const void*, const int*, size_t, hipStream_t);             \
+    template hipError_t launch_conv<T>(int, const Prob*, int, const WorkMap&, const void*, void*, \
+                                       const T*, const void*, const int*, size_t, hipStream_t);   \
+    template hipError_t launch_xinv<T>(const Prob*, int, const WorkMap&, const void*, const T*,   \
+                                       T*, T*, double*, const void*, const int*, int, double,     \
+                                       size_t, hipStream_t);                                       \
+    template hipError_t launch_arc<T>(const Prob*, int, const WorkMap&, const T*, double*,        \
+                                      const int*, hipStream_t);                                    \
+    template hipError_t launch_interp<T>(const Prob*, int, const WorkMap&, const T*, T*,          \
+                                         const int*, const double*, const int*, const int*, int*, \
+                                         hipStream_t);                                             \
+    template hipError_t launch_tan1<T>(const Prob*, int, const WorkMap&, const T*, const T*, T*,  \
+                                       double*, hipStream_t);                                      \
+    template hipError_t launch_tan2<T>(const Prob*, int, const WorkMap&, const T*, const T*,      \
+                                       const T*, T*, const double*, double*, hipStream_t);         \
+    template hipError_t launch_spectrum<T>(const Prob&, T*, double*, double*, const double*,      \
+                                           hipStream_t);
+SSM_INST(float)
+SSM_INST(double)
+
+}  // namespace ssm

@@ -1,0 +1,105 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1804_07135_amd import inputs, ssm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ssm.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ssm_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_list():
+    assert header_functions() == sorted(ssm.ABI_SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(ssm.LIB_PATH)
+    for name in header_functions():
+        assert hasattr(lib, name), name
+
+
+def test_version_and_kernel_names():
+    assert ssm.ssm_version() >= 1
+    names = [ssm.ssm_kernel_name(i) for i in range(ssm.SSM_N_KERNELS)]
+    assert names[0] == "k_xfwd" and names[1] == "k_conv" and names[2] == "k_xinv"
+    assert ssm.ssm_kernel_name(ssm.SSM_N_KERNELS) is None
+    assert ssm.ssm_kernel_name(-1) is None
+
+
+def prob(**kw):
+    p = dict(nx=8, ny=8, nz=1, K=4, J=1.0, d=0.3, ku=0.1, D=0.01)
+    p.update(kw)
+    return p
+
+
+@pytest.mark.parametrize("bad,status", [
+    (dict(K=1), ssm.SSM_EINVAL),
+    (dict(nx=0), ssm.SSM_EINVAL),
+    (dict(nz=0), ssm.SSM_EINVAL),
+    (dict(J=float("nan")), ssm.SSM_EINVAL),
+    (dict(nx=2000), ssm.SSM_EUNSUPPORTED),
+    (dict(nz=17), ssm.SSM_EUNSUPPORTED),
+    (dict(ny=512, nz=8), ssm.SSM_EUNSUPPORTED),
+    (dict(K=2000), ssm.SSM_EUNSUPPORTED),
+])
+def test_workspace_size_rejects(bad, status):
+    with pytest.raises(ssm.SSMError) as ei:
+        ssm.ssm_workspace_size([prob(**bad)], ssm.SSM_FP64)
+    assert ei.value.status == status
+    assert ssm.ssm_last_error(None) != ""
+
+
+def test_workspace_size_rejects_precision_and_mixed_nz():
+    with pytest.raises(ssm.SSMError) as ei:
+        ssm.ssm_workspace_size([prob()], 7)
+    assert ei.value.status == ssm.SSM_EINVAL
+    with pytest.raises(ssm.SSMError) as ei:
+        ssm.ssm_workspace_size([prob(nz=2), prob(nz=8)], ssm.SSM_FP64)
+    assert ei.value.status == ssm.SSM_EUNSUPPORTED
+    # nz 3 and 4 share the padded z length: accepted
+    assert ssm.ssm_workspace_size([prob(nz=3), prob(nz=4)], ssm.SSM_FP64) > 0
+
+
+def test_workspace_sizes_scale():
+    w = inputs.WORKLOADS["tube_256x256x8_k48"]
+    p = dict(nx=w["nx"], ny=w["ny"], nz=w["nz"], K=w["K"], J=1, d=0.3, ku=0.1, D=0.02)
+    b64 = ssm.ssm_workspace_size([p], ssm.SSM_FP64)
+    b32 = ssm.ssm_workspace_size([p], ssm.SSM_FP32_MIXED)
+    n = 48 * 3 * 256 * 256 * 8
+    # spins, stepped spins, field, two x-spectra: about 3*8 + 2*16 bytes per value (FP64)
+    assert 50 * n < b64 < 64 * n
+    assert 0.45 < b32 / b64 < 0.55
+    sweep = inputs.sweep_points()
+    ps = [dict(nx=q["nx"], ny=q["ny"], nz=1, K=q["K"], J=q["J"], d=q["d"], ku=q["ku"], D=q["D"])
+          for q in sweep]
+    assert ssm.ssm_workspace_size(ps, ssm.SSM_FP32_MIXED) > 0
+
+
+def test_create_rejects_null_workspace():
+    lib = ssm.load()
+    arr = ssm._problems([prob()])
+    ctx = ctypes.c_void_p()
+    st = lib.ssm_create(arr, 1, 0, None, 1 << 20, None, ctypes.byref(ctx))
+    assert st == ssm.SSM_EINVAL
+    assert ctx.value is None
+    st = lib.ssm_create(arr, 1, 0, ctypes.c_void_p(4096 + 8), 1 << 20, None, ctypes.byref(ctx))
+    assert st == ssm.SSM_EINVAL  # misaligned
+    assert "aligned" in ssm.ssm_last_error(None)
+
+
+def test_null_context_calls():
+    lib = ssm.load()
+    assert lib.ssm_destroy(None) == ssm.SSM_OK
+    assert lib.ssm_iterate(None, 1, 0.1, 0.0, None) == ssm.SSM_EINVAL
+    assert lib.ssm_set_string(None, None) == ssm.SSM_EINVAL
+    assert lib.ssm_get_barrier(None, None) == ssm.SSM_EINVAL
