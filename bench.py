@@ -100,6 +100,7 @@ def main():
     ap.add_argument("--graph-chunk", type=int, default=10)
     ap.add_argument("--fp64-steps", type=int, default=0, help="steps of the FP64 plain run (0: = --steps)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--fp32-only", action="store_true", help="skip the FP64 plain run (profiling)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -137,6 +138,9 @@ def main():
 
     # --- FP64 plain form, direct launches ----------------------------------
     st64 = args.fp64_steps or steps
+    if args.fp32_only:
+        print(json.dumps({"ms_per_step": dt32 / steps * 1e3, "kernels_ms": prof}), flush=True)
+        return
     sm64 = ssm.StringMethod(prob, ssm.SSM_FP64)
     sm64.set_string(s0)
     sm64.iterate(warm, tau)

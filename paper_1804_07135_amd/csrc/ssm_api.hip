@@ -21,7 +21,7 @@ namespace {
 constexpr int kVersion = 1;
 constexpr size_t kAlign = 256;
 constexpr size_t kLdsMax = 160 * 1024;
-constexpr size_t kLdsBudget = 150 * 1024;
+constexpr int kNumMaps = 6;
 
 thread_local std::string g_create_error;
 
@@ -46,8 +46,9 @@ int ilog2(int m)
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Tiles {
-    int yt;
-    int gconv;
+    int ytf;    // rows per tile, forward x kernel
+    int yt;     // rows per tile, inverse x kernel + epilogue
+    int gconv;  // slices per convolution workgroup
 };
 
 // Everything about a batch that follows from the problem list: descriptors,
@@ -61,23 +62,28 @@ struct Plan {
     std::vector<int> geo;             // problem -> distinct-shape index
     std::vector<std::tuple<int, int, int>> shapes;
     std::vector<long long> nh_size;   // elements per distinct shape
-    std::vector<int> wm_xt, wm_conv, wm_arc, wm_site;
+    std::vector<int> wm_xf, wm_xi, wm_conv, wm_arc, wm_site, wm_img;
     long long n_img = 0, n_spin = 0, n_x = 0, n_nh = 0, n_ep = 0, n_ap = 0, n_fp = 0, n_fm = 0;
-    size_t lds_x = 0, lds_conv = 0;
+    size_t lds_xf = 0, lds_xi = 0, lds_conv = 0;
     size_t scratch_bytes = 0;
     // workspace offsets
     size_t o_P, o_wm, o_tw, o_tw64, o_s, o_ss, o_h, o_nh, o_big, o_ep, o_ap, o_fp, o_E, o_T,
-        o_alpha, o_w, o_tc, o_fn, o_fm, o_j, o_done, o_iters, o_skip, o_flags, o_it0, total;
+        o_alpha, o_w, o_tc, o_fn, o_fm, o_j, o_done, o_iters, o_skip, o_flags, o_seg, o_cnt, total;
 };
 
-size_t lds_xtile(const Prob& p, size_t tsize)
+size_t lds_xfwd(const Prob& p, int yt, size_t tsize)
 {
-    return (size_t)3 * p.yt * p.mx * 2 * tsize + (size_t)3 * p.yt * p.nx * tsize;
+    return (size_t)(2 * p.mx + yt * p.mx) * 2 * tsize;
+}
+
+size_t lds_xinv(const Prob& p, int yt, size_t tsize)
+{
+    return (size_t)(2 * p.mx + yt * p.mx) * 2 * tsize + (size_t)3 * yt * p.nx * tsize;
 }
 
 size_t lds_convg(const Prob& p, int G, size_t tsize)
 {
-    return (size_t)G * 3 * p.nz * p.my * 2 * tsize;
+    return (size_t)(2 * p.my + G * 3 * p.nz * p.my) * 2 * tsize;
 }
 
 ssm_status check_problems(const ssm_problem* pr, int np, int prec, std::string& err)
@@ -112,33 +118,46 @@ ssm_status check_problems(const ssm_problem* pr, int np, int prec, std::string& 
     return SSM_OK;
 }
 
-// default tile shapes; autotuning may replace them
+// Default tile shapes; autotuning may replace them.  Workgroups should fit
+// three to a CU (LDS <= 52 KiB) and write or read >= 64-byte runs of the
+// [img][kx][c][z][y] spectra.
+constexpr size_t kLdsTarget = 52 * 1024;
+
 Tiles default_tiles(const Prob& p, size_t tsize)
 {
     Tiles t;
-    const int cs = (int)(2 * tsize);                  // bytes per complex value
-    int yt = std::max(2, 128 / cs);                   // 128-byte output chunks
+    const int cs = (int)(2 * tsize);
     const int ycap = std::max(2, pow2ceil(p.ny));
-    Prob q = p;
-    while (3 * yt * p.mx < 1536 && yt < ycap) yt *= 2;
-    yt = std::min(yt, ycap);
-    q.yt = yt;
-    while (yt > 2 && lds_xtile(q, tsize) > kLdsBudget) { yt /= 2; q.yt = yt; }
-    t.yt = yt;
+    int yf = std::max(2, 128 / cs);
+    while (yf * p.mx < 4096 && yf < ycap && lds_xfwd(p, 2 * yf, tsize) <= kLdsTarget) yf *= 2;
+    yf = std::min(yf, ycap);
+    while (yf > 2 && lds_xfwd(p, yf, tsize) > kLdsTarget) yf /= 2;
+    t.ytf = yf;
+    int yi = std::max(2, 128 / cs);
+    while (yi * p.mx < 4096 && yi < ycap && lds_xinv(p, 2 * yi, tsize) <= kLdsTarget) yi *= 2;
+    yi = std::min(yi, ycap);
+    while (yi > 2 && lds_xinv(p, yi, tsize) > kLdsTarget) yi /= 2;
+    t.yt = yi;
     const int per = 3 * p.nz * p.ny;
     int gmax = std::max(1, kConvElems / per);
-    while (gmax > 1 && lds_convg(p, gmax, tsize) > kLdsBudget) --gmax;
+    while (gmax > 1 && lds_convg(p, gmax, tsize) > kLdsTarget) --gmax;
     const long long slices = (long long)p.K * (p.mx + 1);
-    int g = (int)std::max<long long>(1, std::min<long long>(gmax, slices / 1024));
-    t.gconv = g;
+    t.gconv = (int)std::max<long long>(1, std::min<long long>(gmax, slices / 1024));
     return t;
 }
 
+int pad8(int n) { return (n + 7) / 8 * 8; }
+
 void apply_tiles(Prob& p, const Tiles& t)
 {
+    p.ytf = t.ytf;
+    p.ntyf = (p.ny + p.ytf - 1) / p.ytf;
+    p.tilesf = p.nz * p.ntyf;
+    p.wgf = pad8(p.K * p.tilesf);
     p.yt = t.yt;
     p.nty = (p.ny + p.yt - 1) / p.yt;
     p.tiles = p.nz * p.nty;
+    p.wgi = pad8(p.K * p.tiles);
     p.gconv = t.gconv;
     p.xcd_remap = (t.gconv == 1) ? 1 : 0;
 }
@@ -177,7 +196,8 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec, const std::vector
         p.N = (long long)q.nx * q.ny * q.nz;
         const Tiles t = tiles ? (*tiles)[i] : default_tiles(p, pl.tsize);
         apply_tiles(p, t);
-        if (lds_xtile(p, pl.tsize) > kLdsMax || lds_convg(p, p.gconv, pl.tsize) > kLdsMax) {
+        if (lds_xfwd(p, p.ytf, pl.tsize) > kLdsMax || lds_xinv(p, p.yt, pl.tsize) > kLdsMax ||
+            lds_convg(p, p.gconv, pl.tsize) > kLdsMax) {
             err = "problem " + std::to_string(i) + ": lattice too large for one workgroup's LDS";
             return SSM_EUNSUPPORTED;
         }
@@ -213,7 +233,8 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec, const std::vector
             pl.geo[i] = it->second;
         }
         pl.mz = p.mz;
-        pl.lds_x = std::max(pl.lds_x, lds_xtile(p, pl.tsize));
+        pl.lds_xf = std::max(pl.lds_xf, lds_xfwd(p, p.ytf, pl.tsize));
+        pl.lds_xi = std::max(pl.lds_xi, lds_xinv(p, p.yt, pl.tsize));
         pl.lds_conv = std::max(pl.lds_conv, lds_convg(p, p.gconv, pl.tsize));
     }
     // kernel-spectrum offsets per shape
@@ -231,16 +252,18 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec, const std::vector
         v.assign(np + 1, 0);
         for (int i = 0; i < np; ++i) v[i + 1] = v[i] + count(pl.P[i]);
     };
-    prefix(pl.wm_xt, [](const Prob& p) { return p.K * p.tiles; });
+    prefix(pl.wm_xf, [](const Prob& p) { return p.wgf; });
+    prefix(pl.wm_xi, [](const Prob& p) { return p.wgi; });
     prefix(pl.wm_conv, [](const Prob& p) { return conv_wgs(p); });
     prefix(pl.wm_arc, [](const Prob& p) { return p.arc_chunks; });
     prefix(pl.wm_site, [](const Prob& p) { return p.K * p.ichunks; });
+    prefix(pl.wm_img, [](const Prob& p) { return p.K; });
     // workspace layout
     const size_t ts = pl.tsize, cs = 2 * ts;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = up(o + std::max<size_t>(bytes, 1)); return r; };
     pl.o_P = take(sizeof(Prob) * np);
-    pl.o_wm = take(sizeof(int) * 4 * (np + 1));
+    pl.o_wm = take(sizeof(int) * kNumMaps * (np + 1));
     pl.o_tw = take(cs * kTwM);
     pl.o_tw64 = take(16 * kTwM);
     pl.o_s = take(ts * spin);
@@ -263,7 +286,8 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec, const std::vector
     pl.o_iters = take(4 * np);
     pl.o_skip = take(4 * np);
     pl.o_flags = take(4);
-    pl.o_it0 = take(4 * np);
+    pl.o_seg = take(8 * img);
+    pl.o_cnt = take(4 * np);
     pl.total = o;
     return SSM_OK;
 }
@@ -302,10 +326,12 @@ struct ssm_ctx {
         w.total = v.back();
         return w;
     }
-    WorkMap wm_xt() const { return wm(0, pl.wm_xt); }
-    WorkMap wm_conv() const { return wm(1, pl.wm_conv); }
-    WorkMap wm_arc() const { return wm(2, pl.wm_arc); }
-    WorkMap wm_site() const { return wm(3, pl.wm_site); }
+    WorkMap wm_xf() const { return wm(0, pl.wm_xf); }
+    WorkMap wm_xi() const { return wm(1, pl.wm_xi); }
+    WorkMap wm_conv() const { return wm(2, pl.wm_conv); }
+    WorkMap wm_arc() const { return wm(3, pl.wm_arc); }
+    WorkMap wm_site() const { return wm(4, pl.wm_site); }
+    WorkMap wm_img() const { return wm(5, pl.wm_img); }
     void* X() const { return ws + pl.o_big; }
     void* Xp() const { return ws + pl.o_big + 2 * pl.tsize * pl.n_x; }
 };
@@ -367,7 +393,7 @@ struct Ops {
         const void* tw = c->at<void>(pl.o_tw);
         hipError_t e;
         e = timed(c, st, KK_XFWD, [&] {
-            return launch_xfwd<T>(c->P(), pl.np, c->wm_xt(), src, c->X(), tw, done, pl.lds_x, st);
+            return launch_xfwd<T>(c->P(), pl.np, c->wm_xf(), src, c->X(), tw, done, pl.lds_xf, st);
         });
         if (e != hipSuccess) return e;
         e = timed(c, st, KK_CONV, [&] {
@@ -376,8 +402,8 @@ struct Ops {
         });
         if (e != hipSuccess) return e;
         return timed(c, st, KK_XINV, [&] {
-            return launch_xinv<T>(c->P(), pl.np, c->wm_xt(), c->Xp(), src, s_star, hdst,
-                                  c->at<double>(pl.o_ep), tw, done, mode, tau, pl.lds_x, st);
+            return launch_xinv<T>(c->P(), pl.np, c->wm_xi(), c->Xp(), src, s_star, hdst,
+                                  c->at<double>(pl.o_ep), tw, done, mode, tau, pl.lds_xi, st);
         });
     }
 
@@ -394,11 +420,13 @@ struct Ops {
         });
         if (e != hipSuccess) return e;
         e = timed(c, st, KK_REDUCE, [&] {
-            return launch_reduce(c->P(), pl.np, c->at<double>(pl.o_ep), c->at<double>(pl.o_ap),
+            return launch_reduce(c->P(), pl.np, (int)pl.n_img, c->wm_img().start,
+                                 c->at<double>(pl.o_ep), c->at<double>(pl.o_ap),
                                  c->at<double>(pl.o_E), nullptr, nullptr, nullptr,
-                                 c->at<double>(pl.o_alpha), c->at<int>(pl.o_j),
-                                 c->at<double>(pl.o_w), c->at<int>(pl.o_skip), done,
-                                 c->at<int>(pl.o_iters), c->at<int>(pl.o_flags), 1, st);
+                                 c->at<double>(pl.o_seg), c->at<double>(pl.o_alpha),
+                                 c->at<int>(pl.o_j), c->at<double>(pl.o_w), c->at<int>(pl.o_skip),
+                                 done, c->at<int>(pl.o_iters), c->at<int>(pl.o_cnt),
+                                 c->at<int>(pl.o_flags), 1, st);
         });
         if (e != hipSuccess) return e;
         return timed(c, st, KK_INTERP, [&] {
@@ -417,10 +445,11 @@ struct Ops {
         hipError_t e = field(c, st, src, nullptr, hdst, mode, 0.0, nullptr);
         if (e != hipSuccess) return e;
         return timed(c, st, KK_REDUCE, [&] {
-            return launch_reduce(c->P(), pl.np, c->at<double>(pl.o_ep), nullptr,
+            return launch_reduce(c->P(), pl.np, (int)pl.n_img, c->wm_img().start,
+                                 c->at<double>(pl.o_ep), nullptr,
                                  store ? c->at<double>(pl.o_E) : nullptr,
                                  store ? c->at<double>(pl.o_T) : nullptr, E_out, T_out, nullptr,
-                                 nullptr, nullptr, nullptr, nullptr, nullptr,
+                                 nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                                  c->at<int>(pl.o_flags), 0, st);
         });
     }
@@ -540,7 +569,7 @@ static ssm_status upload_plan(ssm_ctx* c)
     HIPCHK(c, hipMemcpyAsync(c->ws + pl.o_P, pl.P.data(), sizeof(Prob) * pl.np,
                              hipMemcpyHostToDevice, c->stream), "upload descriptors");
     std::vector<int> wm;
-    for (const auto* v : {&pl.wm_xt, &pl.wm_conv, &pl.wm_arc, &pl.wm_site})
+    for (const auto* v : {&pl.wm_xf, &pl.wm_xi, &pl.wm_conv, &pl.wm_arc, &pl.wm_site, &pl.wm_img})
         wm.insert(wm.end(), v->begin(), v->end());
     HIPCHK(c, hipMemcpyAsync(c->ws + pl.o_wm, wm.data(), sizeof(int) * wm.size(),
                              hipMemcpyHostToDevice, c->stream), "upload work maps");
@@ -615,6 +644,7 @@ ssm_status ssm_create(const ssm_problem* p, int32_t n_problems, int32_t precisio
     if (e == hipSuccess) e = launch_fill_int(c->at<int>(pl.o_iters), pl.np, 0, c->stream);
     if (e == hipSuccess) e = launch_fill_int(c->at<int>(pl.o_skip), pl.np, 0, c->stream);
     if (e == hipSuccess) e = launch_fill_int(c->at<int>(pl.o_flags), 1, 0, c->stream);
+    if (e == hipSuccess) e = launch_fill_int(c->at<int>(pl.o_cnt), pl.np, 0, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) { hipfail(c, e, "create"); return bail(SSM_EHIP); }
     *out = c;

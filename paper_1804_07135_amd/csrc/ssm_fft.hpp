@@ -1,0 +1,200 @@
+// Power-of-two complex FFT building blocks of the gfx950 string-method
+// kernels.  The zero-padded transforms of the dipolar convolution (Sec. II.A,
+// eq. (6): a discrete convolution evaluated with FFTs) are built from these.
+//
+// fft_lines() transforms a set of lines held in LDS with Stockham passes of
+// radix 16, 8, 4 or 2 (the widest radix a kernel instantiates is a template
+// choice).  A wavefront owns a group of lines of 1024 elements in
+// total, so every pass has exactly 1024/R butterflies per group, i.e.
+// 16/R butterflies (16 complex values) per lane, and the lane reads all of
+// its inputs before any lane of the wavefront writes: the pass can run in
+// place with wavefront-level ordering only.
+//
+// The pass bodies are __host__ __device__ so that the host test suite can
+// run them with the 64 lanes of a wavefront emulated one after another
+// (all reads, then all writes), which is exactly the lockstep semantics the
+// device relies on.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ssm {
+
+// exp(-2 pi i k / 16), k = 0..15, to double precision
+constexpr double kW16re[16] = {
+    1.0, 0.92387953251128674, 0.70710678118654752, 0.38268343236508977,
+    0.0, -0.38268343236508977, -0.70710678118654752, -0.92387953251128674,
+    -1.0, -0.92387953251128674, -0.70710678118654752, -0.38268343236508977,
+    0.0, 0.38268343236508977, 0.70710678118654752, 0.92387953251128674};
+constexpr double kW16im[16] = {
+    0.0, -0.38268343236508977, -0.70710678118654752, -0.92387953251128674,
+    -1.0, -0.92387953251128674, -0.70710678118654752, -0.38268343236508977,
+    0.0, 0.38268343236508977, 0.70710678118654752, 0.92387953251128674,
+    1.0, 0.92387953251128674, 0.70710678118654752, 0.38268343236508977};
+
+template <typename V>
+__host__ __device__ __forceinline__ V mk(decltype(V::x) a, decltype(V::x) b) { V r; r.x = a; r.y = b; return r; }
+template <typename V>
+__host__ __device__ __forceinline__ V cadd(V a, V b) { return mk<V>(a.x + b.x, a.y + b.y); }
+template <typename V>
+__host__ __device__ __forceinline__ V csub(V a, V b) { return mk<V>(a.x - b.x, a.y - b.y); }
+template <typename V>
+__host__ __device__ __forceinline__ V cmul(V a, V b) { return mk<V>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+// a * conj(b)
+template <typename V>
+__host__ __device__ __forceinline__ V cmulc(V a, V b) { return mk<V>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y); }
+template <bool INV, typename V>
+__host__ __device__ __forceinline__ V twm(V a, V w) { return INV ? cmulc(a, w) : cmul(a, w); }
+
+// In-register R-point DFT (R = 1, 2, 4, 8, 16), natural order in and out:
+// bit-reversal permutation, then radix-2 decimation-in-time stages.
+template <typename V, int R, bool INV>
+__host__ __device__ __forceinline__ void dft_reg(V (&a)[R])
+{
+    using S = decltype(V::x);
+    if (R == 1) return;
+    constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        int r = 0;
+#pragma unroll
+        for (int b = 0; b < LR; ++b) r |= ((i >> b) & 1) << (LR - 1 - b);
+        if (r > i) { V t = a[i]; a[i] = a[r]; a[r] = t; }
+    }
+#pragma unroll
+    for (int len = 2; len <= R; len <<= 1) {
+        const int half = len >> 1;
+#pragma unroll
+        for (int i = 0; i < R; i += len) {
+#pragma unroll
+            for (int j = 0; j < half; ++j) {
+                const int e = j * (16 / len);
+                const V u = a[i + j];
+                V v = a[i + j + half];
+                if (e != 0) {
+                    const V w = mk<V>((S)kW16re[e], (S)(INV ? -kW16im[e] : kW16im[e]));
+                    v = cmul(v, w);
+                }
+                a[i + j] = cadd(u, v);
+                a[i + j + half] = csub(u, v);
+            }
+        }
+    }
+}
+
+// One radix-R Stockham pass over a group of gl lines of length m = 2^lm
+// (line stride ls) starting at buf.  lns = log2 of the sub-transform length
+// already done.  twl[e] = exp(-2 pi i e / (2m)), e < 2m (conjugated for the
+// inverse), so the pass twiddle W_{Ns R}^{r k} is twl[(r k) << (lm+1-lns-lr)].
+template <typename V, int R, bool INV>
+struct Pass {
+    static constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
+    static constexpr int B = 16 / R;  // butterflies per lane
+
+    __host__ __device__ static void read(const V* buf, int ls, int lm, int lns, int gl,
+                                         const V* twl, int lane, V (&v)[B][R])
+    {
+        const int q = 1 << (lm - LR), lq = lm - LR;
+        const int nbf = gl << lq;
+        const int Ns = 1 << lns;
+        const int tsh = lm + 1 - lns - LR;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int g = lane + 64 * b;
+            if (g < nbf) {
+                const int line = g >> lq, j = g & (q - 1), k = j & (Ns - 1);
+                const V* L = buf + line * ls + j;
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[b][r] = L[r * q];
+                if (lns > 0) {
+#pragma unroll
+                    for (int r = 1; r < R; ++r) v[b][r] = twm<INV>(v[b][r], twl[(r * k) << tsh]);
+                }
+                dft_reg<V, R, INV>(v[b]);
+            }
+        }
+    }
+
+    __host__ __device__ static void write(V* buf, int ls, int lm, int lns, int gl, int lane,
+                                          const V (&v)[B][R])
+    {
+        const int q = 1 << (lm - LR), lq = lm - LR;
+        const int nbf = gl << lq;
+        const int Ns = 1 << lns;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int g = lane + 64 * b;
+            if (g < nbf) {
+                const int line = g >> lq, j = g & (q - 1), k = j & (Ns - 1);
+                V* L = buf + line * ls + ((j >> lns) << (lns + LR)) + k;
+#pragma unroll
+                for (int r = 0; r < R; ++r) L[r * Ns] = v[b][r];
+            }
+        }
+    }
+};
+
+// log2 radix of the next pass when rem bits of the length are left and
+// passes are capped at maxb bits: the widest allowed radix, except that a
+// remainder that would end in a lone radix-2 pass is split more evenly
+// (e.g. 2^5 = 8*4, 2^9 = 8*8*8 with maxb 3; 4*4*2 for 2^5 with maxb 2).
+__host__ __device__ __forceinline__ int fft_next_bits(int rem, int maxb)
+{
+    if (rem <= maxb) return rem;
+    if (maxb >= 4) return (rem == 5) ? 3 : (rem == 9 ? 3 : 4);
+    if (maxb == 3) return (rem == 4) ? 2 : 3;
+    return 2;
+}
+
+// lines per wavefront group: 1024 elements per group
+__host__ __device__ __forceinline__ int fft_group_lines(int lm) { return lm >= 10 ? 1 : (1 << (10 - lm)); }
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename V, int R, bool INV>
+__device__ __forceinline__ void run_pass(V* base, int ls, int lm, int lns, int gl, const V* twl, int lane)
+{
+    V v[Pass<V, R, INV>::B][R];
+    Pass<V, R, INV>::read(base, ls, lm, lns, gl, twl, lane, v);
+    wave_sync();
+    Pass<V, R, INV>::write(base, ls, lm, lns, gl, lane, v);
+    wave_sync();
+}
+
+// Transform nl lines of length 2^lm at buf (stride ls) in LDS; forward
+// (exp(-2 pi i jk/m)) or unnormalised inverse.  twl: the LDS table of
+// exp(-2 pi i e/(2m)), e < 2m.  MAXB (2 or 3) caps the pass radix at 2^MAXB;
+// fewer pass kinds keep the register footprint of the caller small.  Call
+// between workgroup barriers.
+template <typename V, bool INV, int MAXB = 2>
+__device__ __forceinline__ void fft_lines(V* buf, int nl, int ls, int lm, const V* twl)
+{
+    if (lm == 0) return;
+    int lane = threadIdx.x & 63;
+    // opaque copy: per-lane addresses are recomputed at each call instead of
+    // being hoisted (and kept live) across the caller's loops
+    asm volatile("" : "+v"(lane));
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lpg = fft_group_lines(lm);
+    for (int g0 = wave * lpg; g0 < nl; g0 += nw * lpg) {
+        const int gl = min(lpg, nl - g0);
+        V* base = buf + g0 * ls;
+        int lns = 0, rem = lm;
+        while (rem > 0) {
+            const int bits = fft_next_bits(rem, MAXB);
+            if (bits == 4) run_pass<V, 16, INV>(base, ls, lm, lns, gl, twl, lane);
+            else if (bits == 3) run_pass<V, 8, INV>(base, ls, lm, lns, gl, twl, lane);
+            else if (bits == 2) run_pass<V, 4, INV>(base, ls, lm, lns, gl, twl, lane);
+            else run_pass<V, 2, INV>(base, ls, lm, lns, gl, twl, lane);
+            lns += bits;
+            rem -= bits;
+        }
+    }
+}
+
+}  // namespace ssm

@@ -13,7 +13,8 @@ constexpr int kTwLog = 11;
 constexpr int kTwM = 1 << kTwLog;
 constexpr int kMaxLogM = 10;   // half padded length m <= 1024, padded P = 2m <= 2048
 constexpr int kNT = 256;       // threads per workgroup for every kernel
-constexpr int kConvElems = 6144; // target complex values per convolution workgroup
+constexpr int kMaxE = 24;       // register slots per thread of the convolution accumulator
+constexpr int kConvElems = kMaxE * kNT;  // complex values per convolution workgroup
 constexpr int kArcEPT = 8;     // flat elements per thread in the arc-length kernel
 constexpr int kNTerm = 5;      // energy partial slots: E, T_J, T_d, T_ku, T_dip
 
@@ -30,14 +31,15 @@ struct Prob {
     int lmx, lmy, lmz;     // their log2
     int pz;                // padded z length: 2*mz when nz > 1, else 1
     int nhz;               // z halves of the padded z spectrum: 2 when nz > 1, else 1
-    int yt;                // lattice rows per tile of the x-transform kernels
+    int yt;                // lattice rows per tile of the inverse-x / epilogue kernel
     int nty;               // ceil(ny / yt)
-    int tiles;             // x-transform tiles per image = nz * nty
+    int tiles;             // inverse-x tiles per image = nz * nty (energy partials)
+    int ytf, ntyf, tilesf; // the same for the forward x kernel
+    int wgf, wgi;          // forward / inverse x workgroups (K * tiles, padded to 8)
     int img0;              // index of this problem's first image in batch-wide arrays
     int gconv;             // consecutive (image, kx) slices per convolution workgroup
     int arc_chunks;        // arc-length workgroups (flat chunks of 3N) per image
     int xcd_remap;         // convolution kernel: group same-kx slices on one XCD
-    int pad_;
     long long N;           // sites per image
     long long s_off;       // element offset of image 0 in spin / field buffers
     long long x_off;       // complex-element offset in the x-spectrum buffers
@@ -76,10 +78,10 @@ hipError_t launch_xinv(const Prob* P, int np, const WorkMap& wm, const void* Xp,
 template <typename T>
 hipError_t launch_arc(const Prob* P, int np, const WorkMap& wm, const T* ss, double* apart,
                       const int* done, hipStream_t st);
-hipError_t launch_reduce(const Prob* P, int np, const double* epart, const double* apart,
-                         double* E, double* Tm, double* E_out, double* T_out, double* alpha,
-                         int* jidx, double* wgt, int* skip, int* done, int* iters, int* flags,
-                         int with_arc, hipStream_t st);
+hipError_t launch_reduce(const Prob* P, int np, int nimg, const int* istart, const double* epart,
+                         const double* apart, double* E, double* Tm, double* E_out, double* T_out,
+                         double* seg, double* alpha, int* jidx, double* wgt, int* skip, int* done,
+                         int* iters, int* count, int* flags, int with_arc, hipStream_t st);
 template <typename T>
 hipError_t launch_interp(const Prob* P, int np, const WorkMap& wm, const T* ss, T* s,
                          const int* jidx, const double* wgt, const int* skip, const int* done,

@@ -27,6 +27,7 @@
 // Length-m transforms run in LDS as Stockham radix-4 (+ one radix-2) passes;
 // every line belongs to one wavefront, which needs no workgroup barrier
 // between passes.
+#include "ssm_fft.hpp"
 #include "ssm_internal.hpp"
 
 namespace ssm {
@@ -35,32 +36,6 @@ template <typename T> struct CT;
 template <> struct CT<float> { using type = float2; };
 template <> struct CT<double> { using type = double2; };
 template <typename T> using cplx = typename CT<T>::type;
-
-template <typename V>
-__device__ __forceinline__ V mk(decltype(V::x) a, decltype(V::x) b) { V r; r.x = a; r.y = b; return r; }
-template <typename V>
-__device__ __forceinline__ V cadd(V a, V b) { return mk<V>(a.x + b.x, a.y + b.y); }
-template <typename V>
-__device__ __forceinline__ V csub(V a, V b) { return mk<V>(a.x - b.x, a.y - b.y); }
-template <typename V>
-__device__ __forceinline__ V cmul(V a, V b) { return mk<V>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
-// a * conj(b)
-template <typename V>
-__device__ __forceinline__ V cmulc(V a, V b) { return mk<V>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y); }
-template <bool INV, typename V>
-__device__ __forceinline__ V twm(V a, V w) { return INV ? cmulc(a, w) : cmul(a, w); }
-// multiply by -i (forward) or +i (inverse)
-template <bool INV, typename V>
-__device__ __forceinline__ V rot(V a) { return INV ? mk<V>(-a.y, a.x) : mk<V>(a.y, -a.x); }
-
-// Order LDS traffic of one wavefront: LDS executes a wave's instructions in
-// issue order, so a compiler barrier plus wavefront-scope fences suffice.
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __device__ __forceinline__ int find_problem(const int* __restrict__ start, int np, int b)
 {
@@ -72,110 +47,19 @@ __device__ __forceinline__ int find_problem(const int* __restrict__ start, int n
     return lo;
 }
 
-// ---------------------------------------------------------------------------
-// In-LDS transforms of nl lines of length m = 2^lm (line stride ls elements).
-// Forward uses W = exp(-2 pi i / m); inverse is unnormalised.  Lines are
-// handed out to wavefronts in groups of at most 1024 elements.
-// ---------------------------------------------------------------------------
-template <typename T, bool INV>
-__device__ void fft_lines(cplx<T>* buf, int nl, int ls, int lm, const cplx<T>* __restrict__ tw)
-{
-    using V = cplx<T>;
-    if (lm == 0) return;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int m = 1 << lm;
-    // A wave owns whole line groups of 512 elements (one line of 1024, whose
-    // passes are all radix 4), so no pass has more than 256 butterflies and
-    // each lane holds at most 4 of them.
-    const int lpg = (lm >= 9) ? 1 : (1 << (9 - lm));
-    for (int g0 = wave * lpg; g0 < nl; g0 += nw * lpg) {
-        const int gl = min(lpg, nl - g0);
-        V* base0 = buf + g0 * ls;
-        int lns = 0;
-        for (int rem = lm; rem > 0;) {
-            const int r4 = rem >= 2;
-            const int lr = r4 ? 2 : 1;
-            const int q = m >> lr, lq = lm - lr;
-            const int nbf = (gl << lm) >> lr;
-            const int Ns = 1 << lns;
-            const int tsh = kTwLog - lr - lns;
-            V v[16];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int g = lane + 64 * i;
-                if (g < nbf) {
-                    const int line = g >> lq, j = g & (q - 1), k = j & (Ns - 1);
-                    const V* L = base0 + line * ls + j;
-                    if (r4) {
-                        V a0 = L[0], a1 = L[q], a2 = L[2 * q], a3 = L[3 * q];
-                        const int st = k << tsh;
-                        a1 = twm<INV>(a1, tw[st]);
-                        a2 = twm<INV>(a2, tw[2 * st]);
-                        a3 = twm<INV>(a3, tw[3 * st]);
-                        const V t0 = cadd(a0, a2), t1 = csub(a0, a2);
-                        const V t2 = cadd(a1, a3), t3 = rot<INV>(csub(a1, a3));
-                        v[4 * i + 0] = cadd(t0, t2);
-                        v[4 * i + 1] = cadd(t1, t3);
-                        v[4 * i + 2] = csub(t0, t2);
-                        v[4 * i + 3] = csub(t1, t3);
-                    } else {
-                        V a0 = L[0], a1 = twm<INV>(L[q], tw[k << tsh]);
-                        v[4 * i + 0] = cadd(a0, a1);
-                        v[4 * i + 1] = csub(a0, a1);
-                    }
-                }
-            }
-            wave_sync();
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int g = lane + 64 * i;
-                if (g < nbf) {
-                    const int line = g >> lq, j = g & (q - 1), k = j & (Ns - 1);
-                    V* L = base0 + line * ls + ((j >> lns) << (lns + lr)) + k;
-                    L[0] = v[4 * i + 0];
-                    L[Ns] = v[4 * i + 1];
-                    if (r4) {
-                        L[2 * Ns] = v[4 * i + 2];
-                        L[3 * Ns] = v[4 * i + 3];
-                    }
-                }
-            }
-            wave_sync();
-            lns += lr;
-            rem -= lr;
-        }
-    }
-}
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Give each XCD a contiguous run of work items so that neighbouring
+// items (adjacent rows, shared halo) are processed by one L2 back to back.
+// w: workgroup index within the problem, n8: item count padded to 8.
+__device__ __forceinline__ int xcd_item(int w, int n8) { return (w & 7) * (n8 >> 3) + (w >> 3); }
 
-// Length-MZ transform held in registers (radix-2, bit-reversed input).
-template <typename T, int MZ, bool INV>
-__device__ __forceinline__ void fft_reg(cplx<T> (&a)[MZ], const cplx<T>* __restrict__ tw)
+// Load exp(-2 pi i e/(2m)), e < 2m, into LDS.
+template <typename V>
+__device__ __forceinline__ void load_twiddles(V* twl, int lm, const V* __restrict__ tw)
 {
-    using V = cplx<T>;
-    if (MZ == 1) return;
-    constexpr int LZ = (MZ == 2) ? 1 : (MZ == 4) ? 2 : (MZ == 8) ? 3 : 4;
-#pragma unroll
-    for (int i = 0; i < MZ; ++i) {
-        int r = 0;
-#pragma unroll
-        for (int b = 0; b < LZ; ++b) r |= ((i >> b) & 1) << (LZ - 1 - b);
-        if (r > i) { V t = a[i]; a[i] = a[r]; a[r] = t; }
-    }
-#pragma unroll
-    for (int len = 2; len <= MZ; len <<= 1) {
-        const int half = len >> 1;
-#pragma unroll
-        for (int i = 0; i < MZ; i += len) {
-#pragma unroll
-            for (int j = 0; j < half; ++j) {
-                const V w = tw[j * (kTwM / len)];
-                const V u = a[i + j];
-                const V v = twm<INV>(a[i + j + half], w);
-                a[i + j] = cadd(u, v);
-                a[i + j + half] = csub(u, v);
-            }
-        }
-    }
+    const int n = 2 << lm;
+    const int sh = kTwLog - 1 - lm;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) twl[e] = tw[e << sh];
 }
 
 template <typename T>
@@ -195,14 +79,15 @@ __device__ __forceinline__ T wave_max(T v)
 }
 
 // ---------------------------------------------------------------------------
-// k_xfwd: rows of a tile (image, z, yt rows) -> x half-spectra.
-// Two real rows of one spin component form one complex signal a + i b; its
-// length-2m spectrum Z gives A(k) = (Z(k) + conj Z(-k))/2 and
-// B(k) = -i (Z(k) - conj Z(-k))/2 for k = 0..m.
-// Output layout X[img][kx][c][z][y].
+// k_xfwd: rows of a tile (image, z, ytf rows) -> x half-spectra, one spin
+// component at a time.  Two real rows of one component form one complex
+// signal a + i b; its length-2m spectrum Z gives A(k) = (Z(k) + conj Z(-k))/2
+// and B(k) = -i (Z(k) - conj Z(-k))/2 for k = 0..m.
+// Output layout X[img][kx][c][z][y]: a tile writes ytf consecutive y values.
+// LDS: twiddles (2m) + ytf lines of m.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_xfwd(const Prob* __restrict__ P, int np,
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3, 8))) void k_xfwd(const Prob* __restrict__ P, int np,
                                               const int* __restrict__ wstart,
                                               const T* __restrict__ s, cplx<T>* __restrict__ X,
                                               const cplx<T>* __restrict__ tw,
@@ -210,65 +95,88 @@ __global__ __launch_bounds__(kNT) void k_xfwd(const Prob* __restrict__ P, int np
 {
     using V = cplx<T>;
     extern __shared__ double2 smem_[];
-    V* lines = reinterpret_cast<V*>(smem_);
     const int pi = find_problem(wstart, np, blockIdx.x);
     if (done && done[pi]) return;
     const Prob& p = P[pi];
-    const int t = blockIdx.x - wstart[pi];
-    const int ty = t % p.nty, rest = t / p.nty;
+    const int t = xcd_item(blockIdx.x - wstart[pi], p.wgf);
+    if (t >= p.K * p.tilesf) return;
+    const int ty = t % p.ntyf, rest = t / p.ntyf;
     const int z = rest % p.nz, img = rest / p.nz;
-    const int yt = p.yt, hp = yt >> 1, nx = p.nx, ny = p.ny, nz = p.nz, m = p.mx, lm = p.lmx;
-    const int y0 = ty * yt, nq = 3 * hp;
+    const int yt = p.ytf, hp = yt >> 1, nx = p.nx, ny = p.ny, nz = p.nz, m = p.mx, lm = p.lmx;
+    V* twl = reinterpret_cast<V*>(smem_);
+    V* lines = twl + 2 * m;
+    load_twiddles(twl, lm, tw);
     const long long N = p.N;
     const T* si = s + p.s_off + (long long)img * 3 * N + (long long)z * ny * nx;
-    const int tws = kTwLog - 1 - lm;
-
-    for (int idx = threadIdx.x; idx < nq * m; idx += kNT) {
-        const int j = idx & (m - 1), q = idx >> lm;
-        const int c = q / hp, rp = q - c * hp;
-        const int ya = y0 + 2 * rp;
-        T a = 0, b = 0;
-        if (j < nx) {
-            const T* row = si + (long long)c * N;
-            if (ya < ny) a = row[(long long)ya * nx + j];
-            if (ya + 1 < ny) b = row[(long long)(ya + 1) * nx + j];
-        }
-        const V v = mk<V>(a, b);
-        lines[(2 * q) * m + j] = v;
-        lines[(2 * q + 1) * m + j] = cmul(v, tw[j << tws]);
-    }
-    __syncthreads();
-    fft_lines<T, false>(lines, 2 * nq, m, lm, tw);
-    __syncthreads();
-
-    const int P2 = 2 * m;
     V* Xi = X + p.x_off + (long long)img * (m + 1) * 3 * nz * ny;
-    for (int idx = threadIdx.x; idx < (m + 1) * nq; idx += kNT) {
-        const int rp = idx % hp, r2 = idx / hp;
-        const int c = r2 % 3, kx = r2 / 3;
-        const int q = c * hp + rp;
-        const int kr = (P2 - kx) & (P2 - 1);
-        const V Z = lines[(2 * q + (kx & 1)) * m + (kx >> 1)];
-        const V Zr = lines[(2 * q + (kr & 1)) * m + (kr >> 1)];
-        const T hlf = T(0.5);
-        const V A = mk<V>((Z.x + Zr.x) * hlf, (Z.y - Zr.y) * hlf);
-        const V B = mk<V>((Z.y + Zr.y) * hlf, (Zr.x - Z.x) * hlf);
-        const int ya = y0 + 2 * rp;
-        V* dst = Xi + (((long long)kx * 3 + c) * nz + z) * ny;
-        if (ya < ny) dst[ya] = A;
-        if (ya + 1 < ny) dst[ya + 1] = B;
+    const int y0 = ty * yt, P2 = 2 * m;
+    __syncthreads();
+#pragma unroll 1
+    for (int c = 0; c < 3; ++c) {
+        const T* sc = si + (long long)c * N;
+        for (int idx = threadIdx.x; idx < hp * m; idx += kNT) {
+            const int j = idx & (m - 1), rp = idx >> lm;
+            const int ya = y0 + 2 * rp;
+            T a = 0, b = 0;
+            if (j < nx) {
+                if (ya < ny) a = sc[(long long)ya * nx + j];
+                if (ya + 1 < ny) b = sc[(long long)(ya + 1) * nx + j];
+            }
+            const V v = mk<V>(a, b);
+            lines[(2 * rp) * m + j] = v;
+            lines[(2 * rp + 1) * m + j] = cmul(v, twl[j]);
+        }
+        __syncthreads();
+        fft_lines<V, false>(lines, yt, m, lm, twl);
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < (m + 1) * hp; idx += kNT) {
+            const int rp = idx % hp, kx = idx / hp;
+            const int kr = (P2 - kx) & (P2 - 1);
+            const V Z = lines[(2 * rp + (kx & 1)) * m + (kx >> 1)];
+            const V Zr = lines[(2 * rp + (kr & 1)) * m + (kr >> 1)];
+            const T hlf = T(0.5);
+            const V A = mk<V>((Z.x + Zr.x) * hlf, (Z.y - Zr.y) * hlf);
+            const V B = mk<V>((Z.y + Zr.y) * hlf, (Zr.x - Z.x) * hlf);
+            const int ya = y0 + 2 * rp;
+            V* dst = Xi + (((long long)kx * 3 + c) * nz + z) * ny;
+            if (ya < ny) dst[ya] = A;
+            if (ya + 1 < ny) dst[ya + 1] = B;
+        }
+        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
-// k_conv: for G consecutive (image, kx) slices [c][z][y]: for each quarter
-// (hz, hy) of the padded (z, y) spectrum: twiddle, FFT along y (LDS), FFT
-// along z (registers), multiply by the real symmetric dipole-kernel
-// spectrum (xx, xy, xz, yy, yz, zz), inverse z, inverse y, un-twiddle and
-// accumulate.  The kernel spectrum already carries 1/(Px Py Pz).
+// k_conv: for G consecutive (image, kx) slices [c][z][y], the convolution in
+// (y, z) with the dipole-kernel spectrum.  The padded y transform (length
+// 2 m_y) is split into its even and odd halves hy (twiddle W^{hy*y}, then a
+// length-m_y FFT in LDS).  The z twiddle of the padded z transform is a
+// per-line constant, so it commutes with the y FFT: the register z-phase
+// applies it and runs both z halves hz itself (length-mz DFTs), multiplies
+// by the real symmetric kernel spectrum (xx, xy, xz, yy, yz, zz), inverts
+// and sums the halves.  Then inverse y FFT, un-twiddle, and the two y halves
+// are summed in registers (in the output slice itself when a workgroup has
+// more than kMaxE*kNT elements).  The kernel spectrum carries 1/(Px Py Pz).
+// LDS: twiddles (2 m_y) + G*3*nz lines of m_y.
 // ---------------------------------------------------------------------------
+// Widest FFT pass of the convolution kernel (log2): radix 4 for FP32, whose
+// accumulator registers leave little room, radix 16 for FP64.
+template <typename T> constexpr int kConvRadixBits = sizeof(T) == 4 ? 2 : 4;
+
+template <typename V, int MZ>
+__device__ __forceinline__ V wz_pad(int zz, const V* __restrict__ tw)
+{
+    // exp(-2 pi i zz / (2 MZ))
+    using S = decltype(V::x);
+    if (MZ <= 8) {
+        const int e = zz * (8 / MZ);
+        return mk<V>((S)kW16re[e], (S)kW16im[e]);
+    }
+    return tw[zz << (kTwLog - 1 - 4)];
+}
+
 template <typename T, int MZ>
-__global__ __launch_bounds__(kNT) void k_conv(const Prob* __restrict__ P, int np,
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && MZ <= 8 ? 3 : 1, 8))) void k_conv(const Prob* __restrict__ P, int np,
                                               const int* __restrict__ wstart,
                                               const cplx<T>* __restrict__ X,
                                               cplx<T>* __restrict__ Xp, const T* __restrict__ nhat,
@@ -277,7 +185,6 @@ __global__ __launch_bounds__(kNT) void k_conv(const Prob* __restrict__ P, int np
 {
     using V = cplx<T>;
     extern __shared__ double2 smem_[];
-    V* lines = reinterpret_cast<V*>(smem_);
     const int pi = find_problem(wstart, np, blockIdx.x);
     if (done && done[pi]) return;
     const Prob& p = P[pi];
@@ -295,45 +202,74 @@ __global__ __launch_bounds__(kNT) void k_conv(const Prob* __restrict__ P, int np
         if (s0 >= nsl) return;
         G = min(p.gconv, nsl - s0);
     }
-    const int nz = p.nz, ny = p.ny, my = p.my, lmy = p.lmy;
+    const int nz = p.nz, ny = p.ny, my = p.my, lmy = p.lmy, nhz = p.nhz;
     const int per = 3 * nz * ny, nel = G * per, nlines = G * 3 * nz;
+    V* twl = reinterpret_cast<V*>(smem_);
+    V* lines = twl + 2 * my;
+    load_twiddles(twl, lmy, tw);
     const V* in = X + p.x_off + (long long)s0 * per;
-    const int twy = kTwLog - 1 - lmy;
-    const int twz = kTwLog - 1 - p.lmz;
-
     V* out = Xp + p.x_off + (long long)s0 * per;
-    int first = 1;
-    for (int hz = 0; hz < p.nhz; ++hz) {
-        for (int hy = 0; hy < 2; ++hy) {
-            for (int e = threadIdx.x; e < nlines * my; e += kNT) {
-                const int y = e & (my - 1), r = e >> lmy;
-                V v = mk<V>(0, 0);
-                if (y < ny) {
-                    v = in[r * ny + y];
-                    if (hy) v = cmul(v, tw[y << twy]);
-                    if (hz) v = cmul(v, tw[(r % nz) << twz]);
-                }
-                lines[e] = v;
-            }
-            __syncthreads();
-            fft_lines<T, false>(lines, nlines, my, lmy, tw);
-            __syncthreads();
+    const bool racc = nel <= kMaxE * kNT;
+    const int dy = kNT % ny, dr = kNT / ny;
+    const int yb = threadIdx.x % ny, rb = threadIdx.x / ny;
 
-            for (int col = threadIdx.x; col < G * my; col += kNT) {
-                const int g = col >> lmy, qy = col & (my - 1);
-                const int kx = (s0 + g) % nsl_img;
+    V acc[kMaxE];
+#pragma unroll
+    for (int i = 0; i < kMaxE; ++i) acc[i] = mk<V>(0, 0);
+    __syncthreads();
+
+#pragma unroll 1
+    for (int hy = 0; hy < 2; ++hy) {
+        {
+            int y = yb, r = rb;
+            asm volatile("" : "+v"(y), "+v"(r));
+#pragma unroll 4
+            for (int e = threadIdx.x; e < nel; e += kNT) {
+                V v = in[e];
+                if (hy) v = cmul(v, twl[y]);
+                lines[r * my + y] = v;
+                y += dy;
+                r += dr;
+                if (y >= ny) { y -= ny; r += 1; }
+            }
+        }
+        if (my > ny) {
+            const int tail = my - ny;
+            for (int e = threadIdx.x; e < nlines * tail; e += kNT) {
+                const int r = e / tail, y = ny + e % tail;
+                lines[r * my + y] = mk<V>(0, 0);
+            }
+        }
+        __syncthreads();
+        fft_lines<V, false, kConvRadixBits<T>>(lines, nlines, my, lmy, twl);
+        __syncthreads();
+
+        int col0 = threadIdx.x;
+        asm volatile("" : "+v"(col0));
+        for (int col = col0; col < G * my; col += kNT) {
+            const int g = col >> lmy, qy = col & (my - 1);
+            const int kx = (s0 + g) % nsl_img;
+            V* cl = lines + (g * 3 * nz) * my + qy;
+            V b[3][MZ];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int zz = 0; zz < MZ; ++zz) b[c][zz] = mk<V>(0, 0);
+#pragma unroll 1
+            for (int hz = 0; hz < nhz; ++hz) {
                 V a[3][MZ];
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
 #pragma unroll
-                    for (int zz = 0; zz < MZ; ++zz)
-                        a[c][zz] = (zz < nz) ? lines[((g * 3 + c) * nz + zz) * my + qy] : mk<V>(0, 0);
-                if (MZ > 1) {
+                    for (int zz = 0; zz < MZ; ++zz) {
+                        V v = (zz < nz) ? cl[(c * nz + zz) * my] : mk<V>(0, 0);
+                        if (hz) v = cmul(v, wz_pad<V, MZ>(zz, tw));
+                        a[c][zz] = v;
+                    }
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) fft_reg<T, MZ, false>(a[c], tw);
-                }
+                for (int c = 0; c < 3; ++c) dft_reg<V, MZ, false>(a[c]);
                 const T* nh = nhat + p.nh_off +
-                              ((((long long)kx * p.nhz + hz) * 2 + hy) * MZ) * 6 * my + qy;
+                              ((((long long)kx * nhz + hz) * 2 + hy) * MZ) * 6 * my + qy;
 #pragma unroll
                 for (int r = 0; r < MZ; ++r) {
                     const T* q6 = nh + (long long)r * 6 * my;
@@ -344,42 +280,72 @@ __global__ __launch_bounds__(kNT) void k_conv(const Prob* __restrict__ P, int np
                     a[1][r] = mk<V>(nxy * sx.x + nyy * sy.x + nyz * sz.x, nxy * sx.y + nyy * sy.y + nyz * sz.y);
                     a[2][r] = mk<V>(nxz * sx.x + nyz * sy.x + nzz * sz.x, nxz * sx.y + nyz * sy.y + nzz * sz.y);
                 }
-                if (MZ > 1) {
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) fft_reg<T, MZ, true>(a[c], tw);
-                }
+                for (int c = 0; c < 3; ++c) dft_reg<V, MZ, true>(a[c]);
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
 #pragma unroll
-                    for (int zz = 0; zz < MZ; ++zz)
-                        if (zz < nz) lines[((g * 3 + c) * nz + zz) * my + qy] = a[c][zz];
+                    for (int zz = 0; zz < MZ; ++zz) {
+                        V v = a[c][zz];
+                        if (hz) v = cmulc(v, wz_pad<V, MZ>(zz, tw));
+                        b[c][zz] = cadd(b[c][zz], v);
+                    }
             }
-            __syncthreads();
-            fft_lines<T, true>(lines, nlines, my, lmy, tw);
-            __syncthreads();
-            // accumulate this quarter into the workgroup's own output slice
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int zz = 0; zz < MZ; ++zz)
+                    if (zz < nz) cl[(c * nz + zz) * my] = b[c][zz];
+        }
+        __syncthreads();
+        fft_lines<V, true, kConvRadixBits<T>>(lines, nlines, my, lmy, twl);
+        __syncthreads();
+        if (racc) {
+            int y = yb, r = rb;
+            // opaque copy: keeps the compiler from hoisting all kMaxE
+            // addresses and twiddles out of the y-half loop
+            asm volatile("" : "+v"(y), "+v"(r));
+#pragma unroll
+            for (int i = 0; i < kMaxE; ++i) {
+                const int e = threadIdx.x + i * kNT;
+                if (e < nel) {
+                    V v = lines[r * my + y];
+                    if (hy) v = cmulc(v, twl[y]);
+                    acc[i] = cadd(acc[i], v);
+                }
+                y += dy;
+                r += dr;
+                if (y >= ny) { y -= ny; r += 1; }
+            }
+        } else {
             for (int e = threadIdx.x; e < nel; e += kNT) {
                 const int y = e % ny, r = e / ny;
                 V v = lines[r * my + y];
-                if (hy) v = cmulc(v, tw[y << twy]);
-                if (hz) v = cmulc(v, tw[(r % nz) << twz]);
-                out[e] = first ? v : cadd(out[e], v);
+                if (hy) v = cmulc(v, twl[y]);
+                out[e] = hy ? cadd(out[e], v) : v;
             }
-            first = 0;
-            __syncthreads();
+        }
+        __syncthreads();
+    }
+    if (racc) {
+#pragma unroll
+        for (int i = 0; i < kMaxE; ++i) {
+            const int e = threadIdx.x + i * kNT;
+            if (e < nel) out[e] = acc[i];
         }
     }
 }
 
 // ---------------------------------------------------------------------------
 // k_xinv: x half-spectra of the convolved field -> unit-strength dipolar
-// field of a tile, then the per-site epilogue.  Two half-spectra A, B of
-// real rows form Z = A + i B on k = 0..m and conj(A) + i conj(B) on
-// k = m+1..2m-1; the inverse transform gives row a in the real part and
-// row b in the imaginary part.
+// field of a tile (one component at a time), then the per-site epilogue.
+// Two half-spectra A, B of real rows form Z = A + i B on k = 0..m and
+// conj(A) + i conj(B) on k = m+1..2m-1; the inverse transform gives row a
+// in the real part and row b in the imaginary part.
+// LDS: twiddles (2m) + yt lines of m + the tile's dipolar field (3 yt nx).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_xinv(const Prob* __restrict__ P, int np,
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_xinv(const Prob* __restrict__ P, int np,
                                               const int* __restrict__ wstart,
                                               const cplx<T>* __restrict__ Xp,
                                               const T* __restrict__ s, T* __restrict__ ss,
@@ -389,49 +355,49 @@ __global__ __launch_bounds__(kNT) void k_xinv(const Prob* __restrict__ P, int np
 {
     using V = cplx<T>;
     extern __shared__ double2 smem_[];
-    V* lines = reinterpret_cast<V*>(smem_);
     __shared__ double red[kNT / 64][kNTerm];
     const int pi = find_problem(wstart, np, blockIdx.x);
     if (done && done[pi]) return;
     const Prob& p = P[pi];
-    const int t = blockIdx.x - wstart[pi];
+    const int t = xcd_item(blockIdx.x - wstart[pi], p.wgi);
+    if (t >= p.K * p.tiles) return;
     const int ty = t % p.nty, rest = t / p.nty;
     const int z = rest % p.nz, img = rest / p.nz;
     const int yt = p.yt, hp = yt >> 1, nx = p.nx, ny = p.ny, nz = p.nz, m = p.mx, lm = p.lmx;
-    const int y0 = ty * yt, nq = 3 * hp;
+    const int y0 = ty * yt;
     const long long N = p.N;
-    T* hd = reinterpret_cast<T*>(lines + 2 * nq * m);
-
+    V* twl = reinterpret_cast<V*>(smem_);
+    V* lines = twl + 2 * m;
+    T* hd = reinterpret_cast<T*>(lines + yt * m);
+    load_twiddles(twl, lm, tw);
     const V* Xi = Xp + p.x_off + (long long)img * (m + 1) * 3 * nz * ny;
-    for (int idx = threadIdx.x; idx < (m + 1) * nq; idx += kNT) {
-        const int rp = idx % hp, r2 = idx / hp;
-        const int c = r2 % 3, kx = r2 / 3;
-        const int q = c * hp + rp;
-        const int ya = y0 + 2 * rp;
-        const V* src = Xi + (((long long)kx * 3 + c) * nz + z) * ny;
-        const V A = (ya < ny) ? src[ya] : mk<V>(0, 0);
-        const V B = (ya + 1 < ny) ? src[ya + 1] : mk<V>(0, 0);
-        lines[(2 * q + (kx & 1)) * m + (kx >> 1)] = mk<V>(A.x - B.y, A.y + B.x);
-        if (kx > 0 && kx < m) {
-            const int km = 2 * m - kx;
-            lines[(2 * q + (km & 1)) * m + (km >> 1)] = mk<V>(A.x + B.y, B.x - A.y);
+    __syncthreads();
+#pragma unroll 1
+    for (int c = 0; c < 3; ++c) {
+        for (int idx = threadIdx.x; idx < (m + 1) * hp; idx += kNT) {
+            const int rp = idx % hp, kx = idx / hp;
+            const int ya = y0 + 2 * rp;
+            const V* src = Xi + (((long long)kx * 3 + c) * nz + z) * ny;
+            const V A = (ya < ny) ? src[ya] : mk<V>(0, 0);
+            const V B = (ya + 1 < ny) ? src[ya + 1] : mk<V>(0, 0);
+            lines[(2 * rp + (kx & 1)) * m + (kx >> 1)] = mk<V>(A.x - B.y, A.y + B.x);
+            if (kx > 0 && kx < m) {
+                const int km = 2 * m - kx;
+                lines[(2 * rp + (km & 1)) * m + (km >> 1)] = mk<V>(A.x + B.y, B.x - A.y);
+            }
         }
+        __syncthreads();
+        fft_lines<V, true>(lines, yt, m, lm, twl);
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < hp * nx; idx += kNT) {
+            const int x = idx % nx, rp = idx / nx;
+            const V e = lines[(2 * rp) * m + x];
+            const V o = cmulc(lines[(2 * rp + 1) * m + x], twl[x]);
+            hd[(c * yt + 2 * rp) * nx + x] = e.x + o.x;
+            hd[(c * yt + 2 * rp + 1) * nx + x] = e.y + o.y;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    fft_lines<T, true>(lines, 2 * nq, m, lm, tw);
-    __syncthreads();
-    const int tws = kTwLog - 1 - lm;
-    // stage the field into registers first: hd overlaps nothing, but keep
-    // the reads of `lines` and the writes of `hd` in separate loops
-    for (int idx = threadIdx.x; idx < nq * nx; idx += kNT) {
-        const int x = idx % nx, q = idx / nx;
-        const int c = q / hp, rp = q - c * hp;
-        const V e = lines[(2 * q) * m + x];
-        const V o = cmulc(lines[(2 * q + 1) * m + x], tw[x << tws]);
-        hd[(c * yt + 2 * rp) * nx + x] = e.x + o.x;
-        hd[(c * yt + 2 * rp + 1) * nx + x] = e.y + o.y;
-    }
-    __syncthreads();
 
     const double J = p.J, dm = p.d, ku = p.ku, D = p.D;
     const T* si = s + p.s_off + (long long)img * 3 * N;
@@ -445,7 +411,7 @@ __global__ __launch_bounds__(kNT) void k_xinv(const Prob* __restrict__ P, int np
         double sv[3], nb[3] = {0, 0, 0};
         double xp[3] = {0, 0, 0}, xm[3] = {0, 0, 0}, yp[3] = {0, 0, 0}, ym[3] = {0, 0, 0};
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < 3; ++c) {
             const T* sc = si + (long long)c * N;
             sv[c] = (double)sc[i];
             if (x + 1 < nx) xp[c] = (double)sc[i + 1];
@@ -547,90 +513,106 @@ __global__ __launch_bounds__(kNT) void k_arc(const Prob* __restrict__ P, int np,
 }
 
 // ---------------------------------------------------------------------------
-// k_reduce: one workgroup per problem.  Fixed-order sums of the energy
-// partials (E and the four unit-parameter terms) and, with_arc, of the arc
-// partials; then S_k, alpha*_k = S_k/S_{K-1} and for every interior image
-// the interval j = max{j <= K-2 : alpha*_j <= k/(K-1)} and its weight.
+// k_reduce: one workgroup per image.  Fixed-order sums of the image's energy
+// partials (E and the four unit-parameter terms) and, with_arc, of its arc
+// partials (segment length |phi*_k - phi*_{k-1}|).  With with_arc the last
+// workgroup of a problem to finish (atomic counter) forms S_k,
+// alpha*_k = S_k/S_{K-1} and, for every interior image, the interval
+// j = max{j <= K-2 : alpha*_j <= k/(K-1)} and its weight.  Every sum has a
+// fixed order, so results do not depend on which workgroup finishes last.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kNT) void k_reduce(const Prob* __restrict__ P, int np,
+                                                const int* __restrict__ istart,
                                                 const double* __restrict__ epart,
                                                 const double* __restrict__ apart,
                                                 double* E, double* Tm, double* E_out,
-                                                double* T_out, double* alpha, int* jidx,
-                                                double* wgt, int* skip, int* done, int* iters,
-                                                int* flags, int with_arc)
+                                                double* T_out, double* seg, double* alpha,
+                                                int* jidx, double* wgt, int* skip, int* done,
+                                                int* iters, int* count, int* flags, int with_arc)
 {
-    __shared__ double seg[1024];
-    const int pi = blockIdx.x;
-    if (pi >= np) return;
+    __shared__ double red[kNT / 64][kNTerm + 1];
+    __shared__ double red_alpha[1024];
+    __shared__ int last;
+    const int gimg = blockIdx.x;
+    const int pi = find_problem(istart, np, gimg);
     if (with_arc && done && done[pi]) return;
     const Prob& p = P[pi];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = kNT / 64;
-    for (int k = wave; k < p.K; k += nw) {
-        const double* ep = epart + p.ep_off + (long long)k * p.tiles * kNTerm;
-        double v[kNTerm] = {0, 0, 0, 0, 0};
-        for (int t = lane; t < p.tiles; t += 64)
-            for (int j = 0; j < kNTerm; ++j) v[j] += ep[(long long)t * kNTerm + j];
-        for (int j = 0; j < kNTerm; ++j) v[j] = wave_sum(v[j]);
-        if (lane == 0) {
-            const int g = p.img0 + k;
-            if (E) E[g] = v[0];
-            if (E_out) E_out[g] = v[0];
-            for (int j = 0; j < 4; ++j) {
-                if (Tm) Tm[(long long)g * 4 + j] = v[j + 1];
-                if (T_out) T_out[(long long)g * 4 + j] = v[j + 1];
-            }
-            if (!isfinite(v[0])) atomicOr(flags, 1);
+    const int k = gimg - p.img0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double v[kNTerm + 1] = {0, 0, 0, 0, 0, 0};
+    const double* ep = epart + p.ep_off + (long long)k * p.tiles * kNTerm;
+    for (int t = threadIdx.x; t < p.tiles; t += kNT)
+        for (int j = 0; j < kNTerm; ++j) v[j] += ep[(long long)t * kNTerm + j];
+    if (with_arc && k > 0) {
+        const double* ap = apart + p.ap_off + (long long)k * p.arc_chunks * 4;
+        for (int t = threadIdx.x; t < p.arc_chunks * 4; t += kNT) v[kNTerm] += ap[t];
+    }
+    for (int j = 0; j <= kNTerm; ++j) {
+        const double s = wave_sum(v[j]);
+        if (lane == 0) red[wave][j] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r[kNTerm + 1];
+        for (int j = 0; j <= kNTerm; ++j) {
+            r[j] = 0;
+            for (int wv = 0; wv < kNT / 64; ++wv) r[j] += red[wv][j];
         }
+        if (E) E[gimg] = r[0];
+        if (E_out) E_out[gimg] = r[0];
+        for (int j = 0; j < 4; ++j) {
+            if (Tm) Tm[(long long)gimg * 4 + j] = r[j + 1];
+            if (T_out) T_out[(long long)gimg * 4 + j] = r[j + 1];
+        }
+        if (!isfinite(r[0])) atomicOr(flags, 1);
         if (with_arc) {
-            double a = 0;
-            if (k > 0) {
-                const double* ap = apart + p.ap_off + (long long)k * p.arc_chunks * 4;
-                for (int t = lane; t < p.arc_chunks * 4; t += 64) a += ap[t];
-                a = wave_sum(a);
-            }
-            if (lane == 0) seg[k] = sqrt(a);
+            seg[gimg] = sqrt(r[kNTerm]);
+            __threadfence();
+            last = (atomicAdd(&count[pi], 1) == p.K - 1);
         }
     }
     if (!with_arc) return;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const int K = p.K, g0 = p.img0;
-        double S = 0;
-        alpha[g0] = 0;
-        for (int k = 1; k < K; ++k) {
-            S += seg[k];
-            alpha[g0 + k] = S;
-        }
-        const double L = S;
-        if (!(L > 0.0)) {
-            skip[pi] = 1;
-            for (int k = 0; k < K; ++k) {
-                alpha[g0 + k] = 0;
-                jidx[g0 + k] = k;
-                wgt[g0 + k] = 0;
-            }
-        } else {
-            skip[pi] = 0;
-            alpha[g0] = 0;
-            for (int k = 1; k < K; ++k) alpha[g0 + k] = alpha[g0 + k] / L;
-            for (int k = 0; k < K; ++k) {
-                if (k == 0 || k == K - 1) {
-                    jidx[g0 + k] = k;
-                    wgt[g0 + k] = 0;
-                    continue;
-                }
-                const double tk = (double)k / (double)(K - 1);
-                int j = 0;
-                for (int jj = 0; jj <= K - 2; ++jj)
-                    if (alpha[g0 + jj] <= tk) j = jj;
-                const double width = alpha[g0 + j + 1] - alpha[g0 + j];
-                jidx[g0 + k] = j;
-                wgt[g0 + k] = (width > 0.0) ? (tk - alpha[g0 + j]) / width : 0.0;
-            }
-        }
-        iters[pi] += 1;
+    if (!last || threadIdx.x != 0) return;
+    __threadfence();
+    count[pi] = 0;
+    const volatile double* sg = seg;
+    const int K = p.K, g0 = p.img0;
+    double* al = red_alpha;
+    double S = 0;
+    al[0] = 0;
+    for (int kk = 1; kk < K; ++kk) {
+        S += sg[g0 + kk];
+        al[kk] = S;
     }
+    const double L = S;
+    if (!(L > 0.0)) {
+        skip[pi] = 1;
+        for (int kk = 0; kk < K; ++kk) {
+            alpha[g0 + kk] = 0;
+            jidx[g0 + kk] = kk;
+            wgt[g0 + kk] = 0;
+        }
+    } else {
+        skip[pi] = 0;
+        for (int kk = 1; kk < K; ++kk) al[kk] = al[kk] / L;
+        for (int kk = 0; kk < K; ++kk) {
+            alpha[g0 + kk] = al[kk];
+            if (kk == 0 || kk == K - 1) {
+                jidx[g0 + kk] = kk;
+                wgt[g0 + kk] = 0;
+                continue;
+            }
+            const double tk = (double)kk / (double)(K - 1);
+            int j = 0;
+            for (int jj = 0; jj <= K - 2; ++jj)
+                if (al[jj] <= tk) j = jj;
+            const double width = al[j + 1] - al[j];
+            jidx[g0 + kk] = j;
+            wgt[g0 + kk] = (width > 0.0) ? (tk - al[j]) / width : 0.0;
+        }
+    }
+    iters[pi] += 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -707,7 +689,7 @@ __global__ __launch_bounds__(kNT) void k_tan1(const Prob* __restrict__ P, int np
         const T* hk = h + p.s_off + (long long)k * M;
         double v[3], f[3], d[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < 3; ++c) {
             v[c] = (double)sk[c * N + i];
             f[c] = (double)hk[c * N + i];
             d[c] = (double)sp[c * N + i] - (double)sm[c * N + i];
@@ -716,7 +698,7 @@ __global__ __launch_bounds__(kNT) void k_tan1(const Prob* __restrict__ P, int np
         const double sd = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
         T* to = tt + p.s_off + (long long)k * M;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < 3; ++c) {
             const double tc = d[c] - sd * v[c];
             const double hc = f[c] - sh * v[c];
             to[c * N + i] = (T)tc;
@@ -790,7 +772,7 @@ __global__ __launch_bounds__(kNT) void k_tan2(const Prob* __restrict__ P, int np
         const T* tk = tt + p.s_off + (long long)k * M;
         double v[3], f[3], tc[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < 3; ++c) {
             v[c] = (double)sk[c * N + i];
             f[c] = (double)hk[c * N + i];
             tc[c] = (double)tk[c * N + i];
@@ -798,7 +780,7 @@ __global__ __launch_bounds__(kNT) void k_tan2(const Prob* __restrict__ P, int np
         const double sh = v[0] * f[0] + v[1] * f[1] + v[2] * f[2];
         double n2 = 0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < 3; ++c) {
             const double fc = f[c] - sh * v[c] - cf * tc[c];
             n2 += fc * fc;
         }
@@ -1038,13 +1020,13 @@ hipError_t launch_arc(const Prob* P, int np, const WorkMap& wm, const T* ss, dou
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(const Prob* P, int np, const double* epart, const double* apart,
-                         double* E, double* Tm, double* E_out, double* T_out, double* alpha,
-                         int* jidx, double* wgt, int* skip, int* done, int* iters, int* flags,
-                         int with_arc, hipStream_t st)
+hipError_t launch_reduce(const Prob* P, int np, int nimg, const int* istart, const double* epart,
+                         const double* apart, double* E, double* Tm, double* E_out, double* T_out,
+                         double* seg, double* alpha, int* jidx, double* wgt, int* skip, int* done,
+                         int* iters, int* count, int* flags, int with_arc, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(np), dim3(kNT), 0, st, P, np, epart, apart, E, Tm, E_out,
-                       T_out, alpha, jidx, wgt, skip, done, iters, flags, with_arc);
+    hipLaunchKernelGGL(k_reduce, dim3(nimg), dim3(kNT), 0, st, P, np, istart, epart, apart, E, Tm,
+                       E_out, T_out, seg, alpha, jidx, wgt, skip, done, iters, count, flags, with_arc);
     return hipGetLastError();
 }
 

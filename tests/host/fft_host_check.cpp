@@ -1,0 +1,114 @@
+// Host check of the LDS FFT passes (paper_1804_07135_amd/csrc/ssm_fft.hpp):
+// runs the same pass code with the 64 lanes of a wavefront emulated in
+// lockstep (every lane reads, then every lane writes) and compares with a
+// naive DFT in long double.  Prints the worst relative error per length.
+#include "ssm_fft.hpp"
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+#include <vector>
+
+using namespace ssm;
+
+template <typename V, int R, bool INV>
+static void emulate_pass(V* base, int ls, int lm, int lns, int gl, const V* twl)
+{
+    using P = Pass<V, R, INV>;
+    std::vector<V> regs(64 * P::B * R);
+    for (int lane = 0; lane < 64; ++lane)
+        P::read(base, ls, lm, lns, gl, twl, lane, *reinterpret_cast<V(*)[P::B][R]>(&regs[lane * P::B * R]));
+    for (int lane = 0; lane < 64; ++lane)
+        P::write(base, ls, lm, lns, gl, lane, *reinterpret_cast<V(*)[P::B][R]>(&regs[lane * P::B * R]));
+}
+
+template <typename V, bool INV>
+static void host_fft_lines(V* buf, int nl, int ls, int lm, const V* twl, int maxb)
+{
+    if (lm == 0) return;
+    const int lpg = fft_group_lines(lm);
+    for (int g0 = 0; g0 < nl; g0 += lpg) {
+        const int gl = nl - g0 < lpg ? nl - g0 : lpg;
+        int lns = 0;
+        for (int rem = lm; rem > 0;) {
+            const int bits = fft_next_bits(rem, maxb);
+            rem -= bits;
+            V* base = buf + g0 * ls;
+            if (bits == 4) emulate_pass<V, 16, INV>(base, ls, lm, lns, gl, twl);
+            else if (bits == 3) emulate_pass<V, 8, INV>(base, ls, lm, lns, gl, twl);
+            else if (bits == 2) emulate_pass<V, 4, INV>(base, ls, lm, lns, gl, twl);
+            else emulate_pass<V, 2, INV>(base, ls, lm, lns, gl, twl);
+            lns += bits;
+        }
+    }
+}
+
+template <typename V, bool INV>
+static double check(int lm, int nl, int pad, unsigned seed, int maxb)
+{
+    using S = decltype(V::x);
+    const int m = 1 << lm, ls = m + pad;
+    std::vector<V> twl(2 * m);
+    for (int e = 0; e < 2 * m; ++e) {
+        const long double th = 2.0L * 3.14159265358979323846264338327950288L * e / (2.0L * m);
+        twl[e] = mk<V>((S)cosl(th), (S)-sinl(th));
+    }
+    std::mt19937 rng(seed);
+    std::normal_distribution<double> nd;
+    std::vector<V> buf(nl * ls), ref(nl * ls);
+    for (auto& v : buf) v = mk<V>((S)nd(rng), (S)nd(rng));
+    std::vector<long double> xr(m), xi(m), cs(m), sn(m);
+    for (int e = 0; e < m; ++e) {
+        const long double th = (INV ? 2.0L : -2.0L) * 3.14159265358979323846264338327950288L * e / m;
+        cs[e] = cosl(th);
+        sn[e] = sinl(th);
+    }
+    double worst = 0;
+    for (int l = 0; l < nl; ++l) {
+        for (int j = 0; j < m; ++j) { xr[j] = buf[l * ls + j].x; xi[j] = buf[l * ls + j].y; }
+        for (int k = 0; k < m; ++k) {
+            long double sr = 0, si = 0;
+            for (int j = 0; j < m; ++j) {
+                const int e = (int)((long long)j * k % m);
+                sr += xr[j] * cs[e] - xi[j] * sn[e];
+                si += xr[j] * sn[e] + xi[j] * cs[e];
+            }
+            ref[l * ls + k] = mk<V>((S)sr, (S)si);
+        }
+    }
+    host_fft_lines<V, INV>(buf.data(), nl, ls, lm, twl.data(), maxb);
+    double nrm = 0;
+    for (int l = 0; l < nl; ++l)
+        for (int k = 0; k < m; ++k) {
+            const V a = buf[l * ls + k], b = ref[l * ls + k];
+            worst = fmax(worst, fabs((double)a.x - (double)b.x));
+            worst = fmax(worst, fabs((double)a.y - (double)b.y));
+            nrm = fmax(nrm, fabs((double)b.x) + fabs((double)b.y));
+        }
+    return worst / (nrm > 0 ? nrm : 1);
+}
+
+int main()
+{
+    int bad = 0;
+    for (int maxb = 2; maxb <= 4; ++maxb)
+    for (int lm = 0; lm <= 10; ++lm) {
+        // one line, an odd count, and a full group plus a partial one
+        const int nls[3] = {1, 3, (1 << (10 - lm)) + (lm < 10 ? 3 : 1)};
+        for (int t = 0; t < 3; ++t) {
+            const int nl = nls[t];
+            if ((long long)nl << (2 * lm) > (1LL << 22)) continue;  // naive DFT cost cap
+            const int pad = t == 1 ? 1 : 0;
+            const double e64f = check<double2, false>(lm, nl, pad, 11 + lm, maxb);
+            const double e64i = check<double2, true>(lm, nl, pad, 13 + lm, maxb);
+            const double e32f = check<float2, false>(lm, nl, pad, 17 + lm, maxb);
+            const double e32i = check<float2, true>(lm, nl, pad, 19 + lm, maxb);
+            std::printf("maxb=%d m=%5d lines=%5d fp64 %.2e %.2e fp32 %.2e %.2e\n", maxb, 1 << lm, nl,
+                        e64f, e64i, e32f, e32i);
+            if (e64f > 1e-14 || e64i > 1e-14 || e32f > 2e-6 || e32i > 2e-6) bad = 1;
+        }
+    }
+    std::printf(bad ? "FAIL\n" : "OK\n");
+    return bad;
+}
