@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp32-only", action="store_true", help="skip the FP64 plain run (profiling)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method is built and "
@@ -111,6 +113,17 @@ def main():
     import numpy as np
     import torch
     from paper_1804_07135_amd import inputs, ssm
+
+    if args.copy_probe_mib:
+        # known-size copy: reads and writes exactly copy_probe_mib MiB per launch
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 4, "launches": 5}), flush=True)
+        return
 
     w = dict(inputs.WORKLOADS[args.workload])
     prob = dict(nx=w["nx"], ny=w["ny"], nz=w["nz"], K=w["K"], J=w["J"], d=w["d"], ku=w["ku"], D=w["D"])

@@ -1,6 +1,7 @@
 // Host runtime and C ABI of the gfx950 simplified-string-method library.
 // See include/ssm.h for the contract of every entry point.
 #include "ssm.h"
+#include "ssm_fft.hpp"
 #include "ssm_internal.hpp"
 
 #include <algorithm>
@@ -71,19 +72,21 @@ struct Plan {
         o_alpha, o_w, o_tc, o_fn, o_fm, o_j, o_done, o_iters, o_skip, o_flags, o_seg, o_cnt, total;
 };
 
+// LDS bytes of the FFT kernels: twiddle table (2m complex) + line buffer in
+// the padded layout of ssm_fft.hpp (+ the tile's real field for k_xinv).
 size_t lds_xfwd(const Prob& p, int yt, size_t tsize)
 {
-    return (size_t)(2 * p.mx + yt * p.mx) * 2 * tsize;
+    return (size_t)(2 * p.mx + lds_padded_size(yt * p.mx)) * 2 * tsize;
 }
 
 size_t lds_xinv(const Prob& p, int yt, size_t tsize)
 {
-    return (size_t)(2 * p.mx + yt * p.mx) * 2 * tsize + (size_t)3 * yt * p.nx * tsize;
+    return (size_t)(2 * p.mx + lds_padded_size(yt * p.mx)) * 2 * tsize + (size_t)3 * yt * p.nx * tsize;
 }
 
 size_t lds_convg(const Prob& p, int G, size_t tsize)
 {
-    return (size_t)(2 * p.my + G * 3 * p.nz * p.my) * 2 * tsize;
+    return (size_t)(2 * p.my + lds_padded_size(G * 3 * p.nz * p.my)) * 2 * tsize;
 }
 
 ssm_status check_problems(const ssm_problem* pr, int np, int prec, std::string& err)

@@ -82,16 +82,29 @@ __host__ __device__ __forceinline__ void dft_reg(V (&a)[R])
     }
 }
 
+// LDS layout of the line buffers.  With SSM_LDS_PAD=1 one pad element
+// follows every 16, which spreads the strided Stockham writes (stride R) over
+// all banks at the cost of per-element address arithmetic (more registers);
+// measured on gfx950 the registers cost more than the conflicts, so the
+// default layout is dense.  lds_pad(i) is the physical index of element i.
+#ifndef SSM_LDS_PAD
+#define SSM_LDS_PAD 0
+#endif
+__host__ __device__ __forceinline__ int lds_pad(int i) { return SSM_LDS_PAD ? i + (i >> 4) : i; }
+// physical size of a buffer of n elements
+__host__ __device__ __forceinline__ int lds_padded_size(int n) { return SSM_LDS_PAD ? n + (n >> 4) + 1 : n; }
+
 // One radix-R Stockham pass over a group of gl lines of length m = 2^lm
-// (line stride ls) starting at buf.  lns = log2 of the sub-transform length
-// already done.  twl[e] = exp(-2 pi i e / (2m)), e < 2m (conjugated for the
-// inverse), so the pass twiddle W_{Ns R}^{r k} is twl[(r k) << (lm+1-lns-lr)].
+// (line stride ls) starting at element off0 of buf (padded layout).
+// lns = log2 of the sub-transform length already done.  twl[e] =
+// exp(-2 pi i e / (2m)), e < 2m (conjugated for the inverse), so the pass
+// twiddle W_{Ns R}^{r k} is twl[(r k) << (lm+1-lns-lr)].
 template <typename V, int R, bool INV>
 struct Pass {
     static constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
     static constexpr int B = 16 / R;  // butterflies per lane
 
-    __host__ __device__ static void read(const V* buf, int ls, int lm, int lns, int gl,
+    __host__ __device__ static void read(const V* buf, int off0, int ls, int lm, int lns, int gl,
                                          const V* twl, int lane, V (&v)[B][R])
     {
         const int q = 1 << (lm - LR), lq = lm - LR;
@@ -103,9 +116,9 @@ struct Pass {
             const int g = lane + 64 * b;
             if (g < nbf) {
                 const int line = g >> lq, j = g & (q - 1), k = j & (Ns - 1);
-                const V* L = buf + line * ls + j;
+                const int i0 = off0 + line * ls + j;
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[b][r] = L[r * q];
+                for (int r = 0; r < R; ++r) v[b][r] = buf[lds_pad(i0 + r * q)];
                 if (lns > 0) {
 #pragma unroll
                     for (int r = 1; r < R; ++r) v[b][r] = twm<INV>(v[b][r], twl[(r * k) << tsh]);
@@ -115,8 +128,8 @@ struct Pass {
         }
     }
 
-    __host__ __device__ static void write(V* buf, int ls, int lm, int lns, int gl, int lane,
-                                          const V (&v)[B][R])
+    __host__ __device__ static void write(V* buf, int off0, int ls, int lm, int lns, int gl,
+                                          int lane, const V (&v)[B][R])
     {
         const int q = 1 << (lm - LR), lq = lm - LR;
         const int nbf = gl << lq;
@@ -126,9 +139,9 @@ struct Pass {
             const int g = lane + 64 * b;
             if (g < nbf) {
                 const int line = g >> lq, j = g & (q - 1), k = j & (Ns - 1);
-                V* L = buf + line * ls + ((j >> lns) << (lns + LR)) + k;
+                const int i0 = off0 + line * ls + ((j >> lns) << (lns + LR)) + k;
 #pragma unroll
-                for (int r = 0; r < R; ++r) L[r * Ns] = v[b][r];
+                for (int r = 0; r < R; ++r) buf[lds_pad(i0 + r * Ns)] = v[b][r];
             }
         }
     }
@@ -157,16 +170,18 @@ __device__ __forceinline__ void wave_sync()
 }
 
 template <typename V, int R, bool INV>
-__device__ __forceinline__ void run_pass(V* base, int ls, int lm, int lns, int gl, const V* twl, int lane)
+__device__ __forceinline__ void run_pass(V* buf, int off0, int ls, int lm, int lns, int gl,
+                                         const V* twl, int lane)
 {
     V v[Pass<V, R, INV>::B][R];
-    Pass<V, R, INV>::read(base, ls, lm, lns, gl, twl, lane, v);
+    Pass<V, R, INV>::read(buf, off0, ls, lm, lns, gl, twl, lane, v);
     wave_sync();
-    Pass<V, R, INV>::write(base, ls, lm, lns, gl, lane, v);
+    Pass<V, R, INV>::write(buf, off0, ls, lm, lns, gl, lane, v);
     wave_sync();
 }
 
-// Transform nl lines of length 2^lm at buf (stride ls) in LDS; forward
+// Transform nl lines of length 2^lm at buf (stride ls, padded layout) in
+// LDS; forward
 // (exp(-2 pi i jk/m)) or unnormalised inverse.  twl: the LDS table of
 // exp(-2 pi i e/(2m)), e < 2m.  MAXB (2 or 3) caps the pass radix at 2^MAXB;
 // fewer pass kinds keep the register footprint of the caller small.  Call
@@ -183,14 +198,14 @@ __device__ __forceinline__ void fft_lines(V* buf, int nl, int ls, int lm, const 
     const int lpg = fft_group_lines(lm);
     for (int g0 = wave * lpg; g0 < nl; g0 += nw * lpg) {
         const int gl = min(lpg, nl - g0);
-        V* base = buf + g0 * ls;
+        const int off0 = g0 * ls;
         int lns = 0, rem = lm;
         while (rem > 0) {
             const int bits = fft_next_bits(rem, MAXB);
-            if (bits == 4) run_pass<V, 16, INV>(base, ls, lm, lns, gl, twl, lane);
-            else if (bits == 3) run_pass<V, 8, INV>(base, ls, lm, lns, gl, twl, lane);
-            else if (bits == 2) run_pass<V, 4, INV>(base, ls, lm, lns, gl, twl, lane);
-            else run_pass<V, 2, INV>(base, ls, lm, lns, gl, twl, lane);
+            if (bits == 4) run_pass<V, 16, INV>(buf, off0, ls, lm, lns, gl, twl, lane);
+            else if (bits == 3) run_pass<V, 8, INV>(buf, off0, ls, lm, lns, gl, twl, lane);
+            else if (bits == 2) run_pass<V, 4, INV>(buf, off0, ls, lm, lns, gl, twl, lane);
+            else run_pass<V, 2, INV>(buf, off0, ls, lm, lns, gl, twl, lane);
             lns += bits;
             rem -= bits;
         }

@@ -32,6 +32,26 @@
 
 namespace ssm {
 
+// Tuning constants (compile-time): widest FFT pass (log2 radix) of the x
+// kernels and of the convolution kernel, and the occupancy the FP32
+// convolution kernel is compiled for (waves per SIMD; fewer waves leave more
+// registers for its accumulator).
+#ifndef SSM_X_RADIX_BITS
+#define SSM_X_RADIX_BITS 2
+#endif
+#ifndef SSM_CONV_RADIX_BITS
+#define SSM_CONV_RADIX_BITS 2
+#endif
+#ifndef SSM_CONV_WAVES_F32
+#define SSM_CONV_WAVES_F32 3
+#endif
+// 1: the convolution kernel sums its two y halves in registers; 0: in its
+// own output slice (read-modify-write through L2), which frees registers.
+#ifndef SSM_CONV_REG_ACC
+#define SSM_CONV_REG_ACC 0
+#endif
+template <typename T> constexpr int kConvRadixBits = SSM_CONV_RADIX_BITS;
+
 template <typename T> struct CT;
 template <> struct CT<float> { using type = float2; };
 template <> struct CT<double> { using type = double2; };
@@ -84,7 +104,7 @@ __device__ __forceinline__ T wave_max(T v)
 // signal a + i b; its length-2m spectrum Z gives A(k) = (Z(k) + conj Z(-k))/2
 // and B(k) = -i (Z(k) - conj Z(-k))/2 for k = 0..m.
 // Output layout X[img][kx][c][z][y]: a tile writes ytf consecutive y values.
-// LDS: twiddles (2m) + ytf lines of m.
+// LDS: twiddles (2m) + ytf lines of m (padded layout).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3, 8))) void k_xfwd(const Prob* __restrict__ P, int np,
@@ -123,17 +143,17 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
                 if (ya + 1 < ny) b = sc[(long long)(ya + 1) * nx + j];
             }
             const V v = mk<V>(a, b);
-            lines[(2 * rp) * m + j] = v;
-            lines[(2 * rp + 1) * m + j] = cmul(v, twl[j]);
+            lines[lds_pad((2 * rp) * m + j)] = v;
+            lines[lds_pad((2 * rp + 1) * m + j)] = cmul(v, twl[j]);
         }
         __syncthreads();
-        fft_lines<V, false>(lines, yt, m, lm, twl);
+        fft_lines<V, false, SSM_X_RADIX_BITS>(lines, yt, m, lm, twl);
         __syncthreads();
         for (int idx = threadIdx.x; idx < (m + 1) * hp; idx += kNT) {
             const int rp = idx % hp, kx = idx / hp;
             const int kr = (P2 - kx) & (P2 - 1);
-            const V Z = lines[(2 * rp + (kx & 1)) * m + (kx >> 1)];
-            const V Zr = lines[(2 * rp + (kr & 1)) * m + (kr >> 1)];
+            const V Z = lines[lds_pad((2 * rp + (kx & 1)) * m + (kx >> 1))];
+            const V Zr = lines[lds_pad((2 * rp + (kr & 1)) * m + (kr >> 1))];
             const T hlf = T(0.5);
             const V A = mk<V>((Z.x + Zr.x) * hlf, (Z.y - Zr.y) * hlf);
             const V B = mk<V>((Z.y + Zr.y) * hlf, (Zr.x - Z.x) * hlf);
@@ -159,9 +179,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
 // more than kMaxE*kNT elements).  The kernel spectrum carries 1/(Px Py Pz).
 // LDS: twiddles (2 m_y) + G*3*nz lines of m_y.
 // ---------------------------------------------------------------------------
-// Widest FFT pass of the convolution kernel (log2): radix 4 for FP32, whose
-// accumulator registers leave little room, radix 16 for FP64.
-template <typename T> constexpr int kConvRadixBits = sizeof(T) == 4 ? 2 : 4;
+
 
 template <typename V, int MZ>
 __device__ __forceinline__ V wz_pad(int zz, const V* __restrict__ tw)
@@ -176,7 +194,7 @@ __device__ __forceinline__ V wz_pad(int zz, const V* __restrict__ tw)
 }
 
 template <typename T, int MZ>
-__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && MZ <= 8 ? 3 : 1, 8))) void k_conv(const Prob* __restrict__ P, int np,
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && MZ <= 8 ? SSM_CONV_WAVES_F32 : 1, 8))) void k_conv(const Prob* __restrict__ P, int np,
                                               const int* __restrict__ wstart,
                                               const cplx<T>* __restrict__ X,
                                               cplx<T>* __restrict__ Xp, const T* __restrict__ nhat,
@@ -209,13 +227,14 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     load_twiddles(twl, lmy, tw);
     const V* in = X + p.x_off + (long long)s0 * per;
     V* out = Xp + p.x_off + (long long)s0 * per;
-    const bool racc = nel <= kMaxE * kNT;
+    const bool racc = SSM_CONV_REG_ACC && nel <= kMaxE * kNT;
     const int dy = kNT % ny, dr = kNT / ny;
     const int yb = threadIdx.x % ny, rb = threadIdx.x / ny;
 
-    V acc[kMaxE];
+    constexpr int NACC = SSM_CONV_REG_ACC ? kMaxE : 1;
+    V acc[NACC];
 #pragma unroll
-    for (int i = 0; i < kMaxE; ++i) acc[i] = mk<V>(0, 0);
+    for (int i = 0; i < NACC; ++i) acc[i] = mk<V>(0, 0);
     __syncthreads();
 
 #pragma unroll 1
@@ -227,7 +246,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
             for (int e = threadIdx.x; e < nel; e += kNT) {
                 V v = in[e];
                 if (hy) v = cmul(v, twl[y]);
-                lines[r * my + y] = v;
+                lines[lds_pad(r * my + y)] = v;
                 y += dy;
                 r += dr;
                 if (y >= ny) { y -= ny; r += 1; }
@@ -237,7 +256,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
             const int tail = my - ny;
             for (int e = threadIdx.x; e < nlines * tail; e += kNT) {
                 const int r = e / tail, y = ny + e % tail;
-                lines[r * my + y] = mk<V>(0, 0);
+                lines[lds_pad(r * my + y)] = mk<V>(0, 0);
             }
         }
         __syncthreads();
@@ -249,7 +268,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         for (int col = col0; col < G * my; col += kNT) {
             const int g = col >> lmy, qy = col & (my - 1);
             const int kx = (s0 + g) % nsl_img;
-            V* cl = lines + (g * 3 * nz) * my + qy;
+            const int cbase = (g * 3 * nz) * my + qy;
             V b[3][MZ];
 #pragma unroll
             for (int c = 0; c < 3; ++c)
@@ -262,7 +281,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
                 for (int c = 0; c < 3; ++c)
 #pragma unroll
                     for (int zz = 0; zz < MZ; ++zz) {
-                        V v = (zz < nz) ? cl[(c * nz + zz) * my] : mk<V>(0, 0);
+                        V v = (zz < nz) ? lines[lds_pad(cbase + (c * nz + zz) * my)] : mk<V>(0, 0);
                         if (hz) v = cmul(v, wz_pad<V, MZ>(zz, tw));
                         a[c][zz] = v;
                     }
@@ -295,7 +314,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
             for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int zz = 0; zz < MZ; ++zz)
-                    if (zz < nz) cl[(c * nz + zz) * my] = b[c][zz];
+                    if (zz < nz) lines[lds_pad(cbase + (c * nz + zz) * my)] = b[c][zz];
         }
         __syncthreads();
         fft_lines<V, true, kConvRadixBits<T>>(lines, nlines, my, lmy, twl);
@@ -306,10 +325,10 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
             // addresses and twiddles out of the y-half loop
             asm volatile("" : "+v"(y), "+v"(r));
 #pragma unroll
-            for (int i = 0; i < kMaxE; ++i) {
+            for (int i = 0; i < NACC; ++i) {
                 const int e = threadIdx.x + i * kNT;
                 if (e < nel) {
-                    V v = lines[r * my + y];
+                    V v = lines[lds_pad(r * my + y)];
                     if (hy) v = cmulc(v, twl[y]);
                     acc[i] = cadd(acc[i], v);
                 }
@@ -320,7 +339,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         } else {
             for (int e = threadIdx.x; e < nel; e += kNT) {
                 const int y = e % ny, r = e / ny;
-                V v = lines[r * my + y];
+                V v = lines[lds_pad(r * my + y)];
                 if (hy) v = cmulc(v, twl[y]);
                 out[e] = hy ? cadd(out[e], v) : v;
             }
@@ -329,7 +348,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     }
     if (racc) {
 #pragma unroll
-        for (int i = 0; i < kMaxE; ++i) {
+        for (int i = 0; i < NACC; ++i) {
             const int e = threadIdx.x + i * kNT;
             if (e < nel) out[e] = acc[i];
         }
@@ -368,7 +387,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     const long long N = p.N;
     V* twl = reinterpret_cast<V*>(smem_);
     V* lines = twl + 2 * m;
-    T* hd = reinterpret_cast<T*>(lines + yt * m);
+    T* hd = reinterpret_cast<T*>(lines + lds_padded_size(yt * m));
     load_twiddles(twl, lm, tw);
     const V* Xi = Xp + p.x_off + (long long)img * (m + 1) * 3 * nz * ny;
     __syncthreads();
@@ -380,82 +399,121 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
             const V* src = Xi + (((long long)kx * 3 + c) * nz + z) * ny;
             const V A = (ya < ny) ? src[ya] : mk<V>(0, 0);
             const V B = (ya + 1 < ny) ? src[ya + 1] : mk<V>(0, 0);
-            lines[(2 * rp + (kx & 1)) * m + (kx >> 1)] = mk<V>(A.x - B.y, A.y + B.x);
+            lines[lds_pad((2 * rp + (kx & 1)) * m + (kx >> 1))] = mk<V>(A.x - B.y, A.y + B.x);
             if (kx > 0 && kx < m) {
                 const int km = 2 * m - kx;
-                lines[(2 * rp + (km & 1)) * m + (km >> 1)] = mk<V>(A.x + B.y, B.x - A.y);
+                lines[lds_pad((2 * rp + (km & 1)) * m + (km >> 1))] = mk<V>(A.x + B.y, B.x - A.y);
             }
         }
         __syncthreads();
-        fft_lines<V, true>(lines, yt, m, lm, twl);
+        fft_lines<V, true, SSM_X_RADIX_BITS>(lines, yt, m, lm, twl);
         __syncthreads();
         for (int idx = threadIdx.x; idx < hp * nx; idx += kNT) {
             const int x = idx % nx, rp = idx / nx;
-            const V e = lines[(2 * rp) * m + x];
-            const V o = cmulc(lines[(2 * rp + 1) * m + x], twl[x]);
+            const V e = lines[lds_pad((2 * rp) * m + x)];
+            const V o = cmulc(lines[lds_pad((2 * rp + 1) * m + x)], twl[x]);
             hd[(c * yt + 2 * rp) * nx + x] = e.x + o.x;
             hd[(c * yt + 2 * rp + 1) * nx + x] = e.y + o.y;
         }
         __syncthreads();
     }
 
+    // Per-site epilogue.  Each thread owns one column x and walks a run of
+    // the tile's rows keeping rows y-1, y, y+1 in registers; x neighbours come
+    // from the adjacent lanes (the lanes of a wave hold consecutive x), so
+    // only the z neighbours and the wave-edge lanes read global memory.
     const double J = p.J, dm = p.d, ku = p.ku, D = p.D;
-    const T* si = s + p.s_off + (long long)img * 3 * N;
-    T* so = ss + p.s_off + (long long)img * 3 * N;
-    T* ho = hout ? hout + p.s_off + (long long)img * 3 * N : nullptr;
+    const T* si = s + p.s_off + (long long)img * 3 * N + (long long)z * ny * nx;
+    const long long pl = (long long)nx * ny;
+    const long long soff = p.s_off + (long long)img * 3 * N + (long long)z * ny * nx;
+    int nxp = 1;
+    while (nxp < nx && nxp < kNT) nxp <<= 1;
+    const int rgs = kNT / nxp;                    // row groups
+    const int rg = threadIdx.x / nxp, xl = threadIdx.x & (nxp - 1);
+    const int rper = (yt + rgs - 1) / rgs;
+    const int ra = rg * rper, rb = min(yt, ra + rper);
+    const int lane = threadIdx.x & 63;
     double acc[kNTerm] = {0, 0, 0, 0, 0};
-    for (int idx = threadIdx.x; idx < yt * nx; idx += kNT) {
-        const int x = idx % nx, r = idx / nx, y = y0 + r;
-        if (y >= ny) continue;
-        const long long i = ((long long)z * ny + y) * nx + x;
-        double sv[3], nb[3] = {0, 0, 0};
-        double xp[3] = {0, 0, 0}, xm[3] = {0, 0, 0}, yp[3] = {0, 0, 0}, ym[3] = {0, 0, 0};
+    for (int xc = 0; xc < nx; xc += nxp) {
+        const int x = xc + xl;
+        const bool xin = x < nx;
+        T cm[3], cc[3], cp[3];
+        {
+            const int y = y0 + ra;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-            const T* sc = si + (long long)c * N;
-            sv[c] = (double)sc[i];
-            if (x + 1 < nx) xp[c] = (double)sc[i + 1];
-            if (x > 0) xm[c] = (double)sc[i - 1];
-            if (y + 1 < ny) yp[c] = (double)sc[i + nx];
-            if (y > 0) ym[c] = (double)sc[i - nx];
-            double zs = 0;
-            if (z + 1 < nz) zs += (double)sc[i + (long long)nx * ny];
-            if (z > 0) zs += (double)sc[i - (long long)nx * ny];
-            nb[c] = xp[c] + xm[c] + yp[c] + ym[c] + zs;
+            for (int c = 0; c < 3; ++c) {
+                const T* sc = si + (long long)c * N;
+                cc[c] = (xin && ra < rb && y < ny) ? sc[(long long)y * nx + x] : T(0);
+                cm[c] = (xin && ra < rb && y > 0 && y - 1 < ny) ? sc[(long long)(y - 1) * nx + x] : T(0);
+            }
         }
-        // unit-strength DMI field, eq. (4)
-        const double dmx = -(xp[2] - xm[2]);
-        const double dmy = -(yp[2] - ym[2]);
-        const double dmz = -(-xp[0] + xm[0] - yp[1] + ym[1]);
-        const double hu[3] = {(double)hd[(0 * yt + r) * nx + x], (double)hd[(1 * yt + r) * nx + x],
-                              (double)hd[(2 * yt + r) * nx + x]};
-        double h[3];
-        h[0] = J * nb[0] + dm * dmx + D * hu[0];
-        h[1] = J * nb[1] + dm * dmy + D * hu[1];
-        h[2] = J * nb[2] + dm * dmz + 2.0 * ku * sv[2] + D * hu[2];
-        const double sh = sv[0] * h[0] + sv[1] * h[1] + sv[2] * h[2];
-        acc[0] += -0.5 * sh;
-        if (mode & EPI_TERMS) {
-            acc[1] += -0.5 * (sv[0] * nb[0] + sv[1] * nb[1] + sv[2] * nb[2]);
-            acc[2] += -0.5 * (sv[0] * dmx + sv[1] * dmy + sv[2] * dmz);
-            acc[3] += -sv[2] * sv[2];
-            acc[4] += -0.5 * (sv[0] * hu[0] + sv[1] * hu[1] + sv[2] * hu[2]);
-        }
-        if (mode & EPI_FIELD) {
+        for (int r = ra; r < ra + rper; ++r) {
+            const int y = y0 + r;
+            const bool act = xin && r < rb && y < ny;
+            const long long i = (long long)y * nx + x;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) ho[(long long)c * N + i] = (T)h[c];
-        }
-        if (mode & EPI_STEP) {
-            double wv[3];
+            for (int c = 0; c < 3; ++c) {
+                const T* sc = si + (long long)c * N;
+                cp[c] = (xin && r < rb && y + 1 < ny) ? sc[i + nx] : T(0);
+            }
+            double sv[3], xp[3], xm[3], nb[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) wv[c] = sv[c] + tau * (h[c] - sh * sv[c]);
-            const double nrm = sqrt(wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2]);
+            for (int c = 0; c < 3; ++c) {
+                T right = __shfl_down(cc[c], 1);
+                T left = __shfl_up(cc[c], 1);
+                const T* sc = si + (long long)c * N;
+                if (xl == nxp - 1 || lane == 63) right = (act && x + 1 < nx) ? sc[i + 1] : T(0);
+                if (xl == 0 || lane == 0) left = (act && x > 0) ? sc[i - 1] : T(0);
+                if (x + 1 >= nx) right = T(0);
+                sv[c] = (double)cc[c];
+                xp[c] = (double)right;
+                xm[c] = (double)left;
+                double zsum = 0;
+                if (act && z + 1 < nz) zsum += (double)sc[i + pl];
+                if (act && z > 0) zsum += (double)sc[i - pl];
+                nb[c] = xp[c] + xm[c] + (double)cp[c] + (double)cm[c] + zsum;
+            }
+            if (act) {
+                // unit-strength DMI field, eq. (4)
+                const double dmx = -(xp[2] - xm[2]);
+                const double dmy = -((double)cp[2] - (double)cm[2]);
+                const double dmz = -(-xp[0] + xm[0] - (double)cp[1] + (double)cm[1]);
+                const double hu[3] = {(double)hd[(0 * yt + r) * nx + x], (double)hd[(1 * yt + r) * nx + x],
+                                      (double)hd[(2 * yt + r) * nx + x]};
+                double h[3];
+                h[0] = J * nb[0] + dm * dmx + D * hu[0];
+                h[1] = J * nb[1] + dm * dmy + D * hu[1];
+                h[2] = J * nb[2] + dm * dmz + 2.0 * ku * sv[2] + D * hu[2];
+                const double sh = sv[0] * h[0] + sv[1] * h[1] + sv[2] * h[2];
+                acc[0] += -0.5 * sh;
+                if (mode & EPI_TERMS) {
+                    acc[1] += -0.5 * (sv[0] * nb[0] + sv[1] * nb[1] + sv[2] * nb[2]);
+                    acc[2] += -0.5 * (sv[0] * dmx + sv[1] * dmy + sv[2] * dmz);
+                    acc[3] += -sv[2] * sv[2];
+                    acc[4] += -0.5 * (sv[0] * hu[0] + sv[1] * hu[1] + sv[2] * hu[2]);
+                }
+                if (mode & EPI_FIELD) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) so[(long long)c * N + i] = (T)(wv[c] / nrm);
+                    for (int c = 0; c < 3; ++c) hout[soff + (long long)c * N + i] = (T)h[c];
+                }
+                if (mode & EPI_STEP) {
+                    double wv[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) wv[c] = sv[c] + tau * (h[c] - sh * sv[c]);
+                    const double inv = 1.0 / sqrt(wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2]);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) ss[soff + (long long)c * N + i] = (T)(wv[c] * inv);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                cm[c] = cc[c];
+                cc[c] = cp[c];
+            }
         }
     }
     const int nterm = (mode & EPI_TERMS) ? kNTerm : 1;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wave = threadIdx.x >> 6;
     for (int j = 0; j < nterm; ++j) {
         const double v = wave_sum(acc[j]);
         if (lane == 0) red[wave][j] = v;

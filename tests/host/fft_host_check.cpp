@@ -13,14 +13,14 @@
 using namespace ssm;
 
 template <typename V, int R, bool INV>
-static void emulate_pass(V* base, int ls, int lm, int lns, int gl, const V* twl)
+static void emulate_pass(V* buf, int off0, int ls, int lm, int lns, int gl, const V* twl)
 {
     using P = Pass<V, R, INV>;
     std::vector<V> regs(64 * P::B * R);
     for (int lane = 0; lane < 64; ++lane)
-        P::read(base, ls, lm, lns, gl, twl, lane, *reinterpret_cast<V(*)[P::B][R]>(&regs[lane * P::B * R]));
+        P::read(buf, off0, ls, lm, lns, gl, twl, lane, *reinterpret_cast<V(*)[P::B][R]>(&regs[lane * P::B * R]));
     for (int lane = 0; lane < 64; ++lane)
-        P::write(base, ls, lm, lns, gl, lane, *reinterpret_cast<V(*)[P::B][R]>(&regs[lane * P::B * R]));
+        P::write(buf, off0, ls, lm, lns, gl, lane, *reinterpret_cast<V(*)[P::B][R]>(&regs[lane * P::B * R]));
 }
 
 template <typename V, bool INV>
@@ -34,11 +34,10 @@ static void host_fft_lines(V* buf, int nl, int ls, int lm, const V* twl, int max
         for (int rem = lm; rem > 0;) {
             const int bits = fft_next_bits(rem, maxb);
             rem -= bits;
-            V* base = buf + g0 * ls;
-            if (bits == 4) emulate_pass<V, 16, INV>(base, ls, lm, lns, gl, twl);
-            else if (bits == 3) emulate_pass<V, 8, INV>(base, ls, lm, lns, gl, twl);
-            else if (bits == 2) emulate_pass<V, 4, INV>(base, ls, lm, lns, gl, twl);
-            else emulate_pass<V, 2, INV>(base, ls, lm, lns, gl, twl);
+            if (bits == 4) emulate_pass<V, 16, INV>(buf, g0 * ls, ls, lm, lns, gl, twl);
+            else if (bits == 3) emulate_pass<V, 8, INV>(buf, g0 * ls, ls, lm, lns, gl, twl);
+            else if (bits == 2) emulate_pass<V, 4, INV>(buf, g0 * ls, ls, lm, lns, gl, twl);
+            else emulate_pass<V, 2, INV>(buf, g0 * ls, ls, lm, lns, gl, twl);
             lns += bits;
         }
     }
@@ -56,8 +55,8 @@ static double check(int lm, int nl, int pad, unsigned seed, int maxb)
     }
     std::mt19937 rng(seed);
     std::normal_distribution<double> nd;
-    std::vector<V> buf(nl * ls), ref(nl * ls);
-    for (auto& v : buf) v = mk<V>((S)nd(rng), (S)nd(rng));
+    std::vector<V> buf(lds_padded_size(nl * ls)), ref(nl * ls);
+    for (int i = 0; i < nl * ls; ++i) buf[lds_pad(i)] = mk<V>((S)nd(rng), (S)nd(rng));
     std::vector<long double> xr(m), xi(m), cs(m), sn(m);
     for (int e = 0; e < m; ++e) {
         const long double th = (INV ? 2.0L : -2.0L) * 3.14159265358979323846264338327950288L * e / m;
@@ -66,7 +65,10 @@ static double check(int lm, int nl, int pad, unsigned seed, int maxb)
     }
     double worst = 0;
     for (int l = 0; l < nl; ++l) {
-        for (int j = 0; j < m; ++j) { xr[j] = buf[l * ls + j].x; xi[j] = buf[l * ls + j].y; }
+        for (int j = 0; j < m; ++j) {
+            xr[j] = buf[lds_pad(l * ls + j)].x;
+            xi[j] = buf[lds_pad(l * ls + j)].y;
+        }
         for (int k = 0; k < m; ++k) {
             long double sr = 0, si = 0;
             for (int j = 0; j < m; ++j) {
@@ -81,7 +83,7 @@ static double check(int lm, int nl, int pad, unsigned seed, int maxb)
     double nrm = 0;
     for (int l = 0; l < nl; ++l)
         for (int k = 0; k < m; ++k) {
-            const V a = buf[l * ls + k], b = ref[l * ls + k];
+            const V a = buf[lds_pad(l * ls + k)], b = ref[l * ls + k];
             worst = fmax(worst, fabs((double)a.x - (double)b.x));
             worst = fmax(worst, fabs((double)a.y - (double)b.y));
             nrm = fmax(nrm, fabs((double)b.x) + fabs((double)b.y));
