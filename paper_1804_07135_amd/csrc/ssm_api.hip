@@ -60,6 +60,7 @@ struct Plan {
     int mz = 1;
     size_t tsize = 8;                 // bytes of one spin component
     std::vector<Prob> P;
+    std::vector<Tiles> tiles;         // tile shapes in use, per problem
     std::vector<int> geo;             // problem -> distinct-shape index
     std::vector<std::tuple<int, int, int>> shapes;
     std::vector<long long> nh_size;   // elements per distinct shape
@@ -199,6 +200,7 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec, const std::vector
         p.N = (long long)q.nx * q.ny * q.nz;
         const Tiles t = tiles ? (*tiles)[i] : default_tiles(p, pl.tsize);
         apply_tiles(p, t);
+        pl.tiles.push_back(t);
         if (lds_xfwd(p, p.ytf, pl.tsize) > kLdsMax || lds_xinv(p, p.yt, pl.tsize) > kLdsMax ||
             lds_convg(p, p.gconv, pl.tsize) > kLdsMax) {
             err = "problem " + std::to_string(i) + ": lattice too large for one workgroup's LDS";
@@ -217,7 +219,9 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec, const std::vector
         img += p.K;
         spin += (long long)p.K * 3 * p.N;
         xo += (long long)p.K * (p.mx + 1) * 3 * p.nz * p.ny;
-        ep += (long long)p.K * p.tiles * kNTerm;
+        // sized for the smallest inverse tile (2 rows) so that retuned tiles
+        // keep the workspace layout
+        ep += (long long)p.K * p.nz * ((p.ny + 1) / 2) * kNTerm;
         ap += (long long)p.K * p.arc_chunks * 4;
         fp += (long long)p.K * p.ichunks * 2;
         fm += (long long)p.K * p.ichunks;
@@ -535,6 +539,182 @@ void twiddles(std::vector<double>& tw64)
 
 }  // namespace
 
+static ssm_status upload_plan(ssm_ctx* c)
+{
+    const Plan& pl = c->pl;
+    HIPCHK(c, hipMemcpyAsync(c->ws + pl.o_P, pl.P.data(), sizeof(Prob) * pl.np,
+                             hipMemcpyHostToDevice, c->stream), "upload descriptors");
+    std::vector<int> wm;
+    for (const auto* v : {&pl.wm_xf, &pl.wm_xi, &pl.wm_conv, &pl.wm_arc, &pl.wm_site, &pl.wm_img})
+        wm.insert(wm.end(), v->begin(), v->end());
+    HIPCHK(c, hipMemcpyAsync(c->ws + pl.o_wm, wm.data(), sizeof(int) * wm.size(),
+                             hipMemcpyHostToDevice, c->stream), "upload work maps");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    return SSM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: candidate tile shapes per kernel, timed on the live context.
+// ---------------------------------------------------------------------------
+namespace {
+
+// Rebuild descriptors and work maps for new tile shapes; the workspace
+// layout does not depend on them.
+ssm_status retile(ssm_ctx* c, const std::vector<Tiles>& tiles)
+{
+    Plan pl;
+    std::string err;
+    ssm_status st = build_plan(c->probs.data(), (int)c->probs.size(), c->pl.prec, &tiles, pl, err);
+    if (st != SSM_OK) return fail(c, st, err);
+    if (pl.total != c->pl.total) return fail(c, SSM_EUNSUPPORTED, "retiling changed the workspace layout");
+    // keep the parameters set since creation
+    for (size_t i = 0; i < pl.P.size(); ++i) {
+        pl.P[i].J = c->pl.P[i].J;
+        pl.P[i].d = c->pl.P[i].d;
+        pl.P[i].ku = c->pl.P[i].ku;
+        pl.P[i].D = c->pl.P[i].D;
+    }
+    c->pl = pl;
+    drop_graph(c);
+    return upload_plan(c);
+}
+
+// Median time (ms) of `reps` launches of one evaluation kernel kind.
+template <typename T>
+double time_kernel(ssm_ctx* c, int kind, int reps)
+{
+    const Plan& pl = c->pl;
+    const void* tw = c->at<void>(pl.o_tw);
+    const T* s = c->at<T>(pl.o_s);
+    std::vector<float> ts;
+    hipEvent_t a = get_event(c), b = get_event(c);
+    for (int r = 0; r < reps + 1; ++r) {
+        if (hipEventRecord(a, c->stream) != hipSuccess) return 1e30;
+        hipError_t e = hipSuccess;
+        if (kind == KK_XFWD)
+            e = launch_xfwd<T>(c->P(), pl.np, c->wm_xf(), s, c->X(), tw, nullptr, pl.lds_xf, c->stream);
+        else if (kind == KK_CONV)
+            e = launch_conv<T>(pl.mz, c->P(), pl.np, c->wm_conv(), c->X(), c->Xp(), c->at<T>(pl.o_nh), tw,
+                               nullptr, pl.lds_conv, c->stream);
+        else
+            e = launch_xinv<T>(c->P(), pl.np, c->wm_xi(), c->Xp(), s, nullptr, nullptr,
+                               c->at<double>(pl.o_ep), tw, nullptr, EPI_TERMS, 0.0, pl.lds_xi, c->stream);
+        if (e != hipSuccess || hipEventRecord(b, c->stream) != hipSuccess) return 1e30;
+        if (hipEventSynchronize(b) != hipSuccess) return 1e30;
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 1e30;
+        if (r > 0) ts.push_back(ms);  // first launch warms caches
+    }
+    c->pool.push_back(a);
+    c->pool.push_back(b);
+    std::sort(ts.begin(), ts.end());
+    return ts[ts.size() / 2];
+}
+
+std::string device_name()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string n = prop.gcnArchName;
+    for (auto& ch : n) if (ch == ' ') ch = '_';
+    return n;
+}
+
+std::string cache_key(const std::string& dev, int prec, const ssm_problem& q)
+{
+    std::ostringstream os;
+    os << dev << " " << prec << " " << q.nx << "x" << q.ny << "x" << q.nz << " " << q.n_images;
+    return os.str();
+}
+
+ssm_status autotune(ssm_ctx* c, const char* cache_path)
+{
+    const int np = c->pl.np;
+    const size_t ts = c->pl.tsize;
+    const std::string dev = device_name();
+    std::vector<Tiles> cur = c->pl.tiles;
+    std::vector<bool> known(np, false);
+    // cache lookup: "<device> <prec> <nx>x<ny>x<nz> <K> ytf yt gconv"
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        std::map<std::string, Tiles> cache;
+        while (std::getline(in, line)) {
+            std::istringstream is(line);
+            std::string d, shape;
+            int pr, K, a, b, g;
+            if (is >> d >> pr >> shape >> K >> a >> b >> g) {
+                std::ostringstream k;
+                k << d << " " << pr << " " << shape << " " << K;
+                cache[k.str()] = Tiles{a, b, g};
+            }
+        }
+        for (int i = 0; i < np; ++i) {
+            auto it = cache.find(cache_key(dev, c->pl.prec, c->probs[i]));
+            if (it != cache.end()) { cur[i] = it->second; known[i] = true; }
+        }
+    }
+    bool all_known = true;
+    for (bool k : known) all_known = all_known && k;
+    if (!all_known) {
+        // candidates are applied to every problem at once (clamped to what
+        // each problem's LDS admits); kernels are timed one kind at a time
+        auto fits = [&](const Prob& p, const Tiles& t) {
+            return lds_xfwd(p, t.ytf, ts) <= kLdsMax && lds_xinv(p, t.yt, ts) <= kLdsMax &&
+                   lds_convg(p, t.gconv, ts) <= kLdsMax;
+        };
+        auto timed_kind = [&](int kind) {
+            return c->pl.prec == SSM_FP64 ? time_kernel<double>(c, kind, 5) : time_kernel<float>(c, kind, 5);
+        };
+        const int rows[] = {2, 4, 8, 16, 32, 64};
+        for (int kind : {KK_XFWD, KK_XINV, KK_CONV}) {
+            std::vector<Tiles> best = cur;
+            ssm_status st = retile(c, cur);
+            if (st != SSM_OK) return st;
+            double tbest = timed_kind(kind);
+            const int ncand = kind == KK_CONV ? 6 : 6;
+            for (int ci = 0; ci < ncand; ++ci) {
+                std::vector<Tiles> cand = cur;
+                bool any = false;
+                for (int i = 0; i < np; ++i) {
+                    if (known[i]) continue;
+                    Prob p = c->pl.P[i];
+                    Tiles t = cur[i];
+                    const int ycap = std::max(2, pow2ceil(p.ny));
+                    if (kind == KK_XFWD) t.ytf = std::min(rows[ci], ycap);
+                    else if (kind == KK_XINV) t.yt = std::min(rows[ci], ycap);
+                    else t.gconv = 1 << ci;
+                    if (kind == KK_CONV && (long long)t.gconv * 3 * p.nz * p.ny > kConvElems && t.gconv > 1) continue;
+                    if (!fits(p, t)) continue;
+                    if (t.ytf != cur[i].ytf || t.yt != cur[i].yt || t.gconv != cur[i].gconv) any = true;
+                    cand[i] = t;
+                }
+                if (!any) continue;
+                st = retile(c, cand);
+                if (st != SSM_OK) return st;
+                const double tc = timed_kind(kind);
+                if (tc < tbest) { tbest = tc; best = cand; }
+            }
+            cur = best;
+        }
+    }
+    ssm_status st = retile(c, cur);
+    if (st != SSM_OK) return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream), "autotune");
+    c->have_eval = false;  // the scratch buffers were overwritten
+    if (cache_path && !all_known) {
+        std::ofstream out(cache_path, std::ios::app);
+        for (int i = 0; i < np; ++i)
+            if (!known[i])
+                out << cache_key(dev, c->pl.prec, c->probs[i]) << " " << cur[i].ytf << " " << cur[i].yt << " "
+                    << cur[i].gconv << "\n";
+    }
+    return SSM_OK;
+}
+
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -563,20 +743,6 @@ ssm_status ssm_workspace_size(const ssm_problem* p, int32_t n_problems, int32_t 
     ssm_status st = build_plan(p, n_problems, precision, nullptr, pl, err);
     if (st != SSM_OK) return fail(nullptr, st, err);
     *bytes = pl.total;
-    return SSM_OK;
-}
-
-static ssm_status upload_plan(ssm_ctx* c)
-{
-    const Plan& pl = c->pl;
-    HIPCHK(c, hipMemcpyAsync(c->ws + pl.o_P, pl.P.data(), sizeof(Prob) * pl.np,
-                             hipMemcpyHostToDevice, c->stream), "upload descriptors");
-    std::vector<int> wm;
-    for (const auto* v : {&pl.wm_xf, &pl.wm_xi, &pl.wm_conv, &pl.wm_arc, &pl.wm_site, &pl.wm_img})
-        wm.insert(wm.end(), v->begin(), v->end());
-    HIPCHK(c, hipMemcpyAsync(c->ws + pl.o_wm, wm.data(), sizeof(int) * wm.size(),
-                             hipMemcpyHostToDevice, c->stream), "upload work maps");
-    HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     return SSM_OK;
 }
 
@@ -898,8 +1064,8 @@ ssm_status ssm_profile_read(ssm_ctx* ctx, double* h_ms, int32_t* h_counts)
 ssm_status ssm_autotune(ssm_ctx* ctx, const char* cache_path)
 {
     if (!ctx) return SSM_EINVAL;
-    (void)cache_path;
-    return fail(ctx, SSM_EUNSUPPORTED, "autotuning not built yet");
+    if (!ctx->have_string) return fail(ctx, SSM_ESTATE, "no string set");
+    return autotune(ctx, cache_path);
 }
 
 }  // extern "C"

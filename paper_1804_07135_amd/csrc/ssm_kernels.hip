@@ -45,6 +45,17 @@ namespace ssm {
 #ifndef SSM_CONV_WAVES_F32
 #define SSM_CONV_WAVES_F32 3
 #endif
+// Workgroup order of the convolution kernel when it takes one slice per
+// workgroup: 1 = the images of one kx on one XCD back to back (kx spread
+// over XCDs); 0 = kx-major, images innermost.
+#ifndef SSM_CONV_XCD_REMAP
+#define SSM_CONV_XCD_REMAP 1
+#endif
+// 1: load the kernel-spectrum coefficients of one z frequency at a time
+// (fewer live registers in the z-phase).
+#ifndef SSM_CONV_NH_SERIAL
+#define SSM_CONV_NH_SERIAL 0
+#endif
 // 1: the convolution kernel sums its two y halves in registers; 0: in its
 // own output slice (read-modify-write through L2), which frees registers.
 #ifndef SSM_CONV_REG_ACC
@@ -210,8 +221,15 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     const int nsl_img = p.mx + 1, nsl = p.K * nsl_img;
     int s0, G;
     if (p.xcd_remap) {
-        const int xcd = w & 7, j = w >> 3;
-        const int kx = (j / p.K) * 8 + xcd, img = j % p.K;
+        int kx, img;
+        if (SSM_CONV_XCD_REMAP) {
+            const int xcd = w & 7, j = w >> 3;
+            kx = (j / p.K) * 8 + xcd;
+            img = j % p.K;
+        } else {
+            kx = w / p.K;
+            img = w % p.K;
+        }
         if (kx > p.mx || img >= p.K) return;
         s0 = img * nsl_img + kx;
         G = 1;
@@ -292,6 +310,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
 #pragma unroll
                 for (int r = 0; r < MZ; ++r) {
                     const T* q6 = nh + (long long)r * 6 * my;
+                    if (SSM_CONV_NH_SERIAL) asm volatile("" : "+v"(q6));
                     const T nxx = q6[0], nxy = q6[my], nxz = q6[2 * my];
                     const T nyy = q6[3 * my], nyz = q6[4 * my], nzz = q6[5 * my];
                     const V sx = a[0][r], sy = a[1][r], sz = a[2][r];

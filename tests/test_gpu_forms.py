@@ -1,0 +1,172 @@
+"""The three forms beside the plain path: FP32-mixed precision, batched
+graph-replayed contexts with autotuned tiles, and the autograd energy with
+parameter gradients (envelope theorem for the barrier)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1804_07135_amd import inputs, ssm, sweep
+
+pytestmark = pytest.mark.gpu
+
+
+def prob(nx, ny, nz, K, J=1.0, d=0.3, ku=0.1, D=0.01):
+    return dict(nx=nx, ny=ny, nz=nz, K=K, J=J, d=d, ku=ku, D=D)
+
+
+def test_batched_graph_sweep_equals_separate_runs():
+    """Points of different lattice sizes in one context, replayed as a graph,
+    give bitwise the results of running each point alone, eagerly."""
+    pts = [dict(nx=L, ny=L, nz=1, K=5, J=1.0, d=d, ku=k, D=0.01, R=2.5, seed=100 + i)
+           for i, (L, d, k) in enumerate([(11, 0.2, 0.05), (16, 0.3, 0.1), (9, 0.4, 0.15), (14, 0.25, 0.2)])]
+    strings = sweep.initial_strings(pts)
+    sm = ssm.StringMethod(sweep.sweep_problems(pts), ssm.SSM_FP64)
+    sm.set_options(check_every=10, graph_chunk=4)
+    sm.set_string(strings)
+    sm.iterate(12, 0.1)
+    flat = sm.get_string().cpu().numpy()
+    bar = sm.barrier().cpu().numpy()
+    off = 0
+    for i, (p, s0) in enumerate(zip(sweep.sweep_problems(pts), strings)):
+        one = ssm.StringMethod(p, ssm.SSM_FP64)
+        one.set_string(s0)
+        one.iterate(12, 0.1)
+        a = one.get_string().cpu().numpy().ravel()
+        assert np.array_equal(flat[off:off + a.size], a)
+        assert np.array_equal(bar[i], one.barrier().cpu().numpy()[0])
+        off += a.size
+
+
+def test_sweep_workload_batched_fp32(tmp_path):
+    """The 64-point (k_u, d) sweep on lattices 48..96, 16 images, in one
+    FP32-mixed context with autotuned tiles: runs, stays finite, and four
+    sampled points match their own FP64 single-point runs at the barrier."""
+    pts = inputs.sweep_points()
+    cache = str(tmp_path / "tiles.txt")
+    r = sweep.run_sweep(pts, precision=ssm.SSM_FP32_MIXED, max_iter=300, tol_force=0.0,
+                        check_every=50, graph_chunk=50, autotune_cache=cache)
+    assert np.all(np.isfinite(r["barrier"]))
+    assert r["context"].check() == 0
+    assert os.path.getsize(cache) > 0
+    for i in (0, 21, 42, 63):
+        p = pts[i]
+        one = ssm.StringMethod(sweep.sweep_problems([p])[0], ssm.SSM_FP64)
+        one.set_string(sweep.initial_strings([p])[0])
+        one.iterate(300, 0.1)
+        B64 = one.barrier().cpu().numpy()[0][0]
+        assert abs(r["barrier"][i] - B64) <= 1e-4 * max(abs(B64), 1.0), (i, r["barrier"][i], B64)
+
+
+def test_autotune_preserves_results(tmp_path):
+    w = inputs.WORKLOADS["bloch_32x32x1_k10"]
+    p = prob(w["nx"], w["ny"], w["nz"], w["K"], w["J"], w["d"], w["ku"], w["D"])
+    s0 = inputs.build_string(w)
+    ref = ssm.StringMethod(p, ssm.SSM_FP64)
+    ref.set_string(s0)
+    ref.iterate(20, 0.1)
+    sm = ssm.StringMethod(p, ssm.SSM_FP64)
+    sm.set_string(s0)
+    cache = str(tmp_path / "tiles.txt")
+    sm.autotune(cache)
+    sm.set_string(s0)
+    sm.iterate(20, 0.1)
+    a, b = ref.energies().cpu().numpy(), sm.energies().cpu().numpy()
+    np.testing.assert_allclose(b, a, rtol=1e-12)
+    np.testing.assert_allclose(sm.get_string().cpu().numpy(), ref.get_string().cpu().numpy(), atol=1e-12)
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and lines[0].split()[2] == "32x32x1"
+    # a second context reads the cached choice instead of timing again
+    sm2 = ssm.StringMethod(p, ssm.SSM_FP64)
+    sm2.set_string(s0)
+    sm2.autotune(cache)
+    assert open(cache).read().splitlines() == lines
+
+
+def test_fp32_boundary_workload_barrier_vs_fp64(oracle):
+    """64x64x1 boundary annihilation, 20 images: FP32-mixed batched (graph)
+    barrier within 1e-4 of the FP64 plain path; the FP64 path itself against
+    the oracle over the first iterations."""
+    w = inputs.WORKLOADS["boundary_64x64x1_k20"]
+    p = prob(w["nx"], w["ny"], w["nz"], w["K"], w["J"], w["d"], w["ku"], w["D"])
+    s0 = inputs.build_string(w)
+    s32 = ssm.StringMethod(p, ssm.SSM_FP32_MIXED)
+    s32.set_options(10, 20)
+    s32.set_string(s0)
+    s32.iterate(w["iters"], w["tau"])
+    s64 = ssm.StringMethod(p, ssm.SSM_FP64)
+    s64.set_string(s0)
+    s64.iterate(w["iters"], w["tau"])
+    b32 = s32.barrier().cpu().numpy()[0][0]
+    b64 = s64.barrier().cpu().numpy()[0][0]
+    assert abs(b32 - b64) <= 1e-4 * abs(b64)
+    # FP64 path vs oracle, 3 iterations on the full 64x64 lattice
+    g = ssm.StringMethod(p, ssm.SSM_FP64)
+    g.set_string(s0)
+    g.iterate(3, w["tau"])
+    r = oracle.iterate(s0, p["J"], p["d"], p["ku"], p["D"], 3, w["tau"])
+    np.testing.assert_allclose(g.energies().cpu().numpy(), r["E"], rtol=0,
+                               atol=1e-10 * np.abs(r["E"]).max())
+
+
+def test_envelope_gradient_two_minima():
+    """With two images that both relax to minima (skyrmion, ferromagnet), the
+    barrier is a difference of minimum energies and its parameter derivative
+    is exactly T(1) - T(0): compare with central differences of re-relaxed
+    barriers."""
+    L, R = 24, 4.0
+    base = dict(nx=L, ny=L, nz=1, K=2, J=1.0, d=0.35, ku=0.08, D=0.01)
+    s0 = np.stack([inputs.neel_skyrmion(L, L, 1, R), inputs.ferromagnet(L, L, 1)])
+
+    def relaxed(d, ku, start):
+        sm = ssm.StringMethod(dict(base, d=d, ku=ku), ssm.SSM_FP64)
+        sm.set_options(100, 100)
+        sm.set_string(start)
+        it = int(sm.iterate(200000, 0.1, tol_force=1e-7)[0])
+        assert it < 200000
+        return sm
+
+    sm = relaxed(base["d"], base["ku"], s0)
+    bar = sm.barrier().cpu().numpy()[0]
+    assert bar[0] > 0.1 and int(bar[1]) == 1  # the ferromagnet lies above the skyrmion
+    s_min = sm.get_string().cpu().numpy()
+    for name, col, delta in (("ku", 4, 1e-4), ("d", 3, 1e-4)):
+        vals = []
+        for sg in (1, -1):
+            kw = dict(d=base["d"], ku=base["ku"])
+            kw[name] += sg * delta
+            vals.append(relaxed(kw["d"], kw["ku"], s_min).barrier().cpu().numpy()[0][0])
+        fd = (vals[0] - vals[1]) / (2 * delta)
+        env = bar[col]
+        assert abs(fd - env) <= 1e-3 * max(abs(env), 1.0), (name, fd, env)
+
+
+def test_autograd_tube_128x128x4(oracle):
+    """dE/ds and dE/d(J, d, ku, dip) on the 128x128x4 tube workload's lattice:
+    grad_s against central differences of the FP64 energies on sampled
+    entries, grad_theta against the oracle's term energies."""
+    w = inputs.WORKLOADS["bloch_128x128x4_k32"]
+    K = 2
+    p = prob(w["nx"], w["ny"], w["nz"], K, w["J"], w["d"], w["ku"], w["D"])
+    s_np = inputs.build_string(dict(w, K=K))
+    sm = ssm.StringMethod(p, ssm.SSM_FP64)
+    s = torch.tensor(s_np, device="cuda", requires_grad=True)
+    th = torch.tensor([w["J"], w["d"], w["ku"], w["D"]], dtype=torch.float64, requires_grad=True)
+    E = ssm.spin_energy(s, th, sm)
+    g = torch.tensor([0.7, -1.3], dtype=torch.float64, device="cuda")
+    (E * g).sum().backward()
+    gs = s.grad.cpu().numpy()
+    rng = np.random.default_rng(3)
+    eps = 1e-3
+    for _ in range(6):
+        k = int(rng.integers(K))
+        idx = (int(rng.integers(3)), int(rng.integers(4)), int(rng.integers(128)), int(rng.integers(128)))
+        sp = s_np.copy(); sp[(k,) + idx] += eps
+        sn = s_np.copy(); sn[(k,) + idx] -= eps
+        Ep = sm.eval(sp, want_field=False, want_terms=False)[0].cpu().numpy()[k]
+        En = sm.eval(sn, want_field=False, want_terms=False)[0].cpu().numpy()[k]
+        fd = (Ep - En) / (2 * eps)
+        assert abs(gs[(k,) + idx] - float(g[k]) * fd) < 1e-6 * max(1.0, abs(fd))
+    To = np.stack([oracle.energy_terms(si) for si in s_np])
+    np.testing.assert_allclose(th.grad.numpy(), (g.cpu().numpy()[:, None] * To).sum(0), rtol=1e-10)
