@@ -82,13 +82,76 @@ def cpu_baseline(w, s0, budget_s):
         t0 = time.perf_counter()
         oracle.field_at(s0[0], w["J"], w["d"], w["ku"], w["D"], sites)
         t = time.perf_counter() - t0
-        if t > budget_s / 4 or n >= N:
+        if t > budget_s / 2 or n >= N:
             break
-        n = min(N, int(n * max(2.0, budget_s / 4 / max(t, 1e-3))))
+        n = min(N, int(n * max(2.0, 0.75 * budget_s / max(t, 1e-3))))
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": n / t, "unit": "site-field evals/s", "cores": threads, "kind": "oracle",
             "sample": f"direct-sum fields at {n} random sites of image 0 of the "
                       f"{w['nx']}x{w['ny']}x{w['nz']} lattice ({t:.1f} s)"}
+
+
+def _csv_rows(path):
+    import csv
+    import glob
+    files = glob.glob(os.path.join(path, "**", "*.csv"), recursive=True)
+    rows = []
+    for f in files:
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def _kernel_key(name):
+    for k in ("k_xfwd", "k_conv", "k_xinv", "k_arc", "k_reduce", "k_interp", "k_spec1", "k_spec2",
+              "k_spec3", "copyBuffer"):
+        if k in name:
+            return k
+    return None
+
+
+def summarize_profiles(args):
+    """Turn rocprofv3 outputs of the bench and of the copy probe into the
+    committed summaries: per-kernel durations, and HBM traffic of the
+    dominant kernel (FETCH_SIZE/WRITE_SIZE scaled by the copy calibration)."""
+    import statistics
+    d = args.summarize_profiles
+    w = args.workload
+    stats = {}
+    for r in _csv_rows(os.path.join(d, "trace")):
+        if "Kernel_Name" in r and "Start_Timestamp" in r:
+            k = _kernel_key(r["Kernel_Name"])
+            if k:
+                stats.setdefault(k, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
+    counters = {}
+    for sub in ("fetch", "write", "cfetch", "cwrite"):
+        for r in _csv_rows(os.path.join(d, sub)):
+            k = _kernel_key(r.get("Kernel_Name", ""))
+            if k:
+                counters.setdefault((sub, k), []).append(float(r["Counter_Value"]))
+    probe_kib = args.copy_probe_mib * 1024 if args.copy_probe_mib else 1024 * 1024
+    f_cal = probe_kib / statistics.median(counters[("cfetch", "copyBuffer")])
+    w_cal = probe_kib / statistics.median(counters[("cwrite", "copyBuffer")])
+    dom = max((k for k in stats if k.startswith("k_") and not k.startswith("k_spec")),
+              key=lambda k: sum(stats[k]))
+    fetch = statistics.median(counters[("fetch", dom)]) * f_cal * 1024
+    write = statistics.median(counters[("write", dom)]) * w_cal * 1024
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    lines = [f"# Kernel durations: {w}, FP32-mixed form", "",
+             f"Command: `{args.profile_command}`", "",
+             "| kernel | launches | avg ms | total ms |", "|---|---|---|---|"]
+    for k, v in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"| {k} | {len(v)} | {statistics.mean(v):.4f} | {sum(v):.3f} |")
+    lines += ["", f"HBM traffic of {dom} per launch (FETCH_SIZE x {f_cal:.3f}, WRITE_SIZE x {w_cal:.3f}; "
+              f"factors from a {probe_kib // 1024} MiB device copy read by the same counters): "
+              f"read {fetch / 1e6:.1f} MB, write {write / 1e6:.1f} MB", ""]
+    with open(os.path.join(ROOT, "profiles", f"kernels_{w}_fp32.md"), "w") as fh:
+        fh.write("\n".join(lines))
+    with open(os.path.join(ROOT, "profiles", f"traffic_{dom}_{w}_fp32.json"), "w") as fh:
+        json.dump({"kernel": dom, "workload": w, "bytes_per_launch": fetch + write, "read_bytes": fetch,
+                   "write_bytes": write, "fetch_calibration": f_cal, "write_calibration": w_cal,
+                   "kernel_source_hash": kernel_source_hash(), "command": args.profile_command}, fh, indent=1)
+    print(json.dumps({"dominant": dom, "read_MB": fetch / 1e6, "write_MB": write / 1e6}))
 
 
 def main():
@@ -104,7 +167,14 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--summarize-profiles", default="",
+                    help="directory of rocprofv3 CSV outputs (trace/, fetch/, write/, cfetch/, cwrite/): "
+                         "write the kernel and traffic summaries into profiles/ and exit")
+    ap.add_argument("--profile-command", default="", help="command line recorded in the summaries")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method is built and "
               "measured on a single MI355X", file=sys.stderr)
