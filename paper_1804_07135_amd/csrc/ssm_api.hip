@@ -644,7 +644,10 @@ ssm_status autotune(ssm_ctx* c, const char* cache_path)
             std::istringstream is(line);
             std::string d, shape;
             int pr, K, a, b, g;
-            if (is >> d >> pr >> shape >> K >> a >> b >> g) {
+            // row tiles are powers of two >= 2 (the x kernels index with
+            // shifts); anything else in the file is ignored
+            auto pow2ok = [](int v) { return v >= 2 && v <= 1024 && (v & (v - 1)) == 0; };
+            if ((is >> d >> pr >> shape >> K >> a >> b >> g) && pow2ok(a) && pow2ok(b) && g >= 1 && g <= 64) {
                 std::ostringstream k;
                 k << d << " " << pr << " " << shape << " " << K;
                 cache[k.str()] = Tiles{a, b, g};

@@ -46,12 +46,26 @@ __host__ __device__ __forceinline__ V cmulc(V a, V b) { return mk<V>(a.x * b.x +
 template <bool INV, typename V>
 __host__ __device__ __forceinline__ V twm(V a, V w) { return INV ? cmulc(a, w) : cmul(a, w); }
 
+// a * exp(-2 pi i e/16) (conjugate twiddle for INV).  Called with e a
+// compile-time constant after unrolling, so the trivial factors 1, -1, -i, i
+// cost no multiplications (x * 0 cannot be folded away in IEEE arithmetic).
+template <bool INV, typename V>
+__host__ __device__ __forceinline__ V twc16(V a, int e)
+{
+    using S = decltype(V::x);
+    e &= 15;
+    if (e == 0) return a;
+    if (e == 8) return mk<V>(-a.x, -a.y);
+    if (e == 4) return INV ? mk<V>(-a.y, a.x) : mk<V>(a.y, -a.x);
+    if (e == 12) return INV ? mk<V>(a.y, -a.x) : mk<V>(-a.y, a.x);
+    return cmul(a, mk<V>((S)kW16re[e], (S)(INV ? -kW16im[e] : kW16im[e])));
+}
+
 // In-register R-point DFT (R = 1, 2, 4, 8, 16), natural order in and out:
 // bit-reversal permutation, then radix-2 decimation-in-time stages.
 template <typename V, int R, bool INV>
 __host__ __device__ __forceinline__ void dft_reg(V (&a)[R])
 {
-    using S = decltype(V::x);
     if (R == 1) return;
     constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
 #pragma unroll
@@ -70,11 +84,7 @@ __host__ __device__ __forceinline__ void dft_reg(V (&a)[R])
             for (int j = 0; j < half; ++j) {
                 const int e = j * (16 / len);
                 const V u = a[i + j];
-                V v = a[i + j + half];
-                if (e != 0) {
-                    const V w = mk<V>((S)kW16re[e], (S)(INV ? -kW16im[e] : kW16im[e]));
-                    v = cmul(v, w);
-                }
+                const V v = twc16<INV>(a[i + j + half], e);
                 a[i + j] = cadd(u, v);
                 a[i + j + half] = csub(u, v);
             }
@@ -147,11 +157,59 @@ struct Pass {
     }
 };
 
+// One radix-R pass as above with the line length 2^LM, the sub-transform
+// length 2^LNS and the line stride 2^LM fixed at compile time: every index
+// is a per-lane base plus constant offsets.  Groups hold 1024 elements, so
+// butterfly b of a lane is g = lane + 64 b.
+template <typename V, int R, bool INV, int LM, int LNS>
+struct PassCT {
+    static constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
+    static constexpr int B = 16 / R;
+    static constexpr int LQ = LM - LR, Q = 1 << LQ, NS = 1 << LNS, TSH = LM + 1 - LNS - LR;
+    static_assert(LM <= 10 && LR <= LM - LNS, "pass does not fit the line");
+
+    __host__ __device__ static void read(const V* buf, int off0, int gl, const V* twl, int lane,
+                                         V (&v)[B][R])
+    {
+        const int nbf = gl << LQ;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int g = lane | (b << 6);
+            if (g < nbf) {
+                const int line = g >> LQ, j = g & (Q - 1), k = j & (NS - 1);
+                const int i0 = off0 + (line << LM) + j;
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[b][r] = buf[lds_pad(i0 + r * Q)];
+                if (LNS > 0) {
+#pragma unroll
+                    for (int r = 1; r < R; ++r) v[b][r] = twm<INV>(v[b][r], twl[(r * k) << TSH]);
+                }
+                dft_reg<V, R, INV>(v[b]);
+            }
+        }
+    }
+
+    __host__ __device__ static void write(V* buf, int off0, int gl, int lane, const V (&v)[B][R])
+    {
+        const int nbf = gl << LQ;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int g = lane | (b << 6);
+            if (g < nbf) {
+                const int line = g >> LQ, j = g & (Q - 1), k = j & (NS - 1);
+                const int i0 = off0 + (line << LM) + ((j >> LNS) << (LNS + LR)) + k;
+#pragma unroll
+                for (int r = 0; r < R; ++r) buf[lds_pad(i0 + r * NS)] = v[b][r];
+            }
+        }
+    }
+};
+
 // log2 radix of the next pass when rem bits of the length are left and
 // passes are capped at maxb bits: the widest allowed radix, except that a
 // remainder that would end in a lone radix-2 pass is split more evenly
 // (e.g. 2^5 = 8*4, 2^9 = 8*8*8 with maxb 3; 4*4*2 for 2^5 with maxb 2).
-__host__ __device__ __forceinline__ int fft_next_bits(int rem, int maxb)
+__host__ __device__ constexpr int fft_next_bits(int rem, int maxb)
 {
     if (rem <= maxb) return rem;
     if (maxb >= 4) return (rem == 5) ? 3 : (rem == 9 ? 3 : 4);
@@ -160,7 +218,7 @@ __host__ __device__ __forceinline__ int fft_next_bits(int rem, int maxb)
 }
 
 // lines per wavefront group: 1024 elements per group
-__host__ __device__ __forceinline__ int fft_group_lines(int lm) { return lm >= 10 ? 1 : (1 << (10 - lm)); }
+__host__ __device__ constexpr int fft_group_lines(int lm) { return lm >= 10 ? 1 : (1 << (10 - lm)); }
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -209,6 +267,41 @@ __device__ __forceinline__ void fft_lines(V* buf, int nl, int ls, int lm, const 
             lns += bits;
             rem -= bits;
         }
+    }
+}
+
+// The passes of a length-2^LM transform over one group, all sizes fixed at
+// compile time (radix schedule as fft_next_bits with cap MAXB).
+template <typename V, bool INV, int LM, int MAXB, int LNS>
+__device__ __forceinline__ void fft_passes_ct(V* buf, int off0, int gl, const V* twl, int lane)
+{
+    if constexpr (LNS < LM) {
+        constexpr int bits = fft_next_bits(LM - LNS, MAXB);
+        constexpr int R = 1 << bits;
+        V v[16 / R][R];
+        PassCT<V, R, INV, LM, LNS>::read(buf, off0, gl, twl, lane, v);
+        wave_sync();
+        PassCT<V, R, INV, LM, LNS>::write(buf, off0, gl, lane, v);
+        wave_sync();
+        fft_passes_ct<V, INV, LM, MAXB, LNS + bits>(buf, off0, gl, twl, lane);
+    }
+}
+
+// fft_lines for a line length 2^LM known at compile time (line stride
+// 2^LM).  Same result as fft_lines up to rounding order.
+template <typename V, bool INV, int LM, int MAXB>
+__device__ __forceinline__ void fft_lines_ct(V* buf, int nl, const V* twl)
+{
+    if constexpr (LM > 0) {
+        int lane = threadIdx.x;
+        // opaque copy (no per-lane address hoisting across the caller's
+        // loops), then the mask restores the known range 0..63
+        asm volatile("" : "+v"(lane));
+        lane &= 63;
+        const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        constexpr int LPG = fft_group_lines(LM);
+        for (int g0 = wave * LPG; g0 < nl; g0 += nw * LPG)
+            fft_passes_ct<V, INV, LM, MAXB, 0>(buf, g0 << LM, min(LPG, nl - g0), twl, lane);
     }
 }
 

@@ -61,6 +61,22 @@ namespace ssm {
 #ifndef SSM_CONV_REG_ACC
 #define SSM_CONV_REG_ACC 0
 #endif
+// 1: the x kernels use compile-time-length FFT passes for x lengths
+// 32..512; widest pass of those.
+#ifndef SSM_X_CT
+#define SSM_X_CT 1
+#endif
+#ifndef SSM_X_CT_RADIX_BITS
+#define SSM_X_CT_RADIX_BITS 4
+#endif
+// 1: the convolution kernel has compile-time-length bodies for y lengths
+// 32..256 (the others take the runtime-length body); widest pass of those.
+#ifndef SSM_CONV_CT
+#define SSM_CONV_CT 1
+#endif
+#ifndef SSM_CONV_CT_RADIX_BITS
+#define SSM_CONV_CT_RADIX_BITS 4
+#endif
 template <typename T> constexpr int kConvRadixBits = SSM_CONV_RADIX_BITS;
 
 template <typename T> struct CT;
@@ -109,6 +125,21 @@ __device__ __forceinline__ T wave_max(T v)
     return v;
 }
 
+// Transform of nl lines of length 2^lm (stride 2^lm): compile-time-length
+// passes for lengths 32..512, runtime-length passes otherwise.
+template <typename V, bool INV>
+__device__ __forceinline__ void fft_lines_x(V* lines, int nl, int lm, const V* twl)
+{
+    switch (SSM_X_CT ? lm : 0) {
+    case 5: fft_lines_ct<V, INV, 5, SSM_X_CT_RADIX_BITS>(lines, nl, twl); break;
+    case 6: fft_lines_ct<V, INV, 6, SSM_X_CT_RADIX_BITS>(lines, nl, twl); break;
+    case 7: fft_lines_ct<V, INV, 7, SSM_X_CT_RADIX_BITS>(lines, nl, twl); break;
+    case 8: fft_lines_ct<V, INV, 8, SSM_X_CT_RADIX_BITS>(lines, nl, twl); break;
+    case 9: fft_lines_ct<V, INV, 9, SSM_X_CT_RADIX_BITS>(lines, nl, twl); break;
+    default: fft_lines<V, INV, SSM_X_RADIX_BITS>(lines, nl, 1 << lm, lm, twl); break;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // k_xfwd: rows of a tile (image, z, ytf rows) -> x half-spectra, one spin
 // component at a time.  Two real rows of one component form one complex
@@ -134,6 +165,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     const int ty = t % p.ntyf, rest = t / p.ntyf;
     const int z = rest % p.nz, img = rest / p.nz;
     const int yt = p.ytf, hp = yt >> 1, nx = p.nx, ny = p.ny, nz = p.nz, m = p.mx, lm = p.lmx;
+    const int lhp = __ffs(hp) - 1;  // tiles are powers of two
     V* twl = reinterpret_cast<V*>(smem_);
     V* lines = twl + 2 * m;
     load_twiddles(twl, lm, tw);
@@ -158,10 +190,10 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
             lines[lds_pad((2 * rp + 1) * m + j)] = cmul(v, twl[j]);
         }
         __syncthreads();
-        fft_lines<V, false, SSM_X_RADIX_BITS>(lines, yt, m, lm, twl);
+        fft_lines_x<V, false>(lines, yt, lm, twl);
         __syncthreads();
         for (int idx = threadIdx.x; idx < (m + 1) * hp; idx += kNT) {
-            const int rp = idx % hp, kx = idx / hp;
+            const int rp = idx & (hp - 1), kx = idx >> lhp;
             const int kr = (P2 - kx) & (P2 - 1);
             const V Z = lines[lds_pad((2 * rp + (kx & 1)) * m + (kx >> 1))];
             const V Zr = lines[lds_pad((2 * rp + (kr & 1)) * m + (kr >> 1))];
@@ -192,16 +224,176 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
 // ---------------------------------------------------------------------------
 
 
-template <typename V, int MZ>
-__device__ __forceinline__ V wz_pad(int zz, const V* __restrict__ tw)
+
+// multiply by the padded-z twiddle exp(-2 pi i zz / (2 MZ)) (conjugate for
+// INV); zz is a compile-time constant after unrolling
+template <bool INV, typename V, int MZ>
+__device__ __forceinline__ V twz(V v, int zz, const V* __restrict__ tw)
 {
-    // exp(-2 pi i zz / (2 MZ))
-    using S = decltype(V::x);
-    if (MZ <= 8) {
-        const int e = zz * (8 / MZ);
-        return mk<V>((S)kW16re[e], (S)kW16im[e]);
+    if (MZ <= 8) return twc16<INV>(v, zz * (8 / MZ));
+    const V w = tw[zz << (kTwLog - 1 - 4)];
+    return INV ? cmulc(v, w) : cmul(v, w);
+}
+
+// y transform of the convolution: compile-time length when LMY > 0
+template <typename V, bool INV, int LMY>
+__device__ __forceinline__ void conv_fft_y(V* lines, int nlines, int lmy, const V* twl)
+{
+    if constexpr (LMY > 0) fft_lines_ct<V, INV, LMY, SSM_CONV_CT_RADIX_BITS>(lines, nlines, twl);
+    else fft_lines<V, INV, SSM_CONV_RADIX_BITS>(lines, nlines, 1 << lmy, lmy, twl);
+}
+
+// The convolution of G slices starting at s0.  LMY > 0 fixes the y length
+// m_y = 2^LMY at compile time (all FFT indexing constant-folds); LMY = 0
+// takes it from the problem.
+template <typename T, int MZ, int LMY>
+__device__ __forceinline__ void conv_body(const Prob& p, int s0, int G, const cplx<T>* __restrict__ X,
+                                          cplx<T>* __restrict__ Xp, const T* __restrict__ nhat,
+                                          const cplx<T>* __restrict__ tw, cplx<T>* smem)
+{
+    using V = cplx<T>;
+    const int nsl_img = p.mx + 1;
+    const int nz = p.nz, ny = p.ny, nhz = p.nhz;
+    const int lmy = LMY > 0 ? LMY : p.lmy, my = 1 << lmy;
+    const int per = 3 * nz * ny, nel = G * per, nlines = G * 3 * nz;
+    V* twl = smem;
+    V* lines = twl + 2 * my;
+    load_twiddles(twl, lmy, tw);
+    const V* in = X + p.x_off + (long long)s0 * per;
+    V* out = Xp + p.x_off + (long long)s0 * per;
+    const bool racc = SSM_CONV_REG_ACC && nel <= kMaxE * kNT;
+    const int dy = kNT % ny, dr = kNT / ny;
+    const int yb = threadIdx.x % ny, rb = threadIdx.x / ny;
+    const int kx0 = s0 % nsl_img;
+
+    constexpr int NACC = SSM_CONV_REG_ACC ? kMaxE : 1;
+    V acc[NACC];
+#pragma unroll
+    for (int i = 0; i < NACC; ++i) acc[i] = mk<V>(0, 0);
+    __syncthreads();
+
+#pragma unroll 1
+    for (int hy = 0; hy < 2; ++hy) {
+        {
+            int y = yb, r = rb;
+            asm volatile("" : "+v"(y), "+v"(r));
+#pragma unroll 4
+            for (int e = threadIdx.x; e < nel; e += kNT) {
+                V v = in[e];
+                if (hy) v = cmul(v, twl[y]);
+                lines[lds_pad((r << lmy) + y)] = v;
+                y += dy;
+                r += dr;
+                if (y >= ny) { y -= ny; r += 1; }
+            }
+        }
+        if (my > ny) {
+            const int tail = my - ny;
+            for (int e = threadIdx.x; e < nlines * tail; e += kNT) {
+                const int r = e / tail, y = ny + e % tail;
+                lines[lds_pad((r << lmy) + y)] = mk<V>(0, 0);
+            }
+        }
+        __syncthreads();
+        conv_fft_y<V, false, LMY>(lines, nlines, lmy, twl);
+        __syncthreads();
+
+        int col0 = threadIdx.x;
+        asm volatile("" : "+v"(col0));
+        for (int col = col0; col < (G << lmy); col += kNT) {
+            const int g = col >> lmy, qy = col & (my - 1);
+            int kx = kx0 + g;
+            while (kx >= nsl_img) kx -= nsl_img;
+            const int cbase = ((g * 3 * nz) << lmy) + qy;
+            V b[3][MZ];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int zz = 0; zz < MZ; ++zz) b[c][zz] = mk<V>(0, 0);
+#pragma unroll 1
+            for (int hz = 0; hz < nhz; ++hz) {
+                V a[3][MZ];
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int zz = 0; zz < MZ; ++zz) {
+                        V v = (zz < nz) ? lines[lds_pad(cbase + ((c * nz + zz) << lmy))] : mk<V>(0, 0);
+                        if (hz) v = twz<false, V, MZ>(v, zz, tw);
+                        a[c][zz] = v;
+                    }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) dft_reg<V, MZ, false>(a[c]);
+                const T* nh = nhat + p.nh_off + (((((long long)kx * nhz + hz) * 2 + hy) * MZ) * 6 << lmy) + qy;
+#pragma unroll
+                for (int r = 0; r < MZ; ++r) {
+                    const T* q6 = nh + ((long long)r * 6 << lmy);
+                    if (SSM_CONV_NH_SERIAL) asm volatile("" : "+v"(q6));
+                    const T nxx = q6[0], nxy = q6[my], nxz = q6[2 * my];
+                    const T nyy = q6[3 * my], nyz = q6[4 * my], nzz = q6[5 * my];
+                    const V sx = a[0][r], sy = a[1][r], sz = a[2][r];
+                    a[0][r] = mk<V>(nxx * sx.x + nxy * sy.x + nxz * sz.x, nxx * sx.y + nxy * sy.y + nxz * sz.y);
+                    a[1][r] = mk<V>(nxy * sx.x + nyy * sy.x + nyz * sz.x, nxy * sx.y + nyy * sy.y + nyz * sz.y);
+                    a[2][r] = mk<V>(nxz * sx.x + nyz * sy.x + nzz * sz.x, nxz * sx.y + nyz * sy.y + nzz * sz.y);
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) dft_reg<V, MZ, true>(a[c]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int zz = 0; zz < MZ; ++zz) {
+                        V v = a[c][zz];
+                        if (hz) v = twz<true, V, MZ>(v, zz, tw);
+                        b[c][zz] = cadd(b[c][zz], v);
+                    }
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int zz = 0; zz < MZ; ++zz)
+                    if (zz < nz) lines[lds_pad(cbase + ((c * nz + zz) << lmy))] = b[c][zz];
+        }
+        __syncthreads();
+        conv_fft_y<V, true, LMY>(lines, nlines, lmy, twl);
+        __syncthreads();
+        {
+            int y = yb, r = rb;
+            // opaque copy: keeps the compiler from hoisting all kMaxE
+            // addresses and twiddles out of the y-half loop
+            asm volatile("" : "+v"(y), "+v"(r));
+            if (racc) {
+#pragma unroll
+                for (int i = 0; i < NACC; ++i) {
+                    const int e = threadIdx.x + i * kNT;
+                    if (e < nel) {
+                        V v = lines[lds_pad((r << lmy) + y)];
+                        if (hy) v = cmulc(v, twl[y]);
+                        acc[i] = cadd(acc[i], v);
+                    }
+                    y += dy;
+                    r += dr;
+                    if (y >= ny) { y -= ny; r += 1; }
+                }
+            } else {
+#pragma unroll 4
+                for (int e = threadIdx.x; e < nel; e += kNT) {
+                    V v = lines[lds_pad((r << lmy) + y)];
+                    if (hy) v = cadd(out[e], cmulc(v, twl[y]));
+                    out[e] = v;
+                    y += dy;
+                    r += dr;
+                    if (y >= ny) { y -= ny; r += 1; }
+                }
+            }
+        }
+        __syncthreads();
     }
-    return tw[zz << (kTwLog - 1 - 4)];
+    if (racc) {
+#pragma unroll
+        for (int i = 0; i < NACC; ++i) {
+            const int e = threadIdx.x + i * kNT;
+            if (e < nel) out[e] = acc[i];
+        }
+    }
 }
 
 template <typename T, int MZ>
@@ -212,7 +404,6 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
                                               const cplx<T>* __restrict__ tw,
                                               const int* __restrict__ done)
 {
-    using V = cplx<T>;
     extern __shared__ double2 smem_[];
     const int pi = find_problem(wstart, np, blockIdx.x);
     if (done && done[pi]) return;
@@ -238,139 +429,14 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         if (s0 >= nsl) return;
         G = min(p.gconv, nsl - s0);
     }
-    const int nz = p.nz, ny = p.ny, my = p.my, lmy = p.lmy, nhz = p.nhz;
-    const int per = 3 * nz * ny, nel = G * per, nlines = G * 3 * nz;
-    V* twl = reinterpret_cast<V*>(smem_);
-    V* lines = twl + 2 * my;
-    load_twiddles(twl, lmy, tw);
-    const V* in = X + p.x_off + (long long)s0 * per;
-    V* out = Xp + p.x_off + (long long)s0 * per;
-    const bool racc = SSM_CONV_REG_ACC && nel <= kMaxE * kNT;
-    const int dy = kNT % ny, dr = kNT / ny;
-    const int yb = threadIdx.x % ny, rb = threadIdx.x / ny;
-
-    constexpr int NACC = SSM_CONV_REG_ACC ? kMaxE : 1;
-    V acc[NACC];
-#pragma unroll
-    for (int i = 0; i < NACC; ++i) acc[i] = mk<V>(0, 0);
-    __syncthreads();
-
-#pragma unroll 1
-    for (int hy = 0; hy < 2; ++hy) {
-        {
-            int y = yb, r = rb;
-            asm volatile("" : "+v"(y), "+v"(r));
-#pragma unroll 4
-            for (int e = threadIdx.x; e < nel; e += kNT) {
-                V v = in[e];
-                if (hy) v = cmul(v, twl[y]);
-                lines[lds_pad(r * my + y)] = v;
-                y += dy;
-                r += dr;
-                if (y >= ny) { y -= ny; r += 1; }
-            }
-        }
-        if (my > ny) {
-            const int tail = my - ny;
-            for (int e = threadIdx.x; e < nlines * tail; e += kNT) {
-                const int r = e / tail, y = ny + e % tail;
-                lines[lds_pad(r * my + y)] = mk<V>(0, 0);
-            }
-        }
-        __syncthreads();
-        fft_lines<V, false, kConvRadixBits<T>>(lines, nlines, my, lmy, twl);
-        __syncthreads();
-
-        int col0 = threadIdx.x;
-        asm volatile("" : "+v"(col0));
-        for (int col = col0; col < G * my; col += kNT) {
-            const int g = col >> lmy, qy = col & (my - 1);
-            const int kx = (s0 + g) % nsl_img;
-            const int cbase = (g * 3 * nz) * my + qy;
-            V b[3][MZ];
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int zz = 0; zz < MZ; ++zz) b[c][zz] = mk<V>(0, 0);
-#pragma unroll 1
-            for (int hz = 0; hz < nhz; ++hz) {
-                V a[3][MZ];
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-#pragma unroll
-                    for (int zz = 0; zz < MZ; ++zz) {
-                        V v = (zz < nz) ? lines[lds_pad(cbase + (c * nz + zz) * my)] : mk<V>(0, 0);
-                        if (hz) v = cmul(v, wz_pad<V, MZ>(zz, tw));
-                        a[c][zz] = v;
-                    }
-#pragma unroll
-                for (int c = 0; c < 3; ++c) dft_reg<V, MZ, false>(a[c]);
-                const T* nh = nhat + p.nh_off +
-                              ((((long long)kx * nhz + hz) * 2 + hy) * MZ) * 6 * my + qy;
-#pragma unroll
-                for (int r = 0; r < MZ; ++r) {
-                    const T* q6 = nh + (long long)r * 6 * my;
-                    if (SSM_CONV_NH_SERIAL) asm volatile("" : "+v"(q6));
-                    const T nxx = q6[0], nxy = q6[my], nxz = q6[2 * my];
-                    const T nyy = q6[3 * my], nyz = q6[4 * my], nzz = q6[5 * my];
-                    const V sx = a[0][r], sy = a[1][r], sz = a[2][r];
-                    a[0][r] = mk<V>(nxx * sx.x + nxy * sy.x + nxz * sz.x, nxx * sx.y + nxy * sy.y + nxz * sz.y);
-                    a[1][r] = mk<V>(nxy * sx.x + nyy * sy.x + nyz * sz.x, nxy * sx.y + nyy * sy.y + nyz * sz.y);
-                    a[2][r] = mk<V>(nxz * sx.x + nyz * sy.x + nzz * sz.x, nxz * sx.y + nyz * sy.y + nzz * sz.y);
-                }
-#pragma unroll
-                for (int c = 0; c < 3; ++c) dft_reg<V, MZ, true>(a[c]);
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-#pragma unroll
-                    for (int zz = 0; zz < MZ; ++zz) {
-                        V v = a[c][zz];
-                        if (hz) v = cmulc(v, wz_pad<V, MZ>(zz, tw));
-                        b[c][zz] = cadd(b[c][zz], v);
-                    }
-            }
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int zz = 0; zz < MZ; ++zz)
-                    if (zz < nz) lines[lds_pad(cbase + (c * nz + zz) * my)] = b[c][zz];
-        }
-        __syncthreads();
-        fft_lines<V, true, kConvRadixBits<T>>(lines, nlines, my, lmy, twl);
-        __syncthreads();
-        if (racc) {
-            int y = yb, r = rb;
-            // opaque copy: keeps the compiler from hoisting all kMaxE
-            // addresses and twiddles out of the y-half loop
-            asm volatile("" : "+v"(y), "+v"(r));
-#pragma unroll
-            for (int i = 0; i < NACC; ++i) {
-                const int e = threadIdx.x + i * kNT;
-                if (e < nel) {
-                    V v = lines[lds_pad(r * my + y)];
-                    if (hy) v = cmulc(v, twl[y]);
-                    acc[i] = cadd(acc[i], v);
-                }
-                y += dy;
-                r += dr;
-                if (y >= ny) { y -= ny; r += 1; }
-            }
-        } else {
-            for (int e = threadIdx.x; e < nel; e += kNT) {
-                const int y = e % ny, r = e / ny;
-                V v = lines[lds_pad(r * my + y)];
-                if (hy) v = cmulc(v, twl[y]);
-                out[e] = hy ? cadd(out[e], v) : v;
-            }
-        }
-        __syncthreads();
-    }
-    if (racc) {
-#pragma unroll
-        for (int i = 0; i < NACC; ++i) {
-            const int e = threadIdx.x + i * kNT;
-            if (e < nel) out[e] = acc[i];
-        }
+    cplx<T>* sm = reinterpret_cast<cplx<T>*>(smem_);
+    // compile-time bodies for y lengths 32..256 and up to 8 layers
+    switch ((SSM_CONV_CT && MZ <= 8) ? p.lmy : 0) {
+    case 5: conv_body<T, MZ, (MZ <= 8 ? 5 : 0)>(p, s0, G, X, Xp, nhat, tw, sm); break;
+    case 6: conv_body<T, MZ, (MZ <= 8 ? 6 : 0)>(p, s0, G, X, Xp, nhat, tw, sm); break;
+    case 7: conv_body<T, MZ, (MZ <= 8 ? 7 : 0)>(p, s0, G, X, Xp, nhat, tw, sm); break;
+    case 8: conv_body<T, MZ, (MZ <= 8 ? 8 : 0)>(p, s0, G, X, Xp, nhat, tw, sm); break;
+    default: conv_body<T, MZ, 0>(p, s0, G, X, Xp, nhat, tw, sm); break;
     }
 }
 
@@ -402,6 +468,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     const int ty = t % p.nty, rest = t / p.nty;
     const int z = rest % p.nz, img = rest / p.nz;
     const int yt = p.yt, hp = yt >> 1, nx = p.nx, ny = p.ny, nz = p.nz, m = p.mx, lm = p.lmx;
+    const int lhp = __ffs(hp) - 1;  // tiles are powers of two
     const int y0 = ty * yt;
     const long long N = p.N;
     V* twl = reinterpret_cast<V*>(smem_);
@@ -413,7 +480,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 #pragma unroll 1
     for (int c = 0; c < 3; ++c) {
         for (int idx = threadIdx.x; idx < (m + 1) * hp; idx += kNT) {
-            const int rp = idx % hp, kx = idx / hp;
+            const int rp = idx & (hp - 1), kx = idx >> lhp;
             const int ya = y0 + 2 * rp;
             const V* src = Xi + (((long long)kx * 3 + c) * nz + z) * ny;
             const V A = (ya < ny) ? src[ya] : mk<V>(0, 0);
@@ -425,10 +492,11 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
             }
         }
         __syncthreads();
-        fft_lines<V, true, SSM_X_RADIX_BITS>(lines, yt, m, lm, twl);
+        fft_lines_x<V, true>(lines, yt, lm, twl);
         __syncthreads();
-        for (int idx = threadIdx.x; idx < hp * nx; idx += kNT) {
-            const int x = idx % nx, rp = idx / nx;
+        for (int idx = threadIdx.x; idx < (hp << lm); idx += kNT) {
+            const int x = idx & (m - 1), rp = idx >> lm;
+            if (x >= nx) continue;
             const V e = lines[lds_pad((2 * rp) * m + x)];
             const V o = cmulc(lines[lds_pad((2 * rp + 1) * m + x)], twl[x]);
             hd[(c * yt + 2 * rp) * nx + x] = e.x + o.x;

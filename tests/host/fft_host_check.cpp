@@ -1,7 +1,8 @@
 // Host check of the LDS FFT passes (paper_1804_07135_amd/csrc/ssm_fft.hpp):
 // runs the same pass code with the 64 lanes of a wavefront emulated in
 // lockstep (every lane reads, then every lane writes) and compares with a
-// naive DFT in long double.  Prints the worst relative error per length.
+// naive DFT in long double, for the runtime-length passes (Pass) and the
+// compile-time ones (PassCT).  Prints the worst relative error per length.
 #include "ssm_fft.hpp"
 
 #include <cmath>
@@ -43,6 +44,41 @@ static void host_fft_lines(V* buf, int nl, int ls, int lm, const V* twl, int max
     }
 }
 
+// the compile-time passes (PassCT), same lockstep emulation
+template <typename V, bool INV, int LM, int MAXB, int LNS>
+static void host_passes_ct(V* buf, int off0, int gl, const V* twl)
+{
+    if constexpr (LNS < LM) {
+        constexpr int bits = fft_next_bits(LM - LNS, MAXB);
+        constexpr int R = 1 << bits;
+        using P = PassCT<V, R, INV, LM, LNS>;
+        std::vector<V> regs(64 * P::B * R);
+        for (int lane = 0; lane < 64; ++lane)
+            P::read(buf, off0, gl, twl, lane, *reinterpret_cast<V(*)[P::B][R]>(&regs[lane * P::B * R]));
+        for (int lane = 0; lane < 64; ++lane)
+            P::write(buf, off0, gl, lane, *reinterpret_cast<V(*)[P::B][R]>(&regs[lane * P::B * R]));
+        host_passes_ct<V, INV, LM, MAXB, LNS + bits>(buf, off0, gl, twl);
+    }
+}
+
+template <typename V, bool INV, int LM, int MAXB>
+static void host_fft_lines_ct(V* buf, int nl, const V* twl)
+{
+    constexpr int lpg = fft_group_lines(LM);
+    for (int g0 = 0; g0 < nl; g0 += lpg)
+        host_passes_ct<V, INV, LM, MAXB, 0>(buf, g0 << LM, nl - g0 < lpg ? nl - g0 : lpg, twl);
+}
+
+template <typename V, bool INV, int MAXB, int LM = 1>
+static void host_fft_ct_dispatch(V* buf, int nl, int lm, const V* twl)
+{
+    if constexpr (LM <= 10) {
+        if (lm == LM) host_fft_lines_ct<V, INV, LM, MAXB>(buf, nl, twl);
+        else host_fft_ct_dispatch<V, INV, MAXB, LM + 1>(buf, nl, lm, twl);
+    }
+}
+
+// maxb < 0: the compile-time passes with cap -maxb (dense layout only)
 template <typename V, bool INV>
 static double check(int lm, int nl, int pad, unsigned seed, int maxb)
 {
@@ -79,7 +115,10 @@ static double check(int lm, int nl, int pad, unsigned seed, int maxb)
             ref[l * ls + k] = mk<V>((S)sr, (S)si);
         }
     }
-    host_fft_lines<V, INV>(buf.data(), nl, ls, lm, twl.data(), maxb);
+    if (maxb > 0) host_fft_lines<V, INV>(buf.data(), nl, ls, lm, twl.data(), maxb);
+    else if (maxb == -2) host_fft_ct_dispatch<V, INV, 2>(buf.data(), nl, lm, twl.data());
+    else if (maxb == -3) host_fft_ct_dispatch<V, INV, 3>(buf.data(), nl, lm, twl.data());
+    else host_fft_ct_dispatch<V, INV, 4>(buf.data(), nl, lm, twl.data());
     double nrm = 0;
     for (int l = 0; l < nl; ++l)
         for (int k = 0; k < m; ++k) {
@@ -94,14 +133,14 @@ static double check(int lm, int nl, int pad, unsigned seed, int maxb)
 int main()
 {
     int bad = 0;
-    for (int maxb = 2; maxb <= 4; ++maxb)
+    for (int maxb : {2, 3, 4, -2, -3, -4})
     for (int lm = 0; lm <= 10; ++lm) {
         // one line, an odd count, and a full group plus a partial one
         const int nls[3] = {1, 3, (1 << (10 - lm)) + (lm < 10 ? 3 : 1)};
         for (int t = 0; t < 3; ++t) {
             const int nl = nls[t];
             if ((long long)nl << (2 * lm) > (1LL << 22)) continue;  // naive DFT cost cap
-            const int pad = t == 1 ? 1 : 0;
+            const int pad = (t == 1 && maxb > 0) ? 1 : 0;
             const double e64f = check<double2, false>(lm, nl, pad, 11 + lm, maxb);
             const double e64i = check<double2, true>(lm, nl, pad, 13 + lm, maxb);
             const double e32f = check<float2, false>(lm, nl, pad, 17 + lm, maxb);

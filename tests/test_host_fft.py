@@ -1,6 +1,7 @@
 """The LDS FFT passes of the HIP kernels, run on the host with the 64 lanes
 of a wavefront emulated in lockstep, against a naive long-double DFT (all
-lengths 1..1024, FP32 and FP64, forward and inverse, every radix cap)."""
+lengths 1..1024, FP32 and FP64, forward and inverse, every radix cap, for the
+runtime-length passes and the compile-time-length ones)."""
 import os
 import shutil
 import subprocess
