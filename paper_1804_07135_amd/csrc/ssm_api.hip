@@ -58,6 +58,7 @@ struct Plan {
     int prec = 0;
     int np = 0;
     int mz = 1;
+    int conv_kinds = 0;               // convolution builds in use (launch_conv)
     size_t tsize = 8;                 // bytes of one spin component
     std::vector<Prob> P;
     std::vector<Tiles> tiles;         // tile shapes in use, per problem
@@ -240,6 +241,7 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec, const std::vector
             pl.geo[i] = it->second;
         }
         pl.mz = p.mz;
+        pl.conv_kinds |= 1 << conv_build(p.mz, p.lmy);
         pl.lds_xf = std::max(pl.lds_xf, lds_xfwd(p, p.ytf, pl.tsize));
         pl.lds_xi = std::max(pl.lds_xi, lds_xinv(p, p.yt, pl.tsize));
         pl.lds_conv = std::max(pl.lds_conv, lds_convg(p, p.gconv, pl.tsize));
@@ -404,7 +406,7 @@ struct Ops {
         });
         if (e != hipSuccess) return e;
         e = timed(c, st, KK_CONV, [&] {
-            return launch_conv<T>(pl.mz, c->P(), pl.np, c->wm_conv(), c->X(), c->Xp(),
+            return launch_conv<T>(pl.mz, pl.conv_kinds, c->P(), pl.np, c->wm_conv(), c->X(), c->Xp(),
                                   c->at<T>(pl.o_nh), tw, done, pl.lds_conv, st);
         });
         if (e != hipSuccess) return e;
@@ -594,7 +596,7 @@ double time_kernel(ssm_ctx* c, int kind, int reps)
         if (kind == KK_XFWD)
             e = launch_xfwd<T>(c->P(), pl.np, c->wm_xf(), s, c->X(), tw, nullptr, pl.lds_xf, c->stream);
         else if (kind == KK_CONV)
-            e = launch_conv<T>(pl.mz, c->P(), pl.np, c->wm_conv(), c->X(), c->Xp(), c->at<T>(pl.o_nh), tw,
+            e = launch_conv<T>(pl.mz, pl.conv_kinds, c->P(), pl.np, c->wm_conv(), c->X(), c->Xp(), c->at<T>(pl.o_nh), tw,
                                nullptr, pl.lds_conv, c->stream);
         else
             e = launch_xinv<T>(c->P(), pl.np, c->wm_xi(), c->Xp(), s, nullptr, nullptr,

@@ -287,6 +287,31 @@ __device__ __forceinline__ void fft_passes_ct(V* buf, int off0, int gl, const V*
     }
 }
 
+// Passes from sub-length 2^LNS while the sub-length stays below 2^LEND
+// (so passes [LNS, LEND) of the schedule; LEND = LM runs all the rest).
+template <typename V, bool INV, int LM, int MAXB, int LNS, int LEND>
+__device__ __forceinline__ void fft_passes_ct_to(V* buf, int off0, int gl, const V* twl, int lane)
+{
+    if constexpr (LNS < LEND) {
+        constexpr int bits = fft_next_bits(LM - LNS, MAXB);
+        constexpr int R = 1 << bits;
+        V v[16 / R][R];
+        PassCT<V, R, INV, LM, LNS>::read(buf, off0, gl, twl, lane, v);
+        wave_sync();
+        PassCT<V, R, INV, LM, LNS>::write(buf, off0, gl, lane, v);
+        wave_sync();
+        fft_passes_ct_to<V, INV, LM, MAXB, LNS + bits, LEND>(buf, off0, gl, twl, lane);
+    }
+}
+
+// log2 sub-length at which the last pass of the schedule starts
+__host__ __device__ constexpr int fft_last_lns(int lm, int maxb)
+{
+    int lns = 0;
+    while (lns + fft_next_bits(lm - lns, maxb) < lm) lns += fft_next_bits(lm - lns, maxb);
+    return lns;
+}
+
 // fft_lines for a line length 2^LM known at compile time (line stride
 // 2^LM).  Same result as fft_lines up to rounding order.
 template <typename V, bool INV, int LM, int MAXB>

@@ -18,6 +18,22 @@ constexpr int kConvElems = kMaxE * kNT;  // complex values per convolution workg
 constexpr int kArcEPT = 8;     // flat elements per thread in the arc-length kernel
 constexpr int kNTerm = 5;      // energy partial slots: E, T_J, T_d, T_ku, T_dip
 
+// The convolution kernel comes in two builds: one with compile-time-length
+// bodies for y lengths 32..256 and up to 8 layers, one with a runtime-length
+// body for every other shape.  They are separate kernels so that each gets
+// its own register allocation; a launch covers a problem with whichever
+// build serves its shape.
+#ifndef SSM_CONV_CT
+#define SSM_CONV_CT 1
+#endif
+__host__ __device__ constexpr bool conv_ct_shape(int mz, int lmy)
+{
+    return SSM_CONV_CT && mz <= 8 && lmy >= 5 && lmy <= 8;
+}
+// build serving a problem: the y length's log2 (5..8) for the compile-time
+// builds, 0 for the runtime-length one
+__host__ __device__ constexpr int conv_build(int mz, int lmy) { return conv_ct_shape(mz, lmy) ? lmy : 0; }
+
 // Kernel kinds (profiling slots; names in the runtime).
 enum KernelKind {
     KK_XFWD = 0, KK_CONV, KK_XINV, KK_ARC, KK_REDUCE, KK_INTERP,
@@ -65,8 +81,9 @@ struct WorkMap {
 template <typename T>
 hipError_t launch_xfwd(const Prob* P, int np, const WorkMap& wm, const T* s, void* X,
                        const void* tw, const int* done, size_t lds, hipStream_t st);
+// kinds: bit b set = some problem takes build b (conv_build)
 template <typename T>
-hipError_t launch_conv(int mz, const Prob* P, int np, const WorkMap& wm, const void* X,
+hipError_t launch_conv(int mz, int kinds, const Prob* P, int np, const WorkMap& wm, const void* X,
                        void* Xp, const T* nhat, const void* tw, const int* done, size_t lds,
                        hipStream_t st);
 // mode bits for the inverse/epilogue kernel

@@ -69,11 +69,7 @@ namespace ssm {
 #ifndef SSM_X_CT_RADIX_BITS
 #define SSM_X_CT_RADIX_BITS 4
 #endif
-// 1: the convolution kernel has compile-time-length bodies for y lengths
-// 32..256 (the others take the runtime-length body); widest pass of those.
-#ifndef SSM_CONV_CT
-#define SSM_CONV_CT 1
-#endif
+// widest pass of the compile-time-length convolution bodies
 #ifndef SSM_CONV_CT_RADIX_BITS
 #define SSM_CONV_CT_RADIX_BITS 4
 #endif
@@ -243,6 +239,199 @@ __device__ __forceinline__ void conv_fft_y(V* lines, int nlines, int lmy, const 
     else fft_lines<V, INV, SSM_CONV_RADIX_BITS>(lines, nlines, 1 << lmy, lmy, twl);
 }
 
+// z-phase of the compile-time-length convolution body: for every column
+// (slice g, y frequency qy) of the G slices in LDS, both z halves of the
+// padded z transform (length-MZ DFTs), the 3x3 kernel-spectrum multiply,
+// the inverse and the sum of the halves.  NZ > 0 fixes nz at compile time.
+template <typename T, int MZ, int LMY, int NZ>
+__device__ __forceinline__ void conv_zphase(const Prob& p, int G, int kx0, int hy, cplx<T>* lines,
+                                            const T* __restrict__ nhat, const cplx<T>* __restrict__ tw)
+{
+    using V = cplx<T>;
+    constexpr int MY = 1 << LMY;
+    const int nz = NZ > 0 ? NZ : p.nz, nhz = p.nhz, nsl_img = p.mx + 1;
+    int col0 = threadIdx.x;
+    asm volatile("" : "+v"(col0));
+    for (int col = col0; col < (G << LMY); col += kNT) {
+        const int g = col >> LMY, qy = col & (MY - 1);
+        int kx = kx0 + g;
+        while (kx >= nsl_img) kx -= nsl_img;
+        const int cbase = ((g * 3 * nz) << LMY) + qy;
+        V b[3][MZ];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int zz = 0; zz < MZ; ++zz) b[c][zz] = mk<V>(0, 0);
+#pragma unroll 1
+        for (int hz = 0; hz < nhz; ++hz) {
+            V a[3][MZ];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int zz = 0; zz < MZ; ++zz) {
+                    V v = (zz < nz) ? lines[lds_pad(cbase + ((c * nz + zz) << LMY))] : mk<V>(0, 0);
+                    if (hz) v = twz<false, V, MZ>(v, zz, tw);
+                    a[c][zz] = v;
+                }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dft_reg<V, MZ, false>(a[c]);
+            const T* nh = nhat + p.nh_off + (((((long long)kx * nhz + hz) * 2 + hy) * MZ) * 6 << LMY) + qy;
+#pragma unroll
+            for (int r = 0; r < MZ; ++r) {
+                const T* q6 = nh + (r * 6 << LMY);
+                if (SSM_CONV_NH_SERIAL) asm volatile("" : "+v"(q6));
+                const T nxx = q6[0], nxy = q6[MY], nxz = q6[2 * MY];
+                const T nyy = q6[3 * MY], nyz = q6[4 * MY], nzz = q6[5 * MY];
+                const V sx = a[0][r], sy = a[1][r], sz = a[2][r];
+                a[0][r] = mk<V>(nxx * sx.x + nxy * sy.x + nxz * sz.x, nxx * sx.y + nxy * sy.y + nxz * sz.y);
+                a[1][r] = mk<V>(nxy * sx.x + nyy * sy.x + nyz * sz.x, nxy * sx.y + nyy * sy.y + nyz * sz.y);
+                a[2][r] = mk<V>(nxz * sx.x + nyz * sy.x + nzz * sz.x, nxz * sx.y + nyz * sy.y + nzz * sz.y);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dft_reg<V, MZ, true>(a[c]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int zz = 0; zz < MZ; ++zz) {
+                    V v = a[c][zz];
+                    if (hz) v = twz<true, V, MZ>(v, zz, tw);
+                    b[c][zz] = cadd(b[c][zz], v);
+                }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int zz = 0; zz < MZ; ++zz)
+                if (zz < nz) lines[lds_pad(cbase + ((c * nz + zz) << LMY))] = b[c][zz];
+    }
+}
+
+// Compile-time-length body (m_y = 2^LMY) of the convolution of G slices.
+// The forward y transform takes its first pass straight from the slice in
+// global memory (zero beyond ny, the odd-half twiddle W^{hy*y} applied on
+// the way) and the inverse writes its last pass straight to the output
+// slice, so the lines visit LDS only between passes and in the z-phase.
+// Lines belong to wavefronts (groups of 1024 elements), so only the z-phase,
+// which reads every line of a column, needs workgroup barriers.
+template <typename T, int MZ, int LMY>
+__device__ __forceinline__ void conv_body_ct(const Prob& p, int s0, int G, const cplx<T>* __restrict__ X,
+                                             cplx<T>* __restrict__ Xp, const T* __restrict__ nhat,
+                                             const cplx<T>* __restrict__ tw, cplx<T>* smem)
+{
+    using V = cplx<T>;
+    constexpr int MB = SSM_CONV_CT_RADIX_BITS;
+    constexpr int MY = 1 << LMY;
+    constexpr int LPG = fft_group_lines(LMY);
+    // first pass (from global) and last pass (to global) of the schedule
+    constexpr int B0 = fft_next_bits(LMY, MB), R0 = 1 << B0;
+    constexpr int LNSL = fft_last_lns(LMY, MB);
+    constexpr int BL = LMY - LNSL, RL = 1 << BL;
+    static_assert(LNSL >= B0, "the y schedule needs at least two passes");
+    using P0 = PassCT<V, R0, false, LMY, 0>;
+    using PL = PassCT<V, RL, true, LMY, LNSL>;
+    const int nsl_img = p.mx + 1;
+    const int nz = p.nz, ny = p.ny, nhz = p.nhz;
+    const int per = 3 * nz * ny, nlines = G * 3 * nz;
+    V* twl = smem;
+    V* lines = twl + 2 * MY;
+    load_twiddles(twl, LMY, tw);
+    const V* in = X + p.x_off + (long long)s0 * per;
+    V* out = Xp + p.x_off + (long long)s0 * per;
+    const int kx0 = s0 % nsl_img;
+    const int wave = threadIdx.x >> 6;
+    constexpr int NW = kNT / 64;
+    __syncthreads();
+
+#pragma unroll 1
+    for (int hy = 0; hy < 2; ++hy) {
+        // per-lane indices are recomputed in every phase (opaque copy) so
+        // that no address stays live across the register-heavy z-phase
+        int lane = threadIdx.x;
+        asm volatile("" : "+v"(lane));
+        lane &= 63;
+        // forward y transform, wavefront-owned line groups
+        for (int g0 = wave * LPG; g0 < nlines; g0 += NW * LPG) {
+            const int gl = min(LPG, nlines - g0);
+            {
+                V v[P0::B][R0];
+#pragma unroll
+                for (int b = 0; b < P0::B; ++b) {
+                    const int g = lane | (b << 6);
+                    if (g < (gl << P0::LQ)) {
+                        const int line = g >> P0::LQ, j = g & (P0::Q - 1);
+                        const V* src = in + (long long)(g0 + line) * ny;
+                        if (ny == MY) {
+#pragma unroll
+                            for (int r = 0; r < R0; ++r) v[b][r] = src[j + r * P0::Q];
+                        } else {
+#pragma unroll
+                            for (int r = 0; r < R0; ++r) {
+                                const int y = j + r * P0::Q;
+                                v[b][r] = (y < ny) ? src[y] : mk<V>(0, 0);
+                            }
+                        }
+                        if (hy) {
+#pragma unroll
+                            for (int r = 0; r < R0; ++r) v[b][r] = cmul(v[b][r], twl[j + r * P0::Q]);
+                        }
+                        dft_reg<V, R0, false>(v[b]);
+                    }
+                }
+                P0::write(lines, g0 << LMY, gl, lane, v);
+                wave_sync();
+            }
+            fft_passes_ct_to<V, false, LMY, MB, B0, LMY>(lines, g0 << LMY, gl, twl, lane);
+        }
+        __syncthreads();
+
+        // z-phase: per column (slice, qy), z DFT halves, 3x3 multiply,
+        // inverse (nz at run time: compile-time offsets make the scheduler
+        // hoist every load of the column and run out of registers)
+        conv_zphase<T, MZ, LMY, 0>(p, G, kx0, hy, lines, nhat, tw);
+        __syncthreads();
+
+        // inverse y transform; the last pass un-twiddles and sums the y
+        // halves in the output slice (hy = 0 writes, hy = 1 adds)
+        lane = threadIdx.x;
+        asm volatile("" : "+v"(lane));
+        lane &= 63;
+        for (int g0 = wave * LPG; g0 < nlines; g0 += NW * LPG) {
+            const int gl = min(LPG, nlines - g0);
+            fft_passes_ct_to<V, true, LMY, MB, 0, LNSL>(lines, g0 << LMY, gl, twl, lane);
+            V v[PL::B][RL];
+            PL::read(lines, g0 << LMY, gl, twl, lane, v);
+#pragma unroll
+            for (int b = 0; b < PL::B; ++b) {
+                const int g = lane | (b << 6);
+                if (g < (gl << PL::LQ)) {
+                    // last pass: j < NS, so the outputs are y = j + r NS
+                    const int line = g >> PL::LQ, j = g & (PL::Q - 1);
+                    V* dst = out + (long long)(g0 + line) * ny;
+                    if (hy) {
+#pragma unroll
+                        for (int r = 0; r < RL; ++r) v[b][r] = cmulc(v[b][r], twl[j + r * PL::NS]);
+                    }
+                    if (ny == MY) {
+#pragma unroll
+                        for (int r = 0; r < RL; ++r) {
+                            const int y = j + r * PL::NS;
+                            dst[y] = hy ? cadd(dst[y], v[b][r]) : v[b][r];
+                        }
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < RL; ++r) {
+                            const int y = j + r * PL::NS;
+                            if (y < ny) dst[y] = hy ? cadd(dst[y], v[b][r]) : v[b][r];
+                        }
+                    }
+                }
+            }
+            // the next forward pass of this group rewrites these lines
+            wave_sync();
+        }
+    }
+}
+
 // The convolution of G slices starting at s0.  LMY > 0 fixes the y length
 // m_y = 2^LMY at compile time (all FFT indexing constant-folds); LMY = 0
 // takes it from the problem.
@@ -396,7 +585,7 @@ __device__ __forceinline__ void conv_body(const Prob& p, int s0, int G, const cp
     }
 }
 
-template <typename T, int MZ>
+template <typename T, int MZ, int BUILD>
 __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && MZ <= 8 ? SSM_CONV_WAVES_F32 : 1, 8))) void k_conv(const Prob* __restrict__ P, int np,
                                               const int* __restrict__ wstart,
                                               const cplx<T>* __restrict__ X,
@@ -408,6 +597,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     const int pi = find_problem(wstart, np, blockIdx.x);
     if (done && done[pi]) return;
     const Prob& p = P[pi];
+    if (conv_build(MZ, p.lmy) != BUILD) return;  // served by another build
     const int w = blockIdx.x - wstart[pi];
     const int nsl_img = p.mx + 1, nsl = p.K * nsl_img;
     int s0, G;
@@ -430,14 +620,8 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         G = min(p.gconv, nsl - s0);
     }
     cplx<T>* sm = reinterpret_cast<cplx<T>*>(smem_);
-    // compile-time bodies for y lengths 32..256 and up to 8 layers
-    switch ((SSM_CONV_CT && MZ <= 8) ? p.lmy : 0) {
-    case 5: conv_body<T, MZ, (MZ <= 8 ? 5 : 0)>(p, s0, G, X, Xp, nhat, tw, sm); break;
-    case 6: conv_body<T, MZ, (MZ <= 8 ? 6 : 0)>(p, s0, G, X, Xp, nhat, tw, sm); break;
-    case 7: conv_body<T, MZ, (MZ <= 8 ? 7 : 0)>(p, s0, G, X, Xp, nhat, tw, sm); break;
-    case 8: conv_body<T, MZ, (MZ <= 8 ? 8 : 0)>(p, s0, G, X, Xp, nhat, tw, sm); break;
-    default: conv_body<T, MZ, 0>(p, s0, G, X, Xp, nhat, tw, sm); break;
-    }
+    if constexpr (BUILD > 0) conv_body_ct<T, MZ, BUILD>(p, s0, G, X, Xp, nhat, tw, sm);
+    else conv_body<T, MZ, 0>(p, s0, G, X, Xp, nhat, tw, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -1126,8 +1310,31 @@ hipError_t launch_xfwd(const Prob* P, int np, const WorkMap& wm, const T* s, voi
     return hipGetLastError();
 }
 
+template <typename T, int MZ, int BUILD>
+static void launch_conv_b(const Prob* P, int np, const WorkMap& wm, const cplx<T>* x, cplx<T>* xp,
+                          const T* nhat, const cplx<T>* t, const int* done, size_t lds, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_conv<T, MZ, BUILD>), dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start, x, xp,
+                       nhat, t, done);
+}
+
+template <typename T, int MZ>
+static hipError_t launch_conv_mz(int kinds, const Prob* P, int np, const WorkMap& wm, const cplx<T>* x,
+                                 cplx<T>* xp, const T* nhat, const cplx<T>* t, const int* done, size_t lds,
+                                 hipStream_t st)
+{
+    if (kinds & 1) launch_conv_b<T, MZ, 0>(P, np, wm, x, xp, nhat, t, done, lds, st);
+    if constexpr (MZ <= 8 && SSM_CONV_CT) {
+        if (kinds & (1 << 5)) launch_conv_b<T, MZ, 5>(P, np, wm, x, xp, nhat, t, done, lds, st);
+        if (kinds & (1 << 6)) launch_conv_b<T, MZ, 6>(P, np, wm, x, xp, nhat, t, done, lds, st);
+        if (kinds & (1 << 7)) launch_conv_b<T, MZ, 7>(P, np, wm, x, xp, nhat, t, done, lds, st);
+        if (kinds & (1 << 8)) launch_conv_b<T, MZ, 8>(P, np, wm, x, xp, nhat, t, done, lds, st);
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
-hipError_t launch_conv(int mz, const Prob* P, int np, const WorkMap& wm, const void* X, void* Xp,
+hipError_t launch_conv(int mz, int kinds, const Prob* P, int np, const WorkMap& wm, const void* X, void* Xp,
                        const T* nhat, const void* tw, const int* done, size_t lds, hipStream_t st)
 {
     if (wm.total == 0) return hipSuccess;
@@ -1135,14 +1342,13 @@ hipError_t launch_conv(int mz, const Prob* P, int np, const WorkMap& wm, const v
     cplx<T>* xp = (cplx<T>*)Xp;
     const cplx<T>* t = (const cplx<T>*)tw;
     switch (mz) {
-    case 1: hipLaunchKernelGGL((k_conv<T, 1>), dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start, x, xp, nhat, t, done); break;
-    case 2: hipLaunchKernelGGL((k_conv<T, 2>), dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start, x, xp, nhat, t, done); break;
-    case 4: hipLaunchKernelGGL((k_conv<T, 4>), dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start, x, xp, nhat, t, done); break;
-    case 8: hipLaunchKernelGGL((k_conv<T, 8>), dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start, x, xp, nhat, t, done); break;
-    case 16: hipLaunchKernelGGL((k_conv<T, 16>), dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start, x, xp, nhat, t, done); break;
+    case 1: return launch_conv_mz<T, 1>(kinds, P, np, wm, x, xp, nhat, t, done, lds, st);
+    case 2: return launch_conv_mz<T, 2>(kinds, P, np, wm, x, xp, nhat, t, done, lds, st);
+    case 4: return launch_conv_mz<T, 4>(kinds, P, np, wm, x, xp, nhat, t, done, lds, st);
+    case 8: return launch_conv_mz<T, 8>(kinds, P, np, wm, x, xp, nhat, t, done, lds, st);
+    case 16: return launch_conv_mz<T, 16>(kinds, P, np, wm, x, xp, nhat, t, done, lds, st);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 template <typename T>
@@ -1255,7 +1461,7 @@ hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st)
 #define SSM_INST(T)                                                                                \
     template hipError_t launch_xfwd<T>(const Prob*, int, const WorkMap&, const T*, void*,         \
                                        const void*, const int*, size_t, hipStream_t);             \
-    template hipError_t launch_conv<T>(int, const Prob*, int, const WorkMap&, const void*, void*, \
+    template hipError_t launch_conv<T>(int, int, const Prob*, int, const WorkMap&, const void*, void*, \
                                        const T*, const void*, const int*, size_t, hipStream_t);   \
     template hipError_t launch_xinv<T>(const Prob*, int, const WorkMap&, const void*, const T*,   \
                                        T*, T*, double*, const void*, const int*, int, double,     \
