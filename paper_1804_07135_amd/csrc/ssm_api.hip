@@ -78,17 +78,26 @@ struct Plan {
 // the padded layout of ssm_fft.hpp (+ the tile's real field for k_xinv).
 size_t lds_xfwd(const Prob& p, int yt, size_t tsize)
 {
-    return (size_t)(2 * p.mx + lds_padded_size(yt * p.mx)) * 2 * tsize;
+    const int n = yt * p.mx;
+    const int lines = x_padl(p.lmx) ? padded_len(n, x_padl(p.lmx)) : lds_padded_size(n);
+    return (size_t)(2 * p.mx + lines) * 2 * tsize;
 }
 
 size_t lds_xinv(const Prob& p, int yt, size_t tsize)
 {
-    return (size_t)(2 * p.mx + lds_padded_size(yt * p.mx)) * 2 * tsize + (size_t)3 * yt * p.nx * tsize;
+    const int n = yt * p.mx;
+    const int lines = x_padl(p.lmx) ? padded_len(n, x_padl(p.lmx)) : lds_padded_size(n);
+    return (size_t)(2 * p.mx + lines) * 2 * tsize + (size_t)3 * yt * p.nx * tsize;
 }
 
 size_t lds_convg(const Prob& p, int G, size_t tsize)
 {
-    return (size_t)(2 * p.my + lds_padded_size(G * 3 * p.nz * p.my)) * 2 * tsize;
+    const int n = G * 3 * p.nz * p.my;
+    if (conv_ct_shape(p.mz, p.lmy)) {
+        const int tw = conv_tw_lds(p.mz, p.lmy) ? 2 * p.my : 0;
+        return (size_t)(tw + padded_len(n, conv_padl(p.mz, p.lmy))) * 2 * tsize;
+    }
+    return (size_t)(2 * p.my + lds_padded_size(n)) * 2 * tsize;
 }
 
 ssm_status check_problems(const ssm_problem* pr, int np, int prec, std::string& err)

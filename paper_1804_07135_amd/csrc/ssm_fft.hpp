@@ -157,16 +157,39 @@ struct Pass {
     }
 };
 
+// Physical index of element i in a line buffer with one pad element after
+// every 2^PADL (PADL = 0: dense).  Pads spread the strided Stockham
+// accesses over the LDS banks.
+template <int PADL>
+__host__ __device__ __forceinline__ int padx(int i) { return PADL ? i + (i >> PADL) : i; }
+// pad log2 used for lines of length 2^LM: at most the line length, so that
+// every line starts at a multiple of the pad unit
+__host__ __device__ constexpr int pad_for(int padl, int lm) { return padl == 0 ? 0 : (padl < lm ? padl : lm); }
+
 // One radix-R pass as above with the line length 2^LM, the sub-transform
 // length 2^LNS and the line stride 2^LM fixed at compile time: every index
 // is a per-lane base plus constant offsets.  Groups hold 1024 elements, so
-// butterfly b of a lane is g = lane + 64 b.
-template <typename V, int R, bool INV, int LM, int LNS>
+// butterfly b of a lane is g = lane + 64 b.  Lines are stored with pad
+// log2 PADL (padx); the element offsets a pass adds to its per-lane base
+// never cross a pad boundary differently from the offset itself, so
+// padx(i0 + o) = padx(i0) + o + (o >> PADL).  Twiddle e of W_{2^(LM+1)} is
+// twl[e << TWS] (TWS = 0: a table of exactly 2^(LM+1) entries).
+// XOR swizzle of the low 4 index bits with the next 4 (a permutation within
+// every aligned block of 256 elements): the handoff between the two radix-16
+// passes of a length-256 transform is a 16x16 transpose, and the swizzle lets
+// both its strided side and its contiguous side hit distinct LDS banks.
+__host__ __device__ __forceinline__ int swz16(int i) { return i ^ ((i >> 4) & 15); }
+
+template <typename V, int R, bool INV, int LM, int LNS, int PADL = 0, int TWS = 0, bool SWR = false,
+          bool SWW = false>
 struct PassCT {
     static constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
     static constexpr int B = 16 / R;
-    static constexpr int LQ = LM - LR, Q = 1 << LQ, NS = 1 << LNS, TSH = LM + 1 - LNS - LR;
+    static constexpr int LQ = LM - LR, Q = 1 << LQ, NS = 1 << LNS, TSH = LM + 1 - LNS - LR + TWS;
     static_assert(LM <= 10 && LR <= LM - LNS, "pass does not fit the line");
+    static_assert(PADL == 0 || PADL <= LM, "pad unit longer than a line");
+    static_assert(!(SWR || SWW) || (PADL == 0 && LM >= 8), "swizzle needs dense lines of >= 256");
+    static constexpr int po(int o) { return PADL ? o + (o >> PADL) : o; }
 
     __host__ __device__ static void read(const V* buf, int off0, int gl, const V* twl, int lane,
                                          V (&v)[B][R])
@@ -177,9 +200,15 @@ struct PassCT {
             const int g = lane | (b << 6);
             if (g < nbf) {
                 const int line = g >> LQ, j = g & (Q - 1), k = j & (NS - 1);
-                const int i0 = off0 + (line << LM) + j;
+                if constexpr (SWR) {
+                    const int i0 = off0 + (line << LM) + j;
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[b][r] = buf[lds_pad(i0 + r * Q)];
+                    for (int r = 0; r < R; ++r) v[b][r] = buf[swz16(i0 + r * Q)];
+                } else {
+                    const V* base = buf + padx<PADL>(off0 + (line << LM) + j);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) v[b][r] = base[po(r * Q)];
+                }
                 if (LNS > 0) {
 #pragma unroll
                     for (int r = 1; r < R; ++r) v[b][r] = twm<INV>(v[b][r], twl[(r * k) << TSH]);
@@ -197,9 +226,15 @@ struct PassCT {
             const int g = lane | (b << 6);
             if (g < nbf) {
                 const int line = g >> LQ, j = g & (Q - 1), k = j & (NS - 1);
-                const int i0 = off0 + (line << LM) + ((j >> LNS) << (LNS + LR)) + k;
+                if constexpr (SWW) {
+                    const int i0 = off0 + (line << LM) + ((j >> LNS) << (LNS + LR)) + k;
 #pragma unroll
-                for (int r = 0; r < R; ++r) buf[lds_pad(i0 + r * NS)] = v[b][r];
+                    for (int r = 0; r < R; ++r) buf[swz16(i0 + r * NS)] = v[b][r];
+                } else {
+                    V* base = buf + padx<PADL>(off0 + (line << LM) + ((j >> LNS) << (LNS + LR)) + k);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) base[po(r * NS)] = v[b][r];
+                }
             }
         }
     }
@@ -270,37 +305,24 @@ __device__ __forceinline__ void fft_lines(V* buf, int nl, int ls, int lm, const 
     }
 }
 
-// The passes of a length-2^LM transform over one group, all sizes fixed at
-// compile time (radix schedule as fft_next_bits with cap MAXB).
-template <typename V, bool INV, int LM, int MAXB, int LNS>
-__device__ __forceinline__ void fft_passes_ct(V* buf, int off0, int gl, const V* twl, int lane)
-{
-    if constexpr (LNS < LM) {
-        constexpr int bits = fft_next_bits(LM - LNS, MAXB);
-        constexpr int R = 1 << bits;
-        V v[16 / R][R];
-        PassCT<V, R, INV, LM, LNS>::read(buf, off0, gl, twl, lane, v);
-        wave_sync();
-        PassCT<V, R, INV, LM, LNS>::write(buf, off0, gl, lane, v);
-        wave_sync();
-        fft_passes_ct<V, INV, LM, MAXB, LNS + bits>(buf, off0, gl, twl, lane);
-    }
-}
-
 // Passes from sub-length 2^LNS while the sub-length stays below 2^LEND
 // (so passes [LNS, LEND) of the schedule; LEND = LM runs all the rest).
-template <typename V, bool INV, int LM, int MAXB, int LNS, int LEND>
+// SW: the swizzled handoff (swz16) between the passes starting at LNS = 0
+// and LNS = 4: the first pass writes swizzled, the second reads swizzled.
+template <typename V, bool INV, int LM, int MAXB, int LNS, int LEND, int PADL = 0, int TWS = 0, bool SW = false>
 __device__ __forceinline__ void fft_passes_ct_to(V* buf, int off0, int gl, const V* twl, int lane)
 {
+    static_assert(!SW || fft_next_bits(LM, MAXB) == 4, "swizzled handoff needs a radix-16 first pass");
     if constexpr (LNS < LEND) {
         constexpr int bits = fft_next_bits(LM - LNS, MAXB);
         constexpr int R = 1 << bits;
+        using P = PassCT<V, R, INV, LM, LNS, PADL, TWS, SW && LNS == 4, SW && LNS == 0>;
         V v[16 / R][R];
-        PassCT<V, R, INV, LM, LNS>::read(buf, off0, gl, twl, lane, v);
+        P::read(buf, off0, gl, twl, lane, v);
         wave_sync();
-        PassCT<V, R, INV, LM, LNS>::write(buf, off0, gl, lane, v);
+        P::write(buf, off0, gl, lane, v);
         wave_sync();
-        fft_passes_ct_to<V, INV, LM, MAXB, LNS + bits, LEND>(buf, off0, gl, twl, lane);
+        fft_passes_ct_to<V, INV, LM, MAXB, LNS + bits, LEND, PADL, TWS, SW>(buf, off0, gl, twl, lane);
     }
 }
 
@@ -312,9 +334,9 @@ __host__ __device__ constexpr int fft_last_lns(int lm, int maxb)
     return lns;
 }
 
-// fft_lines for a line length 2^LM known at compile time (line stride
-// 2^LM).  Same result as fft_lines up to rounding order.
-template <typename V, bool INV, int LM, int MAXB>
+// fft_lines for a line length 2^LM known at compile time (line stride 2^LM
+// in the pad-PADL layout).  Same result as fft_lines up to rounding order.
+template <typename V, bool INV, int LM, int MAXB, int PADL = 0>
 __device__ __forceinline__ void fft_lines_ct(V* buf, int nl, const V* twl)
 {
     if constexpr (LM > 0) {
@@ -326,7 +348,7 @@ __device__ __forceinline__ void fft_lines_ct(V* buf, int nl, const V* twl)
         const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
         constexpr int LPG = fft_group_lines(LM);
         for (int g0 = wave * LPG; g0 < nl; g0 += nw * LPG)
-            fft_passes_ct<V, INV, LM, MAXB, 0>(buf, g0 << LM, min(LPG, nl - g0), twl, lane);
+            fft_passes_ct_to<V, INV, LM, MAXB, 0, LM, PADL, 0>(buf, g0 << LM, min(LPG, nl - g0), twl, lane);
     }
 }
 

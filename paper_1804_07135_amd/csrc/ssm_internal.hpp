@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ssm_fft.hpp"
+
 namespace ssm {
 
 // Twiddle table: tw[e] = exp(-2 pi i e / kTwM).  A length-L root W_L^e is
@@ -33,6 +35,33 @@ __host__ __device__ constexpr bool conv_ct_shape(int mz, int lmy)
 // build serving a problem: the y length's log2 (5..8) for the compile-time
 // builds, 0 for the runtime-length one
 __host__ __device__ constexpr int conv_build(int mz, int lmy) { return conv_ct_shape(mz, lmy) ? lmy : 0; }
+
+// LDS layout of the line buffers (pad_for, padx in ssm_fft.hpp).  The
+// compile-time-length transforms store lines with one pad element per
+// 2^PADL, which spreads their strided accesses over the banks; the
+// runtime-length ones use the dense layout.  The compile-time convolution
+// can also read its twiddles from the global table instead of an LDS copy.
+#ifndef SSM_X_CT
+#define SSM_X_CT 1
+#endif
+#ifndef SSM_X_PADL
+#define SSM_X_PADL 4
+#endif
+#ifndef SSM_CONV_PADL
+#define SSM_CONV_PADL 0
+#endif
+#ifndef SSM_CONV_TW_GLOBAL
+#define SSM_CONV_TW_GLOBAL 0
+#endif
+__host__ __device__ constexpr bool x_ct_len(int lm) { return SSM_X_CT && lm >= 5 && lm <= 9; }
+__host__ __device__ constexpr int x_padl(int lm) { return x_ct_len(lm) ? pad_for(SSM_X_PADL, lm) : 0; }
+__host__ __device__ constexpr int conv_padl(int mz, int lmy)
+{
+    return conv_ct_shape(mz, lmy) ? pad_for(SSM_CONV_PADL, lmy) : 0;
+}
+__host__ __device__ constexpr bool conv_tw_lds(int mz, int lmy) { return !(conv_ct_shape(mz, lmy) && SSM_CONV_TW_GLOBAL); }
+// elements of a buffer of n elements in the pad-padl layout
+__host__ __device__ constexpr int padded_len(int n, int padl) { return padl ? n + (n >> padl) + 1 : n; }
 
 // Kernel kinds (profiling slots; names in the runtime).
 enum KernelKind {

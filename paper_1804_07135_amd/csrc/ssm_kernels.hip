@@ -61,13 +61,13 @@ namespace ssm {
 #ifndef SSM_CONV_REG_ACC
 #define SSM_CONV_REG_ACC 0
 #endif
-// 1: the x kernels use compile-time-length FFT passes for x lengths
-// 32..512; widest pass of those.
-#ifndef SSM_X_CT
-#define SSM_X_CT 1
-#endif
+// widest pass of the compile-time-length x transforms (x lengths 32..512)
 #ifndef SSM_X_CT_RADIX_BITS
 #define SSM_X_CT_RADIX_BITS 4
+#endif
+// 1: swizzled LDS handoff between the radix-16 passes (y length 256)
+#ifndef SSM_CONV_SWZ
+#define SSM_CONV_SWZ 1
 #endif
 // widest pass of the compile-time-length convolution bodies
 #ifndef SSM_CONV_CT_RADIX_BITS
@@ -122,16 +122,17 @@ __device__ __forceinline__ T wave_max(T v)
 }
 
 // Transform of nl lines of length 2^lm (stride 2^lm): compile-time-length
-// passes for lengths 32..512, runtime-length passes otherwise.
+// passes for lengths 32..512 (pad layout x_padl(lm)), runtime-length passes
+// (dense layout) otherwise.
 template <typename V, bool INV>
 __device__ __forceinline__ void fft_lines_x(V* lines, int nl, int lm, const V* twl)
 {
     switch (SSM_X_CT ? lm : 0) {
-    case 5: fft_lines_ct<V, INV, 5, SSM_X_CT_RADIX_BITS>(lines, nl, twl); break;
-    case 6: fft_lines_ct<V, INV, 6, SSM_X_CT_RADIX_BITS>(lines, nl, twl); break;
-    case 7: fft_lines_ct<V, INV, 7, SSM_X_CT_RADIX_BITS>(lines, nl, twl); break;
-    case 8: fft_lines_ct<V, INV, 8, SSM_X_CT_RADIX_BITS>(lines, nl, twl); break;
-    case 9: fft_lines_ct<V, INV, 9, SSM_X_CT_RADIX_BITS>(lines, nl, twl); break;
+    case 5: fft_lines_ct<V, INV, 5, SSM_X_CT_RADIX_BITS, pad_for(SSM_X_PADL, 5)>(lines, nl, twl); break;
+    case 6: fft_lines_ct<V, INV, 6, SSM_X_CT_RADIX_BITS, pad_for(SSM_X_PADL, 6)>(lines, nl, twl); break;
+    case 7: fft_lines_ct<V, INV, 7, SSM_X_CT_RADIX_BITS, pad_for(SSM_X_PADL, 7)>(lines, nl, twl); break;
+    case 8: fft_lines_ct<V, INV, 8, SSM_X_CT_RADIX_BITS, pad_for(SSM_X_PADL, 8)>(lines, nl, twl); break;
+    case 9: fft_lines_ct<V, INV, 9, SSM_X_CT_RADIX_BITS, pad_for(SSM_X_PADL, 9)>(lines, nl, twl); break;
     default: fft_lines<V, INV, SSM_X_RADIX_BITS>(lines, nl, 1 << lm, lm, twl); break;
     }
 }
@@ -162,6 +163,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     const int z = rest % p.nz, img = rest / p.nz;
     const int yt = p.ytf, hp = yt >> 1, nx = p.nx, ny = p.ny, nz = p.nz, m = p.mx, lm = p.lmx;
     const int lhp = __ffs(hp) - 1;  // tiles are powers of two
+    const int psh = x_padl(lm) ? x_padl(lm) : 31;  // pad layout of the lines
     V* twl = reinterpret_cast<V*>(smem_);
     V* lines = twl + 2 * m;
     load_twiddles(twl, lm, tw);
@@ -182,8 +184,9 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
                 if (ya + 1 < ny) b = sc[(long long)(ya + 1) * nx + j];
             }
             const V v = mk<V>(a, b);
-            lines[lds_pad((2 * rp) * m + j)] = v;
-            lines[lds_pad((2 * rp + 1) * m + j)] = cmul(v, twl[j]);
+            const int i0 = (2 * rp) * m + j, i1 = i0 + m;
+            lines[i0 + (i0 >> psh)] = v;
+            lines[i1 + (i1 >> psh)] = cmul(v, twl[j]);
         }
         __syncthreads();
         fft_lines_x<V, false>(lines, yt, lm, twl);
@@ -191,8 +194,9 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         for (int idx = threadIdx.x; idx < (m + 1) * hp; idx += kNT) {
             const int rp = idx & (hp - 1), kx = idx >> lhp;
             const int kr = (P2 - kx) & (P2 - 1);
-            const V Z = lines[lds_pad((2 * rp + (kx & 1)) * m + (kx >> 1))];
-            const V Zr = lines[lds_pad((2 * rp + (kr & 1)) * m + (kr >> 1))];
+            const int iz = (2 * rp + (kx & 1)) * m + (kx >> 1), ir = (2 * rp + (kr & 1)) * m + (kr >> 1);
+            const V Z = lines[iz + (iz >> psh)];
+            const V Zr = lines[ir + (ir >> psh)];
             const T hlf = T(0.5);
             const V A = mk<V>((Z.x + Zr.x) * hlf, (Z.y - Zr.y) * hlf);
             const V B = mk<V>((Z.y + Zr.y) * hlf, (Zr.x - Z.x) * hlf);
@@ -243,7 +247,7 @@ __device__ __forceinline__ void conv_fft_y(V* lines, int nlines, int lmy, const 
 // (slice g, y frequency qy) of the G slices in LDS, both z halves of the
 // padded z transform (length-MZ DFTs), the 3x3 kernel-spectrum multiply,
 // the inverse and the sum of the halves.  NZ > 0 fixes nz at compile time.
-template <typename T, int MZ, int LMY, int NZ>
+template <typename T, int MZ, int LMY, int NZ, int PADL>
 __device__ __forceinline__ void conv_zphase(const Prob& p, int G, int kx0, int hy, cplx<T>* lines,
                                             const T* __restrict__ nhat, const cplx<T>* __restrict__ tw)
 {
@@ -256,7 +260,9 @@ __device__ __forceinline__ void conv_zphase(const Prob& p, int G, int kx0, int h
         const int g = col >> LMY, qy = col & (MY - 1);
         int kx = kx0 + g;
         while (kx >= nsl_img) kx -= nsl_img;
-        const int cbase = ((g * 3 * nz) << LMY) + qy;
+        // padded offsets: cbase % 2^PADL = qy % 2^PADL and the line offsets
+        // are multiples of the line length, so padx distributes
+        const int cbase = padx<PADL>(((g * 3 * nz) << LMY) + qy);
         V b[3][MZ];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
@@ -269,7 +275,7 @@ __device__ __forceinline__ void conv_zphase(const Prob& p, int G, int kx0, int h
             for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int zz = 0; zz < MZ; ++zz) {
-                    V v = (zz < nz) ? lines[lds_pad(cbase + ((c * nz + zz) << LMY))] : mk<V>(0, 0);
+                    V v = (zz < nz) ? lines[cbase + padx<PADL>((c * nz + zz) << LMY)] : mk<V>(0, 0);
                     if (hz) v = twz<false, V, MZ>(v, zz, tw);
                     a[c][zz] = v;
                 }
@@ -302,7 +308,7 @@ __device__ __forceinline__ void conv_zphase(const Prob& p, int G, int kx0, int h
         for (int c = 0; c < 3; ++c)
 #pragma unroll
             for (int zz = 0; zz < MZ; ++zz)
-                if (zz < nz) lines[lds_pad(cbase + ((c * nz + zz) << LMY))] = b[c][zz];
+                if (zz < nz) lines[cbase + padx<PADL>((c * nz + zz) << LMY)] = b[c][zz];
     }
 }
 
@@ -327,14 +333,28 @@ __device__ __forceinline__ void conv_body_ct(const Prob& p, int s0, int G, const
     constexpr int LNSL = fft_last_lns(LMY, MB);
     constexpr int BL = LMY - LNSL, RL = 1 << BL;
     static_assert(LNSL >= B0, "the y schedule needs at least two passes");
-    using P0 = PassCT<V, R0, false, LMY, 0>;
-    using PL = PassCT<V, RL, true, LMY, LNSL>;
+    // pad layout and twiddle source (LDS copy of W_{2 m_y}, or the global
+    // W_{kTwM} table read at stride 2^TWS)
+    constexpr int PADL = conv_padl(MZ, LMY);
+    constexpr bool TWL = conv_tw_lds(MZ, LMY);
+    constexpr int TWS = TWL ? 0 : kTwLog - 1 - LMY;
+    // swizzled handoff between the two radix-16 passes of length 256
+    constexpr bool SW = SSM_CONV_SWZ && PADL == 0 && LMY == 8 && MB == 4;
+    using P0 = PassCT<V, R0, false, LMY, 0, PADL, TWS, false, SW>;
+    using PL = PassCT<V, RL, true, LMY, LNSL, PADL, TWS, SW, false>;
     const int nsl_img = p.mx + 1;
     const int nz = p.nz, ny = p.ny, nhz = p.nhz;
     const int per = 3 * nz * ny, nlines = G * 3 * nz;
-    V* twl = smem;
-    V* lines = twl + 2 * MY;
-    load_twiddles(twl, LMY, tw);
+    const V* twl;
+    V* lines;
+    if constexpr (TWL) {
+        load_twiddles(smem, LMY, tw);
+        twl = smem;
+        lines = smem + 2 * MY;
+    } else {
+        twl = tw;
+        lines = smem;
+    }
     const V* in = X + p.x_off + (long long)s0 * per;
     V* out = Xp + p.x_off + (long long)s0 * per;
     const int kx0 = s0 % nsl_img;
@@ -372,7 +392,7 @@ __device__ __forceinline__ void conv_body_ct(const Prob& p, int s0, int G, const
                         }
                         if (hy) {
 #pragma unroll
-                            for (int r = 0; r < R0; ++r) v[b][r] = cmul(v[b][r], twl[j + r * P0::Q]);
+                            for (int r = 0; r < R0; ++r) v[b][r] = cmul(v[b][r], twl[(j + r * P0::Q) << TWS]);
                         }
                         dft_reg<V, R0, false>(v[b]);
                     }
@@ -380,14 +400,14 @@ __device__ __forceinline__ void conv_body_ct(const Prob& p, int s0, int G, const
                 P0::write(lines, g0 << LMY, gl, lane, v);
                 wave_sync();
             }
-            fft_passes_ct_to<V, false, LMY, MB, B0, LMY>(lines, g0 << LMY, gl, twl, lane);
+            fft_passes_ct_to<V, false, LMY, MB, B0, LMY, PADL, TWS, SW>(lines, g0 << LMY, gl, twl, lane);
         }
         __syncthreads();
 
         // z-phase: per column (slice, qy), z DFT halves, 3x3 multiply,
         // inverse (nz at run time: compile-time offsets make the scheduler
         // hoist every load of the column and run out of registers)
-        conv_zphase<T, MZ, LMY, 0>(p, G, kx0, hy, lines, nhat, tw);
+        conv_zphase<T, MZ, LMY, 0, PADL>(p, G, kx0, hy, lines, nhat, tw);
         __syncthreads();
 
         // inverse y transform; the last pass un-twiddles and sums the y
@@ -397,7 +417,7 @@ __device__ __forceinline__ void conv_body_ct(const Prob& p, int s0, int G, const
         lane &= 63;
         for (int g0 = wave * LPG; g0 < nlines; g0 += NW * LPG) {
             const int gl = min(LPG, nlines - g0);
-            fft_passes_ct_to<V, true, LMY, MB, 0, LNSL>(lines, g0 << LMY, gl, twl, lane);
+            fft_passes_ct_to<V, true, LMY, MB, 0, LNSL, PADL, TWS, SW>(lines, g0 << LMY, gl, twl, lane);
             V v[PL::B][RL];
             PL::read(lines, g0 << LMY, gl, twl, lane, v);
 #pragma unroll
@@ -409,7 +429,7 @@ __device__ __forceinline__ void conv_body_ct(const Prob& p, int s0, int G, const
                     V* dst = out + (long long)(g0 + line) * ny;
                     if (hy) {
 #pragma unroll
-                        for (int r = 0; r < RL; ++r) v[b][r] = cmulc(v[b][r], twl[j + r * PL::NS]);
+                        for (int r = 0; r < RL; ++r) v[b][r] = cmulc(v[b][r], twl[(j + r * PL::NS) << TWS]);
                     }
                     if (ny == MY) {
 #pragma unroll
@@ -653,11 +673,12 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     const int z = rest % p.nz, img = rest / p.nz;
     const int yt = p.yt, hp = yt >> 1, nx = p.nx, ny = p.ny, nz = p.nz, m = p.mx, lm = p.lmx;
     const int lhp = __ffs(hp) - 1;  // tiles are powers of two
+    const int psh = x_padl(lm) ? x_padl(lm) : 31;  // pad layout of the lines
     const int y0 = ty * yt;
     const long long N = p.N;
     V* twl = reinterpret_cast<V*>(smem_);
     V* lines = twl + 2 * m;
-    T* hd = reinterpret_cast<T*>(lines + lds_padded_size(yt * m));
+    T* hd = reinterpret_cast<T*>(lines + padded_len(yt * m, x_padl(lm)));
     load_twiddles(twl, lm, tw);
     const V* Xi = Xp + p.x_off + (long long)img * (m + 1) * 3 * nz * ny;
     __syncthreads();
@@ -669,10 +690,12 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
             const V* src = Xi + (((long long)kx * 3 + c) * nz + z) * ny;
             const V A = (ya < ny) ? src[ya] : mk<V>(0, 0);
             const V B = (ya + 1 < ny) ? src[ya + 1] : mk<V>(0, 0);
-            lines[lds_pad((2 * rp + (kx & 1)) * m + (kx >> 1))] = mk<V>(A.x - B.y, A.y + B.x);
+            const int i0 = (2 * rp + (kx & 1)) * m + (kx >> 1);
+            lines[i0 + (i0 >> psh)] = mk<V>(A.x - B.y, A.y + B.x);
             if (kx > 0 && kx < m) {
                 const int km = 2 * m - kx;
-                lines[lds_pad((2 * rp + (km & 1)) * m + (km >> 1))] = mk<V>(A.x + B.y, B.x - A.y);
+                const int i1 = (2 * rp + (km & 1)) * m + (km >> 1);
+                lines[i1 + (i1 >> psh)] = mk<V>(A.x + B.y, B.x - A.y);
             }
         }
         __syncthreads();
@@ -681,8 +704,9 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         for (int idx = threadIdx.x; idx < (hp << lm); idx += kNT) {
             const int x = idx & (m - 1), rp = idx >> lm;
             if (x >= nx) continue;
-            const V e = lines[lds_pad((2 * rp) * m + x)];
-            const V o = cmulc(lines[lds_pad((2 * rp + 1) * m + x)], twl[x]);
+            const int ie = (2 * rp) * m + x, io = ie + m;
+            const V e = lines[ie + (ie >> psh)];
+            const V o = cmulc(lines[io + (io >> psh)], twl[x]);
             hd[(c * yt + 2 * rp) * nx + x] = e.x + o.x;
             hd[(c * yt + 2 * rp + 1) * nx + x] = e.y + o.y;
         }

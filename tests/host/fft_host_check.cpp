@@ -45,40 +45,129 @@ static void host_fft_lines(V* buf, int nl, int ls, int lm, const V* twl, int max
 }
 
 // the compile-time passes (PassCT), same lockstep emulation
-template <typename V, bool INV, int LM, int MAXB, int LNS>
+template <typename V, bool INV, int LM, int MAXB, int LNS, int PADL, int TWS, bool SW = false>
 static void host_passes_ct(V* buf, int off0, int gl, const V* twl)
 {
     if constexpr (LNS < LM) {
         constexpr int bits = fft_next_bits(LM - LNS, MAXB);
         constexpr int R = 1 << bits;
-        using P = PassCT<V, R, INV, LM, LNS>;
+        using P = PassCT<V, R, INV, LM, LNS, PADL, TWS, SW && LNS == 4, SW && LNS == 0>;
         std::vector<V> regs(64 * P::B * R);
         for (int lane = 0; lane < 64; ++lane)
             P::read(buf, off0, gl, twl, lane, *reinterpret_cast<V(*)[P::B][R]>(&regs[lane * P::B * R]));
         for (int lane = 0; lane < 64; ++lane)
             P::write(buf, off0, gl, lane, *reinterpret_cast<V(*)[P::B][R]>(&regs[lane * P::B * R]));
-        host_passes_ct<V, INV, LM, MAXB, LNS + bits>(buf, off0, gl, twl);
+        host_passes_ct<V, INV, LM, MAXB, LNS + bits, PADL, TWS, SW>(buf, off0, gl, twl);
     }
 }
 
-template <typename V, bool INV, int LM, int MAXB>
-static void host_fft_lines_ct(V* buf, int nl, const V* twl)
+// naive DFT of every line of buf (element (l, j) at idx(l * m + j))
+template <typename V, bool INV, typename F>
+static std::vector<V> naive(const std::vector<V>& buf, int nl, int lm, F idx)
 {
+    using S = decltype(V::x);
+    const int m = 1 << lm;
+    std::vector<V> ref((size_t)nl * m);
+    std::vector<long double> cs(m), sn(m);
+    for (int e = 0; e < m; ++e) {
+        const long double th = (INV ? 2.0L : -2.0L) * 3.14159265358979323846264338327950288L * e / m;
+        cs[e] = cosl(th);
+        sn[e] = sinl(th);
+    }
+    for (int l = 0; l < nl; ++l)
+        for (int k = 0; k < m; ++k) {
+            long double sr = 0, si = 0;
+            for (int j = 0; j < m; ++j) {
+                const int e = (int)((long long)j * k % m);
+                const V x = buf[idx(l * m + j)];
+                sr += x.x * cs[e] - x.y * sn[e];
+                si += x.x * sn[e] + x.y * cs[e];
+            }
+            ref[(size_t)l * m + k] = mk<V>((S)sr, (S)si);
+        }
+    return ref;
+}
+
+// compile-time passes over nl lines of 2^LM in the pad-PADL layout, with the
+// twiddles read at stride 2^TWS from a longer table
+template <typename V, bool INV, int LM, int MAXB, int PADL, int TWS, bool SW = false>
+static double check_ct(int nl, unsigned seed)
+{
+    using S = decltype(V::x);
+    const int m = 1 << LM;
+    const int nt = (2 * m) << TWS;
+    std::vector<V> twl(nt);
+    for (int e = 0; e < nt; ++e) {
+        const long double th = 2.0L * 3.14159265358979323846264338327950288L * e / nt;
+        twl[e] = mk<V>((S)cosl(th), (S)-sinl(th));
+    }
+    std::mt19937 rng(seed);
+    std::normal_distribution<double> nd;
+    const int n = nl * m;
+    // sentinel-filled buffer: pad slots must stay untouched
+    std::vector<V> buf(padx<PADL>(n - 1) + 1, mk<V>((S)1e30, (S)1e30));
+    for (int i = 0; i < n; ++i) buf[padx<PADL>(i)] = mk<V>((S)nd(rng), (S)nd(rng));
+    const std::vector<V> ref = naive<V, INV>(buf, nl, LM, [](int i) { return padx<PADL>(i); });
     constexpr int lpg = fft_group_lines(LM);
     for (int g0 = 0; g0 < nl; g0 += lpg)
-        host_passes_ct<V, INV, LM, MAXB, 0>(buf, g0 << LM, nl - g0 < lpg ? nl - g0 : lpg, twl);
-}
-
-template <typename V, bool INV, int MAXB, int LM = 1>
-static void host_fft_ct_dispatch(V* buf, int nl, int lm, const V* twl)
-{
-    if constexpr (LM <= 10) {
-        if (lm == LM) host_fft_lines_ct<V, INV, LM, MAXB>(buf, nl, twl);
-        else host_fft_ct_dispatch<V, INV, MAXB, LM + 1>(buf, nl, lm, twl);
+        host_passes_ct<V, INV, LM, MAXB, 0, PADL, TWS, SW>(buf.data(), g0 << LM, nl - g0 < lpg ? nl - g0 : lpg,
+                                                          twl.data());
+    double worst = 0, nrm = 0;
+    for (int i = 0; i < n; ++i) {
+        const V a = buf[padx<PADL>(i)], b = ref[i];
+        worst = fmax(worst, fabs((double)a.x - (double)b.x));
+        worst = fmax(worst, fabs((double)a.y - (double)b.y));
+        nrm = fmax(nrm, fabs((double)b.x) + fabs((double)b.y));
     }
+    for (int i = 0; i < (int)buf.size(); ++i) {
+        bool data = false;
+        // a slot is data iff it is padx of some element; pads keep the sentinel
+        if (PADL == 0) data = true;
+        else {
+            const int e = i - i / ((1 << PADL) + 1);
+            data = padx<PADL>(e) == i;
+        }
+        if (!data && buf[i].x != (S)1e30) return 1e30;
+    }
+    return worst / (nrm > 0 ? nrm : 1);
 }
 
-// maxb < 0: the compile-time passes with cap -maxb (dense layout only)
+template <int LM, int MAXB, int PADL, int TWS, bool SW = false>
+static int run_ct()
+{
+    int bad = 0;
+    const int nls[3] = {1, 3, fft_group_lines(LM) + (LM < 10 ? 3 : 1)};
+    for (int t = 0; t < 3; ++t) {
+        const int nl = nls[t];
+        if ((long long)nl << (2 * LM) > (1LL << 22)) continue;
+        const double e1 = check_ct<double2, false, LM, MAXB, PADL, TWS, SW>(nl, 11 + LM);
+        const double e2 = check_ct<double2, true, LM, MAXB, PADL, TWS, SW>(nl, 13 + LM);
+        const double e3 = check_ct<float2, false, LM, MAXB, PADL, TWS, SW>(nl, 17 + LM);
+        const double e4 = check_ct<float2, true, LM, MAXB, PADL, TWS, SW>(nl, 19 + LM);
+        std::printf("ct maxb=%d pad=%d tws=%d sw=%d m=%5d lines=%5d fp64 %.2e %.2e fp32 %.2e %.2e\n", MAXB, PADL,
+                    TWS, (int)SW, 1 << LM, nl, e1, e2, e3, e4);
+        if (e1 > 1e-14 || e2 > 1e-14 || e3 > 2e-6 || e4 > 2e-6) bad = 1;
+    }
+    return bad;
+}
+
+template <int LM, int MAXB>
+static int run_ct_pads()
+{
+    int bad = run_ct<LM, MAXB, 0, 0>();
+    bad |= run_ct<LM, MAXB, pad_for(4, LM), 0>();
+    bad |= run_ct<LM, MAXB, pad_for(5, LM), 0>();
+    bad |= run_ct<LM, MAXB, pad_for(6, LM), 2>();
+    return bad;
+}
+
+template <int MAXB, int LM = 1>
+static int run_ct_all()
+{
+    if constexpr (LM <= 10) return run_ct_pads<LM, MAXB>() | run_ct_all<MAXB, LM + 1>();
+    else return 0;
+}
+
 template <typename V, bool INV>
 static double check(int lm, int nl, int pad, unsigned seed, int maxb)
 {
@@ -115,10 +204,7 @@ static double check(int lm, int nl, int pad, unsigned seed, int maxb)
             ref[l * ls + k] = mk<V>((S)sr, (S)si);
         }
     }
-    if (maxb > 0) host_fft_lines<V, INV>(buf.data(), nl, ls, lm, twl.data(), maxb);
-    else if (maxb == -2) host_fft_ct_dispatch<V, INV, 2>(buf.data(), nl, lm, twl.data());
-    else if (maxb == -3) host_fft_ct_dispatch<V, INV, 3>(buf.data(), nl, lm, twl.data());
-    else host_fft_ct_dispatch<V, INV, 4>(buf.data(), nl, lm, twl.data());
+    host_fft_lines<V, INV>(buf.data(), nl, ls, lm, twl.data(), maxb);
     double nrm = 0;
     for (int l = 0; l < nl; ++l)
         for (int k = 0; k < m; ++k) {
@@ -133,14 +219,14 @@ static double check(int lm, int nl, int pad, unsigned seed, int maxb)
 int main()
 {
     int bad = 0;
-    for (int maxb : {2, 3, 4, -2, -3, -4})
+    for (int maxb = 2; maxb <= 4; ++maxb)
     for (int lm = 0; lm <= 10; ++lm) {
         // one line, an odd count, and a full group plus a partial one
         const int nls[3] = {1, 3, (1 << (10 - lm)) + (lm < 10 ? 3 : 1)};
         for (int t = 0; t < 3; ++t) {
             const int nl = nls[t];
             if ((long long)nl << (2 * lm) > (1LL << 22)) continue;  // naive DFT cost cap
-            const int pad = (t == 1 && maxb > 0) ? 1 : 0;
+            const int pad = t == 1 ? 1 : 0;
             const double e64f = check<double2, false>(lm, nl, pad, 11 + lm, maxb);
             const double e64i = check<double2, true>(lm, nl, pad, 13 + lm, maxb);
             const double e32f = check<float2, false>(lm, nl, pad, 17 + lm, maxb);
@@ -150,6 +236,12 @@ int main()
             if (e64f > 1e-14 || e64i > 1e-14 || e32f > 2e-6 || e32i > 2e-6) bad = 1;
         }
     }
+    bad |= run_ct_all<2>();
+    bad |= run_ct_all<3>();
+    bad |= run_ct_all<4>();
+    // swizzled handoff between radix-16 passes
+    bad |= run_ct<8, 4, 0, 0, true>();
+    bad |= run_ct<10, 4, 0, 0, true>();
     std::printf(bad ? "FAIL\n" : "OK\n");
     return bad;
 }
