@@ -175,6 +175,8 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
 #pragma unroll 1
     for (int c = 0; c < 3; ++c) {
         const T* sc = si + (long long)c * N;
+        // unrolled so that several loads are in flight per thread
+#pragma unroll 4
         for (int idx = threadIdx.x; idx < hp * m; idx += kNT) {
             const int j = idx & (m - 1), rp = idx >> lm;
             const int ya = y0 + 2 * rp;
@@ -684,6 +686,8 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     __syncthreads();
 #pragma unroll 1
     for (int c = 0; c < 3; ++c) {
+        // unrolled so that several loads are in flight per thread
+#pragma unroll 4
         for (int idx = threadIdx.x; idx < (m + 1) * hp; idx += kNT) {
             const int rp = idx & (hp - 1), kx = idx >> lhp;
             const int ya = y0 + 2 * rp;
@@ -716,7 +720,9 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     // Per-site epilogue.  Each thread owns one column x and walks a run of
     // the tile's rows keeping rows y-1, y, y+1 in registers; x neighbours come
     // from the adjacent lanes (the lanes of a wave hold consecutive x), so
-    // only the z neighbours and the wave-edge lanes read global memory.
+    // only the z neighbours and the wave-edge lanes read global memory.  The
+    // loads a row needs are issued one row ahead, so their latency overlaps
+    // the arithmetic of the row before.
     const double J = p.J, dm = p.d, ku = p.ku, D = p.D;
     const T* si = s + p.s_off + (long long)img * 3 * N + (long long)z * ny * nx;
     const long long pl = (long long)nx * ny;
@@ -728,45 +734,59 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     const int rper = (yt + rgs - 1) / rgs;
     const int ra = rg * rper, rb = min(yt, ra + rper);
     const int lane = threadIdx.x & 63;
+    const bool redge = (xl == nxp - 1 || lane == 63), ledge = (xl == 0 || lane == 0);
     double acc[kNTerm] = {0, 0, 0, 0, 0};
     for (int xc = 0; xc < nx; xc += nxp) {
         const int x = xc + xl;
         const bool xin = x < nx;
-        T cm[3], cc[3], cp[3];
-        {
-            const int y = y0 + ra;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const T* sc = si + (long long)c * N;
-                cc[c] = (xin && ra < rb && y < ny) ? sc[(long long)y * nx + x] : T(0);
-                cm[c] = (xin && ra < rb && y > 0 && y - 1 < ny) ? sc[(long long)(y - 1) * nx + x] : T(0);
-            }
-        }
-        for (int r = ra; r < ra + rper; ++r) {
-            const int y = y0 + r;
-            const bool act = xin && r < rb && y < ny;
+        // spin component c at (x, y0 + rr), zero outside the lattice
+        auto rowv = [&](int rr, int c) -> T {
+            const int y = y0 + rr;
+            return (xin && ra < rb && y >= 0 && y < ny) ? si[(long long)c * N + (long long)y * nx + x] : T(0);
+        };
+        // the z neighbours and (wave-edge lanes) x neighbours of row rr
+        auto fetch = [&](int rr, T (&zu)[3], T (&zd)[3], T (&er)[3], T (&el)[3]) {
+            const int y = y0 + rr;
+            const bool a = xin && rr < rb && y < ny;
             const long long i = (long long)y * nx + x;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const T* sc = si + (long long)c * N;
-                cp[c] = (xin && r < rb && y + 1 < ny) ? sc[i + nx] : T(0);
+                zu[c] = (a && z + 1 < nz) ? sc[i + pl] : T(0);
+                zd[c] = (a && z > 0) ? sc[i - pl] : T(0);
+                er[c] = (a && redge && x + 1 < nx) ? sc[i + 1] : T(0);
+                el[c] = (a && ledge && x > 0) ? sc[i - 1] : T(0);
             }
+        };
+        T cm[3], cc[3], cp[3], zu[3], zd[3], er[3], el[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            cm[c] = rowv(ra - 1, c);
+            cc[c] = rowv(ra, c);
+            cp[c] = rowv(ra + 1, c);
+        }
+        fetch(ra, zu, zd, er, el);
+        for (int r = ra; r < ra + rper; ++r) {
+            const int y = y0 + r;
+            const bool act = xin && r < rb && y < ny;
+            const long long i = (long long)y * nx + x;
+            // next row's loads first
+            T cn[3], zu2[3], zd2[3], er2[3], el2[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) cn[c] = rowv(r + 2, c);
+            fetch(r + 1, zu2, zd2, er2, el2);
             double sv[3], xp[3], xm[3], nb[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 T right = __shfl_down(cc[c], 1);
                 T left = __shfl_up(cc[c], 1);
-                const T* sc = si + (long long)c * N;
-                if (xl == nxp - 1 || lane == 63) right = (act && x + 1 < nx) ? sc[i + 1] : T(0);
-                if (xl == 0 || lane == 0) left = (act && x > 0) ? sc[i - 1] : T(0);
+                if (redge) right = er[c];
+                if (ledge) left = el[c];
                 if (x + 1 >= nx) right = T(0);
                 sv[c] = (double)cc[c];
                 xp[c] = (double)right;
                 xm[c] = (double)left;
-                double zsum = 0;
-                if (act && z + 1 < nz) zsum += (double)sc[i + pl];
-                if (act && z > 0) zsum += (double)sc[i - pl];
-                nb[c] = xp[c] + xm[c] + (double)cp[c] + (double)cm[c] + zsum;
+                nb[c] = xp[c] + xm[c] + (double)cp[c] + (double)cm[c] + ((double)zu[c] + (double)zd[c]);
             }
             if (act) {
                 // unit-strength DMI field, eq. (4)
@@ -804,6 +824,11 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
             for (int c = 0; c < 3; ++c) {
                 cm[c] = cc[c];
                 cc[c] = cp[c];
+                cp[c] = cn[c];
+                zu[c] = zu2[c];
+                zd[c] = zd2[c];
+                er[c] = er2[c];
+                el[c] = el2[c];
             }
         }
     }
