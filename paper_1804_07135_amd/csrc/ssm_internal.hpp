@@ -15,8 +15,7 @@ constexpr int kTwLog = 11;
 constexpr int kTwM = 1 << kTwLog;
 constexpr int kMaxLogM = 10;   // half padded length m <= 1024, padded P = 2m <= 2048
 constexpr int kNT = 256;       // threads per workgroup for every kernel
-constexpr int kMaxE = 24;       // register slots per thread of the convolution accumulator
-constexpr int kConvElems = kMaxE * kNT;  // complex values per convolution workgroup
+constexpr int kConvElems = 24 * kNT;  // complex values per convolution workgroup (slice batching cap)
 constexpr int kArcEPT = 8;     // flat elements per thread in the arc-length kernel
 constexpr int kNTerm = 5;      // energy partial slots: E, T_J, T_d, T_ku, T_dip
 
@@ -112,13 +111,16 @@ hipError_t launch_xfwd(const Prob* P, int np, const WorkMap& wm, const T* s, voi
                        const void* tw, const int* done, size_t lds, hipStream_t st);
 // kinds: bit b set = some problem takes build b (conv_build)
 template <typename T>
-hipError_t launch_conv(int mz, int kinds, const Prob* P, int np, const WorkMap& wm, const void* X,
+// The convolution leaves the convolved spectrum as two parts: the even-y
+// half's contribution in Xp and the odd-y half's over its input X; the
+// inverse-x kernel reads both and sums them.
+hipError_t launch_conv(int mz, int kinds, const Prob* P, int np, const WorkMap& wm, void* X,
                        void* Xp, const T* nhat, const void* tw, const int* done, size_t lds,
                        hipStream_t st);
 // mode bits for the inverse/epilogue kernel
 enum { EPI_STEP = 1, EPI_FIELD = 2, EPI_TERMS = 4 };
 template <typename T>
-hipError_t launch_xinv(const Prob* P, int np, const WorkMap& wm, const void* Xp, const T* s,
+hipError_t launch_xinv(const Prob* P, int np, const WorkMap& wm, const void* Xp, const void* Xq, const T* s,
                        T* s_star, T* h, double* epart, const void* tw, const int* done,
                        int mode, double tau, size_t lds, hipStream_t st);
 template <typename T>

@@ -56,11 +56,6 @@ namespace ssm {
 #ifndef SSM_CONV_NH_SERIAL
 #define SSM_CONV_NH_SERIAL 0
 #endif
-// 1: the convolution kernel sums its two y halves in registers; 0: in its
-// own output slice (read-modify-write through L2), which frees registers.
-#ifndef SSM_CONV_REG_ACC
-#define SSM_CONV_REG_ACC 0
-#endif
 // widest pass of the compile-time-length x transforms (x lengths 32..512)
 #ifndef SSM_X_CT_RADIX_BITS
 #define SSM_X_CT_RADIX_BITS 4
@@ -219,9 +214,10 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
 // per-line constant, so it commutes with the y FFT: the register z-phase
 // applies it and runs both z halves hz itself (length-mz DFTs), multiplies
 // by the real symmetric kernel spectrum (xx, xy, xz, yy, yz, zz), inverts
-// and sums the halves.  Then inverse y FFT, un-twiddle, and the two y halves
-// are summed in registers (in the output slice itself when a workgroup has
-// more than kMaxE*kNT elements).  The kernel spectrum carries 1/(Px Py Pz).
+// and sums the halves.  Then inverse y FFT and un-twiddle; the y half 0
+// result goes to the output slice and the y half 1 result over the
+// workgroup's own input slice (read for the last time by then), and the
+// inverse-x kernel adds the two.  The kernel spectrum carries 1/(Px Py Pz).
 // LDS: twiddles (2 m_y) + G*3*nz lines of m_y.
 // ---------------------------------------------------------------------------
 
@@ -322,7 +318,7 @@ __device__ __forceinline__ void conv_zphase(const Prob& p, int G, int kx0, int h
 // Lines belong to wavefronts (groups of 1024 elements), so only the z-phase,
 // which reads every line of a column, needs workgroup barriers.
 template <typename T, int MZ, int LMY>
-__device__ __forceinline__ void conv_body_ct(const Prob& p, int s0, int G, const cplx<T>* __restrict__ X,
+__device__ __forceinline__ void conv_body_ct(const Prob& p, int s0, int G, cplx<T>* __restrict__ X,
                                              cplx<T>* __restrict__ Xp, const T* __restrict__ nhat,
                                              const cplx<T>* __restrict__ tw, cplx<T>* smem)
 {
@@ -357,7 +353,7 @@ __device__ __forceinline__ void conv_body_ct(const Prob& p, int s0, int G, const
         twl = tw;
         lines = smem;
     }
-    const V* in = X + p.x_off + (long long)s0 * per;
+    V* in = X + p.x_off + (long long)s0 * per;
     V* out = Xp + p.x_off + (long long)s0 * per;
     const int kx0 = s0 % nsl_img;
     const int wave = threadIdx.x >> 6;
@@ -412,8 +408,10 @@ __device__ __forceinline__ void conv_body_ct(const Prob& p, int s0, int G, const
         conv_zphase<T, MZ, LMY, 0, PADL>(p, G, kx0, hy, lines, nhat, tw);
         __syncthreads();
 
-        // inverse y transform; the last pass un-twiddles and sums the y
-        // halves in the output slice (hy = 0 writes, hy = 1 adds)
+        // inverse y transform; the last pass writes y half hy = 0 to the
+        // output slice and hy = 1 (un-twiddled) over the input slice, whose
+        // last reader was this workgroup's hy = 1 forward pass (the inverse
+        // x kernel sums the two)
         lane = threadIdx.x;
         asm volatile("" : "+v"(lane));
         lane &= 63;
@@ -428,22 +426,19 @@ __device__ __forceinline__ void conv_body_ct(const Prob& p, int s0, int G, const
                 if (g < (gl << PL::LQ)) {
                     // last pass: j < NS, so the outputs are y = j + r NS
                     const int line = g >> PL::LQ, j = g & (PL::Q - 1);
-                    V* dst = out + (long long)(g0 + line) * ny;
+                    V* dst = (hy ? in : out) + (long long)(g0 + line) * ny;
                     if (hy) {
 #pragma unroll
                         for (int r = 0; r < RL; ++r) v[b][r] = cmulc(v[b][r], twl[(j + r * PL::NS) << TWS]);
                     }
                     if (ny == MY) {
 #pragma unroll
-                        for (int r = 0; r < RL; ++r) {
-                            const int y = j + r * PL::NS;
-                            dst[y] = hy ? cadd(dst[y], v[b][r]) : v[b][r];
-                        }
+                        for (int r = 0; r < RL; ++r) dst[j + r * PL::NS] = v[b][r];
                     } else {
 #pragma unroll
                         for (int r = 0; r < RL; ++r) {
                             const int y = j + r * PL::NS;
-                            if (y < ny) dst[y] = hy ? cadd(dst[y], v[b][r]) : v[b][r];
+                            if (y < ny) dst[y] = v[b][r];
                         }
                     }
                 }
@@ -458,7 +453,7 @@ __device__ __forceinline__ void conv_body_ct(const Prob& p, int s0, int G, const
 // m_y = 2^LMY at compile time (all FFT indexing constant-folds); LMY = 0
 // takes it from the problem.
 template <typename T, int MZ, int LMY>
-__device__ __forceinline__ void conv_body(const Prob& p, int s0, int G, const cplx<T>* __restrict__ X,
+__device__ __forceinline__ void conv_body(const Prob& p, int s0, int G, cplx<T>* __restrict__ X,
                                           cplx<T>* __restrict__ Xp, const T* __restrict__ nhat,
                                           const cplx<T>* __restrict__ tw, cplx<T>* smem)
 {
@@ -470,17 +465,12 @@ __device__ __forceinline__ void conv_body(const Prob& p, int s0, int G, const cp
     V* twl = smem;
     V* lines = twl + 2 * my;
     load_twiddles(twl, lmy, tw);
-    const V* in = X + p.x_off + (long long)s0 * per;
+    V* in = X + p.x_off + (long long)s0 * per;
     V* out = Xp + p.x_off + (long long)s0 * per;
-    const bool racc = SSM_CONV_REG_ACC && nel <= kMaxE * kNT;
     const int dy = kNT % ny, dr = kNT / ny;
     const int yb = threadIdx.x % ny, rb = threadIdx.x / ny;
     const int kx0 = s0 % nsl_img;
 
-    constexpr int NACC = SSM_CONV_REG_ACC ? kMaxE : 1;
-    V acc[NACC];
-#pragma unroll
-    for (int i = 0; i < NACC; ++i) acc[i] = mk<V>(0, 0);
     __syncthreads();
 
 #pragma unroll 1
@@ -567,50 +557,29 @@ __device__ __forceinline__ void conv_body(const Prob& p, int s0, int G, const cp
         conv_fft_y<V, true, LMY>(lines, nlines, lmy, twl);
         __syncthreads();
         {
+            // y half hy = 0 goes to the output slice, hy = 1 (un-twiddled)
+            // over this workgroup's input slice, which is no longer read
             int y = yb, r = rb;
-            // opaque copy: keeps the compiler from hoisting all kMaxE
-            // addresses and twiddles out of the y-half loop
             asm volatile("" : "+v"(y), "+v"(r));
-            if (racc) {
-#pragma unroll
-                for (int i = 0; i < NACC; ++i) {
-                    const int e = threadIdx.x + i * kNT;
-                    if (e < nel) {
-                        V v = lines[lds_pad((r << lmy) + y)];
-                        if (hy) v = cmulc(v, twl[y]);
-                        acc[i] = cadd(acc[i], v);
-                    }
-                    y += dy;
-                    r += dr;
-                    if (y >= ny) { y -= ny; r += 1; }
-                }
-            } else {
+            V* dst = hy ? in : out;
 #pragma unroll 4
-                for (int e = threadIdx.x; e < nel; e += kNT) {
-                    V v = lines[lds_pad((r << lmy) + y)];
-                    if (hy) v = cadd(out[e], cmulc(v, twl[y]));
-                    out[e] = v;
-                    y += dy;
-                    r += dr;
-                    if (y >= ny) { y -= ny; r += 1; }
-                }
+            for (int e = threadIdx.x; e < nel; e += kNT) {
+                V v = lines[lds_pad((r << lmy) + y)];
+                if (hy) v = cmulc(v, twl[y]);
+                dst[e] = v;
+                y += dy;
+                r += dr;
+                if (y >= ny) { y -= ny; r += 1; }
             }
         }
         __syncthreads();
-    }
-    if (racc) {
-#pragma unroll
-        for (int i = 0; i < NACC; ++i) {
-            const int e = threadIdx.x + i * kNT;
-            if (e < nel) out[e] = acc[i];
-        }
     }
 }
 
 template <typename T, int MZ, int BUILD>
 __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && MZ <= 8 ? SSM_CONV_WAVES_F32 : 1, 8))) void k_conv(const Prob* __restrict__ P, int np,
                                               const int* __restrict__ wstart,
-                                              const cplx<T>* __restrict__ X,
+                                              cplx<T>* __restrict__ X,
                                               cplx<T>* __restrict__ Xp, const T* __restrict__ nhat,
                                               const cplx<T>* __restrict__ tw,
                                               const int* __restrict__ done)
@@ -658,6 +627,7 @@ template <typename T>
 __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_xinv(const Prob* __restrict__ P, int np,
                                               const int* __restrict__ wstart,
                                               const cplx<T>* __restrict__ Xp,
+                                              const cplx<T>* __restrict__ Xq,
                                               const T* __restrict__ s, T* __restrict__ ss,
                                               T* __restrict__ hout, double* __restrict__ epart,
                                               const cplx<T>* __restrict__ tw,
@@ -682,7 +652,9 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     V* lines = twl + 2 * m;
     T* hd = reinterpret_cast<T*>(lines + padded_len(yt * m, x_padl(lm)));
     load_twiddles(twl, lm, tw);
+    // the convolved spectrum arrives as its two y halves (sum of both)
     const V* Xi = Xp + p.x_off + (long long)img * (m + 1) * 3 * nz * ny;
+    const V* Xj = Xq + p.x_off + (long long)img * (m + 1) * 3 * nz * ny;
     __syncthreads();
 #pragma unroll 1
     for (int c = 0; c < 3; ++c) {
@@ -691,9 +663,11 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         for (int idx = threadIdx.x; idx < (m + 1) * hp; idx += kNT) {
             const int rp = idx & (hp - 1), kx = idx >> lhp;
             const int ya = y0 + 2 * rp;
-            const V* src = Xi + (((long long)kx * 3 + c) * nz + z) * ny;
-            const V A = (ya < ny) ? src[ya] : mk<V>(0, 0);
-            const V B = (ya + 1 < ny) ? src[ya + 1] : mk<V>(0, 0);
+            const long long o = (((long long)kx * 3 + c) * nz + z) * ny;
+            const V* src = Xi + o;
+            const V* srq = Xj + o;
+            const V A = (ya < ny) ? cadd(src[ya], srq[ya]) : mk<V>(0, 0);
+            const V B = (ya + 1 < ny) ? cadd(src[ya + 1], srq[ya + 1]) : mk<V>(0, 0);
             const int i0 = (2 * rp + (kx & 1)) * m + (kx >> 1);
             lines[i0 + (i0 >> psh)] = mk<V>(A.x - B.y, A.y + B.x);
             if (kx > 0 && kx < m) {
@@ -951,46 +925,55 @@ __global__ __launch_bounds__(kNT) void k_reduce(const Prob* __restrict__ P, int 
     }
     if (!with_arc) return;
     __syncthreads();
-    if (!last || threadIdx.x != 0) return;
+    if (!last) return;
+    // last workgroup of the problem: every image's segment length is
+    // visible (written before the counter increment); fetch them in
+    // parallel, scan in a fixed order on one thread, then search the
+    // interval of every target image in parallel
     __threadfence();
-    count[pi] = 0;
-    const volatile double* sg = seg;
     const int K = p.K, g0 = p.img0;
     double* al = red_alpha;
-    double S = 0;
-    al[0] = 0;
-    for (int kk = 1; kk < K; ++kk) {
-        S += sg[g0 + kk];
-        al[kk] = S;
+    const volatile double* sg = seg;
+    for (int kk = threadIdx.x; kk < K; kk += kNT) al[kk] = (kk == 0) ? 0.0 : sg[g0 + kk];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        count[pi] = 0;
+        double S = 0;
+        for (int kk = 1; kk < K; ++kk) {
+            S += al[kk];
+            al[kk] = S;
+        }
+        red[0][0] = S;
+        skip[pi] = (S > 0.0) ? 0 : 1;
+        iters[pi] += 1;
     }
-    const double L = S;
+    __syncthreads();
+    const double L = red[0][0];
     if (!(L > 0.0)) {
-        skip[pi] = 1;
-        for (int kk = 0; kk < K; ++kk) {
+        for (int kk = threadIdx.x; kk < K; kk += kNT) {
             alpha[g0 + kk] = 0;
             jidx[g0 + kk] = kk;
             wgt[g0 + kk] = 0;
         }
-    } else {
-        skip[pi] = 0;
-        for (int kk = 1; kk < K; ++kk) al[kk] = al[kk] / L;
-        for (int kk = 0; kk < K; ++kk) {
-            alpha[g0 + kk] = al[kk];
-            if (kk == 0 || kk == K - 1) {
-                jidx[g0 + kk] = kk;
-                wgt[g0 + kk] = 0;
-                continue;
-            }
-            const double tk = (double)kk / (double)(K - 1);
-            int j = 0;
-            for (int jj = 0; jj <= K - 2; ++jj)
-                if (al[jj] <= tk) j = jj;
-            const double width = al[j + 1] - al[j];
-            jidx[g0 + kk] = j;
-            wgt[g0 + kk] = (width > 0.0) ? (tk - al[j]) / width : 0.0;
-        }
+        return;
     }
-    iters[pi] += 1;
+    for (int kk = 1 + threadIdx.x; kk < K; kk += kNT) al[kk] = al[kk] / L;
+    __syncthreads();
+    for (int kk = threadIdx.x; kk < K; kk += kNT) {
+        alpha[g0 + kk] = al[kk];
+        if (kk == 0 || kk == K - 1) {
+            jidx[g0 + kk] = kk;
+            wgt[g0 + kk] = 0;
+            continue;
+        }
+        const double tk = (double)kk / (double)(K - 1);
+        int j = 0;
+        for (int jj = 0; jj <= K - 2; ++jj)
+            if (al[jj] <= tk) j = jj;
+        const double width = al[j + 1] - al[j];
+        jidx[g0 + kk] = j;
+        wgt[g0 + kk] = (width > 0.0) ? (tk - al[j]) / width : 0.0;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1360,7 +1343,7 @@ hipError_t launch_xfwd(const Prob* P, int np, const WorkMap& wm, const T* s, voi
 }
 
 template <typename T, int MZ, int BUILD>
-static void launch_conv_b(const Prob* P, int np, const WorkMap& wm, const cplx<T>* x, cplx<T>* xp,
+static void launch_conv_b(const Prob* P, int np, const WorkMap& wm, cplx<T>* x, cplx<T>* xp,
                           const T* nhat, const cplx<T>* t, const int* done, size_t lds, hipStream_t st)
 {
     hipLaunchKernelGGL((k_conv<T, MZ, BUILD>), dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start, x, xp,
@@ -1368,7 +1351,7 @@ static void launch_conv_b(const Prob* P, int np, const WorkMap& wm, const cplx<T
 }
 
 template <typename T, int MZ>
-static hipError_t launch_conv_mz(int kinds, const Prob* P, int np, const WorkMap& wm, const cplx<T>* x,
+static hipError_t launch_conv_mz(int kinds, const Prob* P, int np, const WorkMap& wm, cplx<T>* x,
                                  cplx<T>* xp, const T* nhat, const cplx<T>* t, const int* done, size_t lds,
                                  hipStream_t st)
 {
@@ -1383,11 +1366,11 @@ static hipError_t launch_conv_mz(int kinds, const Prob* P, int np, const WorkMap
 }
 
 template <typename T>
-hipError_t launch_conv(int mz, int kinds, const Prob* P, int np, const WorkMap& wm, const void* X, void* Xp,
+hipError_t launch_conv(int mz, int kinds, const Prob* P, int np, const WorkMap& wm, void* X, void* Xp,
                        const T* nhat, const void* tw, const int* done, size_t lds, hipStream_t st)
 {
     if (wm.total == 0) return hipSuccess;
-    const cplx<T>* x = (const cplx<T>*)X;
+    cplx<T>* x = (cplx<T>*)X;
     cplx<T>* xp = (cplx<T>*)Xp;
     const cplx<T>* t = (const cplx<T>*)tw;
     switch (mz) {
@@ -1401,13 +1384,14 @@ hipError_t launch_conv(int mz, int kinds, const Prob* P, int np, const WorkMap& 
 }
 
 template <typename T>
-hipError_t launch_xinv(const Prob* P, int np, const WorkMap& wm, const void* Xp, const T* s,
+hipError_t launch_xinv(const Prob* P, int np, const WorkMap& wm, const void* Xp, const void* Xq, const T* s,
                        T* s_star, T* h, double* epart, const void* tw, const int* done, int mode,
                        double tau, size_t lds, hipStream_t st)
 {
     if (wm.total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_xinv<T>, dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start,
-                       (const cplx<T>*)Xp, s, s_star, h, epart, (const cplx<T>*)tw, done, mode, tau);
+                       (const cplx<T>*)Xp, (const cplx<T>*)Xq, s, s_star, h, epart, (const cplx<T>*)tw, done,
+                       mode, tau);
     return hipGetLastError();
 }
 
@@ -1510,9 +1494,10 @@ hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st)
 #define SSM_INST(T)                                                                                \
     template hipError_t launch_xfwd<T>(const Prob*, int, const WorkMap&, const T*, void*,         \
                                        const void*, const int*, size_t, hipStream_t);             \
-    template hipError_t launch_conv<T>(int, int, const Prob*, int, const WorkMap&, const void*, void*, \
+    template hipError_t launch_conv<T>(int, int, const Prob*, int, const WorkMap&, void*, void*,       \
                                        const T*, const void*, const int*, size_t, hipStream_t);   \
-    template hipError_t launch_xinv<T>(const Prob*, int, const WorkMap&, const void*, const T*,   \
+    template hipError_t launch_xinv<T>(const Prob*, int, const WorkMap&, const void*, const void*, \
+                                       const T*,                                                    \
                                        T*, T*, double*, const void*, const int*, int, double,     \
                                        size_t, hipStream_t);                                       \
     template hipError_t launch_arc<T>(const Prob*, int, const WorkMap&, const T*, double*,        \
