@@ -165,6 +165,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp32-only", action="store_true", help="skip the FP64 plain run (profiling)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose the FP32 form's tiles with the library's autotuner before timing")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--summarize-profiles", default="",
@@ -206,6 +208,15 @@ def main():
     sm = ssm.StringMethod(prob, ssm.SSM_FP32_MIXED)
     sm.set_options(check_every=10, graph_chunk=args.graph_chunk)
     sm.set_string(s0)
+    tiles = None
+    if args.autotune:
+        import tempfile
+        with tempfile.TemporaryDirectory() as td:
+            cache = os.path.join(td, "tiles.txt")
+            sm.autotune(cache)
+            with open(cache) as fh:
+                tiles = fh.read().strip()
+        sm.set_string(s0)
     sm.iterate(warm, tau)
     dt32 = time_iterations(sm, steps, tau)
     bar32 = sm.barrier().cpu().numpy()[0]
@@ -222,7 +233,7 @@ def main():
     # --- FP64 plain form, direct launches ----------------------------------
     st64 = args.fp64_steps or steps
     if args.fp32_only:
-        print(json.dumps({"ms_per_step": dt32 / steps * 1e3, "kernels_ms": prof}), flush=True)
+        print(json.dumps({"ms_per_step": dt32 / steps * 1e3, "kernels_ms": prof, "tiles": tiles}), flush=True)
         return
     sm64 = ssm.StringMethod(prob, ssm.SSM_FP64)
     sm64.set_string(s0)
@@ -281,6 +292,7 @@ def main():
                      "algorithmic_bytes_per_launch": ab[dom], "avg_launch_ms": kern[dom]["ms_avg"]},
         "iteration_floor_frac": floor_bytes / (dt32 / steps) / 1e9 / HBM_PEAK_GBS,
         "kernels_ms_avg": {k: round(v["ms_avg"], 5) for k, v in kern.items()},
+        "autotuned_tiles": tiles,
         "ms_per_step_with_events": dt32_ev / steps * 1e3,
     }
     if not args.no_cpu:
