@@ -23,7 +23,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "site-field evals/s + string iters/s; FP32-batched vs FP64 plain at 1e-4 barrier"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_1804_07135_amd/csrc/ssm_kernels.hip", "paper_1804_07135_amd/csrc/ssm_internal.hpp"]
+KERNEL_SOURCES = ["paper_1804_07135_amd/csrc/ssm_kernels.hip", "paper_1804_07135_amd/csrc/ssm_internal.hpp",
+                  "paper_1804_07135_amd/csrc/ssm_fft.hpp"]
 
 
 def kernel_source_hash():
@@ -142,9 +143,33 @@ def summarize_profiles(args):
              "| kernel | launches | avg ms | total ms |", "|---|---|---|---|"]
     for k, v in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
         lines.append(f"| {k} | {len(v)} | {statistics.mean(v):.4f} | {sum(v):.3f} |")
-    lines += ["", f"HBM traffic of {dom} per launch (FETCH_SIZE x {f_cal:.3f}, WRITE_SIZE x {w_cal:.3f}; "
-              f"factors from a {probe_kib // 1024} MiB device copy read by the same counters): "
-              f"read {fetch / 1e6:.1f} MB, write {write / 1e6:.1f} MB", ""]
+    lines += ["", f"HBM traffic per launch (FETCH_SIZE x {f_cal:.3f}, WRITE_SIZE x {w_cal:.3f}; factors from a "
+              f"{probe_kib // 1024} MiB device copy read by the same counters), against the algorithmic bytes "
+              "the method must move:", "",
+              "| kernel | read MB | write MB | algorithmic MB |", "|---|---|---|---|"]
+    ab = algorithmic_bytes(dict(__import__("paper_1804_07135_amd.inputs", fromlist=["WORKLOADS"]).WORKLOADS[w]), 4)
+    for k in sorted(stats, key=lambda k: -sum(stats[k])):
+        if ("fetch", k) in counters and ("write", k) in counters:
+            rd = statistics.median(counters[("fetch", k)]) * f_cal * 1024
+            wr = statistics.median(counters[("write", k)]) * w_cal * 1024
+            lines.append(f"| {k} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | "
+                         f"{(ab[k] / 1e6) if k in ab else float('nan'):.1f} |")
+    # instruction and stall counters, when those passes were collected
+    sq = {}
+    for sub in ("sqa", "sqb"):
+        for r in _csv_rows(os.path.join(d, sub)):
+            k = _kernel_key(r.get("Kernel_Name", ""))
+            if k:
+                sq.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    if sq:
+        names = sorted({c for v in sq.values() for c in v})
+        lines += ["", "SQ counters per launch (medians; instruction counts are per wavefront):", "",
+                  "| kernel | " + " | ".join(names) + " |", "|---" * (len(names) + 1) + "|"]
+        for k in sorted(sq, key=lambda k: -sum(stats.get(k, [0]))):
+            if k.startswith("k_") and not k.startswith("k_spec"):
+                lines.append(f"| {k} | " + " | ".join(
+                    f"{statistics.median(sq[k][c]):.3g}" if c in sq[k] else "" for c in names) + " |")
+    lines.append("")
     with open(os.path.join(ROOT, "profiles", f"kernels_{w}_fp32.md"), "w") as fh:
         fh.write("\n".join(lines))
     with open(os.path.join(ROOT, "profiles", f"traffic_{dom}_{w}_fp32.json"), "w") as fh:
