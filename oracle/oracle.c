@@ -34,7 +34,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define ORACLE_VERSION 1
+#define ORACLE_VERSION 2
 
 int oracle_version(void) { return ORACLE_VERSION; }
 
@@ -466,6 +466,214 @@ int oracle_iterate(int nx, int ny, int nz, double J, double d, double k,
     }
     if (h_or_null) memcpy(h_or_null, h, (size_t)K * M * sizeof(double));
     if (force_norm_out) *force_norm_out = oracle_force_norm(K, N, s, h, NULL);
+    free(h); free(ss); free(al); free(wt); free(jj);
+    return it;
+}
+
+/* ------------------------------------------------------------------------
+ * Step 1 with the paper's integrator (Sec. III): every image is evolved
+ * over an interval T of the damping-only dynamics (second term of eq. (9);
+ * the Appendix identifies it with the potential force) by an explicit
+ * embedded Runge-Kutta method with adaptive step size, here Dormand and
+ * Prince's 5(4) pair (J. Comput. Appl. Math. 6 (1980) 19), local
+ * extrapolation (the 5th-order solution is kept), first stage of a step =
+ * last stage of the accepted step before.  The prefactor gamma alpha /
+ * (1 + alpha^2) is absorbed into the time unit, as for the explicit step.
+ *
+ *   ds/dt = f(s) = -s x (s x h(s)) = (s.s) h - (s.h) s   (per spin)
+ *
+ * Error control (Hairer, Norsett, Wanner, Solving ODEs I, II.4), per image:
+ *   err = sqrt(mean over the 3N components of (e_c / sc_c)^2),
+ *   e = y5 - y4, sc_c = atol + rtol max(|y_c|, |y5_c|);
+ *   accepted iff err <= 1;  h_new = h * clamp(0.9 err^(-1/5), 0.2, 5)
+ *   (at most 1 after a rejection), h the step just attempted;
+ *   a step is shortened to end exactly at T.
+ * The stage states are not normalised; after the interval every spin is
+ * renormalised (the exact flow keeps |s| = 1).
+ * ---------------------------------------------------------------------- */
+static const double DP_A[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5, 0, 0, 0, 0, 0},
+    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+    {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+/* 5th-order weights (= last row of A, weight 0 on the last stage) and the
+ * embedded 4th-order weights */
+static const double DP_B[7] = {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84, 0};
+static const double DP_BS[7] = {5179.0 / 57600, 0, 7571.0 / 16695, 393.0 / 640,
+                                -92097.0 / 339200, 187.0 / 2100, 1.0 / 40};
+static const double DP_C[7] = {0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1, 1};
+
+/* Tableau for the pins: a[49] row-major (7 x 7, zero above the diagonal),
+ * b[7], bs[7], c[7]. */
+void oracle_dopri_tableau(double* a, double* b, double* bs, double* c)
+{
+    for (int i = 0; i < 7; ++i) {
+        for (int j = 0; j < 7; ++j) a[i * 7 + j] = (j < 6) ? DP_A[i][j] : 0.0;
+        b[i] = DP_B[i];
+        bs[i] = DP_BS[i];
+        c[i] = DP_C[i];
+    }
+}
+
+/* f(y) of one image (SoA [3][N]); h receives the field of y. */
+void oracle_rk_rhs(int nx, int ny, int nz, double J, double d, double k, double D,
+                   const double* y, double* f, double* h)
+{
+    const int64_t N = (int64_t)nx * ny * nz;
+    oracle_field(nx, ny, nz, J, d, k, D, y, h);
+    for (int64_t i = 0; i < N; ++i) {
+        const double v[3] = {y[i], y[N + i], y[2 * N + i]};
+        const double w[3] = {h[i], h[N + i], h[2 * N + i]};
+        const double ss = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        const double sh = v[0] * w[0] + v[1] * w[1] + v[2] * w[2];
+        for (int c = 0; c < 3; ++c) f[c * N + i] = ss * w[c] - sh * v[c];
+    }
+}
+
+/* One attempted step of size hs from y.  kk[0..6]: stage slopes, kk[0] =
+ * f(y) on entry; on return kk[6] = f(y5).  y5 receives the 5th-order
+ * solution; returns the scaled error norm. */
+static double dopri_attempt(int nx, int ny, int nz, double J, double d, double k, double D,
+                            const double* y, double hs, double* kk[7], double* y5, double* hscr,
+                            double rtol, double atol)
+{
+    const int64_t M = 3 * (int64_t)nx * ny * nz;
+    for (int i = 1; i < 7; ++i) {
+        for (int64_t m = 0; m < M; ++m) {
+            double acc = 0.0;
+            for (int j = 0; j < i; ++j) acc += DP_A[i][j] * kk[j][m];
+            y5[m] = y[m] + hs * acc;
+        }
+        oracle_rk_rhs(nx, ny, nz, J, d, k, D, y5, kk[i], hscr);
+    }
+    /* y5 now holds the last stage's input, which is the 5th-order solution */
+    double sq = 0.0;
+    for (int64_t m = 0; m < M; ++m) {
+        double e = 0.0;
+        for (int j = 0; j < 7; ++j) e += (DP_B[j] - DP_BS[j]) * kk[j][m];
+        e *= hs;
+        const double sc = atol + rtol * fmax(fabs(y[m]), fabs(y5[m]));
+        sq += (e / sc) * (e / sc);
+    }
+    return sqrt(sq / (double)M);
+}
+
+/* Fixed-size Dormand-Prince steps (no control) for the order pins: n steps
+ * of size hs from y (in place), no renormalisation.  Returns the error
+ * estimate norm of the last step (rtol = 0, atol = 1: the RMS of e). */
+double oracle_dopri_fixed(int nx, int ny, int nz, double J, double d, double k, double D,
+                          double* y, double hs, int n)
+{
+    const int64_t M = 3 * (int64_t)nx * ny * nz;
+    double* kk[7];
+    for (int i = 0; i < 7; ++i) kk[i] = (double*)malloc((size_t)M * sizeof(double));
+    double* y5 = (double*)malloc((size_t)M * sizeof(double));
+    double* hscr = (double*)malloc((size_t)M * sizeof(double));
+    double err = 0.0;
+    for (int st = 0; st < n; ++st) {
+        oracle_rk_rhs(nx, ny, nz, J, d, k, D, y, kk[0], hscr);
+        err = dopri_attempt(nx, ny, nz, J, d, k, D, y, hs, kk, y5, hscr, 0.0, 1.0);
+        memcpy(y, y5, (size_t)M * sizeof(double));
+    }
+    for (int i = 0; i < 7; ++i) free(kk[i]);
+    free(y5);
+    free(hscr);
+    return err;
+}
+
+/* Evolve one image y (in place) over T with step control; *dtp is the
+ * proposed step size (in: start, out: proposal for the next interval).
+ * n_acc, n_rej accumulate the accepted and rejected steps.  Returns 0, or
+ * -1 if max_steps attempts did not reach T. */
+int oracle_rk_interval(int nx, int ny, int nz, double J, double d, double k, double D,
+                       double* y, double T, double rtol, double atol, double* dtp,
+                       int64_t* n_acc, int64_t* n_rej, int max_steps)
+{
+    const int64_t N = (int64_t)nx * ny * nz, M = 3 * N;
+    double* kk[7];
+    for (int i = 0; i < 7; ++i) kk[i] = (double*)malloc((size_t)M * sizeof(double));
+    double* y5 = (double*)malloc((size_t)M * sizeof(double));
+    double* hscr = (double*)malloc((size_t)M * sizeof(double));
+    oracle_rk_rhs(nx, ny, nz, J, d, k, D, y, kk[0], hscr);
+    double t = 0.0;
+    int done = 0, steps = 0, rc = 0;
+    while (!done) {
+        if (steps++ >= max_steps) { rc = -1; break; }
+        const int capped = (*dtp >= T - t);
+        const double hs = capped ? T - t : *dtp;
+        const double err = dopri_attempt(nx, ny, nz, J, d, k, D, y, hs, kk, y5, hscr, rtol, atol);
+        double fac = 0.9 * pow(fmax(err, 1e-10), -0.2);
+        fac = fmin(5.0, fmax(0.2, fac));
+        if (err <= 1.0) {
+            memcpy(y, y5, (size_t)M * sizeof(double));
+            double* tmp = kk[0];
+            kk[0] = kk[6];
+            kk[6] = tmp;
+            if (capped) done = 1;
+            else t += hs;
+            ++*n_acc;
+        } else {
+            fac = fmin(fac, 1.0);
+            ++*n_rej;
+        }
+        *dtp = hs * fac;
+    }
+    for (int64_t i = 0; i < N; ++i) {
+        const double nrm = sqrt(y[i] * y[i] + y[N + i] * y[N + i] + y[2 * N + i] * y[2 * N + i]);
+        for (int c = 0; c < 3; ++c) y[c * N + i] /= nrm;
+    }
+    for (int i = 0; i < 7; ++i) free(kk[i]);
+    free(y5);
+    free(hscr);
+    return rc;
+}
+
+/* The string iteration of oracle_iterate with step 1 done by
+ * oracle_rk_interval over T for every image (dtp[K]: per-image step
+ * proposals, in/out; stats[2K]: accepted, rejected steps per image,
+ * accumulated).  Returns the iterations done, or -1 on a failed interval. */
+int oracle_iterate_rk(int nx, int ny, int nz, double J, double d, double k, double D, int K,
+                      int max_iter, double T, double rtol, double atol, double tol, int every,
+                      double* s, double* E, double* h_or_null, double* force_norm_out,
+                      double* dtp, int64_t* stats)
+{
+    const int64_t N = (int64_t)nx * ny * nz;
+    const int64_t M = 3 * N;
+    double* h = (double*)malloc((size_t)K * M * sizeof(double));
+    double* ss = (double*)malloc((size_t)K * M * sizeof(double));
+    double* al = (double*)malloc((size_t)K * sizeof(double));
+    double* wt = (double*)malloc((size_t)K * sizeof(double));
+    int32_t* jj = (int32_t*)malloc((size_t)K * sizeof(int32_t));
+    int it = 0;
+    if (every < 1) every = 1;
+    for (;;) {
+        if (tol > 0.0 && it % every == 0) {
+            for (int kk = 0; kk < K; ++kk)
+                oracle_field(nx, ny, nz, J, d, k, D, s + kk * M, h + kk * M);
+            if (oracle_force_norm(K, N, s, h, NULL) < tol) break;
+        }
+        if (it >= max_iter) break;
+        memcpy(ss, s, (size_t)K * M * sizeof(double));
+        for (int kk = 0; kk < K; ++kk) {
+            if (oracle_rk_interval(nx, ny, nz, J, d, k, D, ss + kk * M, T, rtol, atol, &dtp[kk],
+                                   &stats[2 * kk], &stats[2 * kk + 1], 1000000) != 0) {
+                it = -1;
+                goto out;
+            }
+        }
+        oracle_reparam(K, N, ss, s, al, jj, wt);
+        ++it;
+    }
+    for (int kk = 0; kk < K; ++kk) {
+        oracle_field(nx, ny, nz, J, d, k, D, s + kk * M, h + kk * M);
+        E[kk] = oracle_energy_from_field(N, s + kk * M, h + kk * M);
+    }
+    if (h_or_null) memcpy(h_or_null, h, (size_t)K * M * sizeof(double));
+    if (force_norm_out) *force_norm_out = oracle_force_norm(K, N, s, h, NULL);
+out:
     free(h); free(ss); free(al); free(wt); free(jj);
     return it;
 }

@@ -56,6 +56,15 @@ def _load():
         lib.oracle_iterate.argtypes = [_i, _i, _i, _d, _d, _d, _d, _i, _i, _d, _d, _i,
                                        _p, _p, _p, _p]
         lib.oracle_iterate.restype = _i
+        lib.oracle_dopri_tableau.argtypes = [_p, _p, _p, _p]
+        lib.oracle_rk_rhs.argtypes = [_i, _i, _i, _d, _d, _d, _d, _p, _p, _p]
+        lib.oracle_dopri_fixed.argtypes = [_i, _i, _i, _d, _d, _d, _d, _p, _d, _i]
+        lib.oracle_dopri_fixed.restype = _d
+        lib.oracle_rk_interval.argtypes = [_i, _i, _i, _d, _d, _d, _d, _p, _d, _d, _d, _p, _p, _p, _i]
+        lib.oracle_rk_interval.restype = _i
+        lib.oracle_iterate_rk.argtypes = [_i, _i, _i, _d, _d, _d, _d, _i, _i, _d, _d, _d, _d, _i,
+                                          _p, _p, _p, _p, _p, _p]
+        lib.oracle_iterate_rk.restype = _i
         _lib = lib
     return _lib
 
@@ -174,3 +183,61 @@ def barrier(E):
     E = np.asarray(E, dtype=np.float64)
     km = int(np.argmax(E))
     return float(E[km] - E[0]), km
+
+
+def dopri_tableau():
+    """Dormand-Prince 5(4) coefficients used by the integrator: (A[7,7], b, b*, c)."""
+    a = np.zeros(49)
+    b = np.zeros(7)
+    bs = np.zeros(7)
+    c = np.zeros(7)
+    _load().oracle_dopri_tableau(_ptr(a), _ptr(b), _ptr(bs), _ptr(c))
+    return a.reshape(7, 7), b, bs, c
+
+
+def rk_rhs(s, J, d, k, D):
+    """Damping-only right-hand side f(s) = (s.s) h - (s.h) s of one image; returns (f, h)."""
+    s = _f64(s)
+    nx, ny, nz = _dims(s)
+    f = np.empty_like(s)
+    h = np.empty_like(s)
+    _load().oracle_rk_rhs(nx, ny, nz, J, d, k, D, _ptr(s), _ptr(f), _ptr(h))
+    return f, h
+
+
+def dopri_fixed(s, J, d, k, D, hs, n):
+    """n fixed Dormand-Prince steps of size hs on a copy of one image (no
+    renormalisation); returns (y, RMS of the last step's error estimate)."""
+    y = _f64(s).copy()
+    nx, ny, nz = _dims(y)
+    err = _load().oracle_dopri_fixed(nx, ny, nz, J, d, k, D, _ptr(y), hs, n)
+    return y, err
+
+
+def rk_interval(s, J, d, k, D, T, rtol, atol, dt0, max_steps=1000000):
+    """Evolve one image over T with step control (copy); returns dict(y, dt, acc, rej, ok)."""
+    y = _f64(s).copy()
+    nx, ny, nz = _dims(y)
+    dtp = np.array([dt0], dtype=np.float64)
+    acc = np.zeros(1, dtype=np.int64)
+    rej = np.zeros(1, dtype=np.int64)
+    rc = _load().oracle_rk_interval(nx, ny, nz, J, d, k, D, _ptr(y), T, rtol, atol, _ptr(dtp),
+                                    _ptr(acc), _ptr(rej), max_steps)
+    return dict(y=y, dt=float(dtp[0]), acc=int(acc[0]), rej=int(rej[0]), ok=rc == 0)
+
+
+def iterate_rk(s, J, d, k, D, max_iter, T, rtol, atol, dt0, tol=0.0, every=1, want_fields=False):
+    """The string method with step 1 by the adaptive Dormand-Prince integrator
+    over T per image.  Returns dict(s, E, iters, force, h, dt[K], stats[K,2])."""
+    s = _f64(s).copy()
+    K = s.shape[0]
+    nx, ny, nz = _dims(s[0])
+    E = np.zeros(K)
+    h = np.empty_like(s) if want_fields else None
+    fn = np.zeros(1)
+    dtp = np.full(K, float(dt0))
+    stats = np.zeros(2 * K, dtype=np.int64)
+    it = _load().oracle_iterate_rk(nx, ny, nz, J, d, k, D, K, max_iter, T, rtol, atol, tol, every,
+                                   _ptr(s), _ptr(E), _ptr(h) if want_fields else None, _ptr(fn),
+                                   _ptr(dtp), _ptr(stats))
+    return dict(s=s, E=E, iters=it, force=float(fn[0]), h=h, dt=dtp, stats=stats.reshape(K, 2))
