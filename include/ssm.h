@@ -82,10 +82,20 @@ typedef int32_t ssm_status;
                              arithmetic, energies, arc lengths, weights and the
                              barrier in FP64 */
 
+/* OR into the precision argument of ssm_workspace_size and ssm_create to
+ * reserve the workspace of the adaptive integrator (8 more string-sized
+ * buffers); needed for SSM_STEP_DOPRI54. */
+#define SSM_WITH_RK 0x100
+
+/* Step 1 of the string iteration (ssm_set_integrator) */
+#define SSM_STEP_EULER 0    /* one explicit projected step of size tau (default) */
+#define SSM_STEP_DOPRI54 1  /* adaptive Dormand-Prince 5(4) over an interval tau */
+
 /* ssm_check flag bits */
 #define SSM_FLAG_NONFINITE_ENERGY 1
 #define SSM_FLAG_ZERO_NORM_SPIN 2
 #define SSM_FLAG_NONFINITE_SPIN 4
+#define SSM_FLAG_RK_ERROR 8  /* the integrator's error estimate was not finite */
 
 /* One lattice + parameter set (reduced units, see above).  K = n_images. */
 typedef struct {
@@ -102,7 +112,8 @@ int32_t ssm_version(void);
 
 /* Bytes of device workspace a context for these problems needs.
  * p[n_problems]: problem descriptions (host memory).  precision: SSM_FP64
- * or SSM_FP32_MIXED.  *bytes receives the size.  Pure host computation. */
+ * or SSM_FP32_MIXED, optionally | SSM_WITH_RK.  *bytes receives the size.
+ * Pure host computation. */
 ssm_status ssm_workspace_size(const ssm_problem* p, int32_t n_problems, int32_t precision,
                               size_t* bytes);
 
@@ -148,6 +159,34 @@ ssm_status ssm_get_string(ssm_ctx* ctx, void* d_spins);
  * iterations each problem performed in this call. */
 ssm_status ssm_iterate(ssm_ctx* ctx, int32_t max_iter, double tau, double tol_force,
                        int32_t* d_iters_done);
+
+/* Choose step 1 of ssm_iterate.  SSM_STEP_EULER (default): one projected
+ * step of size tau.  SSM_STEP_DOPRI54 (Sec. III: each image evolved over an
+ * interval by an explicit embedded Runge-Kutta method with adaptive step
+ * size): every image, endpoints included, evolves over the interval tau of
+ * ds/dt = -s x (s x h(s)) (the damping term of eq. (9) with its prefactor
+ * in the time unit; Appendix) with the Dormand-Prince 5(4) pair, fifth-order
+ * solution propagated, first-same-as-last.  Per image: error norm
+ * err = RMS over its 3N components of (y5 - y4) / (atol + rtol
+ * max(|y|, |y5|)); a step is accepted iff err <= 1; the next step is the
+ * attempted one times clamp(0.9 err^(-1/5), 0.2, 5) (at most 1 after a
+ * rejection), shortened to end exactly at tau; the proposal carries over
+ * to the next iteration.  Stage states are not normalised; every spin is
+ * renormalised at the end of the interval.  The energies of an iteration
+ * are those of the string before its step (as for the Euler step).  Needs a
+ * context created with SSM_WITH_RK (else SSM_EUNSUPPORTED); rtol >= 0,
+ * atol > 0, dt0 > 0 (initial step proposal of every image).  Resets the
+ * proposals and the statistics of ssm_get_rk_stats.  ssm_iterate then runs
+ * without graph replay and synchronises the stream after every attempt
+ * (the number of attempts adapts). */
+ssm_status ssm_set_integrator(ssm_ctx* ctx, int32_t method, double rtol, double atol, double dt0);
+
+/* Integrator statistics since ssm_set_integrator.  d_counts (device
+ * int32[sum K][2] or NULL): accepted and rejected steps per image; d_dt
+ * (device double[sum K] or NULL): current step proposal per image;
+ * h_evals (host, or NULL): field evaluations (of all images at once) done
+ * by the integrator.  SSM_EUNSUPPORTED without SSM_WITH_RK. */
+ssm_status ssm_get_rk_stats(ssm_ctx* ctx, int32_t* d_counts, double* d_dt, int64_t* h_evals);
 
 /* Evaluate field and energies of a string without changing the context's
  * string.  d_spins: a string in the context layout, or NULL for the
@@ -213,7 +252,7 @@ const char* ssm_last_error(const ssm_ctx* ctx);
  * launches).  ssm_profile_read synchronises, adds the elapsed times per
  * kernel kind since enabling into h_ms[SSM_N_KERNELS] (milliseconds) and
  * h_counts[SSM_N_KERNELS] (launches), and resets the accumulators. */
-#define SSM_N_KERNELS 12
+#define SSM_N_KERNELS 13
 ssm_status ssm_profile(ssm_ctx* ctx, int32_t enable);
 ssm_status ssm_profile_read(ssm_ctx* ctx, double* h_ms, int32_t* h_counts);
 

@@ -28,7 +28,7 @@ thread_local std::string g_create_error;
 
 const char* const kKernelNames[SSM_N_KERNELS] = {
     "k_xfwd", "k_conv", "k_xinv", "k_arc", "k_reduce", "k_interp",
-    "k_tan1", "k_tan2", "k_tanred", "k_spec", "k_util", "graph"};
+    "k_tan1", "k_tan2", "k_tanred", "k_spec", "k_util", "graph", "k_rk"};
 
 int pow2ceil(int n)
 {
@@ -59,6 +59,7 @@ struct Plan {
     int np = 0;
     int mz = 1;
     int conv_kinds = 0;               // convolution builds in use (launch_conv)
+    bool rk = false;                  // workspace of the adaptive integrator reserved
     size_t tsize = 8;                 // bytes of one spin component
     std::vector<Prob> P;
     std::vector<Tiles> tiles;         // tile shapes in use, per problem
@@ -72,6 +73,10 @@ struct Plan {
     // workspace offsets
     size_t o_P, o_wm, o_tw, o_tw64, o_s, o_ss, o_h, o_nh, o_big, o_ep, o_ap, o_fp, o_E, o_T,
         o_alpha, o_w, o_tc, o_fn, o_fm, o_j, o_done, o_iters, o_skip, o_flags, o_seg, o_cnt, total;
+    // adaptive integrator (when rk): 7 slopes + stage input (string-sized),
+    // per-image state
+    size_t o_rk_k = 0, o_rk_y = 0, o_rk_t = 0, o_rk_dtp = 0, o_rk_dtu = 0, o_rk_cap = 0, o_rk_act = 0,
+           o_rk_acc = 0, o_rk_cnt = 0, o_rk_nact = 0;
 };
 
 // LDS bytes of the FFT kernels: twiddle table (2m complex) + line buffer in
@@ -184,13 +189,16 @@ int conv_wgs(const Prob& p)
     return (w + 7) / 8 * 8;
 }
 
-ssm_status build_plan(const ssm_problem* pr, int np, int prec, const std::vector<Tiles>* tiles,
+ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::vector<Tiles>* tiles,
                       Plan& pl, std::string& err)
 {
+    const bool rk = (prec_flags & SSM_WITH_RK) != 0;
+    const int prec = prec_flags & ~SSM_WITH_RK;
     ssm_status st = check_problems(pr, np, prec, err);
     if (st != SSM_OK) return st;
     pl = Plan();
     pl.prec = prec;
+    pl.rk = rk;
     pl.np = np;
     pl.tsize = prec == SSM_FP64 ? 8 : 4;
     pl.P.resize(np);
@@ -306,6 +314,18 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec, const std::vector
     pl.o_flags = take(4);
     pl.o_seg = take(8 * img);
     pl.o_cnt = take(4 * np);
+    if (rk) {
+        pl.o_rk_k = take(7 * ts * spin);
+        pl.o_rk_y = take(ts * spin);
+        pl.o_rk_t = take(8 * img);
+        pl.o_rk_dtp = take(8 * img);
+        pl.o_rk_dtu = take(8 * img);
+        pl.o_rk_cap = take(4 * img);
+        pl.o_rk_act = take(4 * img);
+        pl.o_rk_acc = take(4 * img);
+        pl.o_rk_cnt = take(8 * img);
+        pl.o_rk_nact = take(4);
+    }
     pl.total = o;
     return SSM_OK;
 }
@@ -329,6 +349,10 @@ struct ssm_ctx {
     double graph_tau = 0;
     int graph_n = 0;
     bool profiling = false;
+    // step 1 method (ssm_set_integrator)
+    int rk_method = SSM_STEP_EULER;
+    double rk_rtol = 1e-6, rk_atol = 1e-6, rk_dt0 = 0.1;
+    long long rk_nfe = 0;             // field evaluations by the integrator
     struct Ev { int kind; hipEvent_t a, b; };
     std::vector<Ev> events;
     std::vector<hipEvent_t> pool;
@@ -452,6 +476,84 @@ struct Ops {
                                     c->at<double>(pl.o_w), c->at<int>(pl.o_skip), done,
                                     c->at<int>(pl.o_flags), st);
         });
+    }
+
+    // Step 1 by the adaptive Dormand-Prince pair over the interval Tint for
+    // every image, then arc length, reduction and interpolation as in
+    // iteration().  The attempts are driven from the host: after each one
+    // the number of images still integrating is read back.
+    static ssm_status rk_iteration(ssm_ctx* c, double Tint)
+    {
+        const Plan& pl = c->pl;
+        hipStream_t st = c->stream;
+        T* s = c->at<T>(pl.o_s);
+        T* ss = c->at<T>(pl.o_ss);
+        T* y = c->at<T>(pl.o_rk_y);
+        int* done = c->at<int>(pl.o_done);
+        int* flags = c->at<int>(pl.o_flags);
+        RkSlopes<T> ks;
+        for (int j = 0; j < 7; ++j) ks.k[j] = c->at<T>(pl.o_rk_k) + (size_t)j * pl.n_spin;
+        RkState rs{c->at<double>(pl.o_rk_t), c->at<double>(pl.o_rk_dtp), c->at<double>(pl.o_rk_dtu),
+                   c->at<int>(pl.o_rk_cap), c->at<int>(pl.o_rk_act), c->at<int>(pl.o_rk_acc),
+                   c->at<int>(pl.o_rk_cnt), c->at<int>(pl.o_rk_nact)};
+        const int nimg = (int)pl.n_img;
+        const int* istart = c->wm_img().start;
+        HIPCHK(c, timed(c, st, KK_RK, [&] { return launch_rk_init(c->P(), pl.np, nimg, istart, rs, Tint, done, st); }),
+               "integrator");
+        // first slope f(s), and the energies of the string before the step
+        HIPCHK(c, field(c, st, s, nullptr, ks.k[0], EPI_FORCE, 0.0, done), "integrator");
+        HIPCHK(c, timed(c, st, KK_REDUCE, [&] {
+                   return launch_reduce(c->P(), pl.np, nimg, istart, c->at<double>(pl.o_ep), nullptr,
+                                        c->at<double>(pl.o_E), nullptr, nullptr, nullptr, nullptr, nullptr,
+                                        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, flags, 0, st);
+               }), "integrator");
+        c->rk_nfe += 1;
+        constexpr int kMaxAttempts = 100000;
+        int hnact = 0;
+        for (int att = 0;; ++att) {
+            if (att >= kMaxAttempts)
+                return fail(c, SSM_ENONFINITE, "adaptive integrator: interval not completed within the attempt limit");
+            for (int i = 1; i < 7; ++i) {
+                HIPCHK(c, timed(c, st, KK_RK, [&] {
+                           return launch_rk_stage<T>(c->P(), pl.np, c->wm_site(), s, ks, i, rs, y, done, st);
+                       }), "integrator");
+                HIPCHK(c, field(c, st, y, nullptr, ks.k[i], EPI_FORCE, 0.0, done), "integrator");
+            }
+            c->rk_nfe += 6;
+            HIPCHK(c, launch_fill_int(rs.nact, 1, 0, st), "integrator");
+            HIPCHK(c, timed(c, st, KK_RK, [&] {
+                       return launch_rk_err<T>(c->P(), pl.np, c->wm_site(), s, y, ks, rs, c->rk_rtol, c->rk_atol,
+                                               c->at<double>(pl.o_fm), done, st);
+                   }), "integrator");
+            HIPCHK(c, timed(c, st, KK_RK, [&] {
+                       return launch_rk_ctrl(c->P(), pl.np, nimg, istart, c->at<double>(pl.o_fm), rs, Tint, done,
+                                             flags, st);
+                   }), "integrator");
+            HIPCHK(c, timed(c, st, KK_RK, [&] {
+                       return launch_rk_apply<T>(c->P(), pl.np, c->wm_site(), s, y, ks, rs, done, st);
+                   }), "integrator");
+            HIPCHK(c, hipMemcpyAsync(&hnact, rs.nact, sizeof(int), hipMemcpyDeviceToHost, st), "integrator");
+            HIPCHK(c, hipStreamSynchronize(st), "integrator");
+            if (hnact == 0) break;
+        }
+        HIPCHK(c, timed(c, st, KK_RK, [&] {
+                   return launch_rk_norm<T>(c->P(), pl.np, c->wm_site(), s, ss, done, flags, st);
+               }), "integrator");
+        HIPCHK(c, timed(c, st, KK_ARC, [&] {
+                   return launch_arc<T>(c->P(), pl.np, c->wm_arc(), ss, c->at<double>(pl.o_ap), done, st);
+               }), "integrator");
+        HIPCHK(c, timed(c, st, KK_REDUCE, [&] {
+                   return launch_reduce(c->P(), pl.np, nimg, istart, c->at<double>(pl.o_ep),
+                                        c->at<double>(pl.o_ap), nullptr, nullptr, nullptr, nullptr,
+                                        c->at<double>(pl.o_seg), c->at<double>(pl.o_alpha), c->at<int>(pl.o_j),
+                                        c->at<double>(pl.o_w), c->at<int>(pl.o_skip), done,
+                                        c->at<int>(pl.o_iters), c->at<int>(pl.o_cnt), flags, 1, st);
+               }), "integrator");
+        HIPCHK(c, timed(c, st, KK_INTERP, [&] {
+                   return launch_interp<T>(c->P(), pl.np, c->wm_site(), ss, s, c->at<int>(pl.o_j),
+                                           c->at<double>(pl.o_w), c->at<int>(pl.o_skip), done, flags, st);
+               }), "integrator");
+        return SSM_OK;
     }
 
     // evaluation of `src` (current string when store)
@@ -880,6 +982,45 @@ ssm_status ssm_get_string(ssm_ctx* ctx, void* d_spins)
     return SSM_OK;
 }
 
+ssm_status ssm_set_integrator(ssm_ctx* ctx, int32_t method, double rtol, double atol, double dt0)
+{
+    if (!ctx) return SSM_EINVAL;
+    if (method != SSM_STEP_EULER && method != SSM_STEP_DOPRI54)
+        return fail(ctx, SSM_EINVAL, "unknown step method");
+    if (method == SSM_STEP_EULER) {
+        ctx->rk_method = method;
+        return SSM_OK;
+    }
+    if (!ctx->pl.rk) return fail(ctx, SSM_EUNSUPPORTED, "context created without SSM_WITH_RK");
+    if (!(rtol >= 0.0) || !(atol > 0.0) || !(dt0 > 0.0) || !std::isfinite(rtol) || !std::isfinite(atol) ||
+        !std::isfinite(dt0))
+        return fail(ctx, SSM_EINVAL, "rtol >= 0, atol > 0 and dt0 > 0 (finite) required");
+    ctx->rk_method = method;
+    ctx->rk_rtol = rtol;
+    ctx->rk_atol = atol;
+    ctx->rk_dt0 = dt0;
+    ctx->rk_nfe = 0;
+    const Plan& pl = ctx->pl;
+    HIPCHK(ctx, launch_fill_double(ctx->at<double>(pl.o_rk_dtp), (int)pl.n_img, dt0, ctx->stream), "set integrator");
+    HIPCHK(ctx, launch_fill_int(ctx->at<int>(pl.o_rk_cnt), (int)(2 * pl.n_img), 0, ctx->stream), "set integrator");
+    return SSM_OK;
+}
+
+ssm_status ssm_get_rk_stats(ssm_ctx* ctx, int32_t* d_counts, double* d_dt, int64_t* h_evals)
+{
+    if (!ctx) return SSM_EINVAL;
+    const Plan& pl = ctx->pl;
+    if (!pl.rk) return fail(ctx, SSM_EUNSUPPORTED, "context created without SSM_WITH_RK");
+    if (d_counts)
+        HIPCHK(ctx, hipMemcpyAsync(d_counts, ctx->ws + pl.o_rk_cnt, 8 * pl.n_img, hipMemcpyDeviceToDevice,
+                                   ctx->stream), "rk stats");
+    if (d_dt)
+        HIPCHK(ctx, hipMemcpyAsync(d_dt, ctx->ws + pl.o_rk_dtp, 8 * pl.n_img, hipMemcpyDeviceToDevice,
+                                   ctx->stream), "rk stats");
+    if (h_evals) *h_evals = ctx->rk_nfe;
+    return SSM_OK;
+}
+
 ssm_status ssm_set_options(ssm_ctx* ctx, int32_t check_every, int32_t graph_chunk)
 {
     if (!ctx) return SSM_EINVAL;
@@ -939,6 +1080,15 @@ ssm_status ssm_iterate(ssm_ctx* ctx, int32_t max_iter, double tau, double tol_fo
         if (it >= max_iter) break;
         int n = max_iter - it;
         if (check) n = std::min(n, c->check_every - it % c->check_every);
+        if (c->rk_method == SSM_STEP_DOPRI54) {
+            for (int i = 0; i < n; ++i) {
+                ssm_status st = pl.prec == SSM_FP64 ? Ops<double>::rk_iteration(c, tau)
+                                                    : Ops<float>::rk_iteration(c, tau);
+                if (st != SSM_OK) return st;
+            }
+            it += n;
+            continue;
+        }
         if (use_graph && n >= c->graph_chunk) {
             const int reps = n / c->graph_chunk;
             ssm_status st = ensure_graph(c, tau, c->graph_chunk);

@@ -65,7 +65,7 @@ __host__ __device__ constexpr int padded_len(int n, int padl) { return padl ? n 
 // Kernel kinds (profiling slots; names in the runtime).
 enum KernelKind {
     KK_XFWD = 0, KK_CONV, KK_XINV, KK_ARC, KK_REDUCE, KK_INTERP,
-    KK_TAN1, KK_TAN2, KK_TANRED, KK_SPEC, KK_UTIL, KK_COUNT_
+    KK_TAN1, KK_TAN2, KK_TANRED, KK_SPEC, KK_UTIL, KK_GRAPH, KK_RK, KK_COUNT_
 };
 
 // Per-problem descriptor, resident in device memory (read-only in kernels).
@@ -117,8 +117,10 @@ template <typename T>
 hipError_t launch_conv(int mz, int kinds, const Prob* P, int np, const WorkMap& wm, void* X,
                        void* Xp, const T* nhat, const void* tw, const int* done, size_t lds,
                        hipStream_t st);
-// mode bits for the inverse/epilogue kernel
-enum { EPI_STEP = 1, EPI_FIELD = 2, EPI_TERMS = 4 };
+// mode bits for the inverse/epilogue kernel: EPI_STEP writes the stepped
+// string, EPI_FIELD the field h, EPI_FORCE the damping right-hand side
+// (s.s) h - (s.h) s in place of h, EPI_TERMS the four term partials
+enum { EPI_STEP = 1, EPI_FIELD = 2, EPI_TERMS = 4, EPI_FORCE = 8 };
 template <typename T>
 hipError_t launch_xinv(const Prob* P, int np, const WorkMap& wm, const void* Xp, const void* Xq, const T* s,
                        T* s_star, T* h, double* epart, const void* tw, const int* done,
@@ -153,5 +155,42 @@ hipError_t launch_barrier(const Prob* P, int np, const double* E, const double* 
 hipError_t launch_iters_out(int np, const int* iters, const int* iters0, int* out,
                             hipStream_t st);
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st);
+hipError_t launch_fill_double(double* p, int n, double v, hipStream_t st);
+
+// Adaptive Dormand-Prince 5(4) step 1.  Per image (batch-wide index g):
+// t[g] time reached in the interval, dtp[g] proposed step, dtu[g] step of
+// the current attempt, capped[g] whether that attempt ends the interval,
+// act[g] still integrating, acc[g] current attempt accepted, cnt[2g..]
+// accepted / rejected steps; nact counts active images after control.
+struct RkState {
+    double* t;
+    double* dtp;
+    double* dtu;
+    int* capped;
+    int* act;
+    int* acc;
+    int* cnt;
+    int* nact;
+};
+template <typename T>
+struct RkSlopes {
+    T* k[7];
+};
+hipError_t launch_rk_init(const Prob* P, int np, int nimg, const int* istart, RkState rs, double Tint,
+                          const int* done, hipStream_t st);
+template <typename T>
+hipError_t launch_rk_stage(const Prob* P, int np, const WorkMap& wm, const T* s, RkSlopes<T> ks, int stage,
+                           RkState rs, T* y, const int* done, hipStream_t st);
+template <typename T>
+hipError_t launch_rk_err(const Prob* P, int np, const WorkMap& wm, const T* s, const T* y, RkSlopes<T> ks,
+                         RkState rs, double rtol, double atol, double* part, const int* done, hipStream_t st);
+hipError_t launch_rk_ctrl(const Prob* P, int np, int nimg, const int* istart, const double* part, RkState rs,
+                          double Tint, const int* done, int* flags, hipStream_t st);
+template <typename T>
+hipError_t launch_rk_apply(const Prob* P, int np, const WorkMap& wm, T* s, const T* y, RkSlopes<T> ks,
+                           RkState rs, const int* done, hipStream_t st);
+template <typename T>
+hipError_t launch_rk_norm(const Prob* P, int np, const WorkMap& wm, const T* s, T* ss, const int* done,
+                          int* flags, hipStream_t st);
 
 }  // namespace ssm

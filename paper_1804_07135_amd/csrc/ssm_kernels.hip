@@ -781,7 +781,12 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                     acc[3] += -sv[2] * sv[2];
                     acc[4] += -0.5 * (sv[0] * hu[0] + sv[1] * hu[1] + sv[2] * hu[2]);
                 }
-                if (mode & EPI_FIELD) {
+                if (mode & EPI_FORCE) {
+                    // damping right-hand side -s x (s x h) = (s.s) h - (s.h) s
+                    const double s2 = sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) hout[soff + (long long)c * N + i] = (T)(s2 * h[c] - sh * sv[c]);
+                } else if (mode & EPI_FIELD) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) hout[soff + (long long)c * N + i] = (T)h[c];
                 }
@@ -1490,6 +1495,286 @@ hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Step 1 by the adaptive Dormand-Prince 5(4) pair (Sec. III: each image is
+// evolved over an interval by explicit embedded Runge-Kutta with adaptive
+// step size; right-hand side the damping term of eq. (9), f = (s.s) h -
+// (s.h) s, evaluated by the field kernels in EPI_FORCE mode).  Coefficients
+// of Dormand and Prince (1980): stage rows, and the difference of the
+// fifth- and fourth-order weights for the error estimate.  The last stage's
+// input is the fifth-order solution (its row equals the weights).
+// ---------------------------------------------------------------------------
+__constant__ double kDopriA[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5, 0, 0, 0, 0, 0},
+    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+    {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+__constant__ double kDopriE[7] = {35.0 / 384 - 5179.0 / 57600, 0.0, 500.0 / 1113 - 7571.0 / 16695,
+                                  125.0 / 192 - 393.0 / 640, -2187.0 / 6784 + 92097.0 / 339200,
+                                  11.0 / 84 - 187.0 / 2100, -1.0 / 40};
+
+// per-image start of an interval: t = 0, first attempt's step
+__global__ void k_rk_init(const Prob* __restrict__ P, int np, int nimg, const int* __restrict__ istart,
+                          RkState rs, double Tint, const int* __restrict__ done)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nimg) return;
+    const int pi = find_problem(istart, np, g);
+    rs.t[g] = 0.0;
+    rs.acc[g] = 0;
+    const bool on = !(done && done[pi]);
+    rs.act[g] = on ? 1 : 0;
+    const int cap = rs.dtp[g] >= Tint;
+    rs.capped[g] = cap;
+    rs.dtu[g] = cap ? Tint : rs.dtp[g];
+}
+
+// stage input y = s + dtu * sum_{j < stage} a[stage][j] k_j (FP64 sums);
+// images that are not integrating get y = s
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_rk_stage(const Prob* __restrict__ P, int np,
+                                                  const int* __restrict__ wstart, const T* __restrict__ s,
+                                                  RkSlopes<T> ks, int stage, RkState rs, T* __restrict__ y,
+                                                  const int* __restrict__ done)
+{
+    const int pi = find_problem(wstart, np, blockIdx.x);
+    if (done && done[pi]) return;
+    const Prob& p = P[pi];
+    const int w = blockIdx.x - wstart[pi];
+    const int img = w / p.ichunks, chunk = w - img * p.ichunks;
+    const long long N = p.N;
+    const long long i = (long long)chunk * kNT + threadIdx.x;
+    if (i >= N) return;
+    const int g = p.img0 + img;
+    const double h = rs.act[g] ? rs.dtu[g] : 0.0;
+    const long long base = p.s_off + (long long)img * 3 * N + i;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const long long o = base + c * N;
+        double acc = 0.0;
+        for (int j = 0; j < stage; ++j) acc += kDopriA[stage][j] * (double)ks.k[j][o];
+        y[o] = (T)((double)s[o] + h * acc);
+    }
+}
+
+// error partials: sum over the workgroup's sites of (e_c / sc_c)^2, e the
+// difference of the fifth- and fourth-order solutions, sc = atol + rtol
+// max(|s|, |y5|); y holds y5 (the last stage's input)
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_rk_err(const Prob* __restrict__ P, int np,
+                                                const int* __restrict__ wstart, const T* __restrict__ s,
+                                                const T* __restrict__ y, RkSlopes<T> ks, RkState rs,
+                                                double rtol, double atol, double* __restrict__ part,
+                                                const int* __restrict__ done)
+{
+    __shared__ double red[kNT / 64];
+    const int pi = find_problem(wstart, np, blockIdx.x);
+    if (done && done[pi]) return;
+    const Prob& p = P[pi];
+    const int w = blockIdx.x - wstart[pi];
+    const int img = w / p.ichunks, chunk = w - img * p.ichunks;
+    const long long N = p.N;
+    const long long i = (long long)chunk * kNT + threadIdx.x;
+    const int g = p.img0 + img;
+    const double h = rs.dtu[g];
+    double q = 0.0;
+    if (i < N && rs.act[g]) {
+        const long long base = p.s_off + (long long)img * 3 * N + i;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const long long o = base + c * N;
+            double e = 0.0;
+#pragma unroll
+            for (int j = 0; j < 7; ++j) e += kDopriE[j] * (double)ks.k[j][o];
+            e *= h;
+            const double sc = atol + rtol * fmax(fabs((double)s[o]), fabs((double)y[o]));
+            q += (e / sc) * (e / sc);
+        }
+    }
+    q = wave_sum(q);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = 0.0;
+        for (int wv = 0; wv < kNT / 64; ++wv) v += red[wv];
+        part[p.fm_off + (long long)img * p.ichunks + chunk] = v;
+    }
+}
+
+// step control, one workgroup per image: err = sqrt(mean of the partials);
+// accept iff err <= 1; next step = step * clamp(0.9 err^(-1/5), 0.2, 5) (at
+// most 1 after a rejection); the next attempt is shortened to end at Tint
+__global__ __launch_bounds__(kNT) void k_rk_ctrl(const Prob* __restrict__ P, int np,
+                                                 const int* __restrict__ istart, const double* __restrict__ part,
+                                                 RkState rs, double Tint, const int* __restrict__ done,
+                                                 int* flags)
+{
+    __shared__ double red[kNT / 64];
+    const int g = blockIdx.x;
+    const int pi = find_problem(istart, np, g);
+    const Prob& p = P[pi];
+    const int img = g - p.img0;
+    if ((done && done[pi]) || !rs.act[g]) {
+        if (threadIdx.x == 0) rs.acc[g] = 0;
+        return;
+    }
+    double v = 0.0;
+    const double* pp = part + p.fm_off + (long long)img * p.ichunks;
+    for (int t = threadIdx.x; t < p.ichunks; t += kNT) v += pp[t];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double sum = 0.0;
+    for (int wv = 0; wv < kNT / 64; ++wv) sum += red[wv];
+    const double err = sqrt(sum / (double)(3 * p.N));
+    double fac = 0.9 * pow(fmax(err, 1e-10), -0.2);
+    fac = fmin(5.0, fmax(0.2, fac));
+    const double hs = rs.dtu[g];
+    if (!(err <= 1.0) && !isfinite(err)) {
+        // a non-finite error estimate cannot be controlled: stop this image
+        atomicOr(flags, 8);
+        rs.acc[g] = 0;
+        rs.act[g] = 0;
+        return;
+    }
+    if (err <= 1.0) {
+        rs.acc[g] = 1;
+        rs.cnt[2 * g] += 1;
+        if (rs.capped[g]) rs.act[g] = 0;
+        else rs.t[g] += hs;
+    } else {
+        rs.acc[g] = 0;
+        fac = fmin(fac, 1.0);
+        rs.cnt[2 * g + 1] += 1;
+    }
+    rs.dtp[g] = hs * fac;
+    if (rs.act[g]) {
+        const double rem = Tint - rs.t[g];
+        const int cap = rs.dtp[g] >= rem;
+        rs.capped[g] = cap;
+        rs.dtu[g] = cap ? rem : rs.dtp[g];
+        atomicAdd(rs.nact, 1);
+    }
+}
+
+// accepted images: s = y5, first slope of the next attempt = last slope
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_rk_apply(const Prob* __restrict__ P, int np,
+                                                  const int* __restrict__ wstart, T* __restrict__ s,
+                                                  const T* __restrict__ y, RkSlopes<T> ks, RkState rs,
+                                                  const int* __restrict__ done)
+{
+    const int pi = find_problem(wstart, np, blockIdx.x);
+    if (done && done[pi]) return;
+    const Prob& p = P[pi];
+    const int w = blockIdx.x - wstart[pi];
+    const int img = w / p.ichunks, chunk = w - img * p.ichunks;
+    const long long N = p.N;
+    const long long i = (long long)chunk * kNT + threadIdx.x;
+    if (i >= N || !rs.acc[p.img0 + img]) return;
+    const long long base = p.s_off + (long long)img * 3 * N + i;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        s[base + c * N] = y[base + c * N];
+        ks.k[0][base + c * N] = ks.k[6][base + c * N];
+    }
+}
+
+// end of the interval: s* = s / |s| per spin
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_rk_norm(const Prob* __restrict__ P, int np,
+                                                 const int* __restrict__ wstart, const T* __restrict__ s,
+                                                 T* __restrict__ ss, const int* __restrict__ done, int* flags)
+{
+    const int pi = find_problem(wstart, np, blockIdx.x);
+    if (done && done[pi]) return;
+    const Prob& p = P[pi];
+    const int w = blockIdx.x - wstart[pi];
+    const int img = w / p.ichunks, chunk = w - img * p.ichunks;
+    const long long N = p.N;
+    const long long i = (long long)chunk * kNT + threadIdx.x;
+    if (i >= N) return;
+    const long long base = p.s_off + (long long)img * 3 * N + i;
+    const double v[3] = {(double)s[base], (double)s[base + N], (double)s[base + 2 * N]};
+    const double nrm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    if (!(nrm >= 1e-12)) atomicOr(flags, 2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ss[base + c * N] = (T)(v[c] / nrm);
+}
+
+hipError_t launch_rk_init(const Prob* P, int np, int nimg, const int* istart, RkState rs, double Tint,
+                          const int* done, hipStream_t st)
+{
+    if (nimg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rk_init, dim3((nimg + 255) / 256), dim3(256), 0, st, P, np, nimg, istart, rs, Tint,
+                       done);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rk_stage(const Prob* P, int np, const WorkMap& wm, const T* s, RkSlopes<T> ks, int stage,
+                           RkState rs, T* y, const int* done, hipStream_t st)
+{
+    if (wm.total == 0) return hipSuccess;
+    if (stage < 1 || stage > 6) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rk_stage<T>, dim3(wm.total), dim3(kNT), 0, st, P, np, wm.start, s, ks, stage, rs, y,
+                       done);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rk_err(const Prob* P, int np, const WorkMap& wm, const T* s, const T* y, RkSlopes<T> ks,
+                         RkState rs, double rtol, double atol, double* part, const int* done, hipStream_t st)
+{
+    if (wm.total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rk_err<T>, dim3(wm.total), dim3(kNT), 0, st, P, np, wm.start, s, y, ks, rs, rtol, atol,
+                       part, done);
+    return hipGetLastError();
+}
+
+hipError_t launch_rk_ctrl(const Prob* P, int np, int nimg, const int* istart, const double* part, RkState rs,
+                          double Tint, const int* done, int* flags, hipStream_t st)
+{
+    if (nimg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rk_ctrl, dim3(nimg), dim3(kNT), 0, st, P, np, istart, part, rs, Tint, done, flags);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rk_apply(const Prob* P, int np, const WorkMap& wm, T* s, const T* y, RkSlopes<T> ks,
+                           RkState rs, const int* done, hipStream_t st)
+{
+    if (wm.total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rk_apply<T>, dim3(wm.total), dim3(kNT), 0, st, P, np, wm.start, s, y, ks, rs, done);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rk_norm(const Prob* P, int np, const WorkMap& wm, const T* s, T* ss, const int* done,
+                          int* flags, hipStream_t st)
+{
+    if (wm.total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rk_norm<T>, dim3(wm.total), dim3(kNT), 0, st, P, np, wm.start, s, ss, done, flags);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_double(double* p, int n, double v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_double(double* p, int n, double v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_double, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
 // explicit instantiations
 #define SSM_INST(T)                                                                                \
     template hipError_t launch_xfwd<T>(const Prob*, int, const WorkMap&, const T*, void*,         \
@@ -1510,7 +1795,16 @@ hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st)
     template hipError_t launch_tan2<T>(const Prob*, int, const WorkMap&, const T*, const T*,      \
                                        const T*, T*, const double*, double*, hipStream_t);         \
     template hipError_t launch_spectrum<T>(const Prob&, T*, double*, double*, const double*,      \
-                                           hipStream_t);
+                                           hipStream_t);                                           \
+    template hipError_t launch_rk_stage<T>(const Prob*, int, const WorkMap&, const T*, RkSlopes<T>, \
+                                           int, RkState, T*, const int*, hipStream_t);             \
+    template hipError_t launch_rk_err<T>(const Prob*, int, const WorkMap&, const T*, const T*,    \
+                                         RkSlopes<T>, RkState, double, double, double*,           \
+                                         const int*, hipStream_t);                                 \
+    template hipError_t launch_rk_apply<T>(const Prob*, int, const WorkMap&, T*, const T*,        \
+                                           RkSlopes<T>, RkState, const int*, hipStream_t);         \
+    template hipError_t launch_rk_norm<T>(const Prob*, int, const WorkMap&, const T*, T*,         \
+                                          const int*, int*, hipStream_t);
 SSM_INST(float)
 SSM_INST(double)
 

@@ -25,10 +25,14 @@ SSM_ENONFINITE = -4
 SSM_EUNSUPPORTED = -5
 SSM_FP64 = 0
 SSM_FP32_MIXED = 1
-SSM_N_KERNELS = 12
+SSM_WITH_RK = 0x100
+SSM_STEP_EULER = 0
+SSM_STEP_DOPRI54 = 1
+SSM_N_KERNELS = 13
 FLAG_NONFINITE_ENERGY = 1
 FLAG_ZERO_NORM_SPIN = 2
 FLAG_NONFINITE_SPIN = 4
+FLAG_RK_ERROR = 8
 
 # every exported entry point of include/ssm.h
 ABI_SYMBOLS = [
@@ -36,6 +40,7 @@ ABI_SYMBOLS = [
     "ssm_set_string", "ssm_get_string", "ssm_iterate", "ssm_eval", "ssm_get_energies",
     "ssm_get_fields", "ssm_get_tangents", "ssm_get_barrier", "ssm_set_options", "ssm_autotune",
     "ssm_check", "ssm_last_error", "ssm_profile", "ssm_profile_read", "ssm_kernel_name",
+    "ssm_set_integrator", "ssm_get_rk_stats",
 ]
 
 
@@ -87,6 +92,8 @@ def load():
         "ssm_profile": (_i32, [_vp, _i32]),
         "ssm_profile_read": (_i32, [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_i32)]),
         "ssm_kernel_name": (ctypes.c_char_p, [_i32]),
+        "ssm_set_integrator": (_i32, [_vp, _i32, _dbl, _dbl, _dbl]),
+        "ssm_get_rk_stats": (_i32, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -208,6 +215,16 @@ def ssm_autotune(ctx, cache_path=None):
     _check(load().ssm_autotune(ctx, cache_path.encode() if cache_path else None), ctx)
 
 
+def ssm_set_integrator(ctx, method, rtol=1e-6, atol=1e-6, dt0=0.1):
+    _check(load().ssm_set_integrator(ctx, int(method), float(rtol), float(atol), float(dt0)), ctx)
+
+
+def ssm_get_rk_stats(ctx, counts=None, dt=None):
+    n = ctypes.c_int64(0)
+    _check(load().ssm_get_rk_stats(ctx, _ptr(counts), _ptr(dt), ctypes.byref(n)), ctx)
+    return n.value
+
+
 def ssm_check(ctx):
     f = _i32(0)
     st = load().ssm_check(ctx, ctypes.byref(f))
@@ -234,10 +251,11 @@ class StringMethod:
     """A context plus its workspace for one or more problems.
 
     problems: dicts with nx, ny, nz, K, J, d, ku, D.  precision: SSM_FP64 or
-    SSM_FP32_MIXED.  Strings are torch tensors of shape [sum K, 3, nz, ny, nx]
-    (a single problem) or flat [sum K*3*N] (any batch)."""
+    SSM_FP32_MIXED; with_rk reserves the adaptive integrator's workspace.
+    Strings are torch tensors of shape [sum K, 3, nz, ny, nx] (a single
+    problem) or flat [sum K*3*N] (any batch)."""
 
-    def __init__(self, problems, precision=SSM_FP64, device="cuda", stream=None):
+    def __init__(self, problems, precision=SSM_FP64, device="cuda", stream=None, with_rk=False):
         if isinstance(problems, dict):
             problems = [problems]
         self.problems = [dict(p) for p in problems]
@@ -245,11 +263,12 @@ class StringMethod:
         self.dtype = torch.float64 if precision == SSM_FP64 else torch.float32
         self.device = torch.device(device)
         self.stream = stream
-        nbytes = ssm_workspace_size(self.problems, precision)
+        flags = precision | (SSM_WITH_RK if with_rk else 0)
+        nbytes = ssm_workspace_size(self.problems, flags)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         off = (-self.workspace.data_ptr()) % 256
         self._ws = self.workspace[off:off + nbytes]
-        self.ctx = ssm_create(self.problems, precision, self._ws, stream)
+        self.ctx = ssm_create(self.problems, flags, self._ws, stream)
         self.n_img = sum(int(p["K"]) for p in self.problems)
         self.sizes = [int(p["K"]) * 3 * int(p["nx"]) * int(p["ny"]) * int(p["nz"]) for p in self.problems]
         self.n_spin = sum(self.sizes)
@@ -334,6 +353,19 @@ class StringMethod:
 
     def check(self):
         return ssm_check(self.ctx)
+
+    def set_integrator(self, method, rtol=1e-6, atol=1e-6, dt0=0.1):
+        """Step 1 of iterate(): SSM_STEP_EULER (tau = step) or SSM_STEP_DOPRI54
+        (tau = interval of the adaptive Dormand-Prince integration)."""
+        ssm_set_integrator(self.ctx, method, rtol, atol, dt0)
+
+    def rk_stats(self):
+        """(accepted/rejected steps per image [sum K, 2], step proposals [sum K],
+        field evaluations of the whole batch)."""
+        counts = torch.zeros((self.n_img, 2), dtype=torch.int32, device=self.device)
+        dt = torch.zeros(self.n_img, dtype=torch.float64, device=self.device)
+        n = ssm_get_rk_stats(self.ctx, counts, dt)
+        return counts, dt, n
 
     def set_options(self, check_every=10, graph_chunk=0):
         ssm_set_options(self.ctx, check_every, graph_chunk)
