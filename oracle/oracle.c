@@ -34,7 +34,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define ORACLE_VERSION 2
+#define ORACLE_VERSION 3
 
 int oracle_version(void) { return ORACLE_VERSION; }
 
@@ -518,9 +518,14 @@ void oracle_dopri_tableau(double* a, double* b, double* bs, double* c)
     }
 }
 
-/* f(y) of one image (SoA [3][N]); h receives the field of y. */
-void oracle_rk_rhs(int nx, int ny, int nz, double J, double d, double k, double D,
-                   const double* y, double* f, double* h)
+/* Right-hand side of eq. (9) in reduced time (unit mu0|S| / (gamma J)):
+ *   ds/dt = -cp (s x h) - cd s x (s x h) = -cp (s x h) + cd ((s.s) h - (s.h) s)
+ * with cp = 1/(1+alpha^2), cd = alpha/(1+alpha^2) for the full LLG equation,
+ * and cp = 0, cd = 1 for the damping term alone (step 1 of the string
+ * method, whose prefactor is absorbed into the time unit).  One image (SoA
+ * [3][N]); h receives the field of y. */
+void oracle_llg_rhs(int nx, int ny, int nz, double J, double d, double k, double D, double cp, double cd,
+                    const double* y, double* f, double* h)
 {
     const int64_t N = (int64_t)nx * ny * nz;
     oracle_field(nx, ny, nz, J, d, k, D, y, h);
@@ -529,16 +534,24 @@ void oracle_rk_rhs(int nx, int ny, int nz, double J, double d, double k, double 
         const double w[3] = {h[i], h[N + i], h[2 * N + i]};
         const double ss = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
         const double sh = v[0] * w[0] + v[1] * w[1] + v[2] * w[2];
-        for (int c = 0; c < 3; ++c) f[c * N + i] = ss * w[c] - sh * v[c];
+        const double x[3] = {v[1] * w[2] - v[2] * w[1], v[2] * w[0] - v[0] * w[2], v[0] * w[1] - v[1] * w[0]};
+        for (int c = 0; c < 3; ++c) f[c * N + i] = cd * (ss * w[c] - sh * v[c]) - cp * x[c];
     }
+}
+
+/* the damping term alone (step 1 of the string method) */
+void oracle_rk_rhs(int nx, int ny, int nz, double J, double d, double k, double D,
+                   const double* y, double* f, double* h)
+{
+    oracle_llg_rhs(nx, ny, nz, J, d, k, D, 0.0, 1.0, y, f, h);
 }
 
 /* One attempted step of size hs from y.  kk[0..6]: stage slopes, kk[0] =
  * f(y) on entry; on return kk[6] = f(y5).  y5 receives the 5th-order
  * solution; returns the scaled error norm. */
 static double dopri_attempt(int nx, int ny, int nz, double J, double d, double k, double D,
-                            const double* y, double hs, double* kk[7], double* y5, double* hscr,
-                            double rtol, double atol)
+                            double cp, double cd, const double* y, double hs, double* kk[7], double* y5,
+                            double* hscr, double rtol, double atol)
 {
     const int64_t M = 3 * (int64_t)nx * ny * nz;
     for (int i = 1; i < 7; ++i) {
@@ -547,7 +560,7 @@ static double dopri_attempt(int nx, int ny, int nz, double J, double d, double k
             for (int j = 0; j < i; ++j) acc += DP_A[i][j] * kk[j][m];
             y5[m] = y[m] + hs * acc;
         }
-        oracle_rk_rhs(nx, ny, nz, J, d, k, D, y5, kk[i], hscr);
+        oracle_llg_rhs(nx, ny, nz, J, d, k, D, cp, cd, y5, kk[i], hscr);
     }
     /* y5 now holds the last stage's input, which is the 5th-order solution */
     double sq = 0.0;
@@ -575,7 +588,7 @@ double oracle_dopri_fixed(int nx, int ny, int nz, double J, double d, double k, 
     double err = 0.0;
     for (int st = 0; st < n; ++st) {
         oracle_rk_rhs(nx, ny, nz, J, d, k, D, y, kk[0], hscr);
-        err = dopri_attempt(nx, ny, nz, J, d, k, D, y, hs, kk, y5, hscr, 0.0, 1.0);
+        err = dopri_attempt(nx, ny, nz, J, d, k, D, 0.0, 1.0, y, hs, kk, y5, hscr, 0.0, 1.0);
         memcpy(y, y5, (size_t)M * sizeof(double));
     }
     for (int i = 0; i < 7; ++i) free(kk[i]);
@@ -588,23 +601,23 @@ double oracle_dopri_fixed(int nx, int ny, int nz, double J, double d, double k, 
  * proposed step size (in: start, out: proposal for the next interval).
  * n_acc, n_rej accumulate the accepted and rejected steps.  Returns 0, or
  * -1 if max_steps attempts did not reach T. */
-int oracle_rk_interval(int nx, int ny, int nz, double J, double d, double k, double D,
-                       double* y, double T, double rtol, double atol, double* dtp,
-                       int64_t* n_acc, int64_t* n_rej, int max_steps)
+int oracle_llg_interval(int nx, int ny, int nz, double J, double d, double k, double D, double cp,
+                        double cd, double* y, double T, double rtol, double atol, double* dtp,
+                        int64_t* n_acc, int64_t* n_rej, int max_steps)
 {
     const int64_t N = (int64_t)nx * ny * nz, M = 3 * N;
     double* kk[7];
     for (int i = 0; i < 7; ++i) kk[i] = (double*)malloc((size_t)M * sizeof(double));
     double* y5 = (double*)malloc((size_t)M * sizeof(double));
     double* hscr = (double*)malloc((size_t)M * sizeof(double));
-    oracle_rk_rhs(nx, ny, nz, J, d, k, D, y, kk[0], hscr);
+    oracle_llg_rhs(nx, ny, nz, J, d, k, D, cp, cd, y, kk[0], hscr);
     double t = 0.0;
     int done = 0, steps = 0, rc = 0;
     while (!done) {
         if (steps++ >= max_steps) { rc = -1; break; }
         const int capped = (*dtp >= T - t);
         const double hs = capped ? T - t : *dtp;
-        const double err = dopri_attempt(nx, ny, nz, J, d, k, D, y, hs, kk, y5, hscr, rtol, atol);
+        const double err = dopri_attempt(nx, ny, nz, J, d, k, D, cp, cd, y, hs, kk, y5, hscr, rtol, atol);
         double fac = 0.9 * pow(fmax(err, 1e-10), -0.2);
         fac = fmin(5.0, fmax(0.2, fac));
         if (err <= 1.0) {
@@ -629,6 +642,15 @@ int oracle_rk_interval(int nx, int ny, int nz, double J, double d, double k, dou
     free(y5);
     free(hscr);
     return rc;
+}
+
+/* step 1 of the string method: the damping term alone */
+int oracle_rk_interval(int nx, int ny, int nz, double J, double d, double k, double D,
+                       double* y, double T, double rtol, double atol, double* dtp,
+                       int64_t* n_acc, int64_t* n_rej, int max_steps)
+{
+    return oracle_llg_interval(nx, ny, nz, J, d, k, D, 0.0, 1.0, y, T, rtol, atol, dtp, n_acc, n_rej,
+                               max_steps);
 }
 
 /* The string iteration of oracle_iterate with step 1 done by

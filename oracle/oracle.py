@@ -65,6 +65,9 @@ def _load():
         lib.oracle_iterate_rk.argtypes = [_i, _i, _i, _d, _d, _d, _d, _i, _i, _d, _d, _d, _d, _i,
                                           _p, _p, _p, _p, _p, _p]
         lib.oracle_iterate_rk.restype = _i
+        lib.oracle_llg_rhs.argtypes = [_i, _i, _i, _d, _d, _d, _d, _d, _d, _p, _p, _p]
+        lib.oracle_llg_interval.argtypes = [_i, _i, _i, _d, _d, _d, _d, _d, _d, _p, _d, _d, _d, _p, _p, _p, _i]
+        lib.oracle_llg_interval.restype = _i
         _lib = lib
     return _lib
 
@@ -241,3 +244,33 @@ def iterate_rk(s, J, d, k, D, max_iter, T, rtol, atol, dt0, tol=0.0, every=1, wa
                                    _ptr(s), _ptr(E), _ptr(h) if want_fields else None, _ptr(fn),
                                    _ptr(dtp), _ptr(stats))
     return dict(s=s, E=E, iters=it, force=float(fn[0]), h=h, dt=dtp, stats=stats.reshape(K, 2))
+
+
+def llg_coefficients(alpha):
+    """(cp, cd) of eq. (9) in reduced time: 1/(1+alpha^2), alpha/(1+alpha^2)."""
+    return 1.0 / (1.0 + alpha * alpha), alpha / (1.0 + alpha * alpha)
+
+
+def llg_rhs(s, J, d, k, D, alpha):
+    """Full LLG right-hand side of one image; returns (f, h)."""
+    s = _f64(s)
+    nx, ny, nz = _dims(s)
+    cp, cd = llg_coefficients(alpha)
+    f = np.empty_like(s)
+    h = np.empty_like(s)
+    _load().oracle_llg_rhs(nx, ny, nz, J, d, k, D, cp, cd, _ptr(s), _ptr(f), _ptr(h))
+    return f, h
+
+
+def llg_interval(s, J, d, k, D, alpha, T, rtol, atol, dt0, max_steps=1000000):
+    """Evolve one image by eq. (9) over T with the adaptive Dormand-Prince pair
+    (copy; renormalised at the end); returns dict(y, dt, acc, rej, ok)."""
+    y = _f64(s).copy()
+    nx, ny, nz = _dims(y)
+    cp, cd = llg_coefficients(alpha)
+    dtp = np.array([dt0], dtype=np.float64)
+    acc = np.zeros(1, dtype=np.int64)
+    rej = np.zeros(1, dtype=np.int64)
+    rc = _load().oracle_llg_interval(nx, ny, nz, J, d, k, D, cp, cd, _ptr(y), T, rtol, atol, _ptr(dtp),
+                                     _ptr(acc), _ptr(rej), max_steps)
+    return dict(y=y, dt=float(dtp[0]), acc=int(acc[0]), rej=int(rej[0]), ok=rc == 0)
