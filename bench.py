@@ -111,6 +111,34 @@ def _kernel_key(name):
     return None
 
 
+def rk_leg(ssm, torch, prob, s0, KN, args):
+    """The string iteration with the paper's integrator (adaptive Dormand-Prince
+    5(4) over an interval per image), FP32-mixed form: one warm-up iteration,
+    then args.rk_iters timed ones.  Every stage is a field evaluation of all
+    images, so site-field evals/s counts K N per evaluation."""
+    sm = ssm.StringMethod(prob, ssm.SSM_FP32_MIXED, with_rk=True)
+    sm.set_integrator(ssm.SSM_STEP_DOPRI54, args.rk_tol, args.rk_tol, 0.1)
+    sm.set_string(s0)
+    sm.iterate(1, args.rk_interval)
+    _, _, n0 = sm.rk_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sm.iterate(args.rk_iters, args.rk_interval)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    counts, _, n1 = sm.rk_stats()
+    c = counts.cpu().numpy()
+    res = {"interval": args.rk_interval, "rtol": args.rk_tol, "atol": args.rk_tol, "iters": args.rk_iters,
+           "ms_per_iter": dt / args.rk_iters * 1e3, "string_iters_per_s": args.rk_iters / dt,
+           "field_evals_per_iter": (n1 - n0) / args.rk_iters,
+           "site_field_evals_per_s": (n1 - n0) * KN / dt,
+           "accepted_steps_total": int(c[:, 0].sum()), "rejected_steps_total": int(c[:, 1].sum()),
+           "barrier": float(sm.barrier().cpu().numpy()[0][0]), "flags": int(sm.check())}
+    del sm
+    torch.cuda.empty_cache()
+    return res
+
+
 def summarize_profiles(args):
     """Turn rocprofv3 outputs of the bench and of the copy probe into the
     committed summaries: per-kernel durations, and HBM traffic of the
@@ -190,6 +218,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp32-only", action="store_true", help="skip the FP64 plain run (profiling)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--rk-iters", type=int, default=5,
+                    help="string iterations of the adaptive Dormand-Prince leg (0: skip)")
+    ap.add_argument("--rk-interval", type=float, default=0.5)
+    ap.add_argument("--rk-tol", type=float, default=1e-5)
     ap.add_argument("--autotune", action="store_true",
                     help="choose the FP32 form's tiles with the library's autotuner before timing")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -320,6 +352,8 @@ def main():
         "autotuned_tiles": tiles,
         "ms_per_step_with_events": dt32_ev / steps * 1e3,
     }
+    if args.rk_iters > 0:
+        out["rk_dopri54"] = rk_leg(ssm, torch, prob, s0, KN, args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, s0, args.cpu_budget)
     print(json.dumps(out), flush=True)

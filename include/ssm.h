@@ -181,6 +181,18 @@ ssm_status ssm_iterate(ssm_ctx* ctx, int32_t max_iter, double tau, double tol_fo
  * (the number of attempts adapts). */
 ssm_status ssm_set_integrator(ssm_ctx* ctx, int32_t method, double rtol, double atol, double dt0);
 
+/* Landau-Lifshitz-Gilbert time integration (eq. (9), precession and
+ * damping) of every image of the current string over t_total, without the
+ * reparametrisation of the string method:
+ *   ds/dt = -(s x h)/(1 + alpha^2) - alpha/(1 + alpha^2) s x (s x h)
+ * in reduced time (unit mu0 |S| / (gamma J)), with the adaptive
+ * Dormand-Prince pair of ssm_set_integrator (its rtol, atol and the
+ * per-image step proposals, which carry over); spins are renormalised at
+ * the end.  Then evaluates the new string (ssm_get_energies/fields).  Needs
+ * SSM_WITH_RK; alpha >= 0 (0: pure precession), t_total > 0.  Synchronises
+ * the stream after every attempted step. */
+ssm_status ssm_llg(ssm_ctx* ctx, double t_total, double alpha);
+
 /* Integrator statistics since ssm_set_integrator.  d_counts (device
  * int32[sum K][2] or NULL): accepted and rejected steps per image; d_dt
  * (device double[sum K] or NULL): current step proposal per image;

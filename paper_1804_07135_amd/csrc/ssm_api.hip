@@ -429,7 +429,7 @@ template <typename T>
 struct Ops {
     // x transform -> convolution -> inverse x transform + epilogue
     static hipError_t field(ssm_ctx* c, hipStream_t st, const T* src, T* s_star, T* hdst, int mode,
-                            double tau, const int* done)
+                            double tau, const int* done, double fcp = 0.0, double fcd = 1.0)
     {
         const Plan& pl = c->pl;
         const void* tw = c->at<void>(pl.o_tw);
@@ -445,7 +445,7 @@ struct Ops {
         if (e != hipSuccess) return e;
         return timed(c, st, KK_XINV, [&] {
             return launch_xinv<T>(c->P(), pl.np, c->wm_xi(), c->Xp(), c->X(), src, s_star, hdst,
-                                  c->at<double>(pl.o_ep), tw, done, mode, tau, pl.lds_xi, st);
+                                  c->at<double>(pl.o_ep), tw, done, mode, tau, fcp, fcd, pl.lds_xi, st);
         });
     }
 
@@ -478,16 +478,17 @@ struct Ops {
         });
     }
 
-    // Step 1 by the adaptive Dormand-Prince pair over the interval Tint for
-    // every image, then arc length, reduction and interpolation as in
-    // iteration().  The attempts are driven from the host: after each one
-    // the number of images still integrating is read back.
-    static ssm_status rk_iteration(ssm_ctx* c, double Tint)
+    // Adaptive Dormand-Prince integration of every image of the current
+    // string over Tint: ds/dt = -fcp (s x h) + fcd ((s.s) h - (s.h) s).  The
+    // result (not renormalised) replaces the string.  With energies, the
+    // energies of the string before the interval are reduced into E from
+    // the first slope's evaluation.  The attempts are driven from the host:
+    // after each one the number of images still integrating is read back.
+    static ssm_status rk_interval(ssm_ctx* c, double Tint, double fcp, double fcd, bool energies)
     {
         const Plan& pl = c->pl;
         hipStream_t st = c->stream;
         T* s = c->at<T>(pl.o_s);
-        T* ss = c->at<T>(pl.o_ss);
         T* y = c->at<T>(pl.o_rk_y);
         int* done = c->at<int>(pl.o_done);
         int* flags = c->at<int>(pl.o_flags);
@@ -500,13 +501,13 @@ struct Ops {
         const int* istart = c->wm_img().start;
         HIPCHK(c, timed(c, st, KK_RK, [&] { return launch_rk_init(c->P(), pl.np, nimg, istart, rs, Tint, done, st); }),
                "integrator");
-        // first slope f(s), and the energies of the string before the step
-        HIPCHK(c, field(c, st, s, nullptr, ks.k[0], EPI_FORCE, 0.0, done), "integrator");
-        HIPCHK(c, timed(c, st, KK_REDUCE, [&] {
-                   return launch_reduce(c->P(), pl.np, nimg, istart, c->at<double>(pl.o_ep), nullptr,
-                                        c->at<double>(pl.o_E), nullptr, nullptr, nullptr, nullptr, nullptr,
-                                        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, flags, 0, st);
-               }), "integrator");
+        HIPCHK(c, field(c, st, s, nullptr, ks.k[0], EPI_FORCE, 0.0, done, fcp, fcd), "integrator");
+        if (energies)
+            HIPCHK(c, timed(c, st, KK_REDUCE, [&] {
+                       return launch_reduce(c->P(), pl.np, nimg, istart, c->at<double>(pl.o_ep), nullptr,
+                                            c->at<double>(pl.o_E), nullptr, nullptr, nullptr, nullptr, nullptr,
+                                            nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, flags, 0, st);
+                   }), "integrator");
         c->rk_nfe += 1;
         constexpr int kMaxAttempts = 100000;
         int hnact = 0;
@@ -517,7 +518,7 @@ struct Ops {
                 HIPCHK(c, timed(c, st, KK_RK, [&] {
                            return launch_rk_stage<T>(c->P(), pl.np, c->wm_site(), s, ks, i, rs, y, done, st);
                        }), "integrator");
-                HIPCHK(c, field(c, st, y, nullptr, ks.k[i], EPI_FORCE, 0.0, done), "integrator");
+                HIPCHK(c, field(c, st, y, nullptr, ks.k[i], EPI_FORCE, 0.0, done, fcp, fcd), "integrator");
             }
             c->rk_nfe += 6;
             HIPCHK(c, launch_fill_int(rs.nact, 1, 0, st), "integrator");
@@ -536,6 +537,24 @@ struct Ops {
             HIPCHK(c, hipStreamSynchronize(st), "integrator");
             if (hnact == 0) break;
         }
+        return SSM_OK;
+    }
+
+    // Step 1 by the adaptive integrator (damping term alone) over Tint, then
+    // renormalisation, arc length, reduction and interpolation as in
+    // iteration().
+    static ssm_status rk_iteration(ssm_ctx* c, double Tint)
+    {
+        const Plan& pl = c->pl;
+        hipStream_t st = c->stream;
+        T* s = c->at<T>(pl.o_s);
+        T* ss = c->at<T>(pl.o_ss);
+        int* done = c->at<int>(pl.o_done);
+        int* flags = c->at<int>(pl.o_flags);
+        const int nimg = (int)pl.n_img;
+        const int* istart = c->wm_img().start;
+        ssm_status r = rk_interval(c, Tint, 0.0, 1.0, true);
+        if (r != SSM_OK) return r;
         HIPCHK(c, timed(c, st, KK_RK, [&] {
                    return launch_rk_norm<T>(c->P(), pl.np, c->wm_site(), s, ss, done, flags, st);
                }), "integrator");
@@ -553,6 +572,23 @@ struct Ops {
                    return launch_interp<T>(c->P(), pl.np, c->wm_site(), ss, s, c->at<int>(pl.o_j),
                                            c->at<double>(pl.o_w), c->at<int>(pl.o_skip), done, flags, st);
                }), "integrator");
+        return SSM_OK;
+    }
+
+    // eq. (9) over T for every image (no reparametrisation), renormalised
+    static ssm_status llg(ssm_ctx* c, double T_, double alpha)
+    {
+        const Plan& pl = c->pl;
+        T* s = c->at<T>(pl.o_s);
+        const double cp = 1.0 / (1.0 + alpha * alpha), cd = alpha / (1.0 + alpha * alpha);
+        ssm_status r = rk_interval(c, T_, cp, cd, false);
+        if (r != SSM_OK) return r;
+        T* ss = c->at<T>(pl.o_ss);
+        HIPCHK(c, timed(c, c->stream, KK_RK, [&] {
+                   return launch_rk_norm<T>(c->P(), pl.np, c->wm_site(), s, ss, c->at<int>(pl.o_done),
+                                            c->at<int>(pl.o_flags), c->stream);
+               }), "llg");
+        HIPCHK(c, hipMemcpyAsync(s, ss, pl.tsize * pl.n_spin, hipMemcpyDeviceToDevice, c->stream), "llg");
         return SSM_OK;
     }
 
@@ -711,7 +747,8 @@ double time_kernel(ssm_ctx* c, int kind, int reps)
                                nullptr, pl.lds_conv, c->stream);
         else
             e = launch_xinv<T>(c->P(), pl.np, c->wm_xi(), c->Xp(), c->X(), s, nullptr, nullptr,
-                               c->at<double>(pl.o_ep), tw, nullptr, EPI_TERMS, 0.0, pl.lds_xi, c->stream);
+                               c->at<double>(pl.o_ep), tw, nullptr, EPI_TERMS, 0.0, 0.0, 1.0, pl.lds_xi,
+                               c->stream);
         if (e != hipSuccess || hipEventRecord(b, c->stream) != hipSuccess) return 1e30;
         if (hipEventSynchronize(b) != hipSuccess) return 1e30;
         float ms = 0;
@@ -1004,6 +1041,23 @@ ssm_status ssm_set_integrator(ssm_ctx* ctx, int32_t method, double rtol, double 
     HIPCHK(ctx, launch_fill_double(ctx->at<double>(pl.o_rk_dtp), (int)pl.n_img, dt0, ctx->stream), "set integrator");
     HIPCHK(ctx, launch_fill_int(ctx->at<int>(pl.o_rk_cnt), (int)(2 * pl.n_img), 0, ctx->stream), "set integrator");
     return SSM_OK;
+}
+
+static ssm_status run_eval_current(ssm_ctx* c);
+
+ssm_status ssm_llg(ssm_ctx* ctx, double t_total, double alpha)
+{
+    if (!ctx) return SSM_EINVAL;
+    ssm_ctx* c = ctx;
+    const Plan& pl = c->pl;
+    if (!pl.rk) return fail(c, SSM_EUNSUPPORTED, "context created without SSM_WITH_RK");
+    if (!c->have_string) return fail(c, SSM_ESTATE, "no string set");
+    if (!(t_total > 0.0) || !std::isfinite(t_total) || !(alpha >= 0.0) || !std::isfinite(alpha))
+        return fail(c, SSM_EINVAL, "t_total > 0 and alpha >= 0 (finite) required");
+    HIPCHK(c, launch_fill_int(c->at<int>(pl.o_done), pl.np, 0, c->stream), "llg");
+    ssm_status st = pl.prec == SSM_FP64 ? Ops<double>::llg(c, t_total, alpha) : Ops<float>::llg(c, t_total, alpha);
+    if (st != SSM_OK) return st;
+    return run_eval_current(c);
 }
 
 ssm_status ssm_get_rk_stats(ssm_ctx* ctx, int32_t* d_counts, double* d_dt, int64_t* h_evals)

@@ -122,9 +122,10 @@ hipError_t launch_conv(int mz, int kinds, const Prob* P, int np, const WorkMap& 
 // (s.s) h - (s.h) s in place of h, EPI_TERMS the four term partials
 enum { EPI_STEP = 1, EPI_FIELD = 2, EPI_TERMS = 4, EPI_FORCE = 8 };
 template <typename T>
+// fcp, fcd: coefficients of EPI_FORCE (precession, damping)
 hipError_t launch_xinv(const Prob* P, int np, const WorkMap& wm, const void* Xp, const void* Xq, const T* s,
                        T* s_star, T* h, double* epart, const void* tw, const int* done,
-                       int mode, double tau, size_t lds, hipStream_t st);
+                       int mode, double tau, double fcp, double fcd, size_t lds, hipStream_t st);
 template <typename T>
 hipError_t launch_arc(const Prob* P, int np, const WorkMap& wm, const T* ss, double* apart,
                       const int* done, hipStream_t st);

@@ -631,7 +631,8 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                                               const T* __restrict__ s, T* __restrict__ ss,
                                               T* __restrict__ hout, double* __restrict__ epart,
                                               const cplx<T>* __restrict__ tw,
-                                              const int* __restrict__ done, int mode, double tau)
+                                              const int* __restrict__ done, int mode, double tau,
+                                              double fcp, double fcd)
 {
     using V = cplx<T>;
     extern __shared__ double2 smem_[];
@@ -782,10 +783,13 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                     acc[4] += -0.5 * (sv[0] * hu[0] + sv[1] * hu[1] + sv[2] * hu[2]);
                 }
                 if (mode & EPI_FORCE) {
-                    // damping right-hand side -s x (s x h) = (s.s) h - (s.h) s
+                    // eq. (9) in reduced time: -cp (s x h) + cd ((s.s) h - (s.h) s)
                     const double s2 = sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2];
+                    const double x[3] = {sv[1] * h[2] - sv[2] * h[1], sv[2] * h[0] - sv[0] * h[2],
+                                         sv[0] * h[1] - sv[1] * h[0]};
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) hout[soff + (long long)c * N + i] = (T)(s2 * h[c] - sh * sv[c]);
+                    for (int c = 0; c < 3; ++c)
+                        hout[soff + (long long)c * N + i] = (T)(fcd * (s2 * h[c] - sh * sv[c]) - fcp * x[c]);
                 } else if (mode & EPI_FIELD) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) hout[soff + (long long)c * N + i] = (T)h[c];
@@ -1391,12 +1395,12 @@ hipError_t launch_conv(int mz, int kinds, const Prob* P, int np, const WorkMap& 
 template <typename T>
 hipError_t launch_xinv(const Prob* P, int np, const WorkMap& wm, const void* Xp, const void* Xq, const T* s,
                        T* s_star, T* h, double* epart, const void* tw, const int* done, int mode,
-                       double tau, size_t lds, hipStream_t st)
+                       double tau, double fcp, double fcd, size_t lds, hipStream_t st)
 {
     if (wm.total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_xinv<T>, dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start,
                        (const cplx<T>*)Xp, (const cplx<T>*)Xq, s, s_star, h, epart, (const cplx<T>*)tw, done,
-                       mode, tau);
+                       mode, tau, fcp, fcd);
     return hipGetLastError();
 }
 
@@ -1784,7 +1788,7 @@ hipError_t launch_fill_double(double* p, int n, double v, hipStream_t st)
     template hipError_t launch_xinv<T>(const Prob*, int, const WorkMap&, const void*, const void*, \
                                        const T*,                                                    \
                                        T*, T*, double*, const void*, const int*, int, double,     \
-                                       size_t, hipStream_t);                                       \
+                                       double, double, size_t, hipStream_t);                       \
     template hipError_t launch_arc<T>(const Prob*, int, const WorkMap&, const T*, double*,        \
                                       const int*, hipStream_t);                                    \
     template hipError_t launch_interp<T>(const Prob*, int, const WorkMap&, const T*, T*,          \

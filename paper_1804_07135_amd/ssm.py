@@ -40,7 +40,7 @@ ABI_SYMBOLS = [
     "ssm_set_string", "ssm_get_string", "ssm_iterate", "ssm_eval", "ssm_get_energies",
     "ssm_get_fields", "ssm_get_tangents", "ssm_get_barrier", "ssm_set_options", "ssm_autotune",
     "ssm_check", "ssm_last_error", "ssm_profile", "ssm_profile_read", "ssm_kernel_name",
-    "ssm_set_integrator", "ssm_get_rk_stats",
+    "ssm_set_integrator", "ssm_get_rk_stats", "ssm_llg",
 ]
 
 
@@ -94,6 +94,7 @@ def load():
         "ssm_kernel_name": (ctypes.c_char_p, [_i32]),
         "ssm_set_integrator": (_i32, [_vp, _i32, _dbl, _dbl, _dbl]),
         "ssm_get_rk_stats": (_i32, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
+        "ssm_llg": (_i32, [_vp, _dbl, _dbl]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -217,6 +218,10 @@ def ssm_autotune(ctx, cache_path=None):
 
 def ssm_set_integrator(ctx, method, rtol=1e-6, atol=1e-6, dt0=0.1):
     _check(load().ssm_set_integrator(ctx, int(method), float(rtol), float(atol), float(dt0)), ctx)
+
+
+def ssm_llg(ctx, t_total, alpha):
+    _check(load().ssm_llg(ctx, float(t_total), float(alpha)), ctx)
 
 
 def ssm_get_rk_stats(ctx, counts=None, dt=None):
@@ -358,6 +363,11 @@ class StringMethod:
         """Step 1 of iterate(): SSM_STEP_EULER (tau = step) or SSM_STEP_DOPRI54
         (tau = interval of the adaptive Dormand-Prince integration)."""
         ssm_set_integrator(self.ctx, method, rtol, atol, dt0)
+
+    def llg(self, t_total, alpha):
+        """Evolve every image by the LLG equation (eq. (9)) over t_total with the
+        adaptive integrator (set_integrator's tolerances); no reparametrisation."""
+        ssm_llg(self.ctx, t_total, alpha)
 
     def rk_stats(self):
         """(accepted/rejected steps per image [sum K, 2], step proposals [sum K],

@@ -2,7 +2,9 @@
 image evolved over an interval with explicit embedded Runge-Kutta and
 adaptive step size) on the GPU, through the C ABI, against the oracle's
 integrator: strings, energies, per-image accepted/rejected step counts and
-step proposals; the single-spin closed form; FP32 against FP64."""
+step proposals; the single-spin closed form; FP32 against FP64.  Also the
+full LLG time integration (eq. (9), precession and damping) with the same
+integrator: single-spin closed forms, the oracle, energy conservation."""
 import numpy as np
 import pytest
 import torch
@@ -133,3 +135,77 @@ def test_euler_path_unchanged_in_rk_context(oracle):
         sm.set_string(s0)
         sm.iterate(10, 0.1)
     assert torch.equal(a.get_string(), b.get_string())
+
+
+# ---------------------------------------------------------------------------
+# Full LLG time integration (eq. (9)) with the same integrator
+# ---------------------------------------------------------------------------
+def test_llg_single_spin_closed_forms():
+    """Precession (alpha = 0) and the damped spiral (alpha > 0) of single
+    spins in their anisotropy field, against the closed forms."""
+    k, T = 0.35, 3.0
+    th0 = np.array([0.7, 1.1])
+    ph0 = np.array([0.2, -0.5])
+    s = np.zeros((2, 3, 1, 1, 1))
+    s[:, 0, 0, 0, 0] = np.sin(th0) * np.cos(ph0)
+    s[:, 1, 0, 0, 0] = np.sin(th0) * np.sin(ph0)
+    s[:, 2, 0, 0, 0] = np.cos(th0)
+    for al in (0.0, 0.2):
+        sm = ssm.StringMethod(prob(1, 1, 1, 2, J=1.0, d=0.0, ku=k, D=0.0), ssm.SSM_FP64, with_rk=True)
+        sm.set_integrator(ssm.SSM_STEP_DOPRI54, 1e-11, 1e-11, 0.01)
+        sm.set_string(s)
+        sm.llg(T, al)
+        y = sm.get_string().cpu().numpy()[:, :, 0, 0, 0]
+        th = np.arccos(y[:, 2])
+        ph = np.arctan2(y[:, 1], y[:, 0])
+        if al == 0.0:
+            th_e, ph_e = th0, ph0 + 2 * k * np.cos(th0) * T
+        else:
+            b = 2 * k * al / (1 + al * al)
+            c = np.tan(th0)
+            th_e = np.arctan(c * np.exp(-b * T))
+            ph_e = ph0 + (np.arcsinh(np.exp(b * T) / c) - np.arcsinh(1 / c)) / al
+        np.testing.assert_allclose(th, th_e, atol=1e-9)
+        assert np.abs(np.angle(np.exp(1j * (ph - ph_e)))).max() < 1e-9
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.3])
+def test_llg_matches_oracle(oracle, alpha):
+    """Two configurations of a 10x8x2 lattice evolved by eq. (9): FP64 GPU
+    equals the oracle (state, step statistics); energies are those of the
+    evolved states."""
+    p = prob(10, 8, 2, 2, J=1.0, d=0.3, ku=0.1, D=0.05)
+    s0 = inputs.random_unit_spins((2, 3, 2, 8, 10), seed=31)
+    T, rtol, atol, dt0 = 0.6, 1e-7, 1e-7, 0.02
+    sm = ssm.StringMethod(p, ssm.SSM_FP64, with_rk=True)
+    sm.set_integrator(ssm.SSM_STEP_DOPRI54, rtol, atol, dt0)
+    sm.set_string(s0)
+    sm.llg(T, alpha)
+    got = sm.get_string().cpu().numpy()
+    counts, dt, _ = sm.rk_stats()
+    c = counts.cpu().numpy()
+    E = sm.energies().cpu().numpy()
+    for kk in range(2):
+        r = oracle.llg_interval(s0[kk], *params(p), alpha, T, rtol, atol, dt0)
+        np.testing.assert_allclose(got[kk], r["y"], rtol=0, atol=TOL64)
+        assert (c[kk, 0], c[kk, 1]) == (r["acc"], r["rej"])
+        assert abs(dt.cpu().numpy()[kk] - r["dt"]) <= 1e-9 * r["dt"]
+        Eo = oracle.energy(r["y"], *params(p))
+        assert abs(E[kk] - Eo) <= TOL64 * abs(Eo)
+
+
+def test_llg_precession_conserves_energy_fp32():
+    """alpha = 0 on the 64x64 boundary workload's first image (FP32-mixed):
+    the energy is conserved to the integration tolerance."""
+    w = inputs.WORKLOADS["boundary_64x64x1_k20"]
+    p = prob(w["nx"], w["ny"], w["nz"], 2, w["J"], w["d"], w["ku"], w["D"])
+    s0 = inputs.build_string(dict(w, K=2))
+    sm = ssm.StringMethod(p, ssm.SSM_FP32_MIXED, with_rk=True)
+    sm.set_integrator(ssm.SSM_STEP_DOPRI54, 1e-6, 1e-6, 0.05)
+    E0, _, _ = sm.eval(s0, want_field=False, want_terms=False)
+    sm.set_string(s0)
+    sm.llg(2.0, 0.0)
+    E1 = sm.energies()
+    assert torch.allclose(E1, E0, rtol=1e-5, atol=0)
+    moved = (sm.get_string().double().cpu() - torch.as_tensor(s0)).abs().max()
+    assert float(moved) > 1e-3
