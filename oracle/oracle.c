@@ -34,7 +34,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define ORACLE_VERSION 3
+#define ORACLE_VERSION 4
 
 int oracle_version(void) { return ORACLE_VERSION; }
 
@@ -697,5 +697,243 @@ int oracle_iterate_rk(int nx, int ny, int nz, double J, double d, double k, doub
     if (force_norm_out) *force_norm_out = oracle_force_norm(K, N, s, h, NULL);
 out:
     free(h); free(ss); free(al); free(wt); free(jj);
+    return it;
+}
+
+/* ------------------------------------------------------------------------
+ * Variants of step 2 (Sec. III).  The paper interpolates piecewise linearly
+ * and omits the climbing-image refinement of the saddle it mentions; both
+ * options are provided:
+ *  - interpolation by a natural cubic spline in alpha through the images,
+ *    per site and spin component (second derivatives from the tridiagonal
+ *    system that makes the first derivative continuous, zero at both ends;
+ *    Numerical Recipes 3.3), then renormalisation;
+ *  - a climbing image: the image k* of highest energy (smallest index on
+ *    ties), if interior, is stepped with F - 2 (F.t) t, F = h - (s.h) s its
+ *    perpendicular force and t its tangent (per-spin projection of
+ *    phi_{k*+1} - phi_{k*-1}, normalised over the image), and is kept fixed
+ *    by the reparametrisation, which spaces images 0..k* and k*..K-1 to
+ *    equal arc length within their own segment.
+ * ---------------------------------------------------------------------- */
+
+/* Natural cubic spline through (x_k, f_k), k < K, x strictly increasing,
+ * evaluated at t[0..nt-1] (t in [x_0, x_{K-1}]).  Returns 1, or 0 when it
+ * fell back to linear interpolation (K == 2 or an interval of zero width). */
+int oracle_spline_eval(int K, const double* x, const double* f, int nt, const double* t, double* out)
+{
+    int ok = (K > 2);
+    for (int j = 0; j + 1 < K; ++j)
+        if (!(x[j + 1] - x[j] > 0.0)) ok = 0;
+    double* M = (double*)calloc((size_t)K, sizeof(double));
+    if (ok) {
+        double* cp = (double*)calloc((size_t)K, sizeof(double));
+        double* dp = (double*)calloc((size_t)K, sizeof(double));
+        for (int i = 1; i <= K - 2; ++i) {
+            const double hl = x[i] - x[i - 1], hr = x[i + 1] - x[i];
+            const double a = hl / 6.0, b = (hl + hr) / 3.0, c = hr / 6.0;
+            const double r = (f[i + 1] - f[i]) / hr - (f[i] - f[i - 1]) / hl;
+            const double den = b - (i > 1 ? a * cp[i - 1] : 0.0);
+            cp[i] = c / den;
+            dp[i] = (r - (i > 1 ? a * dp[i - 1] : 0.0)) / den;
+        }
+        M[K - 2] = dp[K - 2];
+        for (int i = K - 3; i >= 1; --i) M[i] = dp[i] - cp[i] * M[i + 1];
+        free(cp);
+        free(dp);
+    }
+    for (int q = 0; q < nt; ++q) {
+        int j = 0;
+        for (int jj = 0; jj <= K - 2; ++jj)
+            if (x[jj] <= t[q]) j = jj;
+        const double h = x[j + 1] - x[j];
+        if (!(h > 0.0)) {
+            out[q] = f[j];
+            continue;
+        }
+        const double A = (x[j + 1] - t[q]) / h, B = 1.0 - A;
+        out[q] = A * f[j] + B * f[j + 1];
+        if (ok) out[q] += ((A * A * A - A) * M[j] + (B * B * B - B) * M[j + 1]) * h * h / 6.0;
+    }
+    free(M);
+    return ok;
+}
+
+/* Climbing-image step of one image s (neighbours s_prev, s_next, field h)
+ * with step tau: out = normalise(s + tau (F - 2 (F.t) t)). */
+void oracle_climb_step(int64_t N, const double* s_prev, const double* s, const double* s_next,
+                       const double* h, double tau, double* out)
+{
+    const int64_t M = 3 * N;
+    double* tt = (double*)malloc((size_t)M * sizeof(double));
+    double* F = (double*)malloc((size_t)M * sizeof(double));
+    double* buf = (double*)malloc((size_t)N * sizeof(double));
+    for (int64_t i = 0; i < N; ++i) {
+        double v[3] = {s[i], s[N + i], s[2 * N + i]};
+        double f[3] = {h[i], h[N + i], h[2 * N + i]};
+        double dl[3];
+        for (int c = 0; c < 3; ++c) dl[c] = s_next[c * N + i] - s_prev[c * N + i];
+        const double sh = v[0] * f[0] + v[1] * f[1] + v[2] * f[2];
+        const double sd = v[0] * dl[0] + v[1] * dl[1] + v[2] * dl[2];
+        for (int c = 0; c < 3; ++c) {
+            F[c * N + i] = f[c] - sh * v[c];
+            tt[c * N + i] = dl[c] - sd * v[c];
+        }
+    }
+    for (int64_t i = 0; i < N; ++i) buf[i] = tt[i] * tt[i] + tt[N + i] * tt[N + i] + tt[2 * N + i] * tt[2 * N + i];
+    const double tn2 = psum(buf, N);
+    for (int64_t i = 0; i < N; ++i) buf[i] = F[i] * tt[i] + F[N + i] * tt[N + i] + F[2 * N + i] * tt[2 * N + i];
+    const double ft = psum(buf, N);
+    const double cc = (tn2 > 0.0) ? ft / tn2 : 0.0;  /* (F.t) t = cc t~ */
+    for (int64_t i = 0; i < N; ++i) {
+        double w[3];
+        for (int c = 0; c < 3; ++c) w[c] = s[c * N + i] + tau * (F[c * N + i] - 2.0 * cc * tt[c * N + i]);
+        const double nrm = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        for (int c = 0; c < 3; ++c) out[c * N + i] = w[c] / nrm;
+    }
+    free(tt); free(F); free(buf);
+}
+
+/* Step 2 with the options: spline (0 linear, 1 natural cubic spline) and
+ * kci (climbing image index, or -1).  Same outputs as oracle_reparam (for
+ * the spline, jidx/wts are the intervals and linear weights used for the
+ * renormalisation guard).  Returns 1 if applied, 0 if the total arc length
+ * was zero (string copied). */
+int oracle_reparam_opts(int K, int64_t N, const double* s_star, double* s_out, double* alpha_star,
+                        int32_t* jidx, double* wts, int spline, int kci)
+{
+    const int64_t M = 3 * N;
+    double* seg = (double*)malloc((size_t)K * sizeof(double));
+    double* sq = (double*)malloc((size_t)M * sizeof(double));
+    seg[0] = 0.0;
+    for (int kk = 1; kk < K; ++kk) {
+        const double* a = s_star + (int64_t)kk * M;
+        const double* b = s_star + (int64_t)(kk - 1) * M;
+        for (int64_t q = 0; q < M; ++q) sq[q] = (a[q] - b[q]) * (a[q] - b[q]);
+        seg[kk] = sqrt(psum(sq, M));
+    }
+    double* S = (double*)malloc((size_t)K * sizeof(double));
+    S[0] = 0.0;
+    for (int kk = 1; kk < K; ++kk) S[kk] = S[kk - 1] + seg[kk];
+    const double L = S[K - 1];
+    free(seg);
+    free(sq);
+    if (!(L > 0.0)) {
+        for (int kk = 0; kk < K; ++kk) { alpha_star[kk] = 0.0; jidx[kk] = kk; wts[kk] = 0.0; }
+        memcpy(s_out, s_star, (size_t)K * M * sizeof(double));
+        free(S);
+        return 0;
+    }
+    for (int kk = 0; kk < K; ++kk) alpha_star[kk] = S[kk] / L;
+    free(S);
+    const int ci = (kci > 0 && kci < K - 1);
+    double* tk = (double*)malloc((size_t)K * sizeof(double));
+    for (int kk = 0; kk < K; ++kk) {
+        if (!ci) tk[kk] = (double)kk / (double)(K - 1);
+        else if (kk <= kci) tk[kk] = alpha_star[kci] * (double)kk / (double)kci;
+        else tk[kk] = alpha_star[kci] + (1.0 - alpha_star[kci]) * (double)(kk - kci) / (double)(K - 1 - kci);
+    }
+    for (int kk = 0; kk < K; ++kk) {
+        int j = 0;
+        for (int jj = 0; jj <= K - 2; ++jj)
+            if (alpha_star[jj] <= tk[kk]) j = jj;
+        const double width = alpha_star[j + 1] - alpha_star[j];
+        jidx[kk] = j;
+        wts[kk] = (width > 0.0) ? (tk[kk] - alpha_star[j]) / width : 0.0;
+    }
+    /* endpoints and the climbing image are copied */
+    for (int kk = 0; kk < K; ++kk) {
+        if (kk == 0 || kk == K - 1 || (ci && kk == kci)) {
+            jidx[kk] = kk;
+            wts[kk] = 0.0;
+            memcpy(s_out + (int64_t)kk * M, s_star + (int64_t)kk * M, (size_t)M * sizeof(double));
+        }
+    }
+    #pragma omp parallel
+    {
+        double* fv = (double*)malloc((size_t)K * sizeof(double));
+        double* ov = (double*)malloc((size_t)K * sizeof(double));
+        #pragma omp for schedule(static)
+        for (int64_t i = 0; i < N; ++i) {
+            double v[1024][3];
+            for (int c = 0; c < 3; ++c) {
+                if (spline) {
+                    for (int kk = 0; kk < K; ++kk) fv[kk] = s_star[(int64_t)kk * M + c * N + i];
+                    oracle_spline_eval(K, alpha_star, fv, K, tk, ov);
+                    for (int kk = 0; kk < K; ++kk) v[kk][c] = ov[kk];
+                } else {
+                    for (int kk = 0; kk < K; ++kk) {
+                        const double w = wts[kk];
+                        v[kk][c] = (1.0 - w) * s_star[(int64_t)jidx[kk] * M + c * N + i] +
+                                   w * s_star[(int64_t)(jidx[kk] + 1) * M + c * N + i];
+                    }
+                }
+            }
+            for (int kk = 1; kk < K - 1; ++kk) {
+                if (ci && kk == kci) continue;
+                double* o = s_out + (int64_t)kk * M;
+                const double nrm = sqrt(v[kk][0] * v[kk][0] + v[kk][1] * v[kk][1] + v[kk][2] * v[kk][2]);
+                if (nrm < 1e-12) {
+                    const double* src = s_star + (int64_t)(wts[kk] < 0.5 ? jidx[kk] : jidx[kk] + 1) * M;
+                    for (int c = 0; c < 3; ++c) o[c * N + i] = src[c * N + i];
+                } else {
+                    for (int c = 0; c < 3; ++c) o[c * N + i] = v[kk][c] / nrm;
+                }
+            }
+        }
+        free(fv);
+        free(ov);
+    }
+    free(tk);
+    return 1;
+}
+
+/* oracle_iterate with the step-2 options (spline, climbing image). */
+int oracle_iterate_opts(int nx, int ny, int nz, double J, double d, double k, double D, int K, int max_iter,
+                        double tau, double tol, int every, int spline, int climb, double* s, double* E,
+                        double* h_or_null, double* force_norm_out)
+{
+    const int64_t N = (int64_t)nx * ny * nz;
+    const int64_t M = 3 * N;
+    double* h = (double*)malloc((size_t)K * M * sizeof(double));
+    double* ss = (double*)malloc((size_t)K * M * sizeof(double));
+    double* al = (double*)malloc((size_t)K * sizeof(double));
+    double* wt = (double*)malloc((size_t)K * sizeof(double));
+    double* Ek = (double*)malloc((size_t)K * sizeof(double));
+    int32_t* jj = (int32_t*)malloc((size_t)K * sizeof(int32_t));
+    int it = 0;
+    if (every < 1) every = 1;
+    for (;;) {
+        if (tol > 0.0 && it % every == 0) {
+            for (int kk = 0; kk < K; ++kk)
+                oracle_field(nx, ny, nz, J, d, k, D, s + kk * M, h + kk * M);
+            if (oracle_force_norm(K, N, s, h, NULL) < tol) break;
+        }
+        if (it >= max_iter) break;
+        for (int kk = 0; kk < K; ++kk) {
+            oracle_field(nx, ny, nz, J, d, k, D, s + kk * M, h + kk * M);
+            Ek[kk] = oracle_energy_from_field(N, s + kk * M, h + kk * M);
+        }
+        oracle_step(N, K, s, h, tau, ss);
+        int kci = -1;
+        if (climb) {
+            int km = 0;
+            for (int kk = 1; kk < K; ++kk)
+                if (Ek[kk] > Ek[km]) km = kk;
+            if (km > 0 && km < K - 1) {
+                kci = km;
+                oracle_climb_step(N, s + (km - 1) * M, s + km * M, s + (km + 1) * M, h + km * M, tau,
+                                  ss + km * M);
+            }
+        }
+        oracle_reparam_opts(K, N, ss, s, al, jj, wt, spline, kci);
+        ++it;
+    }
+    for (int kk = 0; kk < K; ++kk) {
+        oracle_field(nx, ny, nz, J, d, k, D, s + kk * M, h + kk * M);
+        E[kk] = oracle_energy_from_field(N, s + kk * M, h + kk * M);
+    }
+    if (h_or_null) memcpy(h_or_null, h, (size_t)K * M * sizeof(double));
+    if (force_norm_out) *force_norm_out = oracle_force_norm(K, N, s, h, NULL);
+    free(h); free(ss); free(al); free(wt); free(Ek); free(jj);
     return it;
 }

@@ -68,6 +68,14 @@ def _load():
         lib.oracle_llg_rhs.argtypes = [_i, _i, _i, _d, _d, _d, _d, _d, _d, _p, _p, _p]
         lib.oracle_llg_interval.argtypes = [_i, _i, _i, _d, _d, _d, _d, _d, _d, _p, _d, _d, _d, _p, _p, _p, _i]
         lib.oracle_llg_interval.restype = _i
+        lib.oracle_spline_eval.argtypes = [_i, _p, _p, _i, _p, _p]
+        lib.oracle_spline_eval.restype = _i
+        lib.oracle_climb_step.argtypes = [_i64, _p, _p, _p, _p, _d, _p]
+        lib.oracle_reparam_opts.argtypes = [_i, _i64, _p, _p, _p, _p, _p, _i, _i]
+        lib.oracle_reparam_opts.restype = _i
+        lib.oracle_iterate_opts.argtypes = [_i, _i, _i, _d, _d, _d, _d, _i, _i, _d, _d, _i, _i, _i,
+                                            _p, _p, _p, _p]
+        lib.oracle_iterate_opts.restype = _i
         _lib = lib
     return _lib
 
@@ -274,3 +282,51 @@ def llg_interval(s, J, d, k, D, alpha, T, rtol, atol, dt0, max_steps=1000000):
     rc = _load().oracle_llg_interval(nx, ny, nz, J, d, k, D, cp, cd, _ptr(y), T, rtol, atol, _ptr(dtp),
                                      _ptr(acc), _ptr(rej), max_steps)
     return dict(y=y, dt=float(dtp[0]), acc=int(acc[0]), rej=int(rej[0]), ok=rc == 0)
+
+
+def spline_eval(x, f, t):
+    """Natural cubic spline through (x, f) at t; returns (values, used_spline)."""
+    x = _f64(x)
+    f = _f64(f)
+    t = _f64(t)
+    out = np.empty_like(t)
+    ok = _load().oracle_spline_eval(len(x), _ptr(x), _ptr(f), len(t), _ptr(t), _ptr(out))
+    return out, bool(ok)
+
+
+def climb_step(s_prev, s, s_next, h, tau):
+    """Climbing-image step of one image (force F - 2 (F.t) t, renormalised)."""
+    s_prev, s, s_next, h = (_f64(a) for a in (s_prev, s, s_next, h))
+    out = np.empty_like(s)
+    _load().oracle_climb_step(s.size // 3, _ptr(s_prev), _ptr(s), _ptr(s_next), _ptr(h), tau, _ptr(out))
+    return out
+
+
+def reparam_opts(s_star, spline=False, kci=-1):
+    """Step 2 with a natural cubic spline and/or a climbing image kci (-1: none).
+    Returns (s_new, alpha_star, j, w, applied)."""
+    s_star = _f64(s_star)
+    K = s_star.shape[0]
+    N = s_star[0].size // 3
+    out = np.empty_like(s_star)
+    al = np.zeros(K)
+    jj = np.zeros(K, dtype=np.int32)
+    w = np.zeros(K)
+    applied = _load().oracle_reparam_opts(K, N, _ptr(s_star), _ptr(out), _ptr(al), _ptr(jj), _ptr(w),
+                                          1 if spline else 0, int(kci))
+    return out, al, jj, w, bool(applied)
+
+
+def iterate_opts(s, J, d, k, D, max_iter, tau, spline=False, climb=False, tol=0.0, every=1,
+                 want_fields=False):
+    """iterate() with the step-2 options.  Returns the same dict as iterate()."""
+    s = _f64(s).copy()
+    K = s.shape[0]
+    nx, ny, nz = _dims(s[0])
+    E = np.zeros(K)
+    h = np.empty_like(s) if want_fields else None
+    fn = np.zeros(1)
+    it = _load().oracle_iterate_opts(nx, ny, nz, J, d, k, D, K, max_iter, tau, tol, every,
+                                     1 if spline else 0, 1 if climb else 0, _ptr(s), _ptr(E),
+                                     _ptr(h) if want_fields else None, _ptr(fn))
+    return dict(s=s, E=E, iters=it, force=float(fn[0]), h=h)

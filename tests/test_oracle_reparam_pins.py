@@ -1,0 +1,159 @@
+"""Pins of the oracle's step-2 variants (Sec. III: reparametrisation of the
+string; the climbing-image refinement of the saddle the paper mentions):
+natural cubic spline interpolation against scipy's CubicSpline, its exact
+cases, the great-circle closed form of segment-wise equal spacing around a
+climbing image, and the climbing step in the two geometric limits (force
+along the path: the step climbs; force across the path: ordinary step)."""
+import math
+
+import numpy as np
+import pytest
+from scipy.interpolate import CubicSpline
+
+from paper_1804_07135_amd import inputs
+
+
+def rotating_string(thetas, N=3):
+    """Every spin of image k at angle theta_k in the x-z plane."""
+    K = len(thetas)
+    s = np.zeros((K, 3, 1, 1, N))
+    for kk, t in enumerate(thetas):
+        s[kk, 0] = math.sin(t)
+        s[kk, 2] = math.cos(t)
+    return s
+
+
+@pytest.mark.parametrize("K", [3, 4, 7, 16])
+def test_spline_matches_scipy(oracle, K):
+    rng = np.random.default_rng(K)
+    x = np.concatenate([[0.0], np.sort(rng.uniform(0.02, 0.98, K - 2)), [1.0]])
+    f = rng.normal(size=K)
+    t = np.concatenate([np.linspace(0, 1, 23), x])
+    v, ok = oracle.spline_eval(x, f, t)
+    assert ok
+    np.testing.assert_allclose(v, CubicSpline(x, f, bc_type="natural")(t), atol=1e-14)
+
+
+def test_spline_exact_cases(oracle):
+    """Knots are reproduced exactly, linear data are reproduced (zero second
+    derivatives solve the system), and K = 2 or a zero-width interval falls
+    back to linear interpolation."""
+    x = np.array([0.0, 0.1, 0.35, 0.4, 0.8, 1.0])
+    f = np.array([0.3, -1.0, 2.0, 0.5, 0.1, 1.5])
+    v, ok = oracle.spline_eval(x, f, x)
+    assert ok and np.array_equal(v, f)
+    t = np.linspace(0, 1, 17)
+    v, _ = oracle.spline_eval(x, 2.0 - 3.0 * x, t)
+    np.testing.assert_allclose(v, 2.0 - 3.0 * t, atol=1e-14)
+    v, ok = oracle.spline_eval(np.array([0.0, 1.0]), np.array([1.0, 3.0]), t)
+    assert not ok and np.allclose(v, 1.0 + 2.0 * t)
+    xz = np.array([0.0, 0.3, 0.3, 1.0])
+    v, ok = oracle.spline_eval(xz, np.array([0.0, 1.0, 1.0, 0.0]), np.array([0.15, 0.65]))
+    assert not ok and np.allclose(v, [0.5, 0.5])
+
+
+def test_linear_options_equal_plain_reparam(oracle):
+    s = inputs.perturb(inputs.bloch_point_string(9, 8, 2, 6, 2.5), 3)
+    a = oracle.reparam(s)
+    b = oracle.reparam_opts(s, spline=False, kci=-1)
+    for x, y in zip(a, b):
+        assert np.array_equal(np.asarray(x), np.asarray(y))
+
+
+def test_spline_reparam_is_scipy_then_renormalise(oracle):
+    """The spline step equals: per site and component, scipy's natural cubic
+    spline through (alpha*_k, phi*_k) at k/(K-1), then per-spin
+    renormalisation; endpoints copied."""
+    s = inputs.perturb(inputs.bloch_point_string(7, 6, 1, 8, 2.0), 5)
+    out, al, jj, w, applied = oracle.reparam_opts(s, spline=True)
+    assert applied
+    K = s.shape[0]
+    t = np.arange(K) / (K - 1)
+    flat = s.reshape(K, 3, -1)
+    v = CubicSpline(al, flat, axis=0, bc_type="natural")(t)
+    v = v / np.linalg.norm(v, axis=1, keepdims=True)
+    got = out.reshape(K, 3, -1)
+    np.testing.assert_allclose(got[1:-1], v[1:-1], atol=1e-13)
+    assert np.array_equal(got[0], flat[0]) and np.array_equal(got[-1], flat[-1])
+
+
+def test_climbing_segments_great_circle(oracle):
+    """With a climbing image k*, targets are equally spaced in (chord) arc
+    length within 0..k* and within k*..K-1; on a great circle the linear
+    interpolant renormalised sits at theta_j + atan2(w sin d, 1 - w + w cos d)."""
+    th = np.array([0.0, 0.15, 0.5, 0.6, 1.3, 1.35, 2.0, 2.9])
+    K, kci = len(th), 4
+    s = rotating_string(th, N=2)
+    out, al, jj, w, applied = oracle.reparam_opts(s, spline=False, kci=kci)
+    chords = 2 * np.sin(np.diff(th) / 2)
+    S = np.concatenate([[0.0], np.cumsum(chords)])
+    alpha = S / S[-1]
+    np.testing.assert_allclose(al, alpha, atol=1e-15)
+    for k in range(K):
+        if k in (0, K - 1, kci):
+            assert np.array_equal(out[k], s[k])
+            continue
+        t = alpha[kci] * k / kci if k < kci else alpha[kci] + (1 - alpha[kci]) * (k - kci) / (K - 1 - kci)
+        j = max(i for i in range(K - 1) if alpha[i] <= t)
+        ww = (t - alpha[j]) / (alpha[j + 1] - alpha[j])
+        dl = th[j + 1] - th[j]
+        ang = th[j] + math.atan2(ww * math.sin(dl), 1 - ww + ww * math.cos(dl))
+        assert jj[k] == j
+        np.testing.assert_allclose(out[k, 0], math.sin(ang), atol=1e-14)
+        np.testing.assert_allclose(out[k, 2], math.cos(ang), atol=1e-14)
+
+
+def single(theta, phi=0.0):
+    s = np.zeros((3, 1, 1, 1))
+    s[:, 0, 0, 0] = [math.sin(theta) * math.cos(phi), math.sin(theta) * math.sin(phi), math.cos(theta)]
+    return s
+
+
+def test_climb_step_geometric_limits(oracle):
+    """One spin under anisotropy (h = 2k s_z z).  Neighbours on its meridian:
+    the perpendicular force lies along the path, so the climbing step is the
+    ordinary step with the force reversed (uphill).  Neighbours on its
+    parallel circle: the force is across the path and the step is the
+    ordinary one."""
+    k, th, tau, dth = 0.4, 0.7, 0.05, 0.1
+    p = (1.0, 0.0, k, 0.0)
+    s = single(th)
+    h = oracle.field(s, *p)
+    F = h - (s * h).sum(0) * s
+    # neighbours on the meridian: force along the path -> reversed
+    up = oracle.climb_step(single(th - dth), s, single(th + dth), h, tau)
+    expect = s - tau * F
+    np.testing.assert_allclose(up, expect / np.linalg.norm(expect), atol=1e-15)
+    # neighbours on the parallel circle: force across the path -> unchanged
+    flat = oracle.climb_step(single(th, -dth), s, single(th, dth), h, tau)
+    expect = s + tau * F
+    np.testing.assert_allclose(flat, expect / np.linalg.norm(expect), atol=1e-15)
+    # the ordinary step is the Euler step of the string method
+    plain = oracle.step(s[None], h[None], tau)[0]
+    np.testing.assert_allclose(flat, plain, atol=1e-15)
+
+
+def test_iterate_opts_defaults_equal_iterate(oracle):
+    w = inputs.WORKLOADS["bloch_32x32x1_k10"]
+    s0 = inputs.build_string(dict(w, nx=10, ny=9, K=5, R=2.5))
+    p = (w["J"], w["d"], w["ku"], w["D"])
+    a = oracle.iterate(s0, *p, 4, 0.1)
+    b = oracle.iterate_opts(s0, *p, 4, 0.1)
+    assert np.array_equal(a["s"], b["s"]) and np.array_equal(a["E"], b["E"])
+
+
+def test_iterate_opts_composition(oracle):
+    """One iteration with both options = field, step, climbing step of the
+    highest interior image, spline reparametrisation around it."""
+    w = inputs.WORKLOADS["bloch_32x32x1_k10"]
+    s0 = inputs.build_string(dict(w, nx=10, ny=9, K=6, R=2.5))
+    p = (w["J"], w["d"], w["ku"], w["D"])
+    r = oracle.iterate_opts(s0, *p, 1, 0.1, spline=True, climb=True)
+    h = np.stack([oracle.field(x, *p) for x in s0])
+    E = np.array([oracle.energy_from_field(x, y) for x, y in zip(s0, h)])
+    ss = oracle.step(s0, h, 0.1)
+    km = int(np.argmax(E))
+    assert 0 < km < 5
+    ss[km] = oracle.climb_step(s0[km - 1], s0[km], s0[km + 1], h[km], 0.1)
+    expect = oracle.reparam_opts(ss, spline=True, kci=km)[0]
+    np.testing.assert_array_equal(r["s"], expect)
