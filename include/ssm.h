@@ -91,6 +91,10 @@ typedef int32_t ssm_status;
 #define SSM_STEP_EULER 0    /* one explicit projected step of size tau (default) */
 #define SSM_STEP_DOPRI54 1  /* adaptive Dormand-Prince 5(4) over an interval tau */
 
+/* Interpolation of step 2 (ssm_set_reparam) */
+#define SSM_INTERP_LINEAR 0  /* piecewise linear in alpha (default) */
+#define SSM_INTERP_SPLINE 1  /* natural cubic spline in alpha */
+
 /* ssm_check flag bits */
 #define SSM_FLAG_NONFINITE_ENERGY 1
 #define SSM_FLAG_ZERO_NORM_SPIN 2
@@ -159,6 +163,24 @@ ssm_status ssm_get_string(ssm_ctx* ctx, void* d_spins);
  * iterations each problem performed in this call. */
 ssm_status ssm_iterate(ssm_ctx* ctx, int32_t max_iter, double tau, double tol_force,
                        int32_t* d_iters_done);
+
+/* Options of step 2 of ssm_iterate (Sec. III: reparametrisation by equal
+ * arc length; the paper interpolates linearly and omits the climbing-image
+ * refinement of the saddle it mentions).  interp: SSM_INTERP_LINEAR, or
+ * SSM_INTERP_SPLINE: every spin component of every site is interpolated by
+ * the natural cubic spline through (alpha*_k, phi*_k) (second derivatives
+ * zero at both ends) and renormalised; with K = 2 or an interval of zero
+ * width a problem falls back to linear interpolation for that iteration.
+ * climbing = 1: in every iteration the image k* of highest energy (smallest
+ * index on ties), if interior, is stepped with F - 2 (F.t) t instead of F
+ * (F = h - (s.h) s its perpendicular force, t the normalised per-spin
+ * projection of phi_{k*+1} - phi_{k*-1}) and kept by the reparametrisation,
+ * which spaces images 0..k* and k*..K-1 to equal arc length within their
+ * own segment.  The climbing image needs SSM_STEP_EULER (ssm_iterate
+ * returns SSM_EUNSUPPORTED otherwise).  Both options apply to all
+ * problems of the context; the spline uses the field buffer as scratch
+ * (ssm_iterate re-evaluates the fields at the end). */
+ssm_status ssm_set_reparam(ssm_ctx* ctx, int32_t interp, int32_t climbing);
 
 /* Choose step 1 of ssm_iterate.  SSM_STEP_EULER (default): one projected
  * step of size tau.  SSM_STEP_DOPRI54 (Sec. III: each image evolved over an

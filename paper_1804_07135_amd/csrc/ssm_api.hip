@@ -22,7 +22,7 @@ namespace {
 constexpr int kVersion = 1;
 constexpr size_t kAlign = 256;
 constexpr size_t kLdsMax = 160 * 1024;
-constexpr int kNumMaps = 6;
+constexpr int kNumMaps = 7;
 
 thread_local std::string g_create_error;
 
@@ -66,7 +66,7 @@ struct Plan {
     std::vector<int> geo;             // problem -> distinct-shape index
     std::vector<std::tuple<int, int, int>> shapes;
     std::vector<long long> nh_size;   // elements per distinct shape
-    std::vector<int> wm_xf, wm_xi, wm_conv, wm_arc, wm_site, wm_img;
+    std::vector<int> wm_xf, wm_xi, wm_conv, wm_arc, wm_site, wm_img, wm_sitep;
     long long n_img = 0, n_spin = 0, n_x = 0, n_nh = 0, n_ep = 0, n_ap = 0, n_fp = 0, n_fm = 0;
     size_t lds_xf = 0, lds_xi = 0, lds_conv = 0;
     size_t scratch_bytes = 0;
@@ -77,6 +77,9 @@ struct Plan {
     // per-image state
     size_t o_rk_k = 0, o_rk_y = 0, o_rk_t = 0, o_rk_dtp = 0, o_rk_dtu = 0, o_rk_cap = 0, o_rk_act = 0,
            o_rk_acc = 0, o_rk_cnt = 0, o_rk_nact = 0;
+    // step-2 options: spline arrays, climbing image per problem, spline
+    // validity per problem, climbing coefficient per problem
+    size_t o_s2 = 0, o_kci = 0, o_splok = 0, o_cic = 0;
 };
 
 // LDS bytes of the FFT kernels: twiddle table (2m complex) + line buffer in
@@ -284,6 +287,7 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
     prefix(pl.wm_arc, [](const Prob& p) { return p.arc_chunks; });
     prefix(pl.wm_site, [](const Prob& p) { return p.K * p.ichunks; });
     prefix(pl.wm_img, [](const Prob& p) { return p.K; });
+    prefix(pl.wm_sitep, [](const Prob& p) { return p.ichunks; });
     // workspace layout
     const size_t ts = pl.tsize, cs = 2 * ts;
     size_t o = 0;
@@ -314,6 +318,10 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
     pl.o_flags = take(4);
     pl.o_seg = take(8 * img);
     pl.o_cnt = take(4 * np);
+    pl.o_s2 = take(8 * 7 * img);   // spline: hh, sa, den, cp, A, B, H per image
+    pl.o_kci = take(4 * np);
+    pl.o_splok = take(4 * np);
+    pl.o_cic = take(8 * np);
     if (rk) {
         pl.o_rk_k = take(7 * ts * spin);
         pl.o_rk_y = take(ts * spin);
@@ -353,6 +361,8 @@ struct ssm_ctx {
     int rk_method = SSM_STEP_EULER;
     double rk_rtol = 1e-6, rk_atol = 1e-6, rk_dt0 = 0.1;
     long long rk_nfe = 0;             // field evaluations by the integrator
+    int interp = SSM_INTERP_LINEAR;   // step 2 (ssm_set_reparam)
+    int climb = 0;
     struct Ev { int kind; hipEvent_t a, b; };
     std::vector<Ev> events;
     std::vector<hipEvent_t> pool;
@@ -374,6 +384,20 @@ struct ssm_ctx {
     WorkMap wm_arc() const { return wm(3, pl.wm_arc); }
     WorkMap wm_site() const { return wm(4, pl.wm_site); }
     WorkMap wm_img() const { return wm(5, pl.wm_img); }
+    WorkMap wm_sitep() const { return wm(6, pl.wm_sitep); }
+    Step2 step2() const
+    {
+        Step2 r;
+        r.opts = (interp == SSM_INTERP_SPLINE ? 1 : 0) | (climb ? 2 : 0);
+        r.E = at<double>(pl.o_E);
+        r.kci = at<int>(pl.o_kci);
+        r.spl_ok = at<int>(pl.o_splok);
+        double* b = at<double>(pl.o_s2);
+        const long long n = pl.n_img;
+        r.hh = b; r.sa = b + n; r.den = b + 2 * n; r.cp = b + 3 * n;
+        r.A = b + 4 * n; r.B = b + 5 * n; r.H = b + 6 * n;
+        return r;
+    }
     void* X() const { return ws + pl.o_big; }
     void* Xp() const { return ws + pl.o_big + 2 * pl.tsize * pl.n_x; }
 };
@@ -449,33 +473,86 @@ struct Ops {
         });
     }
 
-    static hipError_t iteration(ssm_ctx* c, hipStream_t st, double tau)
+    // Step 2: arc lengths of ss, the reduction (energies into E when
+    // write_E; the options' targets and spline factors in its last
+    // workgroup), interpolation into s: linear, or the natural cubic spline
+    // with its second derivatives in the field buffer (problems whose
+    // spline is degenerate fall back to linear)
+    static hipError_t step2(ssm_ctx* c, hipStream_t st, const T* ss, T* s, const int* done, bool write_E)
     {
         const Plan& pl = c->pl;
-        T* s = c->at<T>(pl.o_s);
-        T* ss = c->at<T>(pl.o_ss);
-        int* done = c->at<int>(pl.o_done);
-        hipError_t e = field(c, st, s, ss, nullptr, EPI_STEP, tau, done);
-        if (e != hipSuccess) return e;
-        e = timed(c, st, KK_ARC, [&] {
+        const Step2 o = c->step2();
+        int* flags = c->at<int>(pl.o_flags);
+        hipError_t e = timed(c, st, KK_ARC, [&] {
             return launch_arc<T>(c->P(), pl.np, c->wm_arc(), ss, c->at<double>(pl.o_ap), done, st);
         });
         if (e != hipSuccess) return e;
         e = timed(c, st, KK_REDUCE, [&] {
             return launch_reduce(c->P(), pl.np, (int)pl.n_img, c->wm_img().start,
                                  c->at<double>(pl.o_ep), c->at<double>(pl.o_ap),
-                                 c->at<double>(pl.o_E), nullptr, nullptr, nullptr,
+                                 write_E ? c->at<double>(pl.o_E) : nullptr, nullptr, nullptr, nullptr,
                                  c->at<double>(pl.o_seg), c->at<double>(pl.o_alpha),
                                  c->at<int>(pl.o_j), c->at<double>(pl.o_w), c->at<int>(pl.o_skip),
-                                 done, c->at<int>(pl.o_iters), c->at<int>(pl.o_cnt),
-                                 c->at<int>(pl.o_flags), 1, st);
+                                 const_cast<int*>(done), c->at<int>(pl.o_iters), c->at<int>(pl.o_cnt),
+                                 flags, 1, st, o);
         });
         if (e != hipSuccess) return e;
+        if (o.opts & 1) {
+            T* M = c->at<T>(pl.o_h);
+            e = timed(c, st, KK_INTERP, [&] {
+                return launch_spline_m<T>(c->P(), pl.np, c->wm_sitep(), ss, M, o, done, st);
+            });
+            if (e != hipSuccess) return e;
+            e = timed(c, st, KK_INTERP, [&] {
+                return launch_interp_spline<T>(c->P(), pl.np, c->wm_site(), ss, M, s, c->at<int>(pl.o_j),
+                                               c->at<double>(pl.o_w), o, done, flags, st);
+            });
+            if (e != hipSuccess) return e;
+        }
         return timed(c, st, KK_INTERP, [&] {
             return launch_interp<T>(c->P(), pl.np, c->wm_site(), ss, s, c->at<int>(pl.o_j),
-                                    c->at<double>(pl.o_w), c->at<int>(pl.o_skip), done,
-                                    c->at<int>(pl.o_flags), st);
+                                    c->at<double>(pl.o_w), c->at<int>(pl.o_skip), done, flags, st,
+                                    (o.opts & 2) ? o.kci : nullptr, (o.opts & 1) ? o.spl_ok : nullptr);
         });
+    }
+
+    static hipError_t iteration(ssm_ctx* c, hipStream_t st, double tau)
+    {
+        const Plan& pl = c->pl;
+        T* s = c->at<T>(pl.o_s);
+        T* ss = c->at<T>(pl.o_ss);
+        int* done = c->at<int>(pl.o_done);
+        const bool ci = c->climb != 0;
+        T* h = ci ? c->at<T>(pl.o_h) : nullptr;
+        hipError_t e = field(c, st, s, ss, h, EPI_STEP | (ci ? EPI_FIELD : 0), tau, done);
+        if (e != hipSuccess) return e;
+        if (ci) {
+            // energies of the current string, then the climbing image's step
+            const Step2 o = c->step2();
+            e = timed(c, st, KK_REDUCE, [&] {
+                return launch_reduce(c->P(), pl.np, (int)pl.n_img, c->wm_img().start, c->at<double>(pl.o_ep),
+                                     nullptr, c->at<double>(pl.o_E), nullptr, nullptr, nullptr, nullptr, nullptr,
+                                     nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c->at<int>(pl.o_flags), 0,
+                                     st);
+            });
+            if (e != hipSuccess) return e;
+            e = timed(c, st, KK_TAN1, [&] {
+                return launch_ci_part<T>(c->P(), pl.np, c->wm_sitep(), s, h, c->at<double>(pl.o_E),
+                                         c->at<double>(pl.o_fp), o.kci, done, st);
+            });
+            if (e != hipSuccess) return e;
+            e = timed(c, st, KK_TANRED, [&] {
+                return launch_ci_red(c->P(), pl.np, c->at<double>(pl.o_fp), o.kci, c->at<double>(pl.o_cic), done,
+                                     st);
+            });
+            if (e != hipSuccess) return e;
+            e = timed(c, st, KK_TAN2, [&] {
+                return launch_ci_step<T>(c->P(), pl.np, c->wm_sitep(), s, h, ss, o.kci, c->at<double>(pl.o_cic), tau,
+                                         done, st);
+            });
+            if (e != hipSuccess) return e;
+        }
+        return step2(c, st, ss, s, done, !ci);
     }
 
     // Adaptive Dormand-Prince integration of every image of the current
@@ -551,27 +628,12 @@ struct Ops {
         T* ss = c->at<T>(pl.o_ss);
         int* done = c->at<int>(pl.o_done);
         int* flags = c->at<int>(pl.o_flags);
-        const int nimg = (int)pl.n_img;
-        const int* istart = c->wm_img().start;
         ssm_status r = rk_interval(c, Tint, 0.0, 1.0, true);
         if (r != SSM_OK) return r;
         HIPCHK(c, timed(c, st, KK_RK, [&] {
                    return launch_rk_norm<T>(c->P(), pl.np, c->wm_site(), s, ss, done, flags, st);
                }), "integrator");
-        HIPCHK(c, timed(c, st, KK_ARC, [&] {
-                   return launch_arc<T>(c->P(), pl.np, c->wm_arc(), ss, c->at<double>(pl.o_ap), done, st);
-               }), "integrator");
-        HIPCHK(c, timed(c, st, KK_REDUCE, [&] {
-                   return launch_reduce(c->P(), pl.np, nimg, istart, c->at<double>(pl.o_ep),
-                                        c->at<double>(pl.o_ap), nullptr, nullptr, nullptr, nullptr,
-                                        c->at<double>(pl.o_seg), c->at<double>(pl.o_alpha), c->at<int>(pl.o_j),
-                                        c->at<double>(pl.o_w), c->at<int>(pl.o_skip), done,
-                                        c->at<int>(pl.o_iters), c->at<int>(pl.o_cnt), flags, 1, st);
-               }), "integrator");
-        HIPCHK(c, timed(c, st, KK_INTERP, [&] {
-                   return launch_interp<T>(c->P(), pl.np, c->wm_site(), ss, s, c->at<int>(pl.o_j),
-                                           c->at<double>(pl.o_w), c->at<int>(pl.o_skip), done, flags, st);
-               }), "integrator");
+        HIPCHK(c, step2(c, st, ss, s, done, false), "integrator");
         return SSM_OK;
     }
 
@@ -694,7 +756,7 @@ static ssm_status upload_plan(ssm_ctx* c)
     HIPCHK(c, hipMemcpyAsync(c->ws + pl.o_P, pl.P.data(), sizeof(Prob) * pl.np,
                              hipMemcpyHostToDevice, c->stream), "upload descriptors");
     std::vector<int> wm;
-    for (const auto* v : {&pl.wm_xf, &pl.wm_xi, &pl.wm_conv, &pl.wm_arc, &pl.wm_site, &pl.wm_img})
+    for (const auto* v : {&pl.wm_xf, &pl.wm_xi, &pl.wm_conv, &pl.wm_arc, &pl.wm_site, &pl.wm_img, &pl.wm_sitep})
         wm.insert(wm.end(), v->begin(), v->end());
     HIPCHK(c, hipMemcpyAsync(c->ws + pl.o_wm, wm.data(), sizeof(int) * wm.size(),
                              hipMemcpyHostToDevice, c->stream), "upload work maps");
@@ -1019,6 +1081,18 @@ ssm_status ssm_get_string(ssm_ctx* ctx, void* d_spins)
     return SSM_OK;
 }
 
+ssm_status ssm_set_reparam(ssm_ctx* ctx, int32_t interp, int32_t climbing)
+{
+    if (!ctx) return SSM_EINVAL;
+    if (interp != SSM_INTERP_LINEAR && interp != SSM_INTERP_SPLINE)
+        return fail(ctx, SSM_EINVAL, "unknown interpolation");
+    if (climbing != 0 && climbing != 1) return fail(ctx, SSM_EINVAL, "climbing must be 0 or 1");
+    if (interp != ctx->interp || climbing != ctx->climb) drop_graph(ctx);
+    ctx->interp = interp;
+    ctx->climb = climbing;
+    return SSM_OK;
+}
+
 ssm_status ssm_set_integrator(ssm_ctx* ctx, int32_t method, double rtol, double atol, double dt0)
 {
     if (!ctx) return SSM_EINVAL;
@@ -1108,6 +1182,8 @@ ssm_status ssm_iterate(ssm_ctx* ctx, int32_t max_iter, double tau, double tol_fo
     if (!ctx->have_string) return fail(ctx, SSM_ESTATE, "no string set");
     if (max_iter < 0 || !std::isfinite(tau) || !(tol_force >= 0.0))
         return fail(ctx, SSM_EINVAL, "max_iter >= 0, finite tau and tol_force >= 0 required");
+    if (ctx->climb && ctx->rk_method == SSM_STEP_DOPRI54)
+        return fail(ctx, SSM_EUNSUPPORTED, "the climbing image needs the explicit step");
     ssm_ctx* c = ctx;
     const Plan& pl = c->pl;
     HIPCHK(c, launch_fill_int(c->at<int>(pl.o_done), pl.np, 0, c->stream), "iterate");

@@ -129,14 +129,56 @@ hipError_t launch_xinv(const Prob* P, int np, const WorkMap& wm, const void* Xp,
 template <typename T>
 hipError_t launch_arc(const Prob* P, int np, const WorkMap& wm, const T* ss, double* apart,
                       const int* done, hipStream_t st);
+// Step-2 options of the reduction's last workgroup (ssm_set_reparam): bit 0
+// natural cubic spline, bit 1 climbing image.  E: the current energies
+// (climbing image choice); per problem: kci (climbing image or -1), spl_ok
+// (spline factors valid); per image: interval widths hh, Thomas factors
+// (sa, den, cp); per target image: spline weights A, B and interval width H.
+struct Step2 {
+    int opts = 0;
+    const double* E = nullptr;
+    int* kci = nullptr;
+    int* spl_ok = nullptr;
+    double* hh = nullptr;
+    double* sa = nullptr;
+    double* den = nullptr;
+    double* cp = nullptr;
+    double* A = nullptr;
+    double* B = nullptr;
+    double* H = nullptr;
+};
 hipError_t launch_reduce(const Prob* P, int np, int nimg, const int* istart, const double* epart,
                          const double* apart, double* E, double* Tm, double* E_out, double* T_out,
                          double* seg, double* alpha, int* jidx, double* wgt, int* skip, int* done,
-                         int* iters, int* count, int* flags, int with_arc, hipStream_t st);
+                         int* iters, int* count, int* flags, int with_arc, hipStream_t st,
+                         Step2 s2 = Step2{});
 template <typename T>
+// kci (or NULL): per-problem climbing image, copied like the endpoints;
+// skip_if (or NULL): problems whose flag is set are left to the spline
 hipError_t launch_interp(const Prob* P, int np, const WorkMap& wm, const T* ss, T* s,
                          const int* jidx, const double* wgt, const int* skip, const int* done,
-                         int* flags, hipStream_t st);
+                         int* flags, hipStream_t st, const int* kci = nullptr,
+                         const int* skip_if = nullptr);
+// natural cubic spline: second derivatives M of every site and component
+// (M buffer in the spin layout), then the interpolation at the targets
+template <typename T>
+hipError_t launch_spline_m(const Prob* P, int np, const WorkMap& wm_sitep, const T* ss, T* M, Step2 s2,
+                           const int* done, hipStream_t st);
+template <typename T>
+hipError_t launch_interp_spline(const Prob* P, int np, const WorkMap& wm, const T* ss, const T* M, T* s,
+                                const int* jidx, const double* wgt, Step2 s2, const int* done, int* flags,
+                                hipStream_t st);
+// climbing image: partial sums (|t~|^2, F.t~) over image kci, their
+// per-problem reduction to c = F.t~ / |t~|^2, and the step
+// normalise(s + tau (F - 2 c t~)) into ss
+template <typename T>
+hipError_t launch_ci_part(const Prob* P, int np, const WorkMap& wm, const T* s, const T* h, const double* E,
+                          double* part, int* kci, const int* done, hipStream_t st);
+hipError_t launch_ci_red(const Prob* P, int np, const double* part, const int* kci, double* coef,
+                         const int* done, hipStream_t st);
+template <typename T>
+hipError_t launch_ci_step(const Prob* P, int np, const WorkMap& wm, const T* s, const T* h, T* ss,
+                          const int* kci, const double* coef, double tau, const int* done, hipStream_t st);
 template <typename T>
 hipError_t launch_tan1(const Prob* P, int np, const WorkMap& wm, const T* s, const T* h,
                        T* tt, double* fpart, hipStream_t st);

@@ -889,11 +889,12 @@ __global__ __launch_bounds__(kNT) void k_reduce(const Prob* __restrict__ P, int 
                                                 double* E, double* Tm, double* E_out,
                                                 double* T_out, double* seg, double* alpha,
                                                 int* jidx, double* wgt, int* skip, int* done,
-                                                int* iters, int* count, int* flags, int with_arc)
+                                                int* iters, int* count, int* flags, int with_arc,
+                                                Step2 s2)
 {
     __shared__ double red[kNT / 64][kNTerm + 1];
     __shared__ double red_alpha[1024];
-    __shared__ int last;
+    __shared__ int last, s_kci;
     const int gimg = blockIdx.x;
     const int pi = find_problem(istart, np, gimg);
     if (with_arc && done && done[pi]) return;
@@ -964,24 +965,89 @@ __global__ __launch_bounds__(kNT) void k_reduce(const Prob* __restrict__ P, int 
             jidx[g0 + kk] = kk;
             wgt[g0 + kk] = 0;
         }
+        if (threadIdx.x == 0) {
+            if (s2.kci) s2.kci[pi] = -1;
+            if (s2.spl_ok) s2.spl_ok[pi] = 0;
+        }
         return;
     }
     for (int kk = 1 + threadIdx.x; kk < K; kk += kNT) al[kk] = al[kk] / L;
+    if (threadIdx.x == 0) {
+        // climbing image: the image of highest energy (smallest index on
+        // ties) when it is interior
+        int kci = -1;
+        if (s2.opts & 2) {
+            const volatile double* Ev = s2.E;
+            int km = 0;
+            double em = Ev[g0];
+            for (int kk = 1; kk < K; ++kk) {
+                const double e = Ev[g0 + kk];
+                if (e > em) { em = e; km = kk; }
+            }
+            if (km > 0 && km < K - 1) kci = km;
+        }
+        s_kci = kci;
+        if (s2.kci) s2.kci[pi] = kci;
+    }
     __syncthreads();
+    const int kci = s_kci;
+    // target of image kk: k/(K-1), or equal spacing within 0..kci and
+    // within kci..K-1 around a climbing image
+    auto target = [&](int kk) {
+        if (kci < 0) return (double)kk / (double)(K - 1);
+        if (kk <= kci) return al[kci] * (double)kk / (double)kci;
+        return al[kci] + (1.0 - al[kci]) * (double)(kk - kci) / (double)(K - 1 - kci);
+    };
     for (int kk = threadIdx.x; kk < K; kk += kNT) {
         alpha[g0 + kk] = al[kk];
-        if (kk == 0 || kk == K - 1) {
+        if (kk == 0 || kk == K - 1 || kk == kci) {
             jidx[g0 + kk] = kk;
             wgt[g0 + kk] = 0;
             continue;
         }
-        const double tk = (double)kk / (double)(K - 1);
+        const double tk = target(kk);
         int j = 0;
         for (int jj = 0; jj <= K - 2; ++jj)
             if (al[jj] <= tk) j = jj;
         const double width = al[j + 1] - al[j];
         jidx[g0 + kk] = j;
         wgt[g0 + kk] = (width > 0.0) ? (tk - al[j]) / width : 0.0;
+    }
+    if (!(s2.opts & 1)) return;
+    // natural cubic spline in alpha: interval widths and the Thomas factors
+    // of the tridiagonal system for the interior second derivatives
+    if (threadIdx.x == 0) {
+        int ok = K > 2;
+        for (int j = 0; j + 1 < K; ++j) {
+            const double hw = al[j + 1] - al[j];
+            s2.hh[g0 + j] = hw;
+            if (!(hw > 0.0)) ok = 0;
+        }
+        if (ok) {
+            double cpp = 0.0;
+            for (int i = 1; i <= K - 2; ++i) {
+                const double hl = al[i] - al[i - 1], hr = al[i + 1] - al[i];
+                const double a = hl / 6.0, b = (hl + hr) / 3.0, c = hr / 6.0;
+                const double den = b - (i > 1 ? a * cpp : 0.0);
+                cpp = c / den;
+                s2.sa[g0 + i] = a;
+                s2.den[g0 + i] = den;
+                s2.cp[g0 + i] = cpp;
+            }
+        }
+        s2.spl_ok[pi] = ok;
+    }
+    for (int kk = threadIdx.x; kk < K; kk += kNT) {
+        if (kk == 0 || kk == K - 1 || kk == kci) continue;
+        const double tk = target(kk);
+        int j = 0;
+        for (int jj = 0; jj <= K - 2; ++jj)
+            if (al[jj] <= tk) j = jj;
+        const double h = al[j + 1] - al[j];
+        const double A = (al[j + 1] - tk) / h;
+        s2.A[g0 + kk] = A;
+        s2.B[g0 + kk] = 1.0 - A;
+        s2.H[g0 + kk] = h;
     }
 }
 
@@ -996,10 +1062,13 @@ __global__ __launch_bounds__(kNT) void k_interp(const Prob* __restrict__ P, int 
                                                 const int* __restrict__ jidx,
                                                 const double* __restrict__ wgt,
                                                 const int* __restrict__ skip,
-                                                const int* __restrict__ done, int* flags)
+                                                const int* __restrict__ done, int* flags,
+                                                const int* __restrict__ kci,
+                                                const int* __restrict__ skip_if)
 {
     const int pi = find_problem(wstart, np, blockIdx.x);
     if (done && done[pi]) return;
+    if (skip_if && skip_if[pi]) return;
     const Prob& p = P[pi];
     const int w = blockIdx.x - wstart[pi];
     const int k = w / p.ichunks, chunk = w - k * p.ichunks;
@@ -1008,7 +1077,7 @@ __global__ __launch_bounds__(kNT) void k_interp(const Prob* __restrict__ P, int 
     if (i >= N) return;
     const T* src = ss + p.s_off;
     T* dst = s + p.s_off + (long long)k * M;
-    if (skip[pi] || k == 0 || k == p.K - 1) {
+    if (skip[pi] || k == 0 || k == p.K - 1 || (kci && k == kci[pi])) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) dst[c * N + i] = src[(long long)k * M + c * N + i];
         return;
@@ -1416,21 +1485,21 @@ hipError_t launch_arc(const Prob* P, int np, const WorkMap& wm, const T* ss, dou
 hipError_t launch_reduce(const Prob* P, int np, int nimg, const int* istart, const double* epart,
                          const double* apart, double* E, double* Tm, double* E_out, double* T_out,
                          double* seg, double* alpha, int* jidx, double* wgt, int* skip, int* done,
-                         int* iters, int* count, int* flags, int with_arc, hipStream_t st)
+                         int* iters, int* count, int* flags, int with_arc, hipStream_t st, Step2 s2)
 {
     hipLaunchKernelGGL(k_reduce, dim3(nimg), dim3(kNT), 0, st, P, np, istart, epart, apart, E, Tm,
-                       E_out, T_out, seg, alpha, jidx, wgt, skip, done, iters, count, flags, with_arc);
+                       E_out, T_out, seg, alpha, jidx, wgt, skip, done, iters, count, flags, with_arc, s2);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_interp(const Prob* P, int np, const WorkMap& wm, const T* ss, T* s,
                          const int* jidx, const double* wgt, const int* skip, const int* done,
-                         int* flags, hipStream_t st)
+                         int* flags, hipStream_t st, const int* kci, const int* skip_if)
 {
     if (wm.total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_interp<T>, dim3(wm.total), dim3(kNT), 0, st, P, np, wm.start, ss, s, jidx,
-                       wgt, skip, done, flags);
+                       wgt, skip, done, flags, kci, skip_if);
     return hipGetLastError();
 }
 
@@ -1766,6 +1835,277 @@ hipError_t launch_rk_norm(const Prob* P, int np, const WorkMap& wm, const T* s, 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Step-2 variants (Sec. III).  Natural cubic spline in alpha through the
+// images, per site and spin component: k_spline_m solves the tridiagonal
+// system for the second derivatives M (M_0 = M_{K-1} = 0) with the Thomas
+// factors of the reduction's last workgroup; k_interp_spline evaluates
+// A f_j + B f_{j+1} + ((A^3 - A) M_j + (B^3 - B) M_{j+1}) h^2/6 at every
+// target and renormalises.  Climbing image k*: force F - 2 (F.t) t with F
+// the perpendicular field and t the normalised per-spin-projected central
+// difference of its neighbours.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_spline_m(const Prob* __restrict__ P, int np,
+                                                  const int* __restrict__ wstart, const T* __restrict__ ss,
+                                                  T* __restrict__ M, Step2 s2, const int* __restrict__ done)
+{
+    const int pi = find_problem(wstart, np, blockIdx.x);
+    if ((done && done[pi]) || !s2.spl_ok[pi]) return;
+    const Prob& p = P[pi];
+    const long long N = p.N, Ms = 3 * N;
+    const long long i = (long long)(blockIdx.x - wstart[pi]) * kNT + threadIdx.x;
+    if (i >= N) return;
+    const int K = p.K, g0 = p.img0;
+#pragma unroll 1
+    for (int c = 0; c < 3; ++c) {
+        const long long o = p.s_off + c * N + i;
+        double fm = (double)ss[o], f0 = (double)ss[o + Ms], dpp = 0.0;
+        M[o] = T(0);
+        M[o + (long long)(K - 1) * Ms] = T(0);
+        for (int k = 1; k <= K - 2; ++k) {
+            const double fp = (double)ss[o + (long long)(k + 1) * Ms];
+            const double r = (fp - f0) / s2.hh[g0 + k] - (f0 - fm) / s2.hh[g0 + k - 1];
+            const double dp = (r - (k > 1 ? s2.sa[g0 + k] * dpp : 0.0)) / s2.den[g0 + k];
+            M[o + (long long)k * Ms] = (T)dp;
+            dpp = dp;
+            fm = f0;
+            f0 = fp;
+        }
+        double mn = (double)M[o + (long long)(K - 2) * Ms];
+        for (int k = K - 3; k >= 1; --k) {
+            const double mk = (double)M[o + (long long)k * Ms] - s2.cp[g0 + k] * mn;
+            M[o + (long long)k * Ms] = (T)mk;
+            mn = mk;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_interp_spline(const Prob* __restrict__ P, int np,
+                                                       const int* __restrict__ wstart, const T* __restrict__ ss,
+                                                       const T* __restrict__ M, T* __restrict__ s,
+                                                       const int* __restrict__ jidx,
+                                                       const double* __restrict__ wgt, Step2 s2,
+                                                       const int* __restrict__ done, int* flags)
+{
+    const int pi = find_problem(wstart, np, blockIdx.x);
+    if ((done && done[pi]) || !s2.spl_ok[pi]) return;
+    const Prob& p = P[pi];
+    const int w = blockIdx.x - wstart[pi];
+    const int k = w / p.ichunks, chunk = w - k * p.ichunks;
+    const long long N = p.N, Ms = 3 * N;
+    const long long i = (long long)chunk * kNT + threadIdx.x;
+    if (i >= N) return;
+    const T* src = ss + p.s_off;
+    T* dst = s + p.s_off + (long long)k * Ms;
+    if (k == 0 || k == p.K - 1 || k == s2.kci[pi]) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dst[c * N + i] = src[(long long)k * Ms + c * N + i];
+        return;
+    }
+    const int g = p.img0 + k;
+    const int j = jidx[g];
+    const double A = s2.A[g], B = s2.B[g], h = s2.H[g];
+    const long long oa = (long long)j * Ms + i, ob = oa + Ms;
+    double v[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const long long q = c * N;
+        v[c] = A * (double)src[oa + q] + B * (double)src[ob + q];
+        v[c] += ((A * A * A - A) * (double)M[p.s_off + oa + q] + (B * B * B - B) * (double)M[p.s_off + ob + q]) *
+                h * h / 6.0;
+    }
+    const double nrm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    if (nrm < 1e-12) {
+        atomicOr(flags, 2);
+        const long long on = (wgt[g] < 0.5) ? oa : ob;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dst[c * N + i] = src[on + c * N];
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dst[c * N + i] = (T)(v[c] / nrm);
+    }
+}
+
+// one workgroup per (problem, site chunk): the image of highest energy
+// (every workgroup finds the same one) and, when interior, partial sums of
+// |t~|^2 and F.t~ over the chunk
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_ci_part(const Prob* __restrict__ P, int np,
+                                                 const int* __restrict__ wstart, const T* __restrict__ s,
+                                                 const T* __restrict__ h, const double* __restrict__ E,
+                                                 double* __restrict__ part, int* __restrict__ kci,
+                                                 const int* __restrict__ done)
+{
+    __shared__ double red[kNT / 64][2];
+    __shared__ int s_km;
+    const int pi = find_problem(wstart, np, blockIdx.x);
+    if (done && done[pi]) return;
+    const Prob& p = P[pi];
+    const int chunk = blockIdx.x - wstart[pi];
+    const int K = p.K, g0 = p.img0;
+    if (threadIdx.x == 0) {
+        int km = 0;
+        double em = E[g0];
+        for (int kk = 1; kk < K; ++kk)
+            if (E[g0 + kk] > em) { em = E[g0 + kk]; km = kk; }
+        s_km = km;
+        if (chunk == 0) kci[pi] = (km > 0 && km < K - 1) ? km : -1;
+    }
+    __syncthreads();
+    const int km = s_km;
+    if (km == 0 || km == K - 1) return;
+    const long long N = p.N, Ms = 3 * N;
+    const long long i = (long long)chunk * kNT + threadIdx.x;
+    double q1 = 0.0, q2 = 0.0;
+    if (i < N) {
+        const long long o = p.s_off + (long long)km * Ms + i;
+        double v[3], f[3], dl[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            v[c] = (double)s[o + c * N];
+            f[c] = (double)h[o + c * N];
+            dl[c] = (double)s[o + Ms + c * N] - (double)s[o - Ms + c * N];
+        }
+        const double sh = v[0] * f[0] + v[1] * f[1] + v[2] * f[2];
+        const double sd = v[0] * dl[0] + v[1] * dl[1] + v[2] * dl[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double F = f[c] - sh * v[c], t = dl[c] - sd * v[c];
+            q1 += t * t;
+            q2 += F * t;
+        }
+    }
+    q1 = wave_sum(q1);
+    q2 = wave_sum(q2);
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6][0] = q1;
+        red[threadIdx.x >> 6][1] = q2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int wv = 0; wv < kNT / 64; ++wv) {
+            a += red[wv][0];
+            b += red[wv][1];
+        }
+        part[p.fp_off + (long long)chunk * 2] = a;
+        part[p.fp_off + (long long)chunk * 2 + 1] = b;
+    }
+}
+
+__global__ __launch_bounds__(kNT) void k_ci_red(const Prob* __restrict__ P, int np,
+                                                const double* __restrict__ part, const int* __restrict__ kci,
+                                                double* __restrict__ coef, const int* __restrict__ done)
+{
+    __shared__ double red[kNT / 64][2];
+    const int pi = blockIdx.x;
+    if ((done && done[pi]) || kci[pi] < 0) return;
+    const Prob& p = P[pi];
+    double a = 0.0, b = 0.0;
+    for (int t = threadIdx.x; t < p.ichunks; t += kNT) {
+        a += part[p.fp_off + (long long)t * 2];
+        b += part[p.fp_off + (long long)t * 2 + 1];
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6][0] = a;
+        red[threadIdx.x >> 6][1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tn2 = 0.0, ft = 0.0;
+        for (int wv = 0; wv < kNT / 64; ++wv) {
+            tn2 += red[wv][0];
+            ft += red[wv][1];
+        }
+        coef[pi] = (tn2 > 0.0) ? ft / tn2 : 0.0;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_ci_step(const Prob* __restrict__ P, int np,
+                                                 const int* __restrict__ wstart, const T* __restrict__ s,
+                                                 const T* __restrict__ h, T* __restrict__ ss,
+                                                 const int* __restrict__ kci, const double* __restrict__ coef,
+                                                 double tau, const int* __restrict__ done)
+{
+    const int pi = find_problem(wstart, np, blockIdx.x);
+    if (done && done[pi]) return;
+    const int km = kci[pi];
+    if (km < 0) return;
+    const Prob& p = P[pi];
+    const long long N = p.N, Ms = 3 * N;
+    const long long i = (long long)(blockIdx.x - wstart[pi]) * kNT + threadIdx.x;
+    if (i >= N) return;
+    const long long o = p.s_off + (long long)km * Ms + i;
+    const double cc = coef[pi];
+    double v[3], f[3], dl[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        v[c] = (double)s[o + c * N];
+        f[c] = (double)h[o + c * N];
+        dl[c] = (double)s[o + Ms + c * N] - (double)s[o - Ms + c * N];
+    }
+    const double sh = v[0] * f[0] + v[1] * f[1] + v[2] * f[2];
+    const double sd = v[0] * dl[0] + v[1] * dl[1] + v[2] * dl[2];
+    double w[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) w[c] = v[c] + tau * ((f[c] - sh * v[c]) - 2.0 * cc * (dl[c] - sd * v[c]));
+    const double nrm = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ss[o + c * N] = (T)(w[c] / nrm);
+}
+
+template <typename T>
+hipError_t launch_spline_m(const Prob* P, int np, const WorkMap& wm_sitep, const T* ss, T* M, Step2 s2,
+                           const int* done, hipStream_t st)
+{
+    if (wm_sitep.total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spline_m<T>, dim3(wm_sitep.total), dim3(kNT), 0, st, P, np, wm_sitep.start, ss, M, s2,
+                       done);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_interp_spline(const Prob* P, int np, const WorkMap& wm, const T* ss, const T* M, T* s,
+                                const int* jidx, const double* wgt, Step2 s2, const int* done, int* flags,
+                                hipStream_t st)
+{
+    if (wm.total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_interp_spline<T>, dim3(wm.total), dim3(kNT), 0, st, P, np, wm.start, ss, M, s, jidx, wgt,
+                       s2, done, flags);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ci_part(const Prob* P, int np, const WorkMap& wm, const T* s, const T* h, const double* E,
+                          double* part, int* kci, const int* done, hipStream_t st)
+{
+    if (wm.total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ci_part<T>, dim3(wm.total), dim3(kNT), 0, st, P, np, wm.start, s, h, E, part, kci, done);
+    return hipGetLastError();
+}
+
+hipError_t launch_ci_red(const Prob* P, int np, const double* part, const int* kci, double* coef,
+                         const int* done, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ci_red, dim3(np), dim3(kNT), 0, st, P, np, part, kci, coef, done);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ci_step(const Prob* P, int np, const WorkMap& wm, const T* s, const T* h, T* ss,
+                          const int* kci, const double* coef, double tau, const int* done, hipStream_t st)
+{
+    if (wm.total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ci_step<T>, dim3(wm.total), dim3(kNT), 0, st, P, np, wm.start, s, h, ss, kci, coef, tau,
+                       done);
+    return hipGetLastError();
+}
+
 __global__ void k_fill_double(double* p, int n, double v)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1793,7 +2133,17 @@ hipError_t launch_fill_double(double* p, int n, double v, hipStream_t st)
                                       const int*, hipStream_t);                                    \
     template hipError_t launch_interp<T>(const Prob*, int, const WorkMap&, const T*, T*,          \
                                          const int*, const double*, const int*, const int*, int*, \
-                                         hipStream_t);                                             \
+                                         hipStream_t, const int*, const int*);                     \
+    template hipError_t launch_spline_m<T>(const Prob*, int, const WorkMap&, const T*, T*, Step2,  \
+                                           const int*, hipStream_t);                               \
+    template hipError_t launch_interp_spline<T>(const Prob*, int, const WorkMap&, const T*,        \
+                                                const T*, T*, const int*, const double*, Step2,    \
+                                                const int*, int*, hipStream_t);                    \
+    template hipError_t launch_ci_part<T>(const Prob*, int, const WorkMap&, const T*, const T*,   \
+                                          const double*, double*, int*, const int*, hipStream_t);  \
+    template hipError_t launch_ci_step<T>(const Prob*, int, const WorkMap&, const T*, const T*,   \
+                                          T*, const int*, const double*, double, const int*,       \
+                                          hipStream_t);                                            \
     template hipError_t launch_tan1<T>(const Prob*, int, const WorkMap&, const T*, const T*, T*,  \
                                        double*, hipStream_t);                                      \
     template hipError_t launch_tan2<T>(const Prob*, int, const WorkMap&, const T*, const T*,      \

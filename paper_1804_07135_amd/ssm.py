@@ -28,6 +28,8 @@ SSM_FP32_MIXED = 1
 SSM_WITH_RK = 0x100
 SSM_STEP_EULER = 0
 SSM_STEP_DOPRI54 = 1
+SSM_INTERP_LINEAR = 0
+SSM_INTERP_SPLINE = 1
 SSM_N_KERNELS = 13
 FLAG_NONFINITE_ENERGY = 1
 FLAG_ZERO_NORM_SPIN = 2
@@ -40,7 +42,7 @@ ABI_SYMBOLS = [
     "ssm_set_string", "ssm_get_string", "ssm_iterate", "ssm_eval", "ssm_get_energies",
     "ssm_get_fields", "ssm_get_tangents", "ssm_get_barrier", "ssm_set_options", "ssm_autotune",
     "ssm_check", "ssm_last_error", "ssm_profile", "ssm_profile_read", "ssm_kernel_name",
-    "ssm_set_integrator", "ssm_get_rk_stats", "ssm_llg",
+    "ssm_set_integrator", "ssm_get_rk_stats", "ssm_llg", "ssm_set_reparam",
 ]
 
 
@@ -95,6 +97,7 @@ def load():
         "ssm_set_integrator": (_i32, [_vp, _i32, _dbl, _dbl, _dbl]),
         "ssm_get_rk_stats": (_i32, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
         "ssm_llg": (_i32, [_vp, _dbl, _dbl]),
+        "ssm_set_reparam": (_i32, [_vp, _i32, _i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -218,6 +221,10 @@ def ssm_autotune(ctx, cache_path=None):
 
 def ssm_set_integrator(ctx, method, rtol=1e-6, atol=1e-6, dt0=0.1):
     _check(load().ssm_set_integrator(ctx, int(method), float(rtol), float(atol), float(dt0)), ctx)
+
+
+def ssm_set_reparam(ctx, interp=SSM_INTERP_LINEAR, climbing=False):
+    _check(load().ssm_set_reparam(ctx, int(interp), 1 if climbing else 0), ctx)
 
 
 def ssm_llg(ctx, t_total, alpha):
@@ -363,6 +370,11 @@ class StringMethod:
         """Step 1 of iterate(): SSM_STEP_EULER (tau = step) or SSM_STEP_DOPRI54
         (tau = interval of the adaptive Dormand-Prince integration)."""
         ssm_set_integrator(self.ctx, method, rtol, atol, dt0)
+
+    def set_reparam(self, interp=SSM_INTERP_LINEAR, climbing=False):
+        """Step 2 of iterate(): linear or natural-cubic-spline interpolation,
+        optionally with a climbing image."""
+        ssm_set_reparam(self.ctx, interp, climbing)
 
     def llg(self, t_total, alpha):
         """Evolve every image by the LLG equation (eq. (9)) over t_total with the
