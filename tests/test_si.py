@@ -1,0 +1,106 @@
+"""SI front end (Sec. IV material and interval; Fig. 3 phase diagrams):
+conversions pinned by evaluating eq. (1) directly in SI units and by the
+precession frequency of a spin against CODATA's electron gyromagnetic
+ratio; the phase-diagram driver on the GPU against single-point runs."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+from scipy import constants as sc
+
+from paper_1804_07135_amd import inputs, si
+
+
+def energy_si(s, m, d_meV, k_meV, dipolar=True):
+    """Eq. (1) in joules for unit spins s [3, nz, ny, nx]: exchange and DMI
+    over bonds counted once, anisotropy, and the dipole sum over ordered
+    pairs with the moments |S| mu_B s and distances in metres."""
+    J = m.J_meV * 1e-3 * sc.e
+    d = d_meV * 1e-3 * sc.e
+    k = k_meV * 1e-3 * sc.e
+    nz, ny, nx = s.shape[1:]
+    sites = list(itertools.product(range(nz), range(ny), range(nx)))
+    spin = {q: s[:, q[0], q[1], q[2]] for q in sites}
+    E = 0.0
+    for (z, y, x) in sites:
+        a = spin[(z, y, x)]
+        E -= k * a[2] ** 2
+        for dx, dy, dz in ((1, 0, 0), (0, 1, 0), (0, 0, 1)):
+            q = (z + dz, y + dy, x + dx)
+            if q not in spin:
+                continue
+            b = spin[q]
+            E -= J * a @ b
+            r = np.array([dx, dy, dz], float)
+            E += d * np.cross(r, [0, 0, 1]) @ np.cross(a, b)
+    if not dipolar:
+        return E
+    mom = m.S * sc.physical_constants["Bohr magneton"][0]
+    for p, q in itertools.permutations(sites, 2):
+        r = np.array([q[2] - p[2], q[1] - p[1], q[0] - p[0]], float) * m.a
+        rn = np.linalg.norm(r)
+        e = r / rn
+        Si, Sj = mom * spin[p], mom * spin[q]
+        E -= sc.mu_0 / (8 * math.pi) * (3 * (Si @ e) * (Sj @ e) - Si @ Sj) / rn ** 3
+    return E
+
+
+@pytest.mark.parametrize("d_meV,k_meV,dipolar", [(5.3, 1.7, True), (5.3, 0.0, False),
+                                                 (0.0, 1.7, False), (0.0, 0.0, True)])
+def test_energy_in_si_equals_reduced_times_j(oracle, d_meV, k_meV, dipolar):
+    """Each term separately and all together: the library's reduced problem
+    at (d, k) in meV has energy E_SI / J.  The tolerance covers the CODATA
+    revision between the module's constants and scipy's."""
+    m = si.PAPER
+    s = inputs.random_unit_spins((3, 2, 3, 4), seed=9)
+    p = si.reduced_params(d_meV, k_meV, m, dipolar=dipolar)
+    E_red = oracle.energy(s, p["J"], p["d"], p["ku"], p["D"])
+    E_si = energy_si(s, m, d_meV, k_meV, dipolar)
+    assert abs(E_red * m.J_joule - E_si) <= 1e-9 * abs(E_si)
+    E_meV = E_si / (1e-3 * sc.e)
+    assert abs(si.energy_meV(E_red, m) - E_meV) <= 1e-9 * abs(E_meV)
+
+
+def test_dipolar_strength_is_small_for_the_paper_material():
+    # about 0.015 meV per unit pair at one lattice constant, J = 54.23 meV
+    assert 2.7e-4 < si.dipolar_reduced() < 2.9e-4
+
+
+def test_time_unit_from_precession():
+    """A spin precessing in its anisotropy field: in reduced time the angular
+    velocity is 2 k_red cos(theta); in SI it is gamma_e B with B = 2 k cos(theta)
+    / |S| (|S| in J/T).  The two agree through the time unit."""
+    m = si.PAPER
+    k_meV, th = 1.3, 0.6
+    omega_red = 2 * (k_meV / m.J_meV) * math.cos(th)
+    B = 2 * k_meV * 1e-3 * sc.e * math.cos(th) / (m.S * sc.physical_constants["Bohr magneton"][0])
+    omega_si = sc.physical_constants["electron gyromag. ratio"][0] * B
+    assert abs(omega_red / si.time_unit(m) / omega_si - 1) < 1e-3
+
+
+def test_interval_conversion():
+    t0 = si.time_unit()
+    assert abs(si.llg_time_reduced(5e-14) - 5e-14 / t0) < 1e-15
+    assert abs(si.interval_reduced(5e-14, 1.0) - 0.5 * 5e-14 / t0) < 1e-15
+    assert si.interval_reduced(5e-14, 0.0) == 0.0
+    p = si.paper_problem(5.0, 1.0)
+    assert (p["nx"], p["ny"], p["nz"], p["K"]) == (112, 112, 1, 60)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("integrator", ["euler", "dopri"])
+def test_phase_diagram_points_equal_single_runs(integrator):
+    """Each grid point of the batched phase-diagram run equals the same point
+    run alone (FP64, small lattice)."""
+    from paper_1804_07135_amd import ssm
+    kw = dict(n=20, K=5, R=3.0, iters=12, precision=ssm.SSM_FP64, integrator=integrator,
+              dt_seconds=2e-15, alpha=0.5)
+    d = [5.0, 8.0]
+    k = [1.0, 2.5]
+    full = si.phase_diagram(d, k, **kw)
+    assert full["barrier"].shape == (2, 2)
+    assert np.all(np.isfinite(full["barrier"]))
+    for i, j in itertools.product(range(2), range(2)):
+        one = si.phase_diagram([d[i]], [k[j]], seed=2 * i + j, **kw)
+        assert one["barrier"][0, 0] == full["barrier"][i, j]
