@@ -262,19 +262,17 @@ __device__ __forceinline__ void conv_zphase(const Prob& p, int G, int kx0, int h
         // are multiples of the line length, so padx distributes
         const int cbase = padx<PADL>(((g * 3 * nz) << LMY) + qy);
         V b[3][MZ];
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int zz = 0; zz < MZ; ++zz) b[c][zz] = mk<V>(0, 0);
-#pragma unroll 1
-        for (int hz = 0; hz < nhz; ++hz) {
+        // the two z halves as separate bodies (hz a compile-time constant:
+        // the even half has no twiddles, and no selects between the halves)
+        auto zhalf = [&](auto hzc) {
+            constexpr int hz = decltype(hzc)::value;
             V a[3][MZ];
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int zz = 0; zz < MZ; ++zz) {
                     V v = (zz < nz) ? lines[cbase + padx<PADL>((c * nz + zz) << LMY)] : mk<V>(0, 0);
-                    if (hz) v = twz<false, V, MZ>(v, zz, tw);
+                    if constexpr (hz == 1) v = twz<false, V, MZ>(v, zz, tw);
                     a[c][zz] = v;
                 }
 #pragma unroll
@@ -298,10 +296,16 @@ __device__ __forceinline__ void conv_zphase(const Prob& p, int G, int kx0, int h
 #pragma unroll
                 for (int zz = 0; zz < MZ; ++zz) {
                     V v = a[c][zz];
-                    if (hz) v = twz<true, V, MZ>(v, zz, tw);
-                    b[c][zz] = cadd(b[c][zz], v);
+                    if constexpr (hz == 1) {
+                        v = twz<true, V, MZ>(v, zz, tw);
+                        b[c][zz] = cadd(b[c][zz], v);
+                    } else {
+                        b[c][zz] = v;
+                    }
                 }
-        }
+        };
+        zhalf(std::integral_constant<int, 0>{});
+        if (nhz > 1) zhalf(std::integral_constant<int, 1>{});
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
