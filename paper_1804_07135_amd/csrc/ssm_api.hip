@@ -240,6 +240,7 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
         img += p.K;
         spin += (long long)p.K * 3 * p.N;
         xo += (long long)p.K * (p.mx + 1) * 3 * p.nz * p.ny;
+        xo = (xo + 31) & ~31LL;  // every problem's spectra start 256-byte aligned (paired 16-byte accesses)
         // sized for the smallest inverse tile (2 rows) so that retuned tiles
         // keep the workspace layout
         ep += (long long)p.K * p.nz * ((p.ny + 1) / 2) * kNTerm;

@@ -132,6 +132,32 @@ __device__ __forceinline__ void fft_lines_x(V* lines, int nl, int lm, const V* t
     }
 }
 
+// Two adjacent complex values p[0], p[1] with one 16-byte access in FP32
+// (p 16-byte aligned: the spectra of an even ny, at an even y); in FP64 each
+// value is a 16-byte access already.
+template <typename V>
+__device__ __forceinline__ void load2(const V* p, V& a, V& b)
+{
+    if constexpr (sizeof(V) == 8) {
+        const float4 q = *reinterpret_cast<const float4*>(p);
+        a = mk<V>(q.x, q.y);
+        b = mk<V>(q.z, q.w);
+    } else {
+        a = p[0];
+        b = p[1];
+    }
+}
+template <typename V>
+__device__ __forceinline__ void store2(V* p, V a, V b)
+{
+    if constexpr (sizeof(V) == 8) {
+        *reinterpret_cast<float4*>(p) = make_float4(a.x, a.y, b.x, b.y);
+    } else {
+        p[0] = a;
+        p[1] = b;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // k_xfwd: rows of a tile (image, z, ytf rows) -> x half-spectra, one spin
 // component at a time.  Two real rows of one component form one complex
@@ -199,8 +225,12 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
             const V B = mk<V>((Z.y + Zr.y) * hlf, (Zr.x - Z.x) * hlf);
             const int ya = y0 + 2 * rp;
             V* dst = Xi + (((long long)kx * 3 + c) * nz + z) * ny;
-            if (ya < ny) dst[ya] = A;
-            if (ya + 1 < ny) dst[ya + 1] = B;
+            if (!(ny & 1)) {
+                if (ya < ny) store2(dst + ya, A, B);
+            } else {
+                if (ya < ny) dst[ya] = A;
+                if (ya + 1 < ny) dst[ya + 1] = B;
+            }
         }
         __syncthreads();
     }
@@ -671,8 +701,19 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
             const long long o = (((long long)kx * 3 + c) * nz + z) * ny;
             const V* src = Xi + o;
             const V* srq = Xj + o;
-            const V A = (ya < ny) ? cadd(src[ya], srq[ya]) : mk<V>(0, 0);
-            const V B = (ya + 1 < ny) ? cadd(src[ya + 1], srq[ya + 1]) : mk<V>(0, 0);
+            V A = mk<V>(0, 0), B = mk<V>(0, 0);
+            if (!(ny & 1)) {
+                if (ya < ny) {
+                    V a0, a1, b0, b1;
+                    load2(src + ya, a0, a1);
+                    load2(srq + ya, b0, b1);
+                    A = cadd(a0, b0);
+                    B = cadd(a1, b1);
+                }
+            } else {
+                if (ya < ny) A = cadd(src[ya], srq[ya]);
+                if (ya + 1 < ny) B = cadd(src[ya + 1], srq[ya + 1]);
+            }
             const int i0 = (2 * rp + (kx & 1)) * m + (kx >> 1);
             lines[i0 + (i0 >> psh)] = mk<V>(A.x - B.y, A.y + B.x);
             if (kx > 0 && kx < m) {
