@@ -193,9 +193,33 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     V* Xi = X + p.x_off + (long long)img * (m + 1) * 3 * nz * ny;
     const int y0 = ty * yt, P2 = 2 * m;
     __syncthreads();
+    // FP32 rows of a length divisible by 4 from a 16-byte aligned image are
+    // read four sites per 16-byte load
+    const bool vec4 = sizeof(T) == 4 && !(nx & 3) && !(reinterpret_cast<size_t>(si) & 15);
 #pragma unroll 1
     for (int c = 0; c < 3; ++c) {
         const T* sc = si + (long long)c * N;
+        if (vec4) {
+            const int lm4 = lm - 2;
+#pragma unroll 1
+            for (int idx = threadIdx.x; idx < (hp << lm4); idx += kNT) {
+                const int j = (idx & ((1 << lm4) - 1)) << 2, rp = idx >> lm4;
+                const int ya = y0 + 2 * rp;
+                float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
+                if (j < nx) {
+                    if (ya < ny) a = *reinterpret_cast<const float4*>(sc + (long long)ya * nx + j);
+                    if (ya + 1 < ny) b = *reinterpret_cast<const float4*>(sc + (long long)(ya + 1) * nx + j);
+                }
+                const T av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const V v = mk<V>(av[k], bv[k]);
+                    const int i0 = (2 * rp) * m + j + k, i1 = i0 + m;
+                    lines[i0 + (i0 >> psh)] = v;
+                    lines[i1 + (i1 >> psh)] = cmul(v, twl[j + k]);
+                }
+            }
+        } else {
         // unrolled so that several loads are in flight per thread
 #pragma unroll 4
         for (int idx = threadIdx.x; idx < hp * m; idx += kNT) {
@@ -210,6 +234,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
             const int i0 = (2 * rp) * m + j, i1 = i0 + m;
             lines[i0 + (i0 >> psh)] = v;
             lines[i1 + (i1 >> psh)] = cmul(v, twl[j]);
+        }
         }
         __syncthreads();
         fft_lines_x<V, false>(lines, yt, lm, twl);
