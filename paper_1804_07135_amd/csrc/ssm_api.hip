@@ -22,7 +22,7 @@ namespace {
 constexpr int kVersion = 1;
 constexpr size_t kAlign = 256;
 constexpr size_t kLdsMax = 160 * 1024;
-constexpr int kNumMaps = 7;
+constexpr int kNumMaps = 8;
 
 thread_local std::string g_create_error;
 
@@ -66,7 +66,7 @@ struct Plan {
     std::vector<int> geo;             // problem -> distinct-shape index
     std::vector<std::tuple<int, int, int>> shapes;
     std::vector<long long> nh_size;   // elements per distinct shape
-    std::vector<int> wm_xf, wm_xi, wm_conv, wm_arc, wm_site, wm_img, wm_sitep;
+    std::vector<int> wm_xf, wm_xi, wm_conv, wm_arc, wm_site, wm_img, wm_sitep, wm_site4;
     long long n_img = 0, n_spin = 0, n_x = 0, n_nh = 0, n_ep = 0, n_ap = 0, n_fp = 0, n_fm = 0;
     size_t lds_xf = 0, lds_xi = 0, lds_conv = 0;
     size_t scratch_bytes = 0;
@@ -234,6 +234,10 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
         p.ap_off = ap;
         p.arc_chunks = (int)((3 * p.N + kNT * kArcEPT - 1) / (kNT * kArcEPT));
         p.ichunks = (int)((p.N + kNT - 1) / kNT);
+        // spin buffers are 256-byte aligned, so an image is 16-byte aligned
+        // when its element offset is a multiple of 4
+        p.vec4 = (pl.tsize == 4 && p.N % 4 == 0 && spin % 4 == 0) ? 1 : 0;
+        p.ichunks4 = p.vec4 ? (int)((p.N + 4 * kNT - 1) / (4 * kNT)) : p.ichunks;
         p.fp_off = fp;
         p.fm_off = fm;
         p.J = q.J; p.d = q.d; p.ku = q.ku; p.D = q.dip;
@@ -289,6 +293,7 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
     prefix(pl.wm_site, [](const Prob& p) { return p.K * p.ichunks; });
     prefix(pl.wm_img, [](const Prob& p) { return p.K; });
     prefix(pl.wm_sitep, [](const Prob& p) { return p.ichunks; });
+    prefix(pl.wm_site4, [](const Prob& p) { return p.K * p.ichunks4; });
     // workspace layout
     const size_t ts = pl.tsize, cs = 2 * ts;
     size_t o = 0;
@@ -386,6 +391,7 @@ struct ssm_ctx {
     WorkMap wm_site() const { return wm(4, pl.wm_site); }
     WorkMap wm_img() const { return wm(5, pl.wm_img); }
     WorkMap wm_sitep() const { return wm(6, pl.wm_sitep); }
+    WorkMap wm_site4() const { return wm(7, pl.wm_site4); }
     Step2 step2() const
     {
         Step2 r;
@@ -511,7 +517,7 @@ struct Ops {
             if (e != hipSuccess) return e;
         }
         return timed(c, st, KK_INTERP, [&] {
-            return launch_interp<T>(c->P(), pl.np, c->wm_site(), ss, s, c->at<int>(pl.o_j),
+            return launch_interp<T>(c->P(), pl.np, c->wm_site4(), ss, s, c->at<int>(pl.o_j),
                                     c->at<double>(pl.o_w), c->at<int>(pl.o_skip), done, flags, st,
                                     (o.opts & 2) ? o.kci : nullptr, (o.opts & 1) ? o.spl_ok : nullptr);
         });
@@ -757,7 +763,7 @@ static ssm_status upload_plan(ssm_ctx* c)
     HIPCHK(c, hipMemcpyAsync(c->ws + pl.o_P, pl.P.data(), sizeof(Prob) * pl.np,
                              hipMemcpyHostToDevice, c->stream), "upload descriptors");
     std::vector<int> wm;
-    for (const auto* v : {&pl.wm_xf, &pl.wm_xi, &pl.wm_conv, &pl.wm_arc, &pl.wm_site, &pl.wm_img, &pl.wm_sitep})
+    for (const auto* v : {&pl.wm_xf, &pl.wm_xi, &pl.wm_conv, &pl.wm_arc, &pl.wm_site, &pl.wm_img, &pl.wm_sitep, &pl.wm_site4})
         wm.insert(wm.end(), v->begin(), v->end());
     HIPCHK(c, hipMemcpyAsync(c->ws + pl.o_wm, wm.data(), sizeof(int) * wm.size(),
                              hipMemcpyHostToDevice, c->stream), "upload work maps");

@@ -93,6 +93,8 @@ struct Prob {
     long long fp_off;      // offset (doubles) of tangent partials: [K][ichunks][2]
     long long fm_off;      // offset (doubles) of per-workgroup force maxima: [K][ichunks]
     int ichunks;           // per-site workgroups per image (interp / tangents)
+    int vec4;              // FP32 images of N divisible by 4, 16-byte aligned: 4 sites per thread
+    int ichunks4;          // interpolation workgroups per image (ichunks / 4 with vec4)
     int pad2_;
     double J, d, ku, D;    // eq. (1) parameters
 };

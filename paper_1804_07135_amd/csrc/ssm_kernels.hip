@@ -916,13 +916,47 @@ __global__ __launch_bounds__(kNT) void k_arc(const Prob* __restrict__ P, int np,
     const long long M = 3 * p.N;
     const long long base = (long long)chunk * (kNT * kArcEPT) + threadIdx.x;
     const T* src = ss + p.s_off;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if constexpr (sizeof(T) == 4) {
+        if (p.vec4) {
+            // the chunk's kNT * kArcEPT elements as 16-byte loads (M is a
+            // multiple of 4, so a load is wholly inside or outside)
+            constexpr int NV = kArcEPT / 4;
+            const long long b4 = (long long)chunk * (kNT * kArcEPT) + 4 * threadIdx.x;
+            float4 pv[NV], cv[NV];
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                const long long e = b4 + (long long)j * 4 * kNT;
+                pv[j] = (e < M) ? *reinterpret_cast<const float4*>(src + e) : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            for (int k = 1; k < p.K; ++k) {
+                const T* im = src + (long long)k * M;
+#pragma unroll
+                for (int j = 0; j < NV; ++j) {
+                    const long long e = b4 + (long long)j * 4 * kNT;
+                    cv[j] = (e < M) ? *reinterpret_cast<const float4*>(im + e) : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+                double a = 0;
+#pragma unroll
+                for (int j = 0; j < NV; ++j) {
+                    const double d0 = (double)cv[j].x - (double)pv[j].x, d1 = (double)cv[j].y - (double)pv[j].y;
+                    const double d2 = (double)cv[j].z - (double)pv[j].z, d3 = (double)cv[j].w - (double)pv[j].w;
+                    a += d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
+                    pv[j] = cv[j];
+                }
+                a = wave_sum(a);
+                if (lane == 0)
+                    apart[p.ap_off + ((long long)k * p.arc_chunks + chunk) * 4 + wave] = a;
+            }
+            return;
+        }
+    }
     T prev[kArcEPT], cur[kArcEPT];
 #pragma unroll
     for (int j = 0; j < kArcEPT; ++j) {
         const long long e = base + (long long)j * kNT;
         prev[j] = (e < M) ? src[e] : T(0);
     }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int k = 1; k < p.K; ++k) {
         const T* im = src + (long long)k * M;
 #pragma unroll
@@ -1141,13 +1175,61 @@ __global__ __launch_bounds__(kNT) void k_interp(const Prob* __restrict__ P, int 
     if (skip_if && skip_if[pi]) return;
     const Prob& p = P[pi];
     const int w = blockIdx.x - wstart[pi];
-    const int k = w / p.ichunks, chunk = w - k * p.ichunks;
+    const int k = w / p.ichunks4, chunk = w - k * p.ichunks4;
     const long long N = p.N, M = 3 * N;
-    const long long i = (long long)chunk * kNT + threadIdx.x;
-    if (i >= N) return;
     const T* src = ss + p.s_off;
     T* dst = s + p.s_off + (long long)k * M;
-    if (skip[pi] || k == 0 || k == p.K - 1 || (kci && k == kci[pi])) {
+    const bool copy = skip[pi] || k == 0 || k == p.K - 1 || (kci && k == kci[pi]);
+    if constexpr (sizeof(T) == 4) {
+        if (p.vec4) {
+            // four consecutive sites per thread, 16-byte accesses
+            const long long i = ((long long)chunk * kNT + threadIdx.x) * 4;
+            if (i >= N) return;
+            if (copy) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    *reinterpret_cast<float4*>(dst + c * N + i) =
+                        *reinterpret_cast<const float4*>(src + (long long)k * M + c * N + i);
+                return;
+            }
+            const int j = jidx[p.img0 + k];
+            const double wt = wgt[p.img0 + k];
+            const T* a = src + (long long)j * M;
+            const T* b = a + M;
+            float av[3][4], bv[3][4];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float4 x = *reinterpret_cast<const float4*>(a + c * N + i);
+                const float4 y = *reinterpret_cast<const float4*>(b + c * N + i);
+                av[c][0] = x.x; av[c][1] = x.y; av[c][2] = x.z; av[c][3] = x.w;
+                bv[c][0] = y.x; bv[c][1] = y.y; bv[c][2] = y.z; bv[c][3] = y.w;
+            }
+            float o[3][4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                double v[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[c] = (1.0 - wt) * (double)av[c][q] + wt * (double)bv[c][q];
+                const double nrm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                if (nrm < 1e-12) {
+                    atomicOr(flags, 2);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) o[c][q] = (wt < 0.5) ? av[c][q] : bv[c][q];
+                } else {
+                    const double inv = 1.0 / nrm;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) o[c][q] = (float)(v[c] * inv);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                *reinterpret_cast<float4*>(dst + c * N + i) = make_float4(o[c][0], o[c][1], o[c][2], o[c][3]);
+            return;
+        }
+    }
+    const long long i = (long long)chunk * kNT + threadIdx.x;
+    if (i >= N) return;
+    if (copy) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) dst[c * N + i] = src[(long long)k * M + c * N + i];
         return;
