@@ -64,6 +64,10 @@ namespace ssm {
 #ifndef SSM_CONV_SWZ
 #define SSM_CONV_SWZ 1
 #endif
+// 1: inverse-x tiles ordered with z fastest (0: y tile fastest)
+#ifndef SSM_XINV_ZFAST
+#define SSM_XINV_ZFAST 1
+#endif
 // widest pass of the compile-time-length convolution bodies
 #ifndef SSM_CONV_CT_RADIX_BITS
 #define SSM_CONV_CT_RADIX_BITS 4
@@ -701,8 +705,11 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     const Prob& p = P[pi];
     const int t = xcd_item(blockIdx.x - wstart[pi], p.wgi);
     if (t >= p.K * p.tiles) return;
-    const int ty = t % p.nty, rest = t / p.nty;
-    const int z = rest % p.nz, img = rest / p.nz;
+    // z fastest: the tiles that read a plane's rows as z neighbours run
+    // back to back on one XCD, while the plane is still in its L2
+    const int z = SSM_XINV_ZFAST ? t % p.nz : (t / p.nty) % p.nz;
+    const int ty = SSM_XINV_ZFAST ? (t / p.nz) % p.nty : t % p.nty;
+    const int img = t / (p.nz * p.nty);
     const int yt = p.yt, hp = yt >> 1, nx = p.nx, ny = p.ny, nz = p.nz, m = p.mx, lm = p.lmx;
     const int lhp = __ffs(hp) - 1;  // tiles are powers of two
     const int psh = x_padl(lm) ? x_padl(lm) : 31;  // pad layout of the lines
