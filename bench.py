@@ -200,9 +200,20 @@ def summarize_profiles(args):
     lines.append("")
     with open(os.path.join(ROOT, "profiles", f"kernels_{w}_fp32.md"), "w") as fh:
         fh.write("\n".join(lines))
+    # every kernel's traffic per launch and wavefront VALU instructions per
+    # launch, for the iteration-level fractions the bench line reports
+    per_kernel = {}
+    for k in stats:
+        if ("fetch", k) in counters and ("write", k) in counters:
+            per_kernel[k] = {"read_bytes": statistics.median(counters[("fetch", k)]) * f_cal * 1024,
+                             "write_bytes": statistics.median(counters[("write", k)]) * w_cal * 1024,
+                             "avg_ms": statistics.mean(stats[k])}
+            if k in sq and "SQ_INSTS_VALU" in sq[k]:
+                per_kernel[k]["valu_wave_instructions"] = statistics.median(sq[k]["SQ_INSTS_VALU"])
     with open(os.path.join(ROOT, "profiles", f"traffic_{dom}_{w}_fp32.json"), "w") as fh:
         json.dump({"kernel": dom, "workload": w, "bytes_per_launch": fetch + write, "read_bytes": fetch,
                    "write_bytes": write, "fetch_calibration": f_cal, "write_calibration": w_cal,
+                   "kernels": per_kernel,
                    "kernel_source_hash": kernel_source_hash(), "command": args.profile_command}, fh, indent=1)
     print(json.dumps({"dominant": dom, "read_MB": fetch / 1e6, "write_MB": write / 1e6}))
 
@@ -312,12 +323,27 @@ def main():
     dom = max((k for k in kern if k in ab), key=lambda k: kern[k]["ms_total"])
     achieved = ab[dom] / (kern[dom]["ms_avg"] * 1e-3) / 1e9
     traffic = None
+    iteration = None
+    valu_frac = None
     tpath = os.path.join(ROOT, "profiles", f"traffic_{dom}_{args.workload}_fp32.json")
     if os.path.exists(tpath):
         with open(tpath) as fh:
             tr = json.load(fh)
         if tr.get("kernel_source_hash") == kernel_source_hash():
             traffic = tr.get("bytes_per_launch")
+            pk = tr.get("kernels", {})
+            # measured HBM bytes of one iteration: every kernel of the
+            # iteration once, over the timed iteration (graph replay)
+            it_kernels = [k for k in ("k_xfwd", "k_conv", "k_xinv", "k_arc", "k_reduce", "k_interp") if k in pk]
+            if len(it_kernels) == 6:
+                b = sum(pk[k]["read_bytes"] + pk[k]["write_bytes"] for k in it_kernels)
+                rate = b / (dt32 / steps) / 1e9
+                iteration = {"measured_bytes": b, "GBps": rate, "frac": rate / HBM_PEAK_GBS,
+                             "floor_bytes": 72 * KN}
+            if "valu_wave_instructions" in pk.get(dom, {}):
+                # a wave64 FP32/FP64 VALU instruction takes 4 cycles of one
+                # SIMD; 1024 SIMDs at 2.4 GHz
+                valu_frac = pk[dom]["valu_wave_instructions"] * 4 / (1024 * 2.4e9 * kern[dom]["ms_avg"] * 1e-3)
     floor_bytes = 72 * KN  # read/write floor of one fused FP32 iteration
     out = {
         "metric": METRIC,
@@ -346,8 +372,12 @@ def main():
         "failure_flags": int(flags),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": ab[dom], "avg_launch_ms": kern[dom]["ms_avg"]},
+                     "algorithmic_bytes_per_launch": ab[dom], "avg_launch_ms": kern[dom]["ms_avg"],
+                     "traffic_frac": (traffic / (kern[dom]["ms_avg"] * 1e-3) / 1e9 / HBM_PEAK_GBS)
+                     if traffic else None,
+                     "valu_issue_frac": valu_frac},
         "iteration_floor_frac": floor_bytes / (dt32 / steps) / 1e9 / HBM_PEAK_GBS,
+        "iteration_traffic": iteration,
         "kernels_ms_avg": {k: round(v["ms_avg"], 5) for k, v in kern.items()},
         "autotuned_tiles": tiles,
         "ms_per_step_with_events": dt32_ev / steps * 1e3,
