@@ -921,62 +921,41 @@ __global__ __launch_bounds__(kNT) void k_arc(const Prob* __restrict__ P, int np,
     const Prob& p = P[pi];
     const int chunk = blockIdx.x - wstart[pi];
     const long long M = 3 * p.N;
-    const long long base = (long long)chunk * (kNT * kArcEPT) + threadIdx.x;
     const T* src = ss + p.s_off;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if constexpr (sizeof(T) == 4) {
-        if (p.vec4) {
-            // the chunk's kNT * kArcEPT elements as 16-byte loads (M is a
-            // multiple of 4, so a load is wholly inside or outside)
-            constexpr int NV = kArcEPT / 4;
-            const long long b4 = (long long)chunk * (kNT * kArcEPT) + 4 * threadIdx.x;
-            float4 pv[NV], cv[NV];
-#pragma unroll
-            for (int j = 0; j < NV; ++j) {
-                const long long e = b4 + (long long)j * 4 * kNT;
-                pv[j] = (e < M) ? *reinterpret_cast<const float4*>(src + e) : make_float4(0.f, 0.f, 0.f, 0.f);
+    // the chunk's kNT * kArcEPT elements in groups of 4 consecutive ones
+    // (thread t: 4t + 4 kNT j + q), summed in the same order whether a group
+    // is one 16-byte load (FP32, N divisible by 4, aligned) or four loads
+    constexpr int NV = kArcEPT / 4;
+    static_assert(kArcEPT % 4 == 0, "arc elements per thread come in groups of 4");
+    const long long b4 = (long long)chunk * (kNT * kArcEPT) + 4 * threadIdx.x;
+    const bool v4 = sizeof(T) == 4 && p.vec4;
+    auto load4 = [&](const T* im, long long e, T (&v)[4]) {
+        if constexpr (sizeof(T) == 4) {
+            if (v4) {
+                const float4 q = (e < M) ? *reinterpret_cast<const float4*>(im + e) : make_float4(0.f, 0.f, 0.f, 0.f);
+                v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+                return;
             }
-            for (int k = 1; k < p.K; ++k) {
-                const T* im = src + (long long)k * M;
-#pragma unroll
-                for (int j = 0; j < NV; ++j) {
-                    const long long e = b4 + (long long)j * 4 * kNT;
-                    cv[j] = (e < M) ? *reinterpret_cast<const float4*>(im + e) : make_float4(0.f, 0.f, 0.f, 0.f);
-                }
-                double a = 0;
-#pragma unroll
-                for (int j = 0; j < NV; ++j) {
-                    const double d0 = (double)cv[j].x - (double)pv[j].x, d1 = (double)cv[j].y - (double)pv[j].y;
-                    const double d2 = (double)cv[j].z - (double)pv[j].z, d3 = (double)cv[j].w - (double)pv[j].w;
-                    a += d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
-                    pv[j] = cv[j];
-                }
-                a = wave_sum(a);
-                if (lane == 0)
-                    apart[p.ap_off + ((long long)k * p.arc_chunks + chunk) * 4 + wave] = a;
-            }
-            return;
         }
-    }
-    T prev[kArcEPT], cur[kArcEPT];
 #pragma unroll
-    for (int j = 0; j < kArcEPT; ++j) {
-        const long long e = base + (long long)j * kNT;
-        prev[j] = (e < M) ? src[e] : T(0);
-    }
+        for (int q = 0; q < 4; ++q) v[q] = (e + q < M) ? im[e + q] : T(0);
+    };
+    T pv[NV][4], cv[NV][4];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) load4(src, b4 + (long long)j * 4 * kNT, pv[j]);
     for (int k = 1; k < p.K; ++k) {
         const T* im = src + (long long)k * M;
 #pragma unroll
-        for (int j = 0; j < kArcEPT; ++j) {
-            const long long e = base + (long long)j * kNT;
-            cur[j] = (e < M) ? im[e] : T(0);
-        }
+        for (int j = 0; j < NV; ++j) load4(im, b4 + (long long)j * 4 * kNT, cv[j]);
         double a = 0;
 #pragma unroll
-        for (int j = 0; j < kArcEPT; ++j) {
-            const double d = (double)cur[j] - (double)prev[j];
-            a += d * d;
-            prev[j] = cur[j];
+        for (int j = 0; j < NV; ++j) {
+            const double d0 = (double)cv[j][0] - (double)pv[j][0], d1 = (double)cv[j][1] - (double)pv[j][1];
+            const double d2 = (double)cv[j][2] - (double)pv[j][2], d3 = (double)cv[j][3] - (double)pv[j][3];
+            a += d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pv[j][q] = cv[j][q];
         }
         a = wave_sum(a);
         if (lane == 0)
@@ -1255,8 +1234,11 @@ __global__ __launch_bounds__(kNT) void k_interp(const Prob* __restrict__ P, int 
 #pragma unroll
         for (int c = 0; c < 3; ++c) dst[c * N + i] = n[c * N + i];
     } else {
+        // the same arithmetic as the four-site path, so a problem's result
+        // does not depend on which path its place in a batch selects
+        const double inv = 1.0 / nrm;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) dst[c * N + i] = (T)(v[c] / nrm);
+        for (int c = 0; c < 3; ++c) dst[c * N + i] = (T)(v[c] * inv);
     }
 }
 

@@ -170,3 +170,31 @@ def test_autograd_tube_128x128x4(oracle):
         assert abs(gs[(k,) + idx] - float(g[k]) * fd) < 1e-6 * max(1.0, abs(fd))
     To = np.stack([oracle.energy_terms(si) for si in s_np])
     np.testing.assert_allclose(th.grad.numpy(), (g.cpu().numpy()[:, None] * To).sum(0), rtol=1e-10)
+
+
+def test_fp32_batch_position_does_not_change_results():
+    """FP32 images of N divisible by 4 take 16-byte paths when they start
+    16-byte aligned; placed after a problem of odd size in a batch they take
+    the one-site paths.  Both give bitwise the same string, energies and
+    barrier as the problem run alone."""
+    shapes = [(5, 3, 1, 3, 0.2), (8, 8, 1, 5, 0.3), (16, 12, 1, 4, 0.35)]
+    probs = [prob(nx, ny, nz, K, d=d) for nx, ny, nz, K, d in shapes]
+    strings = [inputs.perturb(inputs.bloch_point_string(nx, ny, nz, K, 2.0), 7 + i)
+               for i, (nx, ny, nz, K, _) in enumerate(shapes)]
+    sm = ssm.StringMethod(probs, ssm.SSM_FP32_MIXED)
+    sm.set_string(strings)
+    sm.iterate(8, 0.1)
+    flat = sm.get_string().cpu().numpy()
+    E = sm.energies().cpu().numpy()
+    bar = sm.barrier().cpu().numpy()
+    off = e0 = 0
+    for i, (p, s0) in enumerate(zip(probs, strings)):
+        one = ssm.StringMethod(p, ssm.SSM_FP32_MIXED)
+        one.set_string(s0)
+        one.iterate(8, 0.1)
+        a = one.get_string().cpu().numpy().ravel()
+        assert np.array_equal(flat[off:off + a.size], a)
+        assert np.array_equal(E[e0:e0 + p["K"]], one.energies().cpu().numpy())
+        assert np.array_equal(bar[i], one.barrier().cpu().numpy()[0])
+        off += a.size
+        e0 += p["K"]
