@@ -295,6 +295,10 @@ def main():
     dt32_ev = time_iterations(sm, steps, tau)
     prof = sm.profile_read()
     sm.profile(False)
+    # field of the initial string (rounded to FP32) in this form, for the
+    # normwise field error against the FP64 form on the same spins
+    s0_32 = s0.astype(np.float32)
+    _, h32, _ = sm.eval(spins=s0_32, want_field=True, want_terms=False)
     del sm
     torch.cuda.empty_cache()
 
@@ -304,6 +308,10 @@ def main():
         print(json.dumps({"ms_per_step": dt32 / steps * 1e3, "kernels_ms": prof, "tiles": tiles}), flush=True)
         return
     sm64 = ssm.StringMethod(prob, ssm.SSM_FP64)
+    _, h64, _ = sm64.eval(spins=s0_32.astype(np.float64), want_field=True, want_terms=False)
+    hd = (h32.double() - h64).reshape(w["K"], -1)
+    field_err = float((hd.norm(dim=1) / h64.reshape(w["K"], -1).norm(dim=1)).max())
+    del h32, h64, hd
     sm64.set_string(s0)
     sm64.iterate(warm, tau)
     dt64 = time_iterations(sm64, st64, tau)
@@ -369,6 +377,7 @@ def main():
         "barrier_fp32": float(bar32[0]),
         "barrier_fp64": float(bar64[0]),
         "barrier_rel_err_fp32_vs_fp64": bar_err,
+        "field_rel_err_fp32_vs_fp64": field_err,
         "failure_flags": int(flags),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

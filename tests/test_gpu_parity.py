@@ -228,16 +228,24 @@ def test_batch_equals_separate_runs():
         e0 += p["K"]
 
 
+@pytest.mark.parametrize("iters", [0, 500])
 @pytest.mark.parametrize("precision", [ssm.SSM_FP64, ssm.SSM_FP32_MIXED])
-def test_full_size_tube_sampled_sites(oracle, precision):
-    """256x256x8, 48 images: fields at sampled sites against the direct sum."""
+def test_full_size_tube_sampled_sites(oracle, precision, iters):
+    """256x256x8, 48 images, at iteration 0 and after the workload's 500
+    iterations (graph replay): fields at sampled sites of the current string
+    against the direct sum."""
     w = inputs.WORKLOADS["tube_256x256x8_k48"]
     p = prob(w["nx"], w["ny"], w["nz"], w["K"], w["J"], w["d"], w["ku"], w["D"])
     s0 = inputs.build_string(w)
     if precision != ssm.SSM_FP64:
         s0 = s0.astype(np.float32).astype(np.float64)
     sm = ssm.StringMethod(p, precision)
+    sm.set_options(check_every=50, graph_chunk=10)
     sm.set_string(s0)
+    if iters:
+        sm.iterate(iters, w["tau"])
+        assert sm.check() == 0
+        s0 = sm.get_string().cpu().numpy().astype(np.float64).reshape(s0.shape)
     sm.eval()
     h = sm.fields().cpu().numpy().astype(np.float64)
     rng = np.random.default_rng(0)
