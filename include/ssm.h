@@ -52,10 +52,12 @@
  *
  * Limits.  1 <= nx, ny <= 1024 and 1 <= nz <= 16; 2 <= n_images <= 1024;
  * at most 256 problems per context; every problem of a context has nz
- * values that round up to the same power of two; one (y, z) plane of
- * x-spectra, 3 * nz * m_y complex values with m_y the power of two >= ny,
- * fits in 160 KiB of LDS (so nz * m_y <= 4096 for SSM_FP64 and 6826 for
- * SSM_FP32_MIXED).  Exceeding a limit returns SSM_EUNSUPPORTED.
+ * values that round up to the same power of two; the convolution's
+ * twiddles and one (y, z) plane of x-spectra, (2 + 3 * nz) * m_y complex
+ * values with m_y the power of two >= ny, fit in 160 KiB of LDS, i.e.
+ * m_y * (2 + 3 * nz) <= 10240 for SSM_FP64 and <= 20480 for SSM_FP32_MIXED
+ * (m_y = 1024: nz <= 2 and <= 6; m_y = 512: nz <= 6 and <= 12; m_y = 256:
+ * nz <= 12 and any nz).  Exceeding a limit returns SSM_EUNSUPPORTED.
  */
 #ifndef SSM_H
 #define SSM_H

@@ -59,6 +59,23 @@ def test_workspace_size_rejects(bad, status):
     assert ssm.ssm_last_error(None) != ""
 
 
+@pytest.mark.parametrize("precision,cap", [(ssm.SSM_FP64, 10240), (ssm.SSM_FP32_MIXED, 20480)])
+@pytest.mark.parametrize("ny", [100, 256, 300, 1024])
+def test_lds_limit_is_the_documented_one(precision, cap, ny):
+    """The convolution keeps its twiddles and one (y, z) plane of x-spectra
+    in LDS: m_y (2 + 3 nz) complex values, at most 10240 in FP64 and 20480 in
+    FP32 (160 KiB), with m_y the power of two >= ny; nz <= 16 regardless."""
+    my = 1 << (ny - 1).bit_length()
+    for nz in range(1, 17):
+        fits = my * (2 + 3 * nz) <= cap
+        if fits:
+            assert ssm.ssm_workspace_size([prob(ny=ny, nz=nz)], precision) > 0
+        else:
+            with pytest.raises(ssm.SSMError) as ei:
+                ssm.ssm_workspace_size([prob(ny=ny, nz=nz)], precision)
+            assert ei.value.status == ssm.SSM_EUNSUPPORTED
+
+
 def test_workspace_size_rejects_precision_and_mixed_nz():
     with pytest.raises(ssm.SSMError) as ei:
         ssm.ssm_workspace_size([prob()], 7)

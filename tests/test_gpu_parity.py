@@ -261,6 +261,37 @@ def test_full_size_tube_sampled_sites(oracle, precision, iters):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("shape,precision", [
+    ((1024, 1024, 1), ssm.SSM_FP64), ((1024, 1024, 1), ssm.SSM_FP32_MIXED),
+    ((6, 1024, 2), ssm.SSM_FP64), ((5, 1000, 6), ssm.SSM_FP32_MIXED),
+    ((1024, 7, 16), ssm.SSM_FP64), ((1000, 9, 16), ssm.SSM_FP32_MIXED)])
+def test_largest_shapes_sampled_sites(oracle, shape, precision):
+    """The largest lattices the limits accept (1024 sites along x or y, the
+    most layers the LDS allows with a 1024-point y transform, 16 layers),
+    random spins: fields at sampled sites against the oracle's direct sum."""
+    nx, ny, nz = shape
+    K = 3
+    p = prob(nx, ny, nz, K, d=0.3, ku=0.1, D=0.02)
+    s0 = inputs.random_unit_spins((K, 3, nz, ny, nx), seed=nx + ny + nz)
+    if precision != ssm.SSM_FP64:
+        s0 = s0.astype(np.float32).astype(np.float64)
+    sm = ssm.StringMethod(p, precision)
+    sm.set_string(s0)
+    _, h, _ = sm.eval(want_terms=False)
+    h = h.cpu().numpy().astype(np.float64)
+    N = nx * ny * nz
+    rng = np.random.default_rng(3)
+    tol = TOL64 if precision == ssm.SSM_FP64 else TOL32_FIELD
+    for k in range(K):
+        sites = rng.choice(N, size=12, replace=False)
+        sites[:4] = [0, N - 1, nx - 1, N // 2]
+        ho = oracle.field_at(s0[k], p["J"], p["d"], p["ku"], p["D"], sites)
+        hk = h[k].reshape(3, N)[:, sites].T
+        assert rel_field(hk, ho) < tol
+    del sm
+    torch.cuda.empty_cache()
+
+
 def test_autograd_matches_finite_differences(oracle):
     p = prob(6, 5, 2, 3, J=1.0, d=0.3, ku=0.1, D=0.05)
     sm = ssm.StringMethod(p, ssm.SSM_FP64)
