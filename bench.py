@@ -158,6 +158,35 @@ def rk_leg(ssm, torch, prob, s0, KN, args):
     return res
 
 
+def paper_shape_leg(ssm, torch, args):
+    """The paper's production shape: a 112x112x1 monolayer, 60 images, with
+    its material in SI units (d = 5.30 meV, k = 0.5 meV), FP32-mixed form,
+    graph replay: one problem alone, then args.paper_batch (d, k) points in
+    one context (the batched phase-diagram form).  Explicit steps of 0.1
+    (the paper's interval of 5e-14 s is 1.74 in these units at damping 1,
+    for the adaptive integrator, whose cost the integrator leg gives)."""
+    from paper_1804_07135_amd import si
+    res = {}
+    tau = 0.1
+    for n_points in (1, args.paper_batch):
+        ds = [5.30 + 0.1 * i for i in range(n_points)]
+        probs = [si.paper_problem(d, 0.5) for d in ds]
+        strings = [si.initial_string("bloch", 112, 60, 10.0, seed=i) for i in range(n_points)]
+        sm = ssm.StringMethod(probs, ssm.SSM_FP32_MIXED)
+        sm.set_options(check_every=10, graph_chunk=10)
+        sm.set_string(strings)
+        sm.iterate(10, tau)
+        steps = args.paper_steps
+        dt = time_iterations(sm, steps, tau)
+        kn = n_points * 60 * 112 * 112
+        res[f"points_{n_points}"] = {"ms_per_step": dt / steps * 1e3, "string_iters_per_s": steps / dt,
+                                     "site_field_evals_per_s": steps * kn / dt, "flags": int(sm.check())}
+        del sm
+        torch.cuda.empty_cache()
+    res.update({"lattice": [112, 112, 1], "images": 60, "tau": tau, "steps": args.paper_steps})
+    return res
+
+
 def summarize_profiles(args):
     """Turn rocprofv3 outputs of the bench and of the copy probe into the
     committed summaries: per-kernel durations, and HBM traffic of the
@@ -251,6 +280,10 @@ def main():
     ap.add_argument("--rk-iters", type=int, default=5,
                     help="string iterations of the adaptive Dormand-Prince leg (0: skip)")
     ap.add_argument("--rk-interval", type=float, default=0.5)
+    ap.add_argument("--paper-steps", type=int, default=200,
+                    help="timed iterations of the paper-shape leg (0: skip)")
+    ap.add_argument("--paper-batch", type=int, default=16,
+                    help="(d, k) points of the batched paper-shape run")
     ap.add_argument("--rk-tol", type=float, default=1e-5)
     ap.add_argument("--autotune", action="store_true",
                     help="choose the FP32 form's tiles with the library's autotuner before timing")
@@ -421,6 +454,8 @@ def main():
         "autotuned_tiles": tiles,
         "ms_per_step_with_events": dt32_ev / steps * 1e3,
     }
+    if args.paper_steps > 0:
+        out["paper_shape_112x112x1_k60"] = paper_shape_leg(ssm, torch, args)
     if args.rk_iters > 0:
         out["rk_dopri54"] = rk_leg(ssm, torch, prob, s0, KN, args)
     if not args.no_cpu:
