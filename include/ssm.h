@@ -273,10 +273,15 @@ ssm_status ssm_set_options(ssm_ctx* ctx, int32_t check_every, int32_t graph_chun
  * and lattice shape; read if present, appended with new results. */
 ssm_status ssm_autotune(ssm_ctx* ctx, const char* cache_path);
 
-/* Synchronise the stream and read the sticky failure flags (SSM_FLAG_*,
- * set by kernels on a non-finite energy or an interpolated spin of norm
- * < 1e-12) into *h_flags, then clear them.  Returns SSM_ENONFINITE when a
- * non-finite flag is set. */
+/* Synchronise the stream and read the sticky failure flags into *h_flags,
+ * then clear them.  Kernels set SSM_FLAG_NONFINITE_ENERGY on a non-finite
+ * image energy; SSM_FLAG_NONFINITE_SPIN when a spin they renormalise (an
+ * interpolated spin, or an image at the end of an integrator interval) has
+ * a non-finite norm; SSM_FLAG_ZERO_NORM_SPIN when that norm is below 1e-12
+ * (an interpolated spin then takes the nearer source image's spin);
+ * SSM_FLAG_RK_ERROR when the integrator's error estimate is not finite.
+ * Returns SSM_ENONFINITE when SSM_FLAG_NONFINITE_ENERGY or
+ * SSM_FLAG_NONFINITE_SPIN is set. */
 ssm_status ssm_check(ssm_ctx* ctx, int32_t* h_flags);
 
 /* Text of the last error on this context ("" if none).  ctx may be NULL for

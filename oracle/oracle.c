@@ -27,7 +27,10 @@
  *     missing neighbours contribute nothing (Sec. II: free boundaries).
  *
  * Every function below names the passage of the paper it follows.
- * Parity pins for each function live in tests/test_oracle_pins.py.
+ * Parity pins for each function live in tests/test_oracle_pins.py (field,
+ * energy, step, reparametrisation, tangents), test_oracle_rk_pins.py and
+ * test_oracle_llg_pins.py (integrators) and test_oracle_reparam_pins.py
+ * (spline and climbing image).
  */
 #include <math.h>
 #include <stdint.h>

@@ -1197,6 +1197,7 @@ __global__ __launch_bounds__(kNT) void k_interp(const Prob* __restrict__ P, int 
 #pragma unroll
                 for (int c = 0; c < 3; ++c) v[c] = (1.0 - wt) * (double)av[c][q] + wt * (double)bv[c][q];
                 const double nrm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                if (!isfinite(nrm)) atomicOr(flags, 4);
                 if (nrm < 1e-12) {
                     atomicOr(flags, 2);
 #pragma unroll
@@ -1228,6 +1229,7 @@ __global__ __launch_bounds__(kNT) void k_interp(const Prob* __restrict__ P, int 
 #pragma unroll
     for (int c = 0; c < 3; ++c) v[c] = (1.0 - wt) * (double)a[c * N + i] + wt * (double)b[c * N + i];
     const double nrm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    if (!isfinite(nrm)) atomicOr(flags, 4);
     if (nrm < 1e-12) {
         atomicOr(flags, 2);
         const T* n = (wt < 0.5) ? a : b;
@@ -1915,7 +1917,8 @@ __global__ __launch_bounds__(kNT) void k_rk_norm(const Prob* __restrict__ P, int
     const long long base = p.s_off + (long long)img * 3 * N + i;
     const double v[3] = {(double)s[base], (double)s[base + N], (double)s[base + 2 * N]};
     const double nrm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-    if (!(nrm >= 1e-12)) atomicOr(flags, 2);
+    if (!isfinite(nrm)) atomicOr(flags, 4);
+    else if (nrm < 1e-12) atomicOr(flags, 2);
 #pragma unroll
     for (int c = 0; c < 3; ++c) ss[base + c * N] = (T)(v[c] / nrm);
 }
@@ -2058,6 +2061,7 @@ __global__ __launch_bounds__(kNT) void k_interp_spline(const Prob* __restrict__ 
                 h * h / 6.0;
     }
     const double nrm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    if (!isfinite(nrm)) atomicOr(flags, 4);
     if (nrm < 1e-12) {
         atomicOr(flags, 2);
         const long long on = (wgt[g] < 0.5) ? oa : ob;

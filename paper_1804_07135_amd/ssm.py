@@ -31,6 +31,10 @@ SSM_STEP_DOPRI54 = 1
 SSM_INTERP_LINEAR = 0
 SSM_INTERP_SPLINE = 1
 SSM_N_KERNELS = 13
+SSM_FLAG_NONFINITE_ENERGY = 1
+SSM_FLAG_ZERO_NORM_SPIN = 2
+SSM_FLAG_NONFINITE_SPIN = 4
+SSM_FLAG_RK_ERROR = 8
 FLAG_NONFINITE_ENERGY = 1
 FLAG_ZERO_NORM_SPIN = 2
 FLAG_NONFINITE_SPIN = 4

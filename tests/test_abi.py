@@ -22,6 +22,15 @@ def test_header_declares_the_binding_list():
     assert header_functions() == sorted(ssm.ABI_SYMBOLS)
 
 
+def test_binding_constants_match_the_header():
+    """Every #define SSM_* of the header has the same value in the binding."""
+    text = open(HEADER).read()
+    defs = re.findall(r"^#define (SSM_[A-Z0-9_]+)\s+\(?(-?(?:0x[0-9a-fA-F]+|\d+))\)?", text, flags=re.M)
+    assert len(defs) >= 18
+    for name, val in defs:
+        assert getattr(ssm, name) == int(val, 0), name
+
+
 def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(ssm.LIB_PATH)
     for name in header_functions():
