@@ -233,6 +233,12 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
         p.ep_off = ep;
         p.ap_off = ap;
         p.arc_chunks = (int)((3 * p.N + kNT * kArcEPT - 1) / (kNT * kArcEPT));
+        // image groups so that a launch has about 2048 workgroups: small
+        // lattices get parallelism over images (each group reads the image
+        // before it once more)
+        p.arc_ng = std::max(1, std::min(p.K - 1, (2048 + p.arc_chunks - 1) / p.arc_chunks));
+        p.arc_g = (p.K - 1 + p.arc_ng - 1) / p.arc_ng;
+        p.arc_ng = (p.K - 1 + p.arc_g - 1) / p.arc_g;
         p.ichunks = (int)((p.N + kNT - 1) / kNT);
         // spin buffers are 256-byte aligned, so an image is 16-byte aligned
         // when its element offset is a multiple of 4
@@ -289,7 +295,7 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
     prefix(pl.wm_xf, [](const Prob& p) { return p.wgf; });
     prefix(pl.wm_xi, [](const Prob& p) { return p.wgi; });
     prefix(pl.wm_conv, [](const Prob& p) { return conv_wgs(p); });
-    prefix(pl.wm_arc, [](const Prob& p) { return p.arc_chunks; });
+    prefix(pl.wm_arc, [](const Prob& p) { return p.arc_chunks * p.arc_ng; });
     prefix(pl.wm_site, [](const Prob& p) { return p.K * p.ichunks; });
     prefix(pl.wm_img, [](const Prob& p) { return p.K; });
     prefix(pl.wm_sitep, [](const Prob& p) { return p.ichunks; });

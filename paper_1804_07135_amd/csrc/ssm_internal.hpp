@@ -95,7 +95,8 @@ struct Prob {
     int ichunks;           // per-site workgroups per image (interp / tangents)
     int vec4;              // FP32 images of N divisible by 4, 16-byte aligned: 4 sites per thread
     int ichunks4;          // interpolation workgroups per image (ichunks / 4 with vec4)
-    int pad2_;
+    int arc_g;             // images per arc-length workgroup (image groups of arc_g)
+    int arc_ng;            // image groups: arc-length workgroups = arc_chunks * arc_ng
     double J, d, ku, D;    // eq. (1) parameters
 };
 

@@ -907,8 +907,9 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 }
 
 // ---------------------------------------------------------------------------
-// k_arc: per flat chunk of the 3N components, partial sums of
-// (phi*_k - phi*_{k-1})^2 for k = 1..K-1, one value per wavefront.
+// k_arc: per flat chunk of the 3N components and group of consecutive
+// images, partial sums of (phi*_k - phi*_{k-1})^2 for the group's k, one
+// value per wavefront (the same values whatever the grouping).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kNT) void k_arc(const Prob* __restrict__ P, int np,
@@ -919,7 +920,11 @@ __global__ __launch_bounds__(kNT) void k_arc(const Prob* __restrict__ P, int np,
     const int pi = find_problem(wstart, np, blockIdx.x);
     if (done && done[pi]) return;
     const Prob& p = P[pi];
-    const int chunk = blockIdx.x - wstart[pi];
+    const int w = blockIdx.x - wstart[pi];
+    const int chunk = w % p.arc_chunks, grp = w / p.arc_chunks;
+    // images k0..k1-1 of this workgroup's group, against image k0 - 1
+    const int k0 = 1 + grp * p.arc_g, k1 = min(p.K, k0 + p.arc_g);
+    if (k0 >= p.K) return;
     const long long M = 3 * p.N;
     const T* src = ss + p.s_off;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -943,8 +948,8 @@ __global__ __launch_bounds__(kNT) void k_arc(const Prob* __restrict__ P, int np,
     };
     T pv[NV][4], cv[NV][4];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) load4(src, b4 + (long long)j * 4 * kNT, pv[j]);
-    for (int k = 1; k < p.K; ++k) {
+    for (int j = 0; j < NV; ++j) load4(src + (long long)(k0 - 1) * M, b4 + (long long)j * 4 * kNT, pv[j]);
+    for (int k = k0; k < k1; ++k) {
         const T* im = src + (long long)k * M;
 #pragma unroll
         for (int j = 0; j < NV; ++j) load4(im, b4 + (long long)j * 4 * kNT, cv[j]);
