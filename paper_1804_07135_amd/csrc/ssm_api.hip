@@ -145,7 +145,9 @@ ssm_status check_problems(const ssm_problem* pr, int np, int prec, std::string& 
 // [img][kx][c][z][y] spectra.
 constexpr size_t kLdsTarget = 52 * 1024;
 
-Tiles default_tiles(const Prob& p, size_t tsize)
+// batch_rows: image rows (K nz ny) of every problem of the context, for the
+// occupancy of a launch covering them all
+Tiles default_tiles(const Prob& p, size_t tsize, long long batch_rows)
 {
     Tiles t;
     const int cs = (int)(2 * tsize);
@@ -154,6 +156,9 @@ Tiles default_tiles(const Prob& p, size_t tsize)
     while (yf * p.mx < 4096 && yf < ycap && lds_xfwd(p, 2 * yf, tsize) <= kLdsTarget) yf *= 2;
     yf = std::min(yf, ycap);
     while (yf > 2 && lds_xfwd(p, yf, tsize) > kLdsTarget) yf /= 2;
+    // small batches: more, shorter tiles (down to 64-byte runs) until a
+    // launch has about four workgroups per CU
+    while (yf * cs > 64 && batch_rows / yf < 1024) yf /= 2;
     t.ytf = yf;
     int yi = std::max(2, 128 / cs);
     while (yi * p.mx < 4096 && yi < ycap && lds_xinv(p, 2 * yi, tsize) <= kLdsTarget) yi *= 2;
@@ -208,6 +213,8 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
     pl.geo.resize(np);
     std::map<std::tuple<int, int, int>, int> shape_id;
     long long img = 0, spin = 0, xo = 0, ep = 0, ap = 0, fp = 0, fm = 0;
+    long long batch_rows = 0;
+    for (int i = 0; i < np; ++i) batch_rows += (long long)pr[i].n_images * pr[i].nz * pr[i].ny;
     for (int i = 0; i < np; ++i) {
         const ssm_problem& q = pr[i];
         Prob& p = pl.P[i];
@@ -219,7 +226,7 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
         p.pz = q.nz > 1 ? 2 * p.mz : 1;
         p.nhz = q.nz > 1 ? 2 : 1;
         p.N = (long long)q.nx * q.ny * q.nz;
-        const Tiles t = tiles ? (*tiles)[i] : default_tiles(p, pl.tsize);
+        const Tiles t = tiles ? (*tiles)[i] : default_tiles(p, pl.tsize, batch_rows);
         apply_tiles(p, t);
         pl.tiles.push_back(t);
         if (lds_xfwd(p, p.ytf, pl.tsize) > kLdsMax || lds_xinv(p, p.yt, pl.tsize) > kLdsMax ||

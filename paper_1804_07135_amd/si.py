@@ -100,13 +100,17 @@ def initial_string(process, n, K, R, seed):
 
 def phase_diagram(d_meV, k_meV, process="bloch", m=PAPER, n=112, K=60, R=10.0, alpha=1.0,
                   dt_seconds=5e-14, iters=1000, tol_force=0.0, precision=None, integrator="dopri",
-                  rtol=1e-5, atol=1e-5, climbing=False, spline=False, check_every=50, seed=0):
+                  rtol=1e-5, atol=1e-5, climbing=False, spline=False, check_every=50, seed=0,
+                  autotune_cache=None):
     """Annihilation barriers (meV) on the grid d_meV x k_meV (Fig. 3).
 
     Every grid point is one problem of a single batched context (all points
     advance together).  integrator: "dopri" evolves each image over the
     paper's interval (Delta t converted with alpha) with the adaptive
     Dormand-Prince pair; "euler" takes one explicit step of that length.
+    autotune_cache: path of a tile cache; when given, the kernels' tiles are
+    tuned on this context first (results then depend on the tiles only
+    through the order of floating-point sums).
     Returns dict(barrier[len(d), len(k)] in meV, argmax, dB_dd and dB_dk (the
     envelope-theorem derivatives, meV per meV), iters, force, context)."""
     from . import ssm
@@ -124,6 +128,8 @@ def phase_diagram(d_meV, k_meV, process="bloch", m=PAPER, n=112, K=60, R=10.0, a
     elif integrator != "euler":
         raise ValueError("integrator must be 'dopri' or 'euler'")
     sm.set_string(strings)
+    if autotune_cache is not None:
+        sm.autotune(autotune_cache)
     it = sm.iterate(iters, tau, tol_force).cpu().numpy()
     bar = sm.barrier().cpu().numpy()
     _, fn = sm.tangents()

@@ -104,3 +104,15 @@ def test_phase_diagram_points_equal_single_runs(integrator):
     for i, j in itertools.product(range(2), range(2)):
         one = si.phase_diagram([d[i]], [k[j]], seed=2 * i + j, **kw)
         assert one["barrier"][0, 0] == full["barrier"][i, j]
+
+
+@pytest.mark.gpu
+def test_phase_diagram_with_tuned_tiles(tmp_path):
+    """Tuned tiles change sums' order only: FP64 barriers agree to 1e-10."""
+    from paper_1804_07135_amd import ssm
+    kw = dict(n=24, K=5, R=3.0, iters=10, precision=ssm.SSM_FP64, integrator="euler",
+              dt_seconds=2e-15, alpha=0.5)
+    a = si.phase_diagram([5.0, 7.0], [1.5], **kw)
+    b = si.phase_diagram([5.0, 7.0], [1.5], autotune_cache=str(tmp_path / "tiles.txt"), **kw)
+    np.testing.assert_allclose(b["barrier"], a["barrier"], rtol=1e-10)
+    assert (tmp_path / "tiles.txt").exists()
