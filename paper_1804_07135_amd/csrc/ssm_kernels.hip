@@ -162,6 +162,19 @@ __device__ __forceinline__ void store2(V* p, V a, V b)
     }
 }
 
+// 16 bytes of T at p (16-byte aligned) into v, or zeros when !ok
+template <typename T>
+__device__ __forceinline__ void load16(const T* p, bool ok, T (&v)[16 / sizeof(T)])
+{
+    if constexpr (sizeof(T) == 4) {
+        const float4 q = ok ? *reinterpret_cast<const float4*>(p) : make_float4(0.f, 0.f, 0.f, 0.f);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+        const double2 q = ok ? *reinterpret_cast<const double2*>(p) : make_double2(0.0, 0.0);
+        v[0] = q.x; v[1] = q.y;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // k_xfwd: rows of a tile (image, z, ytf rows) -> x half-spectra, one spin
 // component at a time.  Two real rows of one component form one complex
@@ -197,26 +210,24 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     V* Xi = X + p.x_off + (long long)img * (m + 1) * 3 * nz * ny;
     const int y0 = ty * yt, P2 = 2 * m;
     __syncthreads();
-    // FP32 rows of a length divisible by 4 from a 16-byte aligned image are
-    // read four sites per 16-byte load
-    const bool vec4 = sizeof(T) == 4 && !(nx & 3) && !(reinterpret_cast<size_t>(si) & 15);
+    // rows of a length divisible by VW = 16 / sizeof(T) from a 16-byte
+    // aligned image are read VW sites per 16-byte load
+    constexpr int VW = 16 / sizeof(T), LVW = VW == 4 ? 2 : 1;
+    const bool vecw = !(nx & (VW - 1)) && !(reinterpret_cast<size_t>(si) & 15);
 #pragma unroll 1
     for (int c = 0; c < 3; ++c) {
         const T* sc = si + (long long)c * N;
-        if (vec4) {
-            const int lm4 = lm - 2;
+        if (vecw) {
+            const int lmv = lm - LVW;
 #pragma unroll 1
-            for (int idx = threadIdx.x; idx < (hp << lm4); idx += kNT) {
-                const int j = (idx & ((1 << lm4) - 1)) << 2, rp = idx >> lm4;
+            for (int idx = threadIdx.x; idx < (hp << lmv); idx += kNT) {
+                const int j = (idx & ((1 << lmv) - 1)) << LVW, rp = idx >> lmv;
                 const int ya = y0 + 2 * rp;
-                float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
-                if (j < nx) {
-                    if (ya < ny) a = *reinterpret_cast<const float4*>(sc + (long long)ya * nx + j);
-                    if (ya + 1 < ny) b = *reinterpret_cast<const float4*>(sc + (long long)(ya + 1) * nx + j);
-                }
-                const T av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+                T av[VW], bv[VW];
+                load16<T>(sc + (long long)ya * nx + j, j < nx && ya < ny, av);
+                load16<T>(sc + (long long)(ya + 1) * nx + j, j < nx && ya + 1 < ny, bv);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
+                for (int k = 0; k < VW; ++k) {
                     const V v = mk<V>(av[k], bv[k]);
                     const int i0 = (2 * rp) * m + j + k, i1 = i0 + m;
                     lines[i0 + (i0 >> psh)] = v;
