@@ -68,6 +68,11 @@ namespace ssm {
 #ifndef SSM_XINV_ZFAST
 #define SSM_XINV_ZFAST 1
 #endif
+// 1: the convolution reads each kernel-spectrum row once per mirror pair
+// of z frequencies (kz and -kz differ only in the sign of xz, yz)
+#ifndef SSM_CONV_NH_MIRROR
+#define SSM_CONV_NH_MIRROR 1
+#endif
 // widest pass of the compile-time-length convolution bodies
 #ifndef SSM_CONV_CT_RADIX_BITS
 #define SSM_CONV_CT_RADIX_BITS 4
@@ -350,10 +355,17 @@ __device__ __forceinline__ void conv_zphase(const Prob& p, int G, int kx0, int h
             const T* nh = nhat + p.nh_off + (((((long long)kx * nhz + hz) * 2 + hy) * MZ) * 6 << LMY) + qy;
 #pragma unroll
             for (int r = 0; r < MZ; ++r) {
-                const T* q6 = nh + (r * 6 << LMY);
+                // z frequency kz = 2r + hz and its mirror -kz (mod 2 MZ) hold
+                // the same spectrum up to the sign of the z-odd components
+                // xz and yz (the tensor is even in z except for those), so
+                // each column reads only the rows r <= mirror (9 of 16 for
+                // MZ = 8) and the unrolled loop folds the repeated loads
+                const bool mir = SSM_CONV_NH_MIRROR && (hz == 0 ? 2 * r > MZ : 2 * r >= MZ);
+                const int rs = mir ? (hz == 0 ? MZ - r : MZ - 1 - r) : r;
+                const T* q6 = nh + (rs * 6 << LMY);
                 if (SSM_CONV_NH_SERIAL) asm volatile("" : "+v"(q6));
-                const T nxx = q6[0], nxy = q6[MY], nxz = q6[2 * MY];
-                const T nyy = q6[3 * MY], nyz = q6[4 * MY], nzz = q6[5 * MY];
+                const T nxx = q6[0], nxy = q6[MY], nxz = mir ? -q6[2 * MY] : q6[2 * MY];
+                const T nyy = q6[3 * MY], nyz = mir ? -q6[4 * MY] : q6[4 * MY], nzz = q6[5 * MY];
                 const V sx = a[0][r], sy = a[1][r], sz = a[2][r];
                 a[0][r] = mk<V>(nxx * sx.x + nxy * sy.x + nxz * sz.x, nxx * sx.y + nxy * sy.y + nxz * sz.y);
                 a[1][r] = mk<V>(nxy * sx.x + nyy * sy.x + nyz * sz.x, nxy * sx.y + nyy * sy.y + nyz * sz.y);
