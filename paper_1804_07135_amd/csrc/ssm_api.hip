@@ -491,7 +491,7 @@ struct Ops {
         });
         if (e != hipSuccess) return e;
         return timed(c, st, KK_XINV, [&] {
-            return launch_xinv<T>(c->P(), pl.np, c->wm_xi(), c->Xp(), c->X(), src, s_star, hdst,
+            return launch_xinv<T>(c->P(), pl.np, c->wm_xi(), c->Xp(), src, s_star, hdst,
                                   c->at<double>(pl.o_ep), tw, done, mode, tau, fcp, fcd, pl.lds_xi, st);
         });
     }
@@ -831,7 +831,7 @@ double time_kernel(ssm_ctx* c, int kind, int reps)
             e = launch_conv<T>(pl.mz, pl.conv_kinds, c->P(), pl.np, c->wm_conv(), c->X(), c->Xp(), c->at<T>(pl.o_nh), tw,
                                nullptr, pl.lds_conv, c->stream);
         else
-            e = launch_xinv<T>(c->P(), pl.np, c->wm_xi(), c->Xp(), c->X(), s, nullptr, nullptr,
+            e = launch_xinv<T>(c->P(), pl.np, c->wm_xi(), c->Xp(), s, nullptr, nullptr,
                                c->at<double>(pl.o_ep), tw, nullptr, EPI_TERMS, 0.0, 0.0, 1.0, pl.lds_xi,
                                c->stream);
         if (e != hipSuccess || hipEventRecord(b, c->stream) != hipSuccess) return 1e30;

@@ -126,7 +126,7 @@ hipError_t launch_conv(int mz, int kinds, const Prob* P, int np, const WorkMap& 
 enum { EPI_STEP = 1, EPI_FIELD = 2, EPI_TERMS = 4, EPI_FORCE = 8 };
 template <typename T>
 // fcp, fcd: coefficients of EPI_FORCE (precession, damping)
-hipError_t launch_xinv(const Prob* P, int np, const WorkMap& wm, const void* Xp, const void* Xq, const T* s,
+hipError_t launch_xinv(const Prob* P, int np, const WorkMap& wm, const void* Xp, const T* s,
                        T* s_star, T* h, double* epart, const void* tw, const int* done,
                        int mode, double tau, double fcp, double fcd, size_t lds, hipStream_t st);
 template <typename T>

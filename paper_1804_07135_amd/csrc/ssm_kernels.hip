@@ -290,9 +290,9 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
 // applies it and runs both z halves hz itself (length-mz DFTs), multiplies
 // by the real symmetric kernel spectrum (xx, xy, xz, yy, yz, zz), inverts
 // and sums the halves.  Then inverse y FFT and un-twiddle; the y half 0
-// result goes to the output slice and the y half 1 result over the
-// workgroup's own input slice (read for the last time by then), and the
-// inverse-x kernel adds the two.  The kernel spectrum carries 1/(Px Py Pz).
+// result goes to the output slice and the y half 1 result is added onto it
+// (each thread adds onto the values it stored itself).  The kernel
+// spectrum carries 1/(Px Py Pz).
 // LDS: twiddles (2 m_y) + G*3*nz lines of m_y.
 // ---------------------------------------------------------------------------
 
@@ -495,9 +495,7 @@ __device__ __forceinline__ void conv_body_ct(const Prob& p, int s0, int G, cplx<
         __syncthreads();
 
         // inverse y transform; the last pass writes y half hy = 0 to the
-        // output slice and hy = 1 (un-twiddled) over the input slice, whose
-        // last reader was this workgroup's hy = 1 forward pass (the inverse
-        // x kernel sums the two)
+        // output slice and adds hy = 1 (un-twiddled) onto it
         lane = threadIdx.x;
         asm volatile("" : "+v"(lane));
         lane &= 63;
@@ -512,10 +510,27 @@ __device__ __forceinline__ void conv_body_ct(const Prob& p, int s0, int G, cplx<
                 if (g < (gl << PL::LQ)) {
                     // last pass: j < NS, so the outputs are y = j + r NS
                     const int line = g >> PL::LQ, j = g & (PL::Q - 1);
-                    V* dst = (hy ? in : out) + (long long)(g0 + line) * ny;
+                    V* dst = out + (long long)(g0 + line) * ny;
                     if (hy) {
+                        // half 1, un-twiddled, added onto half 0, which this
+                        // thread stored to the same places before the
+                        // z-phase barriers of this half (all loads issued
+                        // before any add when the line is full length)
 #pragma unroll
                         for (int r = 0; r < RL; ++r) v[b][r] = cmulc(v[b][r], twl[(j + r * PL::NS) << TWS]);
+                        if (ny == MY) {
+                            V h0[RL];
+#pragma unroll
+                            for (int r = 0; r < RL; ++r) h0[r] = dst[j + r * PL::NS];
+#pragma unroll
+                            for (int r = 0; r < RL; ++r) v[b][r] = cadd(v[b][r], h0[r]);
+                        } else {
+#pragma unroll
+                            for (int r = 0; r < RL; ++r) {
+                                const int y = j + r * PL::NS;
+                                if (y < ny) v[b][r] = cadd(v[b][r], dst[y]);
+                            }
+                        }
                     }
                     if (ny == MY) {
 #pragma unroll
@@ -647,11 +662,11 @@ __device__ __forceinline__ void conv_body(const Prob& p, int s0, int G, cplx<T>*
             // over this workgroup's input slice, which is no longer read
             int y = yb, r = rb;
             asm volatile("" : "+v"(y), "+v"(r));
-            V* dst = hy ? in : out;
+            V* dst = out;
 #pragma unroll 4
             for (int e = threadIdx.x; e < nel; e += kNT) {
                 V v = lines[lds_pad((r << lmy) + y)];
-                if (hy) v = cmulc(v, twl[y]);
+                if (hy) v = cadd(cmulc(v, twl[y]), dst[e]);  // this thread stored half 0 at e
                 dst[e] = v;
                 y += dy;
                 r += dr;
@@ -713,7 +728,6 @@ template <typename T>
 __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_xinv(const Prob* __restrict__ P, int np,
                                               const int* __restrict__ wstart,
                                               const cplx<T>* __restrict__ Xp,
-                                              const cplx<T>* __restrict__ Xq,
                                               const T* __restrict__ s, T* __restrict__ ss,
                                               T* __restrict__ hout, double* __restrict__ epart,
                                               const cplx<T>* __restrict__ tw,
@@ -742,9 +756,8 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     V* lines = twl + 2 * m;
     T* hd = reinterpret_cast<T*>(lines + padded_len(yt * m, x_padl(lm)));
     load_twiddles(twl, lm, tw);
-    // the convolved spectrum arrives as its two y halves (sum of both)
+    // the convolved x half-spectra of the image
     const V* Xi = Xp + p.x_off + (long long)img * (m + 1) * 3 * nz * ny;
-    const V* Xj = Xq + p.x_off + (long long)img * (m + 1) * 3 * nz * ny;
     __syncthreads();
 #pragma unroll 1
     for (int c = 0; c < 3; ++c) {
@@ -755,19 +768,12 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
             const int ya = y0 + 2 * rp;
             const long long o = (((long long)kx * 3 + c) * nz + z) * ny;
             const V* src = Xi + o;
-            const V* srq = Xj + o;
             V A = mk<V>(0, 0), B = mk<V>(0, 0);
             if (!(ny & 1)) {
-                if (ya < ny) {
-                    V a0, a1, b0, b1;
-                    load2(src + ya, a0, a1);
-                    load2(srq + ya, b0, b1);
-                    A = cadd(a0, b0);
-                    B = cadd(a1, b1);
-                }
+                if (ya < ny) load2(src + ya, A, B);
             } else {
-                if (ya < ny) A = cadd(src[ya], srq[ya]);
-                if (ya + 1 < ny) B = cadd(src[ya + 1], srq[ya + 1]);
+                if (ya < ny) A = src[ya];
+                if (ya + 1 < ny) B = src[ya + 1];
             }
             const int i0 = (2 * rp + (kx & 1)) * m + (kx >> 1);
             lines[i0 + (i0 >> psh)] = mk<V>(A.x - B.y, A.y + B.x);
@@ -1633,13 +1639,13 @@ hipError_t launch_conv(int mz, int kinds, const Prob* P, int np, const WorkMap& 
 }
 
 template <typename T>
-hipError_t launch_xinv(const Prob* P, int np, const WorkMap& wm, const void* Xp, const void* Xq, const T* s,
+hipError_t launch_xinv(const Prob* P, int np, const WorkMap& wm, const void* Xp, const T* s,
                        T* s_star, T* h, double* epart, const void* tw, const int* done, int mode,
                        double tau, double fcp, double fcd, size_t lds, hipStream_t st)
 {
     if (wm.total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_xinv<T>, dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start,
-                       (const cplx<T>*)Xp, (const cplx<T>*)Xq, s, s_star, h, epart, (const cplx<T>*)tw, done,
+                       (const cplx<T>*)Xp, s, s_star, h, epart, (const cplx<T>*)tw, done,
                        mode, tau, fcp, fcd);
     return hipGetLastError();
 }
@@ -2298,7 +2304,7 @@ hipError_t launch_fill_double(double* p, int n, double v, hipStream_t st)
                                        const void*, const int*, size_t, hipStream_t);             \
     template hipError_t launch_conv<T>(int, int, const Prob*, int, const WorkMap&, void*, void*,       \
                                        const T*, const void*, const int*, size_t, hipStream_t);   \
-    template hipError_t launch_xinv<T>(const Prob*, int, const WorkMap&, const void*, const void*, \
+    template hipError_t launch_xinv<T>(const Prob*, int, const WorkMap&, const void*,              \
                                        const T*,                                                    \
                                        T*, T*, double*, const void*, const int*, int, double,     \
                                        double, double, size_t, hipStream_t);                       \
