@@ -322,7 +322,12 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
     pl.o_ss = take(ts * spin);
     pl.o_h = take(ts * spin);
     pl.o_nh = take(ts * nh);
-    pl.o_big = take(std::max((size_t)(2 * cs * xo), pl.scratch_bytes));
+    // the convolution's last y pass reads whole transform lines of the
+    // second spectrum buffer (up to m_y - 1 past a ragged line's end): one
+    // line of slack after it keeps those reads inside the workspace
+    int my_max = 1;
+    for (const Prob& q : pl.P) my_max = std::max(my_max, q.my);
+    pl.o_big = take(std::max((size_t)(2 * cs * xo + cs * my_max), pl.scratch_bytes));
     pl.o_ep = take(8 * ep);
     pl.o_ap = take(8 * ap);
     pl.o_fp = take(8 * fp);

@@ -360,7 +360,10 @@ __device__ __forceinline__ void conv_zphase(const Prob& p, int G, int kx0, int h
                 // xz and yz (the tensor is even in z except for those), so
                 // each column reads only the rows r <= mirror (9 of 16 for
                 // MZ = 8) and the unrolled loop folds the repeated loads
-                const bool mir = SSM_CONV_NH_MIRROR && (hz == 0 ? 2 * r > MZ : 2 * r >= MZ);
+                // (not for 8 layers with y lengths below 256, where keeping
+                // the shared rows live costs more registers than it saves)
+                constexpr bool kMir = SSM_CONV_NH_MIRROR && (MZ <= 4 || LMY >= 8);
+                const bool mir = kMir && (hz == 0 ? 2 * r > MZ : 2 * r >= MZ);
                 const int rs = mir ? (hz == 0 ? MZ - r : MZ - 1 - r) : r;
                 const T* q6 = nh + (rs * 6 << LMY);
                 if (SSM_CONV_NH_SERIAL) asm volatile("" : "+v"(q6));
@@ -515,22 +518,18 @@ __device__ __forceinline__ void conv_body_ct(const Prob& p, int s0, int G, cplx<
                         // half 1, un-twiddled, added onto half 0, which this
                         // thread stored to the same places before the
                         // z-phase barriers of this half (all loads issued
-                        // before any add when the line is full length)
+                        // before any add)
 #pragma unroll
                         for (int r = 0; r < RL; ++r) v[b][r] = cmulc(v[b][r], twl[(j + r * PL::NS) << TWS]);
-                        if (ny == MY) {
-                            V h0[RL];
+                        // (a ragged line also reads the positions past ny:
+                        // the next line's values, or the slack the
+                        // workspace keeps after the buffer; those sums are
+                        // never stored)
+                        V h0[RL];
 #pragma unroll
-                            for (int r = 0; r < RL; ++r) h0[r] = dst[j + r * PL::NS];
+                        for (int r = 0; r < RL; ++r) h0[r] = dst[j + r * PL::NS];
 #pragma unroll
-                            for (int r = 0; r < RL; ++r) v[b][r] = cadd(v[b][r], h0[r]);
-                        } else {
-#pragma unroll
-                            for (int r = 0; r < RL; ++r) {
-                                const int y = j + r * PL::NS;
-                                if (y < ny) v[b][r] = cadd(v[b][r], dst[y]);
-                            }
-                        }
+                        for (int r = 0; r < RL; ++r) v[b][r] = cadd(v[b][r], h0[r]);
                     }
                     if (ny == MY) {
 #pragma unroll
