@@ -73,6 +73,11 @@ namespace ssm {
 #ifndef SSM_CONV_NH_MIRROR
 #define SSM_CONV_NH_MIRROR 1
 #endif
+// 1: x-neighbour exchange of the inverse-x epilogue by DPP wavefront shifts
+// (0: LDS permutes)
+#ifndef SSM_XINV_DPP
+#define SSM_XINV_DPP 1
+#endif
 // widest pass of the compile-time-length convolution bodies
 #ifndef SSM_CONV_CT_RADIX_BITS
 #define SSM_CONV_CT_RADIX_BITS 4
@@ -715,6 +720,38 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     else conv_body<T, MZ, 0>(p, s0, G, X, Xp, nhat, tw, sm);
 }
 
+// The value of the next (previous) lane of the wavefront: DPP wavefront
+// shifts by one lane (one VALU move, no LDS permute); the last (first) lane
+// receives 0, which callers replace.
+__device__ __forceinline__ int dpp_next(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_prev(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+template <typename T>
+__device__ __forceinline__ T lane_next(T v)
+{
+    if constexpr (!SSM_XINV_DPP) {
+        return __shfl_down(v, 1);
+    } else if constexpr (sizeof(T) == 4) {
+        return __int_as_float(dpp_next(__float_as_int(v)));
+    } else {
+        const long long b = __double_as_longlong(v);
+        const int lo = dpp_next((int)(b & 0xffffffffLL)), hi = dpp_next((int)(b >> 32));
+        return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    }
+}
+template <typename T>
+__device__ __forceinline__ T lane_prev(T v)
+{
+    if constexpr (!SSM_XINV_DPP) {
+        return __shfl_up(v, 1);
+    } else if constexpr (sizeof(T) == 4) {
+        return __int_as_float(dpp_prev(__float_as_int(v)));
+    } else {
+        const long long b = __double_as_longlong(v);
+        const int lo = dpp_prev((int)(b & 0xffffffffLL)), hi = dpp_prev((int)(b >> 32));
+        return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // k_xinv: x half-spectra of the convolved field -> unit-strength dipolar
 // field of a tile (one component at a time), then the per-site epilogue.
@@ -858,8 +895,8 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
             double sv[3], xp[3], xm[3], nb[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                T right = __shfl_down(cc[c], 1);
-                T left = __shfl_up(cc[c], 1);
+                T right = lane_next(cc[c]);
+                T left = lane_prev(cc[c]);
                 if (redge) right = er[c];
                 if (ledge) left = el[c];
                 if (x + 1 >= nx) right = T(0);
