@@ -124,6 +124,8 @@ ssm_status check_problems(const ssm_problem* pr, int np, int prec, std::string& 
             err = "problem " + std::to_string(i) + ": non-finite parameter";
             return SSM_EINVAL;
         }
+        // (the inverse-x epilogue addresses an image with 32-bit byte
+        // offsets, which these limits keep below 2^32)
         if (q.nx > 1024 || q.ny > 1024 || q.nz > 16 || q.n_images > 1024) {
             err = "problem " + std::to_string(i) + ": size beyond the supported limits";
             return SSM_EUNSUPPORTED;

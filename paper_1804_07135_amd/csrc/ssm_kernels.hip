@@ -841,9 +841,13 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     // loads a row needs are issued one row ahead, so their latency overlaps
     // the arithmetic of the row before.
     const double J = p.J, dm = p.d, ku = p.ku, D = p.D;
-    const T* si = s + p.s_off + (long long)img * 3 * N + (long long)z * ny * nx;
-    const long long pl = (long long)nx * ny;
-    const long long soff = p.s_off + (long long)img * 3 * N + (long long)z * ny * nx;
+    // Global accesses take the image's first element (uniform) plus a 32-bit
+    // byte offset: an image spans at most 3 * 2^24 sites, under 2^32 bytes.
+    const long long ib = p.s_off + (long long)img * 3 * N;
+    const char* const sb = reinterpret_cast<const char*>(s + ib);
+    const unsigned cb = (unsigned)N * sizeof(T), plb = (unsigned)(nx * ny) * sizeof(T), xb = sizeof(T);
+    const unsigned zb = (unsigned)z * plb;
+    auto at = [&](unsigned o) -> T { return *reinterpret_cast<const T*>(sb + o); };
     int nxp = 1;
     while (nxp < nx && nxp < kNT) nxp <<= 1;
     const int rgs = kNT / nxp;                    // row groups
@@ -859,20 +863,20 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         // spin component c at (x, y0 + rr), zero outside the lattice
         auto rowv = [&](int rr, int c) -> T {
             const int y = y0 + rr;
-            return (xin && ra < rb && y >= 0 && y < ny) ? si[(long long)c * N + (long long)y * nx + x] : T(0);
+            return (xin && ra < rb && y >= 0 && y < ny) ? at(c * cb + zb + (unsigned)(y * nx + x) * xb) : T(0);
         };
         // the z neighbours and (wave-edge lanes) x neighbours of row rr
         auto fetch = [&](int rr, T (&zu)[3], T (&zd)[3], T (&er)[3], T (&el)[3]) {
             const int y = y0 + rr;
             const bool a = xin && rr < rb && y < ny;
-            const long long i = (long long)y * nx + x;
+            const unsigned o = zb + (unsigned)(y * nx + x) * xb;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const T* sc = si + (long long)c * N;
-                zu[c] = (a && z + 1 < nz) ? sc[i + pl] : T(0);
-                zd[c] = (a && z > 0) ? sc[i - pl] : T(0);
-                er[c] = (a && redge && x + 1 < nx) ? sc[i + 1] : T(0);
-                el[c] = (a && ledge && x > 0) ? sc[i - 1] : T(0);
+                const unsigned oc = o + c * cb;
+                zu[c] = (a && z + 1 < nz) ? at(oc + plb) : T(0);
+                zd[c] = (a && z > 0) ? at(oc - plb) : T(0);
+                er[c] = (a && redge && x + 1 < nx) ? at(oc + xb) : T(0);
+                el[c] = (a && ledge && x > 0) ? at(oc - xb) : T(0);
             }
         };
         T cm[3], cc[3], cp[3], zu[3], zd[3], er[3], el[3];
@@ -886,7 +890,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         for (int r = ra; r < ra + rper; ++r) {
             const int y = y0 + r;
             const bool act = xin && r < rb && y < ny;
-            const long long i = (long long)y * nx + x;
+            const unsigned o = zb + (unsigned)(y * nx + x) * xb;
             // next row's loads first
             T cn[3], zu2[3], zd2[3], er2[3], el2[3];
 #pragma unroll
@@ -931,18 +935,21 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                                          sv[0] * h[1] - sv[1] * h[0]};
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
-                        hout[soff + (long long)c * N + i] = (T)(fcd * (s2 * h[c] - sh * sv[c]) - fcp * x[c]);
+                        *reinterpret_cast<T*>(reinterpret_cast<char*>(hout + ib) + o + c * cb) =
+                            (T)(fcd * (s2 * h[c] - sh * sv[c]) - fcp * x[c]);
                 } else if (mode & EPI_FIELD) {
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) hout[soff + (long long)c * N + i] = (T)h[c];
+                    for (int c = 0; c < 3; ++c)
+                        *reinterpret_cast<T*>(reinterpret_cast<char*>(hout + ib) + o + c * cb) = (T)h[c];
                 }
                 if (mode & EPI_STEP) {
                     double wv[3];
 #pragma unroll
                     for (int c = 0; c < 3; ++c) wv[c] = sv[c] + tau * (h[c] - sh * sv[c]);
-                    const double inv = 1.0 / sqrt(wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2]);
+                    const double inv = rsqrt(wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2]);
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) ss[soff + (long long)c * N + i] = (T)(wv[c] * inv);
+                    for (int c = 0; c < 3; ++c)
+                        *reinterpret_cast<T*>(reinterpret_cast<char*>(ss + ib) + o + c * cb) = (T)(wv[c] * inv);
                 }
             }
 #pragma unroll
