@@ -217,7 +217,9 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     load_twiddles(twl, lm, tw);
     const long long N = p.N;
     const T* si = s + p.s_off + (long long)img * 3 * N + (long long)z * ny * nx;
-    V* Xi = X + p.x_off + (long long)img * (m + 1) * 3 * nz * ny;
+    // the image's spectra as a uniform base and 32-bit byte offsets (they
+    // span at most 1025 * 3 * 16 * 1024 complex values, under 2^32 bytes)
+    char* const Xi = reinterpret_cast<char*>(X + p.x_off + (long long)img * (m + 1) * 3 * nz * ny);
     const int y0 = ty * yt, P2 = 2 * m;
     __syncthreads();
     // rows of a length divisible by VW = 16 / sizeof(T) from a 16-byte
@@ -274,12 +276,13 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
             const V A = mk<V>((Z.x + Zr.x) * hlf, (Z.y - Zr.y) * hlf);
             const V B = mk<V>((Z.y + Zr.y) * hlf, (Zr.x - Z.x) * hlf);
             const int ya = y0 + 2 * rp;
-            V* dst = Xi + (((long long)kx * 3 + c) * nz + z) * ny;
+            const unsigned o = (unsigned)(((kx * 3 + c) * nz + z) * ny + ya) * (unsigned)sizeof(V);
+            V* dst = reinterpret_cast<V*>(Xi + o);  // row ya
             if (!(ny & 1)) {
-                if (ya < ny) store2(dst + ya, A, B);
+                if (ya < ny) store2(dst, A, B);
             } else {
-                if (ya < ny) dst[ya] = A;
-                if (ya + 1 < ny) dst[ya + 1] = B;
+                if (ya < ny) dst[0] = A;
+                if (ya + 1 < ny) *reinterpret_cast<V*>(Xi + o + (unsigned)sizeof(V)) = B;
             }
         }
         __syncthreads();
@@ -793,7 +796,9 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     T* hd = reinterpret_cast<T*>(lines + padded_len(yt * m, x_padl(lm)));
     load_twiddles(twl, lm, tw);
     // the convolved x half-spectra of the image
-    const V* Xi = Xp + p.x_off + (long long)img * (m + 1) * 3 * nz * ny;
+    // (as a uniform base and 32-bit byte offsets: an image's spectra span
+    // at most 1025 * 3 * 16 * 1024 complex values, under 2^32 bytes)
+    const char* const Xi = reinterpret_cast<const char*>(Xp + p.x_off + (long long)img * (m + 1) * 3 * nz * ny);
     __syncthreads();
 #pragma unroll 1
     for (int c = 0; c < 3; ++c) {
@@ -802,14 +807,14 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         for (int idx = threadIdx.x; idx < (m + 1) * hp; idx += kNT) {
             const int rp = idx & (hp - 1), kx = idx >> lhp;
             const int ya = y0 + 2 * rp;
-            const long long o = (((long long)kx * 3 + c) * nz + z) * ny;
-            const V* src = Xi + o;
+            const unsigned o = (unsigned)(((kx * 3 + c) * nz + z) * ny + ya) * (unsigned)sizeof(V);
+            const V* src = reinterpret_cast<const V*>(Xi + o);  // row ya
             V A = mk<V>(0, 0), B = mk<V>(0, 0);
             if (!(ny & 1)) {
-                if (ya < ny) load2(src + ya, A, B);
+                if (ya < ny) load2(src, A, B);
             } else {
-                if (ya < ny) A = src[ya];
-                if (ya + 1 < ny) B = src[ya + 1];
+                if (ya < ny) A = src[0];
+                if (ya + 1 < ny) B = *reinterpret_cast<const V*>(Xi + o + (unsigned)sizeof(V));
             }
             const int i0 = (2 * rp + (kx & 1)) * m + (kx >> 1);
             lines[i0 + (i0 >> psh)] = mk<V>(A.x - B.y, A.y + B.x);
