@@ -865,49 +865,59 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     for (int xc = 0; xc < nx; xc += nxp) {
         const int x = xc + xl;
         const bool xin = x < nx;
-        // spin component c at (x, y0 + rr), zero outside the lattice
+        // a wavefront-edge lane loads its one neighbour outside the wavefront
+        // (lane 63 the right one, lane 0 the left one; a lane at both edges
+        // has nx = 1 and no neighbours)
+        const bool egok = redge ? x + 1 < nx : (ledge && x > 0);
+        const int xcl = min(x, nx - 1);
+        // spin component c at (x, y0 + rr), zero outside the lattice in y
+        // (loaded from the site clamped into the lattice, then selected: the
+        // values of lanes outside it in x reach no site that is updated)
         auto rowv = [&](int rr, int c) -> T {
             const int y = y0 + rr;
-            return (xin && ra < rb && y >= 0 && y < ny) ? at(c * cb + zb + (unsigned)(y * nx + x) * xb) : T(0);
+            const T v = at(c * cb + zb + (unsigned)(min(max(y, 0), ny - 1) * nx + xcl) * xb);
+            return (y >= 0 && y < ny) ? v : T(0);
         };
-        // the z neighbours and (wave-edge lanes) x neighbours of row rr
-        auto fetch = [&](int rr, T (&zu)[3], T (&zd)[3], T (&er)[3], T (&el)[3]) {
+        // the z neighbours and (wave-edge lanes) x neighbours of row rr.  A
+        // lane outside the lattice or past its run uses none of them, so the
+        // z neighbours are loaded by every lane from the site clamped into
+        // the lattice, with no per-lane predicate
+        auto fetch = [&](int rr, T (&zu)[3], T (&zd)[3], T (&eg)[3]) {
             const int y = y0 + rr;
             const bool a = xin && rr < rb && y < ny;
-            const unsigned o = zb + (unsigned)(y * nx + x) * xb;
+            const unsigned o = zb + (unsigned)(min(y, ny - 1) * nx + xcl) * xb;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const unsigned oc = o + c * cb;
-                zu[c] = (a && z + 1 < nz) ? at(oc + plb) : T(0);
-                zd[c] = (a && z > 0) ? at(oc - plb) : T(0);
-                er[c] = (a && redge && x + 1 < nx) ? at(oc + xb) : T(0);
-                el[c] = (a && ledge && x > 0) ? at(oc - xb) : T(0);
+                zu[c] = (z + 1 < nz) ? at(oc + plb) : T(0);
+                zd[c] = (z > 0) ? at(oc - plb) : T(0);
+                eg[c] = (a && egok) ? at(redge ? oc + xb : oc - xb) : T(0);
             }
         };
-        T cm[3], cc[3], cp[3], zu[3], zd[3], er[3], el[3];
+        T cm[3], cc[3], cp[3], zu[3], zd[3], eg[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             cm[c] = rowv(ra - 1, c);
             cc[c] = rowv(ra, c);
             cp[c] = rowv(ra + 1, c);
         }
-        fetch(ra, zu, zd, er, el);
+        fetch(ra, zu, zd, eg);
         for (int r = ra; r < ra + rper; ++r) {
             const int y = y0 + r;
             const bool act = xin && r < rb && y < ny;
             const unsigned o = zb + (unsigned)(y * nx + x) * xb;
             // next row's loads first
-            T cn[3], zu2[3], zd2[3], er2[3], el2[3];
+            T cn[3], zu2[3], zd2[3], eg2[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) cn[c] = rowv(r + 2, c);
-            fetch(r + 1, zu2, zd2, er2, el2);
+            fetch(r + 1, zu2, zd2, eg2);
             double sv[3], xp[3], xm[3], nb[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 T right = lane_next(cc[c]);
                 T left = lane_prev(cc[c]);
-                if (redge) right = er[c];
-                if (ledge) left = el[c];
+                if (redge) right = eg[c];
+                if (ledge) left = eg[c];
                 if (x + 1 >= nx) right = T(0);
                 sv[c] = (double)cc[c];
                 xp[c] = (double)right;
@@ -964,8 +974,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                 cp[c] = cn[c];
                 zu[c] = zu2[c];
                 zd[c] = zd2[c];
-                er[c] = er2[c];
-                el[c] = el2[c];
+                eg[c] = eg2[c];
             }
         }
     }
