@@ -807,11 +807,15 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         for (int idx = threadIdx.x; idx < (m + 1) * hp; idx += kNT) {
             const int rp = idx & (hp - 1), kx = idx >> lhp;
             const int ya = y0 + 2 * rp;
-            const unsigned o = (unsigned)(((kx * 3 + c) * nz + z) * ny + ya) * (unsigned)sizeof(V);
-            const V* src = reinterpret_cast<const V*>(Xi + o);  // row ya
+            // even ny: a row pair past the lattice reads the last pair
+            // instead (rows transform independently, and no field of a row
+            // past the lattice is used), so the load needs no predicate
+            const int yl = (ny & 1) ? ya : min(ya, ny - 2);
+            const unsigned o = (unsigned)(((kx * 3 + c) * nz + z) * ny + yl) * (unsigned)sizeof(V);
+            const V* src = reinterpret_cast<const V*>(Xi + o);  // row yl
             V A = mk<V>(0, 0), B = mk<V>(0, 0);
             if (!(ny & 1)) {
-                if (ya < ny) load2(src, A, B);
+                load2(src, A, B);
             } else {
                 if (ya < ny) A = src[0];
                 if (ya + 1 < ny) B = *reinterpret_cast<const V*>(Xi + o + (unsigned)sizeof(V));
