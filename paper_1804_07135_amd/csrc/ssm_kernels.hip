@@ -869,9 +869,9 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     for (int xc = 0; xc < nx; xc += nxp) {
         const int x = xc + xl;
         const bool xin = x < nx;
-        // a wavefront-edge lane loads its one neighbour outside the wavefront
-        // (lane 63 the right one, lane 0 the left one; a lane at both edges
-        // has nx = 1 and no neighbours)
+        // a lane at the edge of its wavefront or row group loads its one
+        // neighbour outside it (the last lane the right one, the first lane
+        // the left one; a lane at both edges has nx = 1 and no neighbours)
         const bool egok = redge ? x + 1 < nx : (ledge && x > 0);
         const int xcl = min(x, nx - 1);
         // spin component c at (x, y0 + rr), zero outside the lattice in y
