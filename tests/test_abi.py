@@ -85,6 +85,29 @@ def test_lds_limit_is_the_documented_one(precision, cap, ny):
             assert ei.value.status == ssm.SSM_EUNSUPPORTED
 
 
+def test_accepted_images_fit_32_bit_byte_offsets():
+    """The x kernels address one image's spins (3 N values) and its x half
+    spectra ((m_x + 1) 3 nz ny complex values, m_x the power of two >= nx)
+    with 32-bit byte offsets: every lattice the limits accept keeps both
+    under 2^32 bytes, counted at FP64 width in either form."""
+    nx = 1024
+    mx = 1 << (nx - 1).bit_length()
+    accepted = []
+    for precision in (ssm.SSM_FP64, ssm.SSM_FP32_MIXED):
+        for ny in (1, 7, 64, 100, 256, 300, 512, 640, 1000, 1024):
+            for nz in range(1, 17):
+                try:
+                    ssm.ssm_workspace_size([prob(nx=nx, ny=ny, nz=nz)], precision)
+                except ssm.SSMError:
+                    continue
+                accepted.append((ny, nz))
+                assert 3 * nx * ny * nz * 8 < 2 ** 32
+                assert (mx + 1) * 3 * nz * ny * 16 < 2 ** 32
+    assert (1024, 1) in accepted and max(nz for _, nz in accepted) == 16
+    with pytest.raises(ssm.SSMError):
+        ssm.ssm_workspace_size([prob(nx=nx + 1)], ssm.SSM_FP32_MIXED)
+
+
 def test_workspace_size_rejects_precision_and_mixed_nz():
     with pytest.raises(ssm.SSMError) as ei:
         ssm.ssm_workspace_size([prob()], 7)
