@@ -24,7 +24,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "site-field evals/s + string iters/s; FP32-batched vs FP64 plain at 1e-4 barrier"
 HBM_PEAK_GBS = 8000.0
-FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak (packed FP32 FMA)
+# FP32 vector ceiling of the instructions this build issues: 256 CUs x 4 SIMDs
+# x 16 lanes x 2 flops per FMA x 2.4 GHz (the published 157.3 TFLOP/s counts
+# packed FP32, which the build leaves off)
+FP32_VECTOR_NONPACKED_TFLOPS = 78.6
 KERNEL_SOURCES = ["paper_1804_07135_amd/csrc/ssm_kernels.hip", "paper_1804_07135_amd/csrc/ssm_internal.hpp",
                   "paper_1804_07135_amd/csrc/ssm_fft.hpp"]
 
@@ -51,31 +54,15 @@ def algorithmic_bytes(w, ts):
     spins = K * 3 * N * ts                         # one string
     xspec = K * (mx + 1) * 3 * nz * ny * 2 * ts    # x half-spectra of one string
     nhat = (mx + 1) * 2 * my * pz * 6 * ts         # dipole-kernel spectrum
-    interior = K - 2
     return {
         "k_xfwd": spins + xspec,
         "k_conv": 2 * xspec + nhat,
         "k_xinv": xspec + 2 * spins,
         "k_arc": spins,
-        "k_interp": spins * (2 * interior + 2) / K + spins,
+        # every source image read once (consecutive targets share their
+        # sources), every image of the new string written once
+        "k_interp": 2 * spins,
     }
-
-
-def conv_algorithmic_flops(w):
-    """Flops of one convolution launch by the standard count of the FFT
-    convolution: 2.5 P log2 P per real 3D transform of the padded grid P
-    (the real-input form of 5 n log2 n), taken for the y and z passes that
-    the convolution kernel runs, for the 3 forward and 3 inverse transforms
-    of every image, plus the 3x3 real spectral multiply (30 flops per
-    complex frequency of the half spectrum)."""
-    nx, ny, nz, K = w["nx"], w["ny"], w["nz"], w["K"]
-    px = 2 * (1 << (nx - 1).bit_length())
-    py = 2 * (1 << (ny - 1).bit_length())
-    pz = 1 if nz == 1 else 2 * (1 << (nz - 1).bit_length())
-    P = px * py * pz
-    yz_log = math.log2(py) + math.log2(pz)
-    freqs = (px // 2 + 1) * py * pz
-    return K * (6 * 2.5 * P * yz_log + 30 * freqs)
 
 
 def time_iterations(sm, steps, tau):
@@ -87,28 +74,78 @@ def time_iterations(sm, steps, tau):
     return time.perf_counter() - t0
 
 
-def cpu_baseline(w, s0, budget_s):
-    """The oracle (direct O(N^2) dipole sum, FP64, OpenMP) timed on this host:
-    fields at a sample of sites of image 0."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _omp():
+    """The OpenMP runtime the oracle library runs on (same process)."""
+    import ctypes
+    for name in ("libgomp.so.1", "libgomp.so"):
+        try:
+            lib = ctypes.CDLL(name)
+            lib.omp_get_max_threads.restype = ctypes.c_int
+            return lib
+        except OSError:
+            continue
+    return None
+
+
+def _sample_rate(oracle, w, s0, budget_s, seed):
+    """Direct-sum fields at random sites of image 0 for about budget_s."""
     import numpy as np
-    from oracle import oracle
-    oracle.build()
     N = w["nx"] * w["ny"] * w["nz"]
-    rng = np.random.default_rng(0)
-    n = 64
-    t = 0.0
+    rng = np.random.default_rng(seed)
+    n, t = 16, 0.0
     while True:
         sites = rng.choice(N, size=n, replace=False)
         t0 = time.perf_counter()
         oracle.field_at(s0[0], w["J"], w["d"], w["ku"], w["D"], sites)
         t = time.perf_counter() - t0
         if t > budget_s / 2 or n >= N:
-            break
+            return n, t
         n = min(N, int(n * max(2.0, 0.75 * budget_s / max(t, 1e-3))))
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": n / t, "unit": "site-field evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"direct-sum fields at {n} random sites of image 0 of the "
-                      f"{w['nx']}x{w['ny']}x{w['nz']} lattice ({t:.1f} s)"}
+
+
+def cpu_baseline(w, s0, budget_s):
+    """The oracle (direct O(N^2) dipole sum, FP64, OpenMP), as it stands,
+    timed on this host: fields at a sample of sites of image 0 of the
+    workload with every host thread and with one thread, and the full
+    200-iteration run of the 32x32x1, 10-image workload with every thread."""
+    from oracle import oracle
+    from paper_1804_07135_amd import inputs
+    oracle.build()
+    omp = _omp()
+    threads = omp.omp_get_max_threads() if omp else int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    n, t = _sample_rate(oracle, w, s0, budget_s, 0)
+    out = {"value": n / t, "unit": "site-field evals/s", "cores": threads, "kind": "oracle",
+           "sample": f"direct-sum fields at {n} random sites of image 0 of the "
+                     f"{w['nx']}x{w['ny']}x{w['nz']} lattice ({t:.1f} s, {threads} threads)",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    if omp:
+        omp.omp_set_num_threads(1)
+        n1, t1 = _sample_rate(oracle, w, s0, budget_s / 3, 1)
+        omp.omp_set_num_threads(threads)
+        out["value_1_thread"] = n1 / t1
+        out["sample_1_thread"] = f"{n1} sites ({t1:.1f} s)"
+    c1 = dict(inputs.WORKLOADS["bloch_32x32x1_k10"])
+    s1 = inputs.build_string(c1)
+    t0 = time.perf_counter()
+    oracle.iterate(s1, c1["J"], c1["d"], c1["ku"], c1["D"], c1["iters"], c1["tau"])
+    t = time.perf_counter() - t0
+    kn = c1["K"] * c1["nx"] * c1["ny"] * c1["nz"]
+    # iterations plus the closing evaluation, one field per image each
+    out["bloch_32x32x1_k10_full_run"] = {"iters": c1["iters"], "seconds": t, "threads": threads,
+                                         "string_iters_per_s": c1["iters"] / t,
+                                         "site_field_evals_per_s": (c1["iters"] + 1) * kn / t}
+    return out
 
 
 def _csv_rows(path):
@@ -154,6 +191,55 @@ def rk_leg(ssm, torch, prob, s0, KN, args):
            "accepted_steps_total": int(c[:, 0].sum()), "rejected_steps_total": int(c[:, 1].sum()),
            "barrier": float(sm.barrier().cpu().numpy()[0][0]), "flags": int(sm.check())}
     del sm
+    torch.cuda.empty_cache()
+    return res
+
+
+def full_run_leg(ssm, torch, prob, s0, iters, tau, chunk):
+    """The workload's full run in both forms from the same initial string
+    (FP32-mixed replayed as graphs, FP64 plain with direct launches): the
+    barrier of each after `iters` iterations and their relative difference
+    (target 1e-4), with each form's time."""
+    res = {"iters": iters}
+    bars = {}
+    for name, prec, gc in (("fp32_mixed", ssm.SSM_FP32_MIXED, chunk), ("fp64_plain", ssm.SSM_FP64, 0)):
+        sm = ssm.StringMethod(prob, prec)
+        sm.set_options(check_every=10, graph_chunk=gc)
+        sm.set_string(s0)
+        dt = time_iterations(sm, iters, tau)
+        b = sm.barrier().cpu().numpy()[0]
+        bars[name] = float(b[0])
+        res[name] = {"barrier": float(b[0]), "argmax": int(b[1]), "ms_per_step": dt / iters * 1e3,
+                     "flags": int(sm.check())}
+        del sm
+        torch.cuda.empty_cache()
+    res["barrier_rel_err_fp32_vs_fp64"] = abs(bars["fp32_mixed"] - bars["fp64_plain"]) / abs(bars["fp64_plain"])
+    return res
+
+
+def small_workloads_leg(ssm, torch, inputs, steps, chunk):
+    """Rates of the 32x32x1 (10 images) and 64x64x1 (20 images) workloads in
+    both forms: FP64 plain (direct launches) and FP32-mixed (graph replay).
+    Too small to fill the GPU; they run in L2 and are launch- and
+    latency-bound."""
+    res = {}
+    for name in ("bloch_32x32x1_k10", "boundary_64x64x1_k20"):
+        w = dict(inputs.WORKLOADS[name])
+        prob = dict(nx=w["nx"], ny=w["ny"], nz=w["nz"], K=w["K"], J=w["J"], d=w["d"], ku=w["ku"], D=w["D"])
+        s0 = inputs.build_string(w)
+        kn = w["K"] * w["nx"] * w["ny"] * w["nz"]
+        r = {}
+        for form, prec, gc in (("fp64_plain", ssm.SSM_FP64, 0), ("fp32_mixed", ssm.SSM_FP32_MIXED, chunk)):
+            sm = ssm.StringMethod(prob, prec)
+            sm.set_options(check_every=10, graph_chunk=gc)
+            sm.set_string(s0)
+            sm.iterate(chunk, w["tau"])
+            dt = time_iterations(sm, steps, w["tau"])
+            r[form] = {"ms_per_step": dt / steps * 1e3, "string_iters_per_s": steps / dt,
+                       "site_field_evals_per_s": steps * kn / dt}
+            del sm
+        r["speedup_fp32_vs_fp64"] = r["fp64_plain"]["ms_per_step"] / r["fp32_mixed"]["ms_per_step"]
+        res[name] = r
     torch.cuda.empty_cache()
     return res
 
@@ -258,6 +344,12 @@ def summarize_profiles(args):
                              "avg_ms": statistics.mean(stats[k])}
             if k in sq and "SQ_INSTS_VALU" in sq[k]:
                 per_kernel[k]["valu_wave_instructions"] = statistics.median(sq[k]["SQ_INSTS_VALU"])
+            if k in sq and all(c in sq[k] for c in ("SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_ADD_F32",
+                                                    "SQ_INSTS_VALU_MUL_F32")):
+                # executed FP32 flops: 64 lanes per wave instruction, 2 per FMA
+                med = {c: statistics.median(sq[k][c]) for c in sq[k]}
+                per_kernel[k]["fp32_flops"] = 64 * (2 * med["SQ_INSTS_VALU_FMA_F32"] + med["SQ_INSTS_VALU_ADD_F32"]
+                                                    + med["SQ_INSTS_VALU_MUL_F32"])
     with open(os.path.join(ROOT, "profiles", f"traffic_{dom}_{w}_fp32.json"), "w") as fh:
         json.dump({"kernel": dom, "workload": w, "bytes_per_launch": fetch + write, "read_bytes": fetch,
                    "write_bytes": write, "fetch_calibration": f_cal, "write_calibration": w_cal,
@@ -285,6 +377,10 @@ def main():
     ap.add_argument("--paper-batch", type=int, default=16,
                     help="(d, k) points of the batched paper-shape run")
     ap.add_argument("--rk-tol", type=float, default=1e-5)
+    ap.add_argument("--full-run-iters", type=int, default=500,
+                    help="iterations of the full-run barrier comparison of both forms (0: skip)")
+    ap.add_argument("--config-steps", type=int, default=200,
+                    help="timed iterations of the small-workload rates (0: skip)")
     ap.add_argument("--autotune", action="store_true",
                     help="choose the FP32 form's tiles with the library's autotuner before timing")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -382,8 +478,8 @@ def main():
     kern = {k: {"ms_total": v[0], "launches": v[1], "ms_avg": v[0] / max(v[1], 1)} for k, v in prof.items()}
     ranked = sorted((k for k in kern if k in ab), key=lambda k: -kern[k]["ms_total"])
     dom = ranked[0]
-    # per-kernel measured traffic and VALU counts from the committed
-    # rocprofv3 summary of the same kernel sources
+    # per-kernel measured traffic and instruction counts from the committed
+    # rocprofv3 summary, used only while it covers the same kernel sources
     pk = {}
     for name in sorted(os.listdir(os.path.join(ROOT, "profiles"))):
         if name.startswith("traffic_") and name.endswith(f"_{args.workload}_fp32.json"):
@@ -394,38 +490,42 @@ def main():
     floor_bytes = 72 * KN  # read/write floor of one fused FP32 iteration
 
     def roofline_of(k):
+        """HBM roofline of kernel k: algorithmic bytes per launch over its
+        average launch duration (HIP events on the launch stream)."""
         t_avg = kern[k]["ms_avg"] * 1e-3
         traffic = (pk[k]["read_bytes"] + pk[k]["write_bytes"]) if k in pk else None
-        valu = pk[k].get("valu_wave_instructions") if k in pk else None
-        # a wave64 FP32/FP64 VALU instruction takes 4 cycles of one SIMD;
-        # 1024 SIMDs at 2.4 GHz
-        valu_frac = valu * 4 / (1024 * 2.4e9 * t_avg) if valu else None
         achieved = ab[k] / t_avg / 1e9
-        hbm_view = {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                    "algorithmic_bytes_per_launch": ab[k],
-                    "traffic_frac": traffic / t_avg / 1e9 / HBM_PEAK_GBS if traffic else None}
-        if k == "k_conv":
-            # the convolution is bound by vector-ALU issue, not by HBM: report
-            # it against the FP32 vector peak with the standard FFT flop count
-            fl = conv_algorithmic_flops(w)
-            tf = fl / t_avg / 1e12
-            return {"bound": "alu", "kernel": k, "achieved": tf, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": tf / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
-                    "algorithmic_flops_per_launch": fl, "avg_launch_ms": kern[k]["ms_avg"],
-                    "valu_issue_frac": valu_frac, "hbm_view": hbm_view}
-        return dict({"bound": "hbm", "kernel": k, "traffic": traffic, "avg_launch_ms": kern[k]["ms_avg"],
-                     "valu_issue_frac": valu_frac}, **hbm_view)
+        r = {"bound": "hbm", "kernel": k, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes_per_launch": ab[k],
+             "avg_launch_ms": kern[k]["ms_avg"],
+             "traffic_frac": traffic / t_avg / 1e9 / HBM_PEAK_GBS if traffic else None}
+        q = pk.get(k, {})
+        if "valu_wave_instructions" in q:
+            # a wave64 FP32/FP64 VALU instruction occupies one SIMD for 4
+            # cycles; 1024 SIMDs at 2.4 GHz
+            r["valu_issue_frac"] = q["valu_wave_instructions"] * 4 / (1024 * 2.4e9 * t_avg)
+        if "fp32_flops" in q:
+            # the vector-ALU view: FP32 flops the kernel executes (counters:
+            # 64 lanes x (2 FMA + ADD + MUL) per wave instruction) against
+            # the non-packed FP32 ceiling
+            tf = q["fp32_flops"] / t_avg / 1e12
+            r["alu_view"] = {"executed_flops_per_launch": q["fp32_flops"], "achieved": tf,
+                             "peak": FP32_VECTOR_NONPACKED_TFLOPS, "unit": "TFLOP/s",
+                             "frac": tf / FP32_VECTOR_NONPACKED_TFLOPS}
+        return r
 
     roofline = roofline_of(dom)
     roofline_second = roofline_of(ranked[1]) if len(ranked) > 1 else None
     iteration = None
     it_kernels = ("k_xfwd", "k_conv", "k_xinv", "k_arc", "k_reduce", "k_interp")
     if all(k in pk for k in it_kernels):
-        # measured HBM bytes of one iteration: every kernel of the iteration
-        # once, over the timed iteration (graph replay)
+        # measured HBM bytes of one iteration (counter traffic, redundant
+        # re-reads included): every kernel of the iteration once, over the
+        # timed iteration (graph replay)
         b = sum(pk[k]["read_bytes"] + pk[k]["write_bytes"] for k in it_kernels)
         rate = b / (dt32 / steps) / 1e9
-        iteration = {"measured_bytes": b, "GBps": rate, "frac": rate / HBM_PEAK_GBS, "floor_bytes": floor_bytes}
+        iteration = {"measured_bytes_incl_redundant": b, "GBps": rate, "frac": rate / HBM_PEAK_GBS,
+                     "floor_bytes": floor_bytes}
     out = {
         "metric": METRIC,
         "value": value,
@@ -460,6 +560,10 @@ def main():
         "autotuned_tiles": tiles,
         "ms_per_step_with_events": dt32_ev / steps * 1e3,
     }
+    if args.full_run_iters > 0:
+        out["full_run"] = full_run_leg(ssm, torch, prob, s0, args.full_run_iters, tau, args.graph_chunk)
+    if args.config_steps > 0:
+        out["small_workloads"] = small_workloads_leg(ssm, torch, inputs, args.config_steps, args.graph_chunk)
     if args.paper_steps > 0:
         out["paper_shape_112x112x1_k60"] = paper_shape_leg(ssm, torch, args)
     if args.rk_iters > 0:

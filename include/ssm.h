@@ -159,10 +159,12 @@ ssm_status ssm_get_string(ssm_ctx* ctx, void* d_spins);
  * tol_force > 0: the perpendicular-force norm (ssm_get_tangents) of the
  * current string is checked every check_every iterations (ssm_set_options)
  * before iterating, and a problem whose norm is below tol_force stops; the
- * call synchronises the stream at every check.  After the loop the string
- * is evaluated once more: ssm_get_energies/fields/barrier return that
- * evaluation.  d_iters_done (device int32[n_problems] or NULL) receives the
- * iterations each problem performed in this call. */
+ * call synchronises the stream at every check.  The energies, fields,
+ * tangents and barrier of the final string are evaluated when first asked
+ * for (ssm_get_energies/fields/tangents/barrier enqueue that evaluation on
+ * the stream), so the work this call enqueues is its iterations and
+ * convergence checks only.  d_iters_done (device int32[n_problems] or NULL)
+ * receives the iterations each problem performed in this call. */
 ssm_status ssm_iterate(ssm_ctx* ctx, int32_t max_iter, double tau, double tol_force,
                        int32_t* d_iters_done);
 
@@ -214,7 +216,8 @@ ssm_status ssm_set_integrator(ssm_ctx* ctx, int32_t method, double rtol, double 
  * per-image step proposals, which carry over); spins are renormalised at
  * the end.  Then evaluates the new string (ssm_get_energies/fields).  Needs
  * SSM_WITH_RK; alpha >= 0 (0: pure precession), t_total > 0.  Synchronises
- * the stream after every attempted step. */
+ * the stream after every attempted step.  The getters evaluate the new
+ * string when first called. */
 ssm_status ssm_llg(ssm_ctx* ctx, double t_total, double alpha);
 
 /* Integrator statistics since ssm_set_integrator.  d_counts (device
@@ -235,10 +238,14 @@ ssm_status ssm_get_rk_stats(ssm_ctx* ctx, int32_t* d_counts, double* d_dt, int64
 ssm_status ssm_eval(ssm_ctx* ctx, const void* d_spins, void* d_field_or_null,
                     double* d_energy, double* d_terms_or_null);
 
-/* Energies of the current string from the last evaluation (double[sum K]). */
+/* Energies of the current string (double[sum K]).  Every getter below
+ * returns the evaluation of the current string and parameters: if the
+ * string or a parameter changed since the last evaluation, the getter first
+ * enqueues one (field, energies and term energies of every image).
+ * SSM_ESTATE before any ssm_set_string. */
 ssm_status ssm_get_energies(ssm_ctx* ctx, double* d_energy);
 
-/* Field h of the current string from the last evaluation (spin layout). */
+/* Field h of the current string (spin layout). */
 ssm_status ssm_get_fields(ssm_ctx* ctx, void* d_field);
 
 /* Path tangents of the current string and the perpendicular-force norm.
@@ -246,14 +253,15 @@ ssm_status ssm_get_fields(ssm_ctx* ctx, void* d_field);
  * t_k: phi_{k+1} - phi_{k-1} (one-sided at the endpoints), each spin's part
  * projected onto that spin's tangent plane, normalised in R^{3N}.  Force:
  * h_perp = h - (s.h)s per spin (Appendix); F_perp = h_perp - (h_perp.t)t
- * for interior images and h_perp at the endpoints.  Needs the field of the
- * current string (ssm_iterate or ssm_eval(ctx, NULL, ...) first, else
- * SSM_ESTATE).  d_tangent (spin layout, or NULL) receives t;
+ * for interior images and h_perp at the endpoints.  Uses the field of the
+ * current string (evaluated first if needed).  A force that is not finite
+ * counts as +infinity, so a diverged problem never passes tol_force.
+ * d_tangent (spin layout, or NULL) receives t;
  * d_force_norm_or_null (double[n_problems]) receives
  * max_k max_i |F_perp,k,i| per problem. */
 ssm_status ssm_get_tangents(ssm_ctx* ctx, void* d_tangent, double* d_force_norm_or_null);
 
-/* Barrier of every problem from the last evaluation (Sec. III: the energy of
+/* Barrier of every problem for the current string (Sec. III: the energy of
  * the highest image relative to the first).  d_out: double[n_problems][6] =
  * {B = max_k E_k - E_0, argmax k (smallest on ties),
  *  dB/dJ, dB/dd, dB/dku, dB/ddip}; the derivatives are the envelope-theorem

@@ -855,9 +855,11 @@ int oracle_reparam_opts(int K, int64_t N, const double* s_star, double* s_out, d
     {
         double* fv = (double*)malloc((size_t)K * sizeof(double));
         double* ov = (double*)malloc((size_t)K * sizeof(double));
+        /* interpolated (unnormalised) spin of every target image at site i,
+         * sized by K (no limit on the number of images) */
+        double (*v)[3] = (double (*)[3])malloc((size_t)K * sizeof(*v));
         #pragma omp for schedule(static)
         for (int64_t i = 0; i < N; ++i) {
-            double v[1024][3];
             for (int c = 0; c < 3; ++c) {
                 if (spline) {
                     for (int kk = 0; kk < K; ++kk) fv[kk] = s_star[(int64_t)kk * M + c * N + i];
@@ -885,6 +887,7 @@ int oracle_reparam_opts(int K, int64_t N, const double* s_star, double* s_out, d
         }
         free(fv);
         free(ov);
+        free(v);
     }
     free(tk);
     return 1;

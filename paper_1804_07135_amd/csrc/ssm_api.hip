@@ -960,6 +960,49 @@ ssm_status autotune(ssm_ctx* c, const char* cache_path)
 
 }  // namespace
 
+// Twiddle tables, descriptors and work maps, and the FFT of the point-dipole
+// tensor (eq. (7)) on the padded grid of every distinct lattice shape, in the
+// context's workspace.  Synchronises the stream (the host copies' sources
+// are locals).
+static ssm_status setup_tables(ssm_ctx* c)
+{
+    const Plan& pl = c->pl;
+    std::vector<double> tw64;
+    twiddles(tw64);
+    std::vector<unsigned char> twt(2 * pl.tsize * kTwM);
+    if (pl.tsize == 8) {
+        std::memcpy(twt.data(), tw64.data(), twt.size());
+    } else {
+        float* f = reinterpret_cast<float*>(twt.data());
+        for (int i = 0; i < 2 * kTwM; ++i) f[i] = (float)tw64[i];
+    }
+    hipError_t e = hipMemcpyAsync(c->ws + pl.o_tw, twt.data(), twt.size(), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->ws + pl.o_tw64, tw64.data(), 16 * kTwM, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) { return hipfail(c, e, "upload twiddles"); }
+    ssm_status st = upload_plan(c);
+    if (st != SSM_OK) return st;
+    // dipole-kernel spectrum of every distinct shape (FP64, then stored as T)
+    for (size_t g = 0; g < pl.shapes.size(); ++g) {
+        int i = 0;
+        while (pl.geo[i] != (int)g) ++i;
+        const Prob& pr = pl.P[i];
+        double* f1 = c->at<double>(pl.o_big);
+        double* f2 = f1 + 6LL * (pr.mx + 1) * (2 * pr.ny - 1) * (2 * pr.nz - 1);
+        if (pl.prec == SSM_FP64)
+            e = launch_spectrum<double>(pr, c->at<double>(pl.o_nh) + pr.nh_off, f1, f2,
+                                        c->at<double>(pl.o_tw64), c->stream);
+        else
+            e = launch_spectrum<float>(pr, c->at<float>(pl.o_nh) + pr.nh_off, f1, f2,
+                                       c->at<double>(pl.o_tw64), c->stream);
+        if (e != hipSuccess) { return hipfail(c, e, "kernel spectrum"); }
+        // scratch reuse by the next shape needs this one finished
+        e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) { return hipfail(c, e, "kernel spectrum"); }
+    }
+    return SSM_OK;
+}
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1021,39 +1064,9 @@ ssm_status ssm_create(const ssm_problem* p, int32_t n_problems, int32_t precisio
         c->err = "hipStreamCreateWithFlags failed";
         return bail(SSM_EHIP);
     }
+    if ((st = setup_tables(c)) != SSM_OK) return bail(st);
     const Plan& pl = c->pl;
-    std::vector<double> tw64;
-    twiddles(tw64);
-    std::vector<unsigned char> twt(2 * pl.tsize * kTwM);
-    if (pl.tsize == 8) {
-        std::memcpy(twt.data(), tw64.data(), twt.size());
-    } else {
-        float* f = reinterpret_cast<float*>(twt.data());
-        for (int i = 0; i < 2 * kTwM; ++i) f[i] = (float)tw64[i];
-    }
-    hipError_t e = hipMemcpyAsync(c->ws + pl.o_tw, twt.data(), twt.size(), hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(c->ws + pl.o_tw64, tw64.data(), 16 * kTwM, hipMemcpyHostToDevice, c->stream);
-    if (e != hipSuccess) { hipfail(c, e, "upload twiddles"); return bail(SSM_EHIP); }
-    if ((st = upload_plan(c)) != SSM_OK) return bail(st);
-    // dipole-kernel spectrum of every distinct shape (FP64, then stored as T)
-    for (size_t g = 0; g < pl.shapes.size(); ++g) {
-        int i = 0;
-        while (pl.geo[i] != (int)g) ++i;
-        const Prob& pr = pl.P[i];
-        double* f1 = c->at<double>(pl.o_big);
-        double* f2 = f1 + 6LL * (pr.mx + 1) * (2 * pr.ny - 1) * (2 * pr.nz - 1);
-        if (pl.prec == SSM_FP64)
-            e = launch_spectrum<double>(pr, c->at<double>(pl.o_nh) + pr.nh_off, f1, f2,
-                                        c->at<double>(pl.o_tw64), c->stream);
-        else
-            e = launch_spectrum<float>(pr, c->at<float>(pl.o_nh) + pr.nh_off, f1, f2,
-                                       c->at<double>(pl.o_tw64), c->stream);
-        if (e != hipSuccess) { hipfail(c, e, "kernel spectrum"); return bail(SSM_EHIP); }
-        // scratch reuse by the next shape needs this one finished
-        e = hipStreamSynchronize(c->stream);
-        if (e != hipSuccess) { hipfail(c, e, "kernel spectrum"); return bail(SSM_EHIP); }
-    }
+    hipError_t e;
     e = launch_fill_int(c->at<int>(pl.o_done), pl.np, 0, c->stream);
     if (e == hipSuccess) e = launch_fill_int(c->at<int>(pl.o_iters), pl.np, 0, c->stream);
     if (e == hipSuccess) e = launch_fill_int(c->at<int>(pl.o_skip), pl.np, 0, c->stream);
@@ -1085,6 +1098,7 @@ ssm_status ssm_set_params(ssm_ctx* ctx, int32_t problem, double J, double d, dou
         return fail(ctx, SSM_EINVAL, "non-finite parameter");
     Prob& p = ctx->pl.P[problem];
     p.J = J; p.d = d; p.ku = ku; p.D = dip;
+    ctx->have_eval = false;  // energies and fields depend on the parameters
     HIPCHK(ctx, hipMemcpyAsync(ctx->ws + ctx->pl.o_P + sizeof(Prob) * problem, &p, sizeof(Prob),
                                hipMemcpyHostToDevice, ctx->stream), "set params");
     // the source must stay valid until the copy has run
@@ -1159,9 +1173,8 @@ ssm_status ssm_llg(ssm_ctx* ctx, double t_total, double alpha)
     if (!(t_total > 0.0) || !std::isfinite(t_total) || !(alpha >= 0.0) || !std::isfinite(alpha))
         return fail(c, SSM_EINVAL, "t_total > 0 and alpha >= 0 (finite) required");
     HIPCHK(c, launch_fill_int(c->at<int>(pl.o_done), pl.np, 0, c->stream), "llg");
-    ssm_status st = pl.prec == SSM_FP64 ? Ops<double>::llg(c, t_total, alpha) : Ops<float>::llg(c, t_total, alpha);
-    if (st != SSM_OK) return st;
-    return run_eval_current(c);
+    c->have_eval = false;
+    return pl.prec == SSM_FP64 ? Ops<double>::llg(c, t_total, alpha) : Ops<float>::llg(c, t_total, alpha);
 }
 
 ssm_status ssm_get_rk_stats(ssm_ctx* ctx, int32_t* d_counts, double* d_dt, int64_t* h_evals)
@@ -1205,6 +1218,15 @@ static ssm_status run_eval_current(ssm_ctx* c)
     return SSM_OK;
 }
 
+// The getters' view of the current string: evaluated on first use after the
+// string or the parameters changed (enqueued on the context's stream).
+static ssm_status ensure_eval(ssm_ctx* c)
+{
+    if (c->have_eval) return SSM_OK;
+    if (!c->have_string) return fail(c, SSM_ESTATE, "no string set");
+    return run_eval_current(c);
+}
+
 ssm_status ssm_iterate(ssm_ctx* ctx, int32_t max_iter, double tau, double tol_force,
                        int32_t* d_iters_done)
 {
@@ -1240,6 +1262,7 @@ ssm_status ssm_iterate(ssm_ctx* ctx, int32_t max_iter, double tau, double tol_fo
         if (it >= max_iter) break;
         int n = max_iter - it;
         if (check) n = std::min(n, c->check_every - it % c->check_every);
+        c->have_eval = false;  // the string changes from here on
         if (c->rk_method == SSM_STEP_DOPRI54) {
             for (int i = 0; i < n; ++i) {
                 ssm_status st = pl.prec == SSM_FP64 ? Ops<double>::rk_iteration(c, tau)
@@ -1264,8 +1287,7 @@ ssm_status ssm_iterate(ssm_ctx* ctx, int32_t max_iter, double tau, double tol_fo
         if (e != hipSuccess) return hipfail(c, e, "iteration");
         it += n;
     }
-    ssm_status st = run_eval_current(c);
-    if (st != SSM_OK) return st;
+    // the final string is evaluated when a getter first needs it
     if (d_iters_done)
         HIPCHK(c, launch_iters_out(pl.np, c->at<int>(pl.o_iters), nullptr, d_iters_done, c->stream),
                "iterate");
@@ -1305,7 +1327,8 @@ ssm_status ssm_eval(ssm_ctx* ctx, const void* d_spins, void* d_field_or_null, do
 ssm_status ssm_get_energies(ssm_ctx* ctx, double* d_energy)
 {
     if (!ctx || !d_energy) return ctx ? fail(ctx, SSM_EINVAL, "d_energy is NULL") : SSM_EINVAL;
-    if (!ctx->have_eval) return fail(ctx, SSM_ESTATE, "no evaluation of the current string");
+    ssm_status st = ensure_eval(ctx);
+    if (st != SSM_OK) return st;
     HIPCHK(ctx, hipMemcpyAsync(d_energy, ctx->ws + ctx->pl.o_E, 8 * ctx->pl.n_img,
                                hipMemcpyDeviceToDevice, ctx->stream), "get energies");
     return SSM_OK;
@@ -1314,7 +1337,8 @@ ssm_status ssm_get_energies(ssm_ctx* ctx, double* d_energy)
 ssm_status ssm_get_fields(ssm_ctx* ctx, void* d_field)
 {
     if (!ctx || !d_field) return ctx ? fail(ctx, SSM_EINVAL, "d_field is NULL") : SSM_EINVAL;
-    if (!ctx->have_eval) return fail(ctx, SSM_ESTATE, "no evaluation of the current string");
+    ssm_status st = ensure_eval(ctx);
+    if (st != SSM_OK) return st;
     HIPCHK(ctx, hipMemcpyAsync(d_field, ctx->ws + ctx->pl.o_h, ctx->pl.tsize * ctx->pl.n_spin,
                                hipMemcpyDeviceToDevice, ctx->stream), "get fields");
     return SSM_OK;
@@ -1323,7 +1347,8 @@ ssm_status ssm_get_fields(ssm_ctx* ctx, void* d_field)
 ssm_status ssm_get_tangents(ssm_ctx* ctx, void* d_tangent, double* d_force_norm_or_null)
 {
     if (!ctx) return SSM_EINVAL;
-    if (!ctx->have_eval) return fail(ctx, SSM_ESTATE, "no evaluation of the current string");
+    ssm_status st = ensure_eval(ctx);
+    if (st != SSM_OK) return st;
     hipError_t e;
     if (ctx->pl.prec == SSM_FP64)
         e = Ops<double>::tangents(ctx, ctx->stream, (double*)d_tangent, d_force_norm_or_null, 0.0);
@@ -1336,7 +1361,8 @@ ssm_status ssm_get_tangents(ssm_ctx* ctx, void* d_tangent, double* d_force_norm_
 ssm_status ssm_get_barrier(ssm_ctx* ctx, double* d_out)
 {
     if (!ctx || !d_out) return ctx ? fail(ctx, SSM_EINVAL, "d_out is NULL") : SSM_EINVAL;
-    if (!ctx->have_eval) return fail(ctx, SSM_ESTATE, "no evaluation of the current string");
+    ssm_status st = ensure_eval(ctx);
+    if (st != SSM_OK) return st;
     HIPCHK(ctx, launch_barrier(ctx->P(), ctx->pl.np, ctx->at<double>(ctx->pl.o_E),
                                ctx->at<double>(ctx->pl.o_T), d_out, ctx->stream), "barrier");
     return SSM_OK;

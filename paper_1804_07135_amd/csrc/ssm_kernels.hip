@@ -1461,7 +1461,9 @@ __global__ __launch_bounds__(kNT) void k_tan2(const Prob* __restrict__ P, int np
             const double fc = f[c] - sh * v[c] - cf * tc[c];
             n2 += fc * fc;
         }
-        fm = sqrt(n2);
+        // a non-finite force counts as infinitely large, so that a diverged
+        // problem can never pass the convergence test (fmax would drop NaN)
+        fm = isfinite(n2) ? sqrt(n2) : (double)INFINITY;
         if (t_out) {
             T* to = t_out + p.s_off + (long long)k * M;
 #pragma unroll

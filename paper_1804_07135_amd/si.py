@@ -112,7 +112,9 @@ def phase_diagram(d_meV, k_meV, process="bloch", m=PAPER, n=112, K=60, R=10.0, a
     tuned on this context first (results then depend on the tiles only
     through the order of floating-point sums).
     Returns dict(barrier[len(d), len(k)] in meV, argmax, dB_dd and dB_dk (the
-    envelope-theorem derivatives, meV per meV), iters, force, context)."""
+    envelope-theorem derivatives, meV per meV; NaN where the path did not
+    converge), converged (final perpendicular-force norm finite and below
+    tol_force), iters, force, flags (ssm_check bits of the run), context)."""
     from . import ssm
     if precision is None:
         precision = ssm.SSM_FP32_MIXED
@@ -133,9 +135,14 @@ def phase_diagram(d_meV, k_meV, process="bloch", m=PAPER, n=112, K=60, R=10.0, a
     it = sm.iterate(iters, tau, tol_force).cpu().numpy()
     bar = sm.barrier().cpu().numpy()
     _, fn = sm.tangents()
+    force = fn.cpu().numpy()
+    flags = sm.check()
+    from .sweep import converged_mask, mask_unconverged
+    conv = converged_mask(force, tol_force) & np.isfinite(bar[:, 0])
+    dB = mask_unconverged(bar[:, 2:6], conv)
     shape = dd.shape
     # barrier derivatives: dB/d(d_red) * d(d_red)/d(d_meV) with d_red = d/J,
     # and B in meV = B_red * J, so dB_meV/dd_meV = dB_red/dd_red
     return dict(barrier=energy_meV(bar[:, 0]).reshape(shape), argmax=bar[:, 1].astype(int).reshape(shape),
-                dB_dd=bar[:, 3].reshape(shape), dB_dk=bar[:, 4].reshape(shape), iters=it.reshape(shape),
-                force=fn.cpu().numpy().reshape(shape), context=sm)
+                dB_dd=dB[:, 1].reshape(shape), dB_dk=dB[:, 2].reshape(shape), converged=conv.reshape(shape),
+                iters=it.reshape(shape), force=force.reshape(shape), flags=flags, context=sm)

@@ -26,18 +26,19 @@ def test_algorithmic_bytes_of_the_tube_workload():
     assert ab["k_conv"] == 2 * xspec + nhat == 1263206400
     assert ab["k_xinv"] == xspec + 2 * spins
     assert ab["k_arc"] == spins
-    # interpolation: 2 sources per interior image, 1 per endpoint, plus the write
-    assert ab["k_interp"] == pytest.approx(spins * (2 * 46 + 2) / 48 + spins)
+    # interpolation: every source image read once (consecutive targets
+    # share their sources) and every image written once
+    assert ab["k_interp"] == 2 * spins
 
 
-def test_convolution_flop_count():
-    P = 512 * 512 * 16
-    expect = 48 * (6 * 2.5 * P * (9 + 4) + 30 * 257 * 512 * 16)
-    assert bench.conv_algorithmic_flops(TUBE) == expect == 42290380800.0
-    # a monolayer has no z transform: Pz = 1 adds nothing to the log
-    mono = dict(TUBE, nz=1)
-    P1 = 512 * 512
-    assert bench.conv_algorithmic_flops(mono) == 48 * (6 * 2.5 * P1 * 9 + 30 * 257 * 512)
+def test_roofline_is_hbm_with_executed_flop_alu_view():
+    """The headline roofline is the HBM one (algorithmic bytes over the
+    launch time against 8 TB/s); the vector-ALU view uses executed flops
+    from the counters against the non-packed FP32 ceiling (256 CUs x 4 SIMDs
+    x 16 lanes x 2 flops x 2.4 GHz)."""
+    assert bench.HBM_PEAK_GBS == 8000.0
+    assert abs(bench.FP32_VECTOR_NONPACKED_TFLOPS - 256 * 4 * 16 * 2 * 2.4e9 / 1e12) < 0.05
+    assert not hasattr(bench, "conv_algorithmic_flops")
 
 
 def test_bench_refuses_more_than_one_gpu():

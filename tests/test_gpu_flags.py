@@ -47,3 +47,40 @@ def test_nonfinite_spin_is_flagged(precision):
     flags = sm.check()
     assert flags & ssm.SSM_FLAG_NONFINITE_ENERGY
     assert sm.check() == 0
+
+
+@pytest.mark.parametrize("precision", [ssm.SSM_FP64, ssm.SSM_FP32_MIXED])
+def test_nonfinite_problem_never_counts_as_converged(precision):
+    """A point whose string holds a NaN spin has a non-finite force norm: with
+    tol_force > 0 it must not stop as converged, the flag must be raised,
+    and the sweep driver must report it unconverged with NaN envelope
+    derivatives, while a finite point of the same batch converges."""
+    from paper_1804_07135_amd import sweep
+    pts = [dict(nx=4, ny=3, nz=1, K=3, J=1.0, d=0.0, ku=0.2, D=0.0, R=1.0, seed=1),
+           dict(nx=6, ny=5, nz=1, K=4, J=1.0, d=0.2, ku=0.1, D=0.01, R=1.0, seed=2)]
+    fm = np.zeros((3, 3, 1, 3, 4))
+    fm[:, 2] = 1.0  # every image the +z ferromagnet: force exactly 0
+    rng = np.random.default_rng(0)
+    bad = rng.standard_normal((4, 3, 1, 5, 6))
+    bad /= np.linalg.norm(bad, axis=1, keepdims=True)
+    bad[2, 0, 0, 2, 3] = np.nan
+    r = sweep.run_sweep(pts, precision=precision, max_iter=40, tau=0.1, tol_force=1e-6,
+                        check_every=10, graph_chunk=10, strings=[fm, bad])
+    assert r["flags"] & ssm.SSM_FLAG_NONFINITE_ENERGY
+    assert np.isinf(r["force"][1]) and not r["converged"][1]
+    assert int(r["iters"][1]) == 40
+    assert np.all(np.isnan(r["dB"][1]))
+    assert r["converged"][0] and int(r["iters"][0]) == 0
+    assert np.all(np.isfinite(r["dB"][0]))
+
+
+def test_fixed_iteration_sweep_reports_no_convergence():
+    """tol_force = 0 (a fixed number of iterations) proves nothing about
+    convergence: every point is reported unconverged, its envelope
+    derivatives NaN."""
+    from paper_1804_07135_amd import sweep
+    pts = [dict(nx=8, ny=8, nz=1, K=4, J=1.0, d=0.3, ku=0.1, D=0.01, R=2.0, seed=3)]
+    r = sweep.run_sweep(pts, precision=ssm.SSM_FP64, max_iter=5, tol_force=0.0, check_every=5,
+                        graph_chunk=0)
+    assert not r["converged"][0]
+    assert np.all(np.isnan(r["dB"][0])) and np.isfinite(r["barrier"][0])
