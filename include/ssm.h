@@ -238,6 +238,32 @@ ssm_status ssm_get_rk_stats(ssm_ctx* ctx, int32_t* d_counts, double* d_dt, int64
 ssm_status ssm_eval(ssm_ctx* ctx, const void* d_spins, void* d_field_or_null,
                     double* d_energy, double* d_terms_or_null);
 
+/* Allocation-free evaluation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same field and energies as ssm_eval, for
+ * n_problems (1..16) problems in the batch layout above, with no context
+ * and no workspace.  Its scratch (descriptors, twiddles, the kernel spectra
+ * of eq. (7), x half-spectra, energy partials) is a fixed device array of
+ * SSM_NOALLOC_SCRATCH_MIB MiB inside the library, one per GPU, held until
+ * the process ends; the call makes no hipMalloc, hipFree or other allocating
+ * call.  d_spins (spin layout and dtype of the precision), d_energy
+ * (double[sum K]) and the optional d_field_or_null and d_terms_or_null are
+ * the caller's, as in ssm_eval.  Work is enqueued on `stream` (a
+ * hipStream_t as void*, NULL = default stream) on the current device.
+ * When the problem shapes, image counts or precision differ from the
+ * previous call on this device, the call first rebuilds the tables (kernel
+ * spectra) and synchronises the stream once; later calls with the same
+ * layout are asynchronous, whatever their parameters.  Calls on one device
+ * share its scratch: calls that overlap in time on that device (other
+ * streams, other host threads' work still running) race and give undefined
+ * results.  Returns SSM_EUNSUPPORTED if the problems need more scratch than
+ * the fixed size (ssm_workspace_size-sized contexts have no such limit) or
+ * n_problems is outside 1..16, SSM_EINVAL for bad arguments; errors are
+ * reported by ssm_last_error(NULL). */
+#define SSM_NOALLOC_SCRATCH_MIB 64
+ssm_status ssm_eval_noalloc(const ssm_problem* p, int32_t n_problems, int32_t precision, const void* d_spins,
+                            void* d_field_or_null, double* d_energy, double* d_terms_or_null, void* stream);
+
 /* Energies of the current string (double[sum K]).  Every getter below
  * returns the evaluation of the current string and parameters: if the
  * string or a parameter changed since the last evaluation, the getter first

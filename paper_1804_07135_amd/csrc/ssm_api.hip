@@ -10,6 +10,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <tuple>
@@ -1003,6 +1004,86 @@ static ssm_status setup_tables(ssm_ctx* c)
     return SSM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Evaluation without any device allocation (ssm_eval_noalloc).  Its scratch
+// (descriptors, twiddles, kernel spectra, x half-spectra, energy partials,
+// flags) is one file-scope device array; every GPU the library runs on holds
+// its own copy until the process ends.  Host code never uses the array's
+// name as an address: the device address comes from hipGetSymbolAddress, once
+// per device, with that device current.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = size_t(SSM_NOALLOC_SCRATCH_MIB) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+constexpr int kStaticMaxProblems = 16;
+
+// Offsets of the evaluation's buffers packed into the static scratch (the
+// string buffers of a context are the caller's inputs and outputs here).
+void carve_static(Plan& pl)
+{
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = up(o + std::max<size_t>(bytes, 1)); return r; };
+    const size_t ts = pl.tsize, cs = 2 * ts;
+    int my_max = 1;
+    for (const Prob& q : pl.P) my_max = std::max(my_max, q.my);
+    // buffers the evaluation never touches share offset 0
+    pl.o_s = pl.o_ss = pl.o_h = pl.o_ap = pl.o_fp = pl.o_E = pl.o_T = pl.o_alpha = pl.o_w = pl.o_tc = 0;
+    pl.o_fn = pl.o_fm = pl.o_j = pl.o_done = pl.o_iters = pl.o_skip = pl.o_seg = pl.o_cnt = 0;
+    pl.o_s2 = pl.o_kci = pl.o_splok = pl.o_cic = 0;
+    pl.o_P = take(sizeof(Prob) * pl.np);
+    pl.o_wm = take(sizeof(int) * kNumMaps * (pl.np + 1));
+    pl.o_tw = take(cs * kTwM);
+    pl.o_tw64 = take(16 * kTwM);
+    pl.o_nh = take(ts * pl.n_nh);
+    pl.o_big = take(std::max((size_t)(2 * cs * pl.n_x + cs * my_max), pl.scratch_bytes));
+    pl.o_ep = take(8 * pl.n_ep);
+    pl.o_flags = take(4);
+    pl.total = o;
+}
+
+// Per device: the scratch's device address and the layout (problem shapes,
+// image counts, precision) whose tables it currently holds.
+struct StaticDev {
+    unsigned char* ptr = nullptr;
+    bool have_tables = false;
+    int prec = -1;
+    int np = 0;
+    int shape[kStaticMaxProblems][4] = {};
+    ssm_ctx ctx;  // host description of the layout (no workspace of its own)
+};
+StaticDev g_static[kMaxDevices];
+std::mutex g_static_mu;
+
+bool same_layout(const StaticDev& d, const ssm_problem* p, int np, int prec)
+{
+    if (!d.have_tables || d.prec != prec || d.np != np) return false;
+    for (int i = 0; i < np; ++i)
+        if (d.shape[i][0] != p[i].nx || d.shape[i][1] != p[i].ny || d.shape[i][2] != p[i].nz ||
+            d.shape[i][3] != p[i].n_images)
+            return false;
+    return true;
+}
+
+// Copy host bytes to device memory through kernel arguments (no host buffer
+// has to outlive the call).
+hipError_t put_bytes(void* dst, const void* src, size_t n, hipStream_t st)
+{
+    const unsigned char* b = static_cast<const unsigned char*>(src);
+    for (size_t o = 0; o < n; o += kBlobBytes) {
+        Blob blob;
+        blob.n = (int)std::min<size_t>(kBlobBytes, n - o);
+        std::memcpy(blob.b, b + o, blob.n);
+        hipError_t e = launch_put(static_cast<unsigned char*>(dst) + o, blob, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1416,6 +1497,82 @@ ssm_status ssm_autotune(ssm_ctx* ctx, const char* cache_path)
     if (!ctx) return SSM_EINVAL;
     if (!ctx->have_string) return fail(ctx, SSM_ESTATE, "no string set");
     return autotune(ctx, cache_path);
+}
+
+ssm_status ssm_eval_noalloc(const ssm_problem* p, int32_t n_problems, int32_t precision, const void* d_spins,
+                            void* d_field_or_null, double* d_energy, double* d_terms_or_null, void* stream)
+{
+    if (!p || !d_spins || !d_energy) return fail(nullptr, SSM_EINVAL, "p, d_spins and d_energy are required");
+    if (n_problems < 1 || n_problems > kStaticMaxProblems)
+        return fail(nullptr, SSM_EUNSUPPORTED, "ssm_eval_noalloc takes 1 to 16 problems");
+    if (precision != SSM_FP64 && precision != SSM_FP32_MIXED)
+        return fail(nullptr, SSM_EINVAL, "precision must be SSM_FP64 or SSM_FP32_MIXED");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(nullptr, SSM_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(nullptr, SSM_EUNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticDev& sd = g_static[dev];
+    ssm_ctx* c = &sd.ctx;
+    const hipStream_t st = (hipStream_t)stream;
+    if (!sd.ptr) {
+        // once per device, with that device current: the device address of
+        // this device's copy of the scratch array
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(nullptr, SSM_EHIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                                (e != hipSuccess ? hipGetErrorString(e) : "null address"));
+        sd.ptr = static_cast<unsigned char*>(ptr);
+    }
+    if (!same_layout(sd, p, n_problems, precision)) {
+        Plan pl;
+        std::string err;
+        ssm_status s = build_plan(p, n_problems, precision, nullptr, pl, err);
+        if (s != SSM_OK) return fail(nullptr, s, err);
+        carve_static(pl);
+        if (pl.total > kStaticScratchBytes)
+            return fail(nullptr, SSM_EUNSUPPORTED,
+                        "ssm_eval_noalloc: these problems need " + std::to_string(pl.total) +
+                            " bytes of scratch, more than its fixed " + std::to_string(kStaticScratchBytes));
+        sd.have_tables = false;
+        c->pl = pl;
+        c->probs.assign(p, p + n_problems);
+        c->ws = sd.ptr;
+        c->ws_bytes = kStaticScratchBytes;
+        c->stream = st;
+        c->err.clear();
+        s = setup_tables(c);
+        if (s != SSM_OK) return fail(nullptr, s, c->err);
+        sd.prec = precision;
+        sd.np = n_problems;
+        for (int i = 0; i < n_problems; ++i) {
+            sd.shape[i][0] = p[i].nx; sd.shape[i][1] = p[i].ny;
+            sd.shape[i][2] = p[i].nz; sd.shape[i][3] = p[i].n_images;
+        }
+        sd.have_tables = true;
+    }
+    c->stream = st;
+    // this call's parameters into the descriptors, then the evaluation
+    Plan& pl = c->pl;
+    for (int i = 0; i < n_problems; ++i) {
+        if (!std::isfinite(p[i].J) || !std::isfinite(p[i].d) || !std::isfinite(p[i].ku) || !std::isfinite(p[i].dip))
+            return fail(nullptr, SSM_EINVAL, "non-finite parameter");
+        pl.P[i].J = p[i].J; pl.P[i].d = p[i].d; pl.P[i].ku = p[i].ku; pl.P[i].D = p[i].dip;
+    }
+    e = put_bytes(sd.ptr + pl.o_P, pl.P.data(), sizeof(Prob) * pl.np, st);
+    // the flags must start at zero: the scratch keeps the last call's contents
+    if (e == hipSuccess) e = launch_fill_int(c->at<int>(pl.o_flags), 1, 0, st);
+    if (e == hipSuccess) {
+        if (pl.prec == SSM_FP64)
+            e = Ops<double>::eval(c, st, (const double*)d_spins, (double*)d_field_or_null, d_energy,
+                                  d_terms_or_null, false);
+        else
+            e = Ops<float>::eval(c, st, (const float*)d_spins, (float*)d_field_or_null, d_energy,
+                                 d_terms_or_null, false);
+    }
+    if (e != hipSuccess) return fail(nullptr, SSM_EHIP, std::string("ssm_eval_noalloc: ") + hipGetErrorString(e));
+    return SSM_OK;
 }
 
 }  // extern "C"

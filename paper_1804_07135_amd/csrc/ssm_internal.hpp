@@ -201,6 +201,14 @@ hipError_t launch_barrier(const Prob* P, int np, const double* E, const double* 
 hipError_t launch_iters_out(int np, const int* iters, const int* iters0, int* out,
                             hipStream_t st);
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t st);
+// up to kBlobBytes bytes copied to device memory by a kernel whose argument
+// carries them
+constexpr int kBlobBytes = 2048;
+struct Blob {
+    int n;
+    unsigned char b[kBlobBytes];
+};
+hipError_t launch_put(void* dst, const Blob& b, hipStream_t st);
 hipError_t launch_fill_double(double* p, int n, double v, hipStream_t st);
 
 // Adaptive Dormand-Prince 5(4) step 1.  Per image (batch-wide index g):

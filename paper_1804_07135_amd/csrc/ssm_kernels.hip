@@ -2348,6 +2348,20 @@ hipError_t launch_ci_step(const Prob* P, int np, const WorkMap& wm, const T* s, 
     return hipGetLastError();
 }
 
+// Copy of a small host blob passed by value as the kernel argument (the
+// launch itself carries the bytes, so the host copy needs no lifetime and the
+// call allocates nothing).
+__global__ void k_put(unsigned char* dst, Blob b)
+{
+    for (int i = threadIdx.x; i < b.n; i += blockDim.x) dst[i] = b.b[i];
+}
+
+hipError_t launch_put(void* dst, const Blob& b, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_put, dim3(1), dim3(256), 0, st, static_cast<unsigned char*>(dst), b);
+    return hipGetLastError();
+}
+
 __global__ void k_fill_double(double* p, int n, double v)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;

@@ -35,6 +35,7 @@ SSM_FLAG_NONFINITE_ENERGY = 1
 SSM_FLAG_ZERO_NORM_SPIN = 2
 SSM_FLAG_NONFINITE_SPIN = 4
 SSM_FLAG_RK_ERROR = 8
+SSM_NOALLOC_SCRATCH_MIB = 64
 FLAG_NONFINITE_ENERGY = 1
 FLAG_ZERO_NORM_SPIN = 2
 FLAG_NONFINITE_SPIN = 4
@@ -46,7 +47,7 @@ ABI_SYMBOLS = [
     "ssm_set_string", "ssm_get_string", "ssm_iterate", "ssm_eval", "ssm_get_energies",
     "ssm_get_fields", "ssm_get_tangents", "ssm_get_barrier", "ssm_set_options", "ssm_autotune",
     "ssm_check", "ssm_last_error", "ssm_profile", "ssm_profile_read", "ssm_kernel_name",
-    "ssm_set_integrator", "ssm_get_rk_stats", "ssm_llg", "ssm_set_reparam",
+    "ssm_set_integrator", "ssm_get_rk_stats", "ssm_llg", "ssm_set_reparam", "ssm_eval_noalloc",
 ]
 
 
@@ -102,6 +103,7 @@ def load():
         "ssm_get_rk_stats": (_i32, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
         "ssm_llg": (_i32, [_vp, _dbl, _dbl]),
         "ssm_set_reparam": (_i32, [_vp, _i32, _i32]),
+        "ssm_eval_noalloc": (_i32, [ctypes.POINTER(ssm_problem), _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -197,6 +199,14 @@ def ssm_iterate(ctx, max_iter, tau, tol_force=0.0, iters_out=None):
 
 def ssm_eval(ctx, spins=None, field=None, energy=None, terms=None):
     _check(load().ssm_eval(ctx, _ptr(spins), _ptr(field), _ptr(energy), _ptr(terms)), ctx)
+
+
+def ssm_eval_noalloc(problems, precision, spins, field=None, energy=None, terms=None, stream=None):
+    """Field/energy evaluation through the library's fixed device scratch (no
+    context, no workspace, no device allocation)."""
+    arr = _problems(problems)
+    _check(load().ssm_eval_noalloc(arr, len(problems), int(precision), _ptr(spins), _ptr(field), _ptr(energy),
+                                   _ptr(terms), _stream_handle(stream)))
 
 
 def ssm_get_energies(ctx, out):
