@@ -273,10 +273,19 @@ def paper_shape_leg(ssm, torch, args):
     return res
 
 
+RDREQ = ("TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum")
+
+
 def summarize_profiles(args):
-    """Turn rocprofv3 outputs of the bench and of the copy probe into the
-    committed summaries: per-kernel durations, and HBM traffic of the
-    dominant kernel (FETCH_SIZE/WRITE_SIZE scaled by the copy calibration)."""
+    """Turn rocprofv3 outputs of the bench (and of the copy probe) into the
+    committed summaries: per-kernel durations, and HBM traffic per kernel.
+
+    Read bytes come from the L2-to-memory read requests by size (32, 64 and
+    128 bytes: TCC_EA0_RDREQ_{32B,64B,128B}), write bytes from WRITE_SIZE
+    (the write requests are 32 or 64 bytes).  The copy probe's passes, when
+    present, check both against a copy of known size; FETCH_SIZE, whose
+    formula takes 128-byte requests from TCC_BUBBLE, is reported beside the
+    request-size count for comparison."""
     import statistics
     d = args.summarize_profiles
     w = args.workload
@@ -286,43 +295,68 @@ def summarize_profiles(args):
             k = _kernel_key(r["Kernel_Name"])
             if k:
                 stats.setdefault(k, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
-    counters = {}
-    for sub in ("fetch", "write", "cfetch", "cwrite"):
+
+    def per_dispatch(sub):
+        """{kernel: {counter: [value per dispatch]}} of one pass."""
+        out = {}
         for r in _csv_rows(os.path.join(d, sub)):
             k = _kernel_key(r.get("Kernel_Name", ""))
             if k:
-                counters.setdefault((sub, k), []).append(float(r["Counter_Value"]))
-    probe_kib = args.copy_probe_mib * 1024 if args.copy_probe_mib else 1024 * 1024
-    f_cal = probe_kib / statistics.median(counters[("cfetch", "copyBuffer")])
-    w_cal = probe_kib / statistics.median(counters[("cwrite", "copyBuffer")])
+                out.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        return out
+
+    def read_bytes(pas, k):
+        c = pas.get(k, {})
+        if not all(n in c for n in RDREQ):
+            return None
+        return statistics.median([32 * a + 64 * b + 128 * e for a, b, e in zip(*(c[n] for n in RDREQ))])
+
+    def med(pas, k, name, scale=1.0):
+        c = pas.get(k, {})
+        return statistics.median(c[name]) * scale if name in c else None
+
+    rd, wr, fe = per_dispatch("rdreq"), per_dispatch("write"), per_dispatch("fetch")
+    check = {}
+    if args.copy_probe_mib:
+        nbytes = args.copy_probe_mib * (1 << 20)
+        crd, cwr, cfe = per_dispatch("crdreq"), per_dispatch("cwrite"), per_dispatch("cfetch")
+        check = {"copy_bytes": nbytes,
+                 "read_by_request_size_over_copy": (read_bytes(crd, "copyBuffer") or float("nan")) / nbytes,
+                 "write_size_over_copy": (med(cwr, "copyBuffer", "WRITE_SIZE", 1024) or float("nan")) / nbytes,
+                 "fetch_size_over_copy": (med(cfe, "copyBuffer", "FETCH_SIZE", 1024) or float("nan")) / nbytes}
     dom = max((k for k in stats if k.startswith("k_") and not k.startswith("k_spec")),
               key=lambda k: sum(stats[k]))
-    fetch = statistics.median(counters[("fetch", dom)]) * f_cal * 1024
-    write = statistics.median(counters[("write", dom)]) * w_cal * 1024
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    lines = [f"# Kernel durations: {w}, FP32-mixed form", "",
+    lines = [f"# Kernel durations and HBM traffic: {w}, FP32-mixed form", "",
              f"Command: `{args.profile_command}`", "",
              "| kernel | launches | avg ms | total ms |", "|---|---|---|---|"]
     for k, v in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
         lines.append(f"| {k} | {len(v)} | {statistics.mean(v):.4f} | {sum(v):.3f} |")
-    lines += ["", f"HBM traffic per launch (FETCH_SIZE x {f_cal:.3f}, WRITE_SIZE x {w_cal:.3f}; factors from a "
-              f"{probe_kib // 1024} MiB device copy read by the same counters), against the algorithmic bytes "
-              "the method must move:", "",
-              "| kernel | read MB | write MB | algorithmic MB |", "|---|---|---|---|"]
+    lines += ["", "HBM traffic per launch: reads = 32/64/128-byte L2-to-memory read requests "
+              "(TCC_EA0_RDREQ_32B/64B/128B) times their sizes, writes = WRITE_SIZE; FETCH_SIZE "
+              "(which counts 128-byte requests from TCC_BUBBLE) beside the reads for comparison; "
+              "algorithmic bytes = what the method must move:", "",
+              "| kernel | read MB | FETCH_SIZE MB | write MB | algorithmic MB |", "|---|---|---|---|---|"]
     ab = algorithmic_bytes(dict(__import__("paper_1804_07135_amd.inputs", fromlist=["WORKLOADS"]).WORKLOADS[w]), 4)
+    per_kernel = {}
     for k in sorted(stats, key=lambda k: -sum(stats[k])):
-        if ("fetch", k) in counters and ("write", k) in counters:
-            rd = statistics.median(counters[("fetch", k)]) * f_cal * 1024
-            wr = statistics.median(counters[("write", k)]) * w_cal * 1024
-            lines.append(f"| {k} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | "
-                         f"{(ab[k] / 1e6) if k in ab else float('nan'):.1f} |")
+        r_, w_, f_ = read_bytes(rd, k), med(wr, k, "WRITE_SIZE", 1024), med(fe, k, "FETCH_SIZE", 1024)
+        if r_ is not None and w_ is not None:
+            per_kernel[k] = {"read_bytes": r_, "write_bytes": w_, "avg_ms": statistics.mean(stats[k])}
+            if f_ is not None:
+                per_kernel[k]["fetch_size_bytes"] = f_
+        lines.append(f"| {k} | {(r_ or float('nan')) / 1e6:.1f} | {(f_ or float('nan')) / 1e6:.1f} | "
+                     f"{(w_ or float('nan')) / 1e6:.1f} | {(ab[k] / 1e6) if k in ab else float('nan'):.1f} |")
+    if check:
+        lines += ["", f"Counter check on a {args.copy_probe_mib} MiB device copy: reads by request size "
+                  f"{check['read_by_request_size_over_copy']:.4f} x the copied bytes, WRITE_SIZE "
+                  f"{check['write_size_over_copy']:.4f} x, FETCH_SIZE {check['fetch_size_over_copy']:.4f} x."]
     # instruction and stall counters, when those passes were collected
     sq = {}
     for sub in ("sqa", "sqb"):
-        for r in _csv_rows(os.path.join(d, sub)):
-            k = _kernel_key(r.get("Kernel_Name", ""))
-            if k:
-                sq.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        for k, cs in per_dispatch(sub).items():
+            for c, v in cs.items():
+                sq.setdefault(k, {})[c] = v
     if sq:
         names = sorted({c for v in sq.values() for c in v})
         lines += ["", "SQ counters per launch (medians; instruction counts are per wavefront):", "",
@@ -331,31 +365,27 @@ def summarize_profiles(args):
             if k.startswith("k_") and not k.startswith("k_spec"):
                 lines.append(f"| {k} | " + " | ".join(
                     f"{statistics.median(sq[k][c]):.3g}" if c in sq[k] else "" for c in names) + " |")
-    lines.append("")
-    with open(os.path.join(ROOT, "profiles", f"kernels_{w}_fp32.md"), "w") as fh:
-        fh.write("\n".join(lines))
-    # every kernel's traffic per launch and wavefront VALU instructions per
-    # launch, for the iteration-level fractions the bench line reports
-    per_kernel = {}
-    for k in stats:
-        if ("fetch", k) in counters and ("write", k) in counters:
-            per_kernel[k] = {"read_bytes": statistics.median(counters[("fetch", k)]) * f_cal * 1024,
-                             "write_bytes": statistics.median(counters[("write", k)]) * w_cal * 1024,
-                             "avg_ms": statistics.mean(stats[k])}
+        for k in per_kernel:
             if k in sq and "SQ_INSTS_VALU" in sq[k]:
                 per_kernel[k]["valu_wave_instructions"] = statistics.median(sq[k]["SQ_INSTS_VALU"])
             if k in sq and all(c in sq[k] for c in ("SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_ADD_F32",
                                                     "SQ_INSTS_VALU_MUL_F32")):
                 # executed FP32 flops: 64 lanes per wave instruction, 2 per FMA
-                med = {c: statistics.median(sq[k][c]) for c in sq[k]}
-                per_kernel[k]["fp32_flops"] = 64 * (2 * med["SQ_INSTS_VALU_FMA_F32"] + med["SQ_INSTS_VALU_ADD_F32"]
-                                                    + med["SQ_INSTS_VALU_MUL_F32"])
+                m = {c: statistics.median(sq[k][c]) for c in sq[k]}
+                per_kernel[k]["fp32_flops"] = 64 * (2 * m["SQ_INSTS_VALU_FMA_F32"] + m["SQ_INSTS_VALU_ADD_F32"]
+                                                    + m["SQ_INSTS_VALU_MUL_F32"])
+    lines.append("")
+    with open(os.path.join(ROOT, "profiles", f"kernels_{w}_fp32.md"), "w") as fh:
+        fh.write("\n".join(lines))
+    dk = per_kernel.get(dom, {})
     with open(os.path.join(ROOT, "profiles", f"traffic_{dom}_{w}_fp32.json"), "w") as fh:
-        json.dump({"kernel": dom, "workload": w, "bytes_per_launch": fetch + write, "read_bytes": fetch,
-                   "write_bytes": write, "fetch_calibration": f_cal, "write_calibration": w_cal,
-                   "kernels": per_kernel,
+        json.dump({"kernel": dom, "workload": w,
+                   "bytes_per_launch": dk.get("read_bytes", 0) + dk.get("write_bytes", 0),
+                   "read_bytes": dk.get("read_bytes"), "write_bytes": dk.get("write_bytes"),
+                   "counter_check": check, "kernels": per_kernel,
                    "kernel_source_hash": kernel_source_hash(), "command": args.profile_command}, fh, indent=1)
-    print(json.dumps({"dominant": dom, "read_MB": fetch / 1e6, "write_MB": write / 1e6}))
+    print(json.dumps({"dominant": dom, "read_MB": (dk.get("read_bytes") or 0) / 1e6,
+                      "write_MB": (dk.get("write_bytes") or 0) / 1e6, "check": check}))
 
 
 def main():
@@ -386,8 +416,9 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--summarize-profiles", default="",
-                    help="directory of rocprofv3 CSV outputs (trace/, fetch/, write/, cfetch/, cwrite/): "
-                         "write the kernel and traffic summaries into profiles/ and exit")
+                    help="directory of rocprofv3 CSV outputs (trace/, rdreq/, write/, fetch/, sqa/, sqb/ and the "
+                         "copy probe's crdreq/, cwrite/, cfetch/): write the kernel and traffic summaries into "
+                         "profiles/ and exit")
     ap.add_argument("--profile-command", default="", help="command line recorded in the summaries")
     args = ap.parse_args()
     if args.summarize_profiles:
