@@ -866,7 +866,9 @@ int oracle_reparam_opts(int K, int64_t N, const double* s_star, double* s_out, d
                     oracle_spline_eval(K, alpha_star, fv, K, tk, ov);
                     for (int kk = 0; kk < K; ++kk) v[kk][c] = ov[kk];
                 } else {
-                    for (int kk = 0; kk < K; ++kk) {
+                    /* interior targets only: the endpoints are copied, and
+                     * the last one's interval index is K-1 (no image K) */
+                    for (int kk = 1; kk < K - 1; ++kk) {
                         const double w = wts[kk];
                         v[kk][c] = (1.0 - w) * s_star[(int64_t)jidx[kk] * M + c * N + i] +
                                    w * s_star[(int64_t)(jidx[kk] + 1) * M + c * N + i];

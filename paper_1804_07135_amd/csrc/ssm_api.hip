@@ -1128,8 +1128,9 @@ ssm_status ssm_create(const ssm_problem* p, int32_t n_problems, int32_t precisio
     ssm_status st = build_plan(p, n_problems, precision, nullptr, c->pl, err);
     if (st != SSM_OK) { delete c; return fail(nullptr, st, err); }
     if (ws_bytes < c->pl.total) {
+        const size_t need = c->pl.total;
         delete c;
-        return fail(nullptr, SSM_EINVAL, "workspace too small: need " + std::to_string(c->pl.total));
+        return fail(nullptr, SSM_EINVAL, "workspace too small: need " + std::to_string(need));
     }
     c->probs.assign(p, p + n_problems);
     c->stream = (hipStream_t)stream;

@@ -157,3 +157,17 @@ def test_iterate_opts_composition(oracle):
     ss[km] = oracle.climb_step(s0[km - 1], s0[km], s0[km + 1], h[km], 0.1)
     expect = oracle.reparam_opts(ss, spline=True, kci=km)[0]
     np.testing.assert_array_equal(r["s"], expect)
+
+
+def test_many_images_linear_options_equal_plain_reparam(oracle):
+    """More images than the GPU path accepts (1500): the options routine
+    with linear interpolation and no climbing image equals the plain step 2
+    (buffers sized by the number of images)."""
+    rng = np.random.default_rng(21)
+    K = 1500
+    s = rng.standard_normal((K, 3, 1, 2, 2))
+    s /= np.linalg.norm(s, axis=1, keepdims=True)
+    a = oracle.reparam(s)
+    b = oracle.reparam_opts(s, spline=False, kci=-1)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
