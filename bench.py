@@ -244,6 +244,67 @@ def small_workloads_leg(ssm, torch, inputs, steps, chunk):
     return res
 
 
+def sweep_leg(ssm, torch, inputs, args):
+    """The (k_u, d) sweep: 64 points on lattices 48..96 (16 images each) in
+    one FP32-mixed context, tiles from the autotuner, iterations replayed as
+    HIP graphs, spline interpolation with the climbing image, run to a
+    perpendicular-force norm of args.sweep_tol (cap args.sweep_iters).
+    Reports which points converged, their barriers and envelope derivatives
+    (NaN where not converged), the rate over the iterations each point ran,
+    and the graph replay's time against the summed kernel time."""
+    import tempfile
+    import numpy as np
+    from paper_1804_07135_amd import sweep
+    pts = inputs.sweep_points()
+    chunk = 100
+    sm = ssm.StringMethod(sweep.sweep_problems(pts), ssm.SSM_FP32_MIXED)
+    sm.set_options(check_every=chunk, graph_chunk=chunk)
+    sm.set_reparam(ssm.SSM_INTERP_SPLINE, True)
+    s0 = sweep.initial_strings(pts)
+    sm.set_string(s0)
+    with tempfile.TemporaryDirectory() as td:
+        sm.autotune(os.path.join(td, "tiles.txt"))
+    sm.set_string(s0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it = sm.iterate(args.sweep_iters, 0.1, args.sweep_tol)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = it.cpu().numpy()
+    bar = sm.barrier().cpu().numpy()
+    _, fn = sm.tangents()
+    force = fn.cpu().numpy()
+    flags = sm.check()
+    conv = sweep.converged_mask(force, args.sweep_tol) & np.isfinite(bar[:, 0])
+    dB = sweep.mask_unconverged(bar[:, 2:6], conv)
+    kn = np.array([p["K"] * p["nx"] * p["ny"] * p["nz"] for p in pts], dtype=np.float64)
+    evals = float((iters * kn).sum())
+    # graph replay against the kernels' own time on this many-small-problem
+    # batch: the same 200 iterations replayed, then launched one by one with
+    # HIP events around every kernel
+    n = 200
+    sm.set_string(s0)
+    g = time_iterations(sm, n, 0.1) / n
+    sm.profile(True)
+    sm.profile_read()
+    sm.set_string(s0)
+    sm.iterate(n, 0.1)
+    kern = sum(v[0] for v in sm.profile_read().values()) / n * 1e-3
+    sm.profile(False)
+    res = {"points": len(pts), "images_per_point": 16, "tol_force": args.sweep_tol, "max_iter": args.sweep_iters,
+           "reparam": "spline + climbing image", "converged": int(conv.sum()), "seconds": dt,
+           "iterations_max": int(iters.max()), "iterations_mean": float(iters.mean()),
+           "site_field_evals_per_s": evals / dt, "flags": int(flags),
+           "graph_ms_per_iter": g * 1e3, "kernel_ms_per_iter": kern * 1e3, "graph_gap_frac": (g - kern) / g,
+           "per_point": [[int(p["nx"]), round(p["ku"], 4), round(p["d"], 4), bool(c), int(i), float(f),
+                          float(b), float(dd[2]), float(dd[1])]
+                         for p, c, i, f, b, dd in zip(pts, conv, iters, force, bar[:, 0], dB)],
+           "per_point_columns": ["L", "ku", "d", "converged", "iters", "force", "barrier", "dB_dku", "dB_dd"]}
+    del sm
+    torch.cuda.empty_cache()
+    return res
+
+
 def paper_shape_leg(ssm, torch, args):
     """The paper's production shape: a 112x112x1 monolayer, 60 images, with
     its material in SI units (d = 5.30 meV, k = 0.5 meV), FP32-mixed form,
@@ -409,6 +470,9 @@ def main():
     ap.add_argument("--rk-tol", type=float, default=1e-5)
     ap.add_argument("--full-run-iters", type=int, default=500,
                     help="iterations of the full-run barrier comparison of both forms (0: skip)")
+    ap.add_argument("--sweep-iters", type=int, default=20000,
+                    help="iteration cap of the 64-point sweep leg (0: skip)")
+    ap.add_argument("--sweep-tol", type=float, default=1e-4)
     ap.add_argument("--config-steps", type=int, default=200,
                     help="timed iterations of the small-workload rates (0: skip)")
     ap.add_argument("--autotune", action="store_true",
@@ -595,6 +659,8 @@ def main():
         out["full_run"] = full_run_leg(ssm, torch, prob, s0, args.full_run_iters, tau, args.graph_chunk)
     if args.config_steps > 0:
         out["small_workloads"] = small_workloads_leg(ssm, torch, inputs, args.config_steps, args.graph_chunk)
+    if args.sweep_iters > 0:
+        out["sweep_64_points"] = sweep_leg(ssm, torch, inputs, args)
     if args.paper_steps > 0:
         out["paper_shape_112x112x1_k60"] = paper_shape_leg(ssm, torch, args)
     if args.rk_iters > 0:
