@@ -40,15 +40,24 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def half_len(n, axis="x", nz=1):
+    """The documented half padded length of the x or y axis: the power of
+    two >= n, or for n > 32 the length 3 2^a >= n (a >= 4, at most 768) when
+    that is smaller and the power of two exceeds 512 (x) or 256 (y; or the
+    padded layer count m_z exceeds 8 for y)."""
+    p2 = 1 << (n - 1).bit_length()
+    mz = 1 if nz == 1 else 1 << (nz - 1).bit_length()
+    slow = p2 > 512 if axis == "x" else (p2 > 256 or mz > 8)
+    t = 48
+    while t < n:
+        t *= 2
+    return t if n > 32 and slow and t < p2 and t <= 768 else p2
+
+
 def algorithmic_bytes(w, ts):
     """Bytes each kernel must move per launch (one iteration), spin scalar size ts."""
     nx, ny, nz, K = w["nx"], w["ny"], w["nz"], w["K"]
-    mx = 1
-    while mx < nx:
-        mx *= 2
-    my = 1
-    while my < ny:
-        my *= 2
+    mx, my = half_len(nx, "x"), half_len(ny, "y", nz)
     pz = 1 if nz == 1 else 2 * (1 << (nz - 1).bit_length())
     N = nx * ny * nz
     spins = K * 3 * N * ts                         # one string

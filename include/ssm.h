@@ -54,10 +54,20 @@
  * at most 256 problems per context; every problem of a context has nz
  * values that round up to the same power of two; the convolution's
  * twiddles and one (y, z) plane of x-spectra, (2 + 3 * nz) * m_y complex
- * values with m_y the power of two >= ny, fit in 160 KiB of LDS, i.e.
- * m_y * (2 + 3 * nz) <= 10240 for SSM_FP64 and <= 20480 for SSM_FP32_MIXED
- * (m_y = 1024: nz <= 2 and <= 6; m_y = 512: nz <= 6 and <= 12; m_y = 256:
- * nz <= 12 and any nz).  Exceeding a limit returns SSM_EUNSUPPORTED.
+ * values with m_y the half padded y length (below), fit in 160 KiB of LDS,
+ * i.e. m_y * (2 + 3 * nz) <= 10240 for SSM_FP64 and <= 20480 for
+ * SSM_FP32_MIXED (m_y = 1024: nz <= 2 and <= 6; m_y = 512: nz <= 6 and
+ * <= 12; m_y = 256: nz <= 12 and any nz).  Exceeding a limit returns
+ * SSM_EUNSUPPORTED.
+ *
+ * Padding.  The dipolar convolution runs on a zero-padded grid of 2 m_x by
+ * 2 m_y by (2 m_z, or 1 for nz = 1) sites; any padded length >= 2n - 1 per
+ * axis gives the same field (Sec. II.A: circular sorting).  m_z is the
+ * power of two >= nz; m_x and m_y are the power of two >= n or, for n > 32,
+ * the length 3 * 2^a >= n (a >= 4, at most 768) when that is smaller and
+ * the power of two exceeds 512 (x) or 256 (y; or m_z > 8 for y), e.g.
+ * m_x = 768 for nx = 513..768 and m_y = 96 for ny = 65..96 with 9..16
+ * layers.
  */
 #ifndef SSM_H
 #define SSM_H

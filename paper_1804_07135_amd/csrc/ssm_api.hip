@@ -47,6 +47,29 @@ int ilog2(int m)
 
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// Half padded transform length m >= n of an x or y axis.  Any padded
+// length 2m >= 2n - 1 gives the same zero-padded convolution, so this only
+// chooses the cheaper transform: the power of two >= n, or the length
+// 3 2^a >= n (a >= 4, m <= 768) when that is smaller and the power of two
+// would not take the compile-time-length transforms either (x: above 512;
+// y: above 256, or more than 8 padded layers), which run faster than the
+// runtime-length ones that 3 2^a takes.  lg = log2 of the power-of-two
+// factor, f3 = 1 for 3 2^a.
+#ifndef SSM_LEN3
+#define SSM_LEN3 1
+#endif
+void transform_len(int n, bool pow2_fast, int& m, int& lg, int& f3)
+{
+    m = pow2ceil(n);
+    lg = ilog2(m);
+    f3 = 0;
+    if (SSM_LEN3 && n > 32 && !pow2_fast) {
+        int t = 48, a = 4;
+        while (t < n) { t *= 2; ++a; }
+        if (t < m && t <= 768) { m = t; lg = a; f3 = 1; }
+    }
+}
+
 struct Tiles {
     int ytf;    // rows per tile, forward x kernel
     int yt;     // rows per tile, inverse x kernel + epilogue
@@ -88,24 +111,24 @@ struct Plan {
 size_t lds_xfwd(const Prob& p, int yt, size_t tsize)
 {
     const int n = yt * p.mx;
-    const int lines = x_padl(p.lmx) ? padded_len(n, x_padl(p.lmx)) : lds_padded_size(n);
+    const int pl = x_padl(p.lmx, p.f3x);
+    const int lines = pl ? padded_len(n, pl) : lds_padded_size(n);
     return (size_t)(2 * p.mx + lines) * 2 * tsize;
 }
 
 size_t lds_xinv(const Prob& p, int yt, size_t tsize)
 {
     const int n = yt * p.mx;
-    const int lines = x_padl(p.lmx) ? padded_len(n, x_padl(p.lmx)) : lds_padded_size(n);
+    const int pl = x_padl(p.lmx, p.f3x);
+    const int lines = pl ? padded_len(n, pl) : lds_padded_size(n);
     return (size_t)(2 * p.mx + lines) * 2 * tsize + (size_t)3 * yt * p.nx * tsize;
 }
 
 size_t lds_convg(const Prob& p, int G, size_t tsize)
 {
     const int n = G * 3 * p.nz * p.my;
-    if (conv_ct_shape(p.mz, p.lmy)) {
-        const int tw = conv_tw_lds(p.mz, p.lmy) ? 2 * p.my : 0;
-        return (size_t)(tw + padded_len(n, conv_padl(p.mz, p.lmy))) * 2 * tsize;
-    }
+    if (conv_ct_shape(p.mz, p.lmy, p.f3y))
+        return (size_t)(2 * p.my + padded_len(n, conv_padl(p.mz, p.lmy, p.f3y))) * 2 * tsize;
     return (size_t)(2 * p.my + lds_padded_size(n)) * 2 * tsize;
 }
 
@@ -148,9 +171,10 @@ ssm_status check_problems(const ssm_problem* pr, int np, int prec, std::string& 
 // [img][kx][c][z][y] spectra.
 constexpr size_t kLdsTarget = 52 * 1024;
 
-// batch_rows: image rows (K nz ny) of every problem of the context, for the
-// occupancy of a launch covering them all
-Tiles default_tiles(const Prob& p, size_t tsize, long long batch_rows)
+// batch_rows: image rows (K nz ny), batch_slices: convolution slices
+// (K (m_x + 1)) of every problem of the context, for the occupancy of a
+// launch covering them all
+Tiles default_tiles(const Prob& p, size_t tsize, long long batch_rows, long long batch_slices)
 {
     Tiles t;
     const int cs = (int)(2 * tsize);
@@ -171,8 +195,10 @@ Tiles default_tiles(const Prob& p, size_t tsize, long long batch_rows)
     const int per = 3 * p.nz * p.ny;
     int gmax = std::max(1, kConvElems / per);
     while (gmax > 1 && lds_convg(p, gmax, tsize) > kLdsTarget) --gmax;
-    const long long slices = (long long)p.K * (p.mx + 1);
-    t.gconv = (int)std::max<long long>(1, std::min<long long>(gmax, slices / 1024));
+    // as many slices per workgroup as keep about 1024 workgroups in a
+    // launch over the whole batch (small lattices: several wavefronts' line
+    // groups per workgroup)
+    t.gconv = (int)std::max<long long>(1, std::min<long long>(gmax, batch_slices / 1024));
     return t;
 }
 
@@ -216,20 +242,26 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
     pl.geo.resize(np);
     std::map<std::tuple<int, int, int>, int> shape_id;
     long long img = 0, spin = 0, xo = 0, ep = 0, ap = 0, fp = 0, fm = 0;
-    long long batch_rows = 0;
-    for (int i = 0; i < np; ++i) batch_rows += (long long)pr[i].n_images * pr[i].nz * pr[i].ny;
+    long long batch_rows = 0, batch_slices = 0;
+    for (int i = 0; i < np; ++i) {
+        batch_rows += (long long)pr[i].n_images * pr[i].nz * pr[i].ny;
+        int mx, lg, f3;
+        transform_len(pr[i].nx, x_ct_len(ilog2(pow2ceil(pr[i].nx)), 0), mx, lg, f3);
+        batch_slices += (long long)pr[i].n_images * (mx + 1);
+    }
     for (int i = 0; i < np; ++i) {
         const ssm_problem& q = pr[i];
         Prob& p = pl.P[i];
         std::memset(&p, 0, sizeof(p));
         p.nx = q.nx; p.ny = q.ny; p.nz = q.nz; p.K = q.n_images;
-        p.mx = pow2ceil(q.nx); p.my = pow2ceil(q.ny);
         p.mz = q.nz > 1 ? pow2ceil(q.nz) : 1;
-        p.lmx = ilog2(p.mx); p.lmy = ilog2(p.my); p.lmz = ilog2(p.mz);
+        p.lmz = ilog2(p.mz);
+        transform_len(q.nx, x_ct_len(ilog2(pow2ceil(q.nx)), 0), p.mx, p.lmx, p.f3x);
+        transform_len(q.ny, conv_ct_shape(p.mz, ilog2(pow2ceil(q.ny)), 0), p.my, p.lmy, p.f3y);
         p.pz = q.nz > 1 ? 2 * p.mz : 1;
         p.nhz = q.nz > 1 ? 2 : 1;
         p.N = (long long)q.nx * q.ny * q.nz;
-        const Tiles t = tiles ? (*tiles)[i] : default_tiles(p, pl.tsize, batch_rows);
+        const Tiles t = tiles ? (*tiles)[i] : default_tiles(p, pl.tsize, batch_rows, batch_slices);
         apply_tiles(p, t);
         pl.tiles.push_back(t);
         if (lds_xfwd(p, p.ytf, pl.tsize) > kLdsMax || lds_xinv(p, p.yt, pl.tsize) > kLdsMax ||
@@ -285,7 +317,7 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
             pl.geo[i] = it->second;
         }
         pl.mz = p.mz;
-        pl.conv_kinds |= 1 << conv_build(p.mz, p.lmy);
+        pl.conv_kinds |= 1 << conv_build(p.mz, p.lmy, p.f3y);
         pl.lds_xf = std::max(pl.lds_xf, lds_xfwd(p, p.ytf, pl.tsize));
         pl.lds_xi = std::max(pl.lds_xi, lds_xinv(p, p.yt, pl.tsize));
         pl.lds_conv = std::max(pl.lds_conv, lds_convg(p, p.gconv, pl.tsize));

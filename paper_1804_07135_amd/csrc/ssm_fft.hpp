@@ -142,9 +142,11 @@ __host__ __device__ __forceinline__ int lds_padded_size(int n) { return SSM_LDS_
 // One radix-R Stockham pass over a group of gl lines of length m = 2^lm
 // (line stride ls) starting at element off0 of buf (padded layout).
 // lns = log2 of the sub-transform length already done.  twl[e] =
-// exp(-2 pi i e / (2m)), e < 2m (conjugated for the inverse), so the pass
-// twiddle W_{Ns R}^{r k} is twl[(r k) << (lm+1-lns-lr)].
-template <typename V, int R, bool INV>
+// exp(-2 pi i e / (2 TST m)), e < 2 TST m (conjugated for the inverse), so
+// the pass twiddle W_{Ns R}^{r k} is twl[TST ((r k) << (lm+1-lns-lr))]
+// (TST = 3: the lines are the thirds of lines of length 3m, whose table
+// serves them).
+template <typename V, int R, bool INV, int TST = 1>
 struct Pass {
     static constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
     static constexpr int B = 16 / R;  // butterflies per lane
@@ -166,7 +168,7 @@ struct Pass {
                 for (int r = 0; r < R; ++r) v[b][r] = buf[lds_pad(i0 + r * q)];
                 if (lns > 0) {
 #pragma unroll
-                    for (int r = 1; r < R; ++r) v[b][r] = twm<INV>(v[b][r], twl[(r * k) << tsh]);
+                    for (int r = 1; r < R; ++r) v[b][r] = twm<INV>(v[b][r], twl[TST * ((r * k) << tsh)]);
                 }
                 dft_reg<V, R, INV>(v[b]);
             }
@@ -297,14 +299,15 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename V, int R, bool INV>
+template <typename V, int R, bool INV, int TST = 1>
 __device__ __forceinline__ void run_pass(V* buf, int off0, int ls, int lm, int lns, int gl,
                                          const V* twl, int lane)
 {
-    V v[Pass<V, R, INV>::B][R];
-    Pass<V, R, INV>::read(buf, off0, ls, lm, lns, gl, twl, lane, v);
+    using P = Pass<V, R, INV, TST>;
+    V v[P::B][R];
+    P::read(buf, off0, ls, lm, lns, gl, twl, lane, v);
     wave_sync();
-    Pass<V, R, INV>::write(buf, off0, ls, lm, lns, gl, lane, v);
+    P::write(buf, off0, ls, lm, lns, gl, lane, v);
     wave_sync();
 }
 
@@ -314,7 +317,7 @@ __device__ __forceinline__ void run_pass(V* buf, int off0, int ls, int lm, int l
 // exp(-2 pi i e/(2m)), e < 2m.  MAXB (2 or 3) caps the pass radix at 2^MAXB;
 // fewer pass kinds keep the register footprint of the caller small.  Call
 // between workgroup barriers.
-template <typename V, bool INV, int MAXB = 2>
+template <typename V, bool INV, int MAXB = 2, int TST = 1>
 __device__ __forceinline__ void fft_lines(V* buf, int nl, int ls, int lm, const V* twl)
 {
     if (lm == 0) return;
@@ -330,10 +333,10 @@ __device__ __forceinline__ void fft_lines(V* buf, int nl, int ls, int lm, const 
         int lns = 0, rem = lm;
         while (rem > 0) {
             const int bits = fft_next_bits(rem, MAXB);
-            if (bits == 4) run_pass<V, 16, INV>(buf, off0, ls, lm, lns, gl, twl, lane);
-            else if (bits == 3) run_pass<V, 8, INV>(buf, off0, ls, lm, lns, gl, twl, lane);
-            else if (bits == 2) run_pass<V, 4, INV>(buf, off0, ls, lm, lns, gl, twl, lane);
-            else run_pass<V, 2, INV>(buf, off0, ls, lm, lns, gl, twl, lane);
+            if (bits == 4) run_pass<V, 16, INV, TST>(buf, off0, ls, lm, lns, gl, twl, lane);
+            else if (bits == 3) run_pass<V, 8, INV, TST>(buf, off0, ls, lm, lns, gl, twl, lane);
+            else if (bits == 2) run_pass<V, 4, INV, TST>(buf, off0, ls, lm, lns, gl, twl, lane);
+            else run_pass<V, 2, INV, TST>(buf, off0, ls, lm, lns, gl, twl, lane);
             lns += bits;
             rem -= bits;
         }
@@ -384,6 +387,90 @@ __device__ __forceinline__ void fft_lines_ct(V* buf, int nl, const V* twl)
         constexpr int LPG = fft_group_lines(LM);
         for (int g0 = wave * LPG; g0 < nl; g0 += nw * LPG)
             fft_passes_ct_to<V, INV, LM, MAXB, 0, LM, PADL, 0>(buf, g0 << LM, min(LPG, nl - g0), twl, lane);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Lengths m = 3 M, M = 2^lm (padded lengths 2m = 3 2^(lm+1): any padded
+// length >= 2n - 1 gives the same convolution, and 3 2^a is often the
+// smaller one).  A line of length m is three sub-lines of length M,
+// sub-line r occupying positions [r M, (r + 1) M).
+//
+// Forward, decimation in frequency on natural-order input: for k < M the
+// inputs x[k], x[k + M], x[k + 2M] become
+//   y_r = sum_j x[k + j M] w^{j r} * W_m^{r k},  w = exp(-2 pi i / 3),
+// stored at r M + k; the length-M transform of sub-line r then holds
+// X[3 n + r] at position r M + n (output order permuted).
+// Inverse, decimation in time: sub-line r holds at position n the input of
+// frequency 3 n + r; after the length-M inverse transforms G_r of the
+// sub-lines, x[k + j M] = sum_r G_r[k] W_m^{-r k} w^{-r j} in natural order.
+// twl[e] = exp(-2 pi i e / (2m)), e < 2m, so W_m^{r k} = twl[2 r k].
+// ---------------------------------------------------------------------------
+// position of frequency q (forward output, inverse input) and its inverse
+__host__ __device__ __forceinline__ int perm3(int q, int lm)
+{
+    // q / 3 for 0 <= q < 98304 by a multiply and shift
+    const int d = (q * 43691) >> 17;
+    return ((q - 3 * d) << lm) + d;
+}
+__host__ __device__ __forceinline__ int unperm3(int pos, int lm)
+{
+    return 3 * (pos & ((1 << lm) - 1)) + (pos >> lm);
+}
+
+template <bool INV, typename V>
+__host__ __device__ __forceinline__ void radix3_bfly(V& a, V& b, V& c, V w1, V w2)
+{
+    using S = decltype(V::x);
+    const S h = S(0.5), s3 = S(0.86602540378443864676);  // sqrt(3)/2
+    if (INV) {
+        b = cmulc(b, w1);
+        c = cmulc(c, w2);
+    }
+    const V t1 = cadd(b, c), t2 = csub(b, c);
+    const V m1 = mk<V>(a.x - h * t1.x, a.y - h * t1.y);
+    // -i s3 t2 (forward), +i s3 t2 (inverse)
+    const V rot = INV ? mk<V>(-s3 * t2.y, s3 * t2.x) : mk<V>(s3 * t2.y, -s3 * t2.x);
+    a = cadd(a, t1);
+    b = cadd(m1, rot);
+    c = csub(m1, rot);
+    if (!INV) {
+        b = cmul(b, w1);
+        c = cmul(c, w2);
+    }
+}
+
+// The radix-3 step over nl lines of length 3M (stride ls) by all threads of
+// the workgroup; in place, each butterfly on its own three elements.
+template <typename V, bool INV>
+__device__ __forceinline__ void radix3_step(V* buf, int nl, int ls, int lm, const V* twl)
+{
+    const int M = 1 << lm;
+    for (int i = threadIdx.x; i < (nl << lm); i += blockDim.x) {
+        const int line = i >> lm, k = i & (M - 1);
+        const int i0 = line * ls + k;
+        V a = buf[lds_pad(i0)], b = buf[lds_pad(i0 + M)], c = buf[lds_pad(i0 + 2 * M)];
+        radix3_bfly<INV>(a, b, c, twl[2 * k], twl[4 * k]);
+        buf[lds_pad(i0)] = a;
+        buf[lds_pad(i0 + M)] = b;
+        buf[lds_pad(i0 + 2 * M)] = c;
+    }
+}
+
+// Transform of nl contiguous lines of length 3 2^lm (dense layout): forward
+// with permuted output, inverse from permuted input (see above).  Call
+// between workgroup barriers.
+template <typename V, bool INV, int MAXB = 2>
+__device__ __forceinline__ void fft_lines3(V* buf, int nl, int lm, const V* twl)
+{
+    if (!INV) {
+        radix3_step<V, false>(buf, nl, 3 << lm, lm, twl);
+        __syncthreads();
+    }
+    fft_lines<V, INV, MAXB, 3>(buf, 3 * nl, 1 << lm, lm, twl);
+    if (INV) {
+        __syncthreads();
+        radix3_step<V, true>(buf, nl, 3 << lm, lm, twl);
     }
 }
 

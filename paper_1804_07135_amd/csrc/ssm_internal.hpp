@@ -10,9 +10,9 @@
 namespace ssm {
 
 // Twiddle table: tw[e] = exp(-2 pi i e / kTwM).  A length-L root W_L^e is
-// tw[e * (kTwM / L)], so every transform length divides kTwM.
-constexpr int kTwLog = 11;
-constexpr int kTwM = 1 << kTwLog;
+// tw[e * (kTwM / L)]; every padded length 2m (m = 2^a <= 1024 or
+// m = 3 2^a <= 768) and every sub-length divides kTwM = 3 * 2^11.
+constexpr int kTwM = 3 << 11;
 constexpr int kMaxLogM = 10;   // half padded length m <= 1024, padded P = 2m <= 2048
 constexpr int kNT = 256;       // threads per workgroup for every kernel
 constexpr int kConvElems = 24 * kNT;  // complex values per convolution workgroup (slice batching cap)
@@ -27,13 +27,16 @@ constexpr int kNTerm = 5;      // energy partial slots: E, T_J, T_d, T_ku, T_dip
 #ifndef SSM_CONV_CT
 #define SSM_CONV_CT 1
 #endif
-__host__ __device__ constexpr bool conv_ct_shape(int mz, int lmy)
+__host__ __device__ constexpr bool conv_ct_shape(int mz, int lmy, int f3y)
 {
-    return SSM_CONV_CT && mz <= 8 && lmy >= 5 && lmy <= 8;
+    return SSM_CONV_CT && !f3y && mz <= 8 && lmy >= 5 && lmy <= 8;
 }
 // build serving a problem: the y length's log2 (5..8) for the compile-time
-// builds, 0 for the runtime-length one
-__host__ __device__ constexpr int conv_build(int mz, int lmy) { return conv_ct_shape(mz, lmy) ? lmy : 0; }
+// builds, 0 for the runtime-length one (also every y length 3 2^a)
+__host__ __device__ constexpr int conv_build(int mz, int lmy, int f3y)
+{
+    return conv_ct_shape(mz, lmy, f3y) ? lmy : 0;
+}
 
 // LDS layout of the line buffers (pad_for, padx in ssm_fft.hpp).  The
 // compile-time-length transforms store lines with one pad element per
@@ -49,16 +52,14 @@ __host__ __device__ constexpr int conv_build(int mz, int lmy) { return conv_ct_s
 #ifndef SSM_CONV_PADL
 #define SSM_CONV_PADL 0
 #endif
-#ifndef SSM_CONV_TW_GLOBAL
-#define SSM_CONV_TW_GLOBAL 0
-#endif
-__host__ __device__ constexpr bool x_ct_len(int lm) { return SSM_X_CT && lm >= 5 && lm <= 9; }
-__host__ __device__ constexpr int x_padl(int lm) { return x_ct_len(lm) ? pad_for(SSM_X_PADL, lm) : 0; }
-__host__ __device__ constexpr int conv_padl(int mz, int lmy)
+// x lengths with compile-time passes: powers of two 32..512 (lm = log2 m;
+// lengths 3 2^lm take the runtime passes)
+__host__ __device__ constexpr bool x_ct_len(int lm, int f3) { return SSM_X_CT && !f3 && lm >= 5 && lm <= 9; }
+__host__ __device__ constexpr int x_padl(int lm, int f3) { return x_ct_len(lm, f3) ? pad_for(SSM_X_PADL, lm) : 0; }
+__host__ __device__ constexpr int conv_padl(int mz, int lmy, int f3y)
 {
-    return conv_ct_shape(mz, lmy) ? pad_for(SSM_CONV_PADL, lmy) : 0;
+    return conv_ct_shape(mz, lmy, f3y) ? pad_for(SSM_CONV_PADL, lmy) : 0;
 }
-__host__ __device__ constexpr bool conv_tw_lds(int mz, int lmy) { return !(conv_ct_shape(mz, lmy) && SSM_CONV_TW_GLOBAL); }
 // elements of a buffer of n elements in the pad-padl layout
 __host__ __device__ constexpr int padded_len(int n, int padl) { return padl ? n + (n >> padl) + 1 : n; }
 
@@ -71,8 +72,9 @@ enum KernelKind {
 // Per-problem descriptor, resident in device memory (read-only in kernels).
 struct Prob {
     int nx, ny, nz, K;
-    int mx, my, mz;        // half padded lengths: powers of two >= nx, ny, nz
-    int lmx, lmy, lmz;     // their log2
+    int mx, my, mz;        // half padded lengths >= nx, ny, nz: 2^a, or 3 2^a (a >= 4) along x and y
+    int lmx, lmy, lmz;     // log2 of their power-of-two factor
+    int f3x, f3y;          // 1: mx (my) = 3 2^lmx (3 2^lmy)
     int pz;                // padded z length: 2*mz when nz > 1, else 1
     int nhz;               // z halves of the padded z spectrum: 2 when nz > 1, else 1
     int yt;                // lattice rows per tile of the inverse-x / epilogue kernel

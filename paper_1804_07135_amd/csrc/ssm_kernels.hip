@@ -105,14 +105,28 @@ __device__ __forceinline__ int find_problem(const int* __restrict__ start, int n
 // w: workgroup index within the problem, n8: item count padded to 8.
 __device__ __forceinline__ int xcd_item(int w, int n8) { return (w & 7) * (n8 >> 3) + (w >> 3); }
 
-// Load exp(-2 pi i e/(2m)), e < 2m, into LDS.
+// Load exp(-2 pi i e/(2m)), e < 2m, into LDS; m = 2^lm, or 3 2^lm when f3.
 template <typename V>
-__device__ __forceinline__ void load_twiddles(V* twl, int lm, const V* __restrict__ tw)
+__device__ __forceinline__ void load_twiddles(V* twl, int lm, int f3, const V* __restrict__ tw)
 {
-    const int n = 2 << lm;
-    const int sh = kTwLog - 1 - lm;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) twl[e] = tw[e << sh];
+    const int n = (f3 ? 6 : 2) << lm;
+    const int stride = (f3 ? 1 : 3) << (10 - lm);  // kTwM / (2m)
+    for (int e = threadIdx.x; e < n; e += blockDim.x) twl[e] = tw[e * stride];
 }
+
+// q = i / L and r = i % L for a transform length L = 2^lg (f3 = 0) or
+// 3 2^lg (f3 = 1); i < 3 2^17
+__device__ __forceinline__ void divlen(int i, int lg, int f3, int& q, int& r)
+{
+    q = i >> lg;
+    if (f3) q = (q * 43691) >> 17;  // / 3
+    r = i - ((q * (f3 ? 3 : 1)) << lg);
+}
+
+// position in a transformed line of length m of x frequency q (within a
+// half transform): lengths 3 2^lm leave the forward transform's output and
+// take the inverse transform's input in the permuted order of fft_lines3
+__device__ __forceinline__ int fpos(int q, int lm, int f3) { return f3 ? perm3(q, lm) : q; }
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v)
@@ -134,8 +148,12 @@ __device__ __forceinline__ T wave_max(T v)
 // passes for lengths 32..512 (pad layout x_padl(lm)), runtime-length passes
 // (dense layout) otherwise.
 template <typename V, bool INV>
-__device__ __forceinline__ void fft_lines_x(V* lines, int nl, int lm, const V* twl)
+__device__ __forceinline__ void fft_lines_x(V* lines, int nl, int lm, int f3, const V* twl)
 {
+    if (f3) {
+        fft_lines3<V, INV, SSM_X_RADIX_BITS>(lines, nl, lm, twl);
+        return;
+    }
     switch (SSM_X_CT ? lm : 0) {
     case 5: fft_lines_ct<V, INV, 5, SSM_X_CT_RADIX_BITS, pad_for(SSM_X_PADL, 5)>(lines, nl, twl); break;
     case 6: fft_lines_ct<V, INV, 6, SSM_X_CT_RADIX_BITS, pad_for(SSM_X_PADL, 6)>(lines, nl, twl); break;
@@ -209,12 +227,12 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     if (t >= p.K * p.tilesf) return;
     const int ty = t % p.ntyf, rest = t / p.ntyf;
     const int z = rest % p.nz, img = rest / p.nz;
-    const int yt = p.ytf, hp = yt >> 1, nx = p.nx, ny = p.ny, nz = p.nz, m = p.mx, lm = p.lmx;
+    const int yt = p.ytf, hp = yt >> 1, nx = p.nx, ny = p.ny, nz = p.nz, m = p.mx, lm = p.lmx, f3 = p.f3x;
     const int lhp = __ffs(hp) - 1;  // tiles are powers of two
-    const int psh = x_padl(lm) ? x_padl(lm) : 31;  // pad layout of the lines
+    const int psh = x_padl(lm, f3) ? x_padl(lm, f3) : 31;  // pad layout of the lines
     V* twl = reinterpret_cast<V*>(smem_);
     V* lines = twl + 2 * m;
-    load_twiddles(twl, lm, tw);
+    load_twiddles(twl, lm, f3, tw);
     const long long N = p.N;
     const T* si = s + p.s_off + (long long)img * 3 * N + (long long)z * ny * nx;
     // the image's spectra as a uniform base and 32-bit byte offsets (they
@@ -230,10 +248,12 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     for (int c = 0; c < 3; ++c) {
         const T* sc = si + (long long)c * N;
         if (vecw) {
-            const int lmv = lm - LVW;
+            const int lmv = lm - LVW;  // a line is m / VW chunks of VW sites
 #pragma unroll 1
-            for (int idx = threadIdx.x; idx < (hp << lmv); idx += kNT) {
-                const int j = (idx & ((1 << lmv) - 1)) << LVW, rp = idx >> lmv;
+            for (int idx = threadIdx.x; idx < hp * (m >> LVW); idx += kNT) {
+                int rp, jc;
+                divlen(idx, lmv, f3, rp, jc);
+                const int j = jc << LVW;
                 const int ya = y0 + 2 * rp;
                 T av[VW], bv[VW];
                 load16<T>(sc + (long long)ya * nx + j, j < nx && ya < ny, av);
@@ -250,7 +270,8 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         // unrolled so that several loads are in flight per thread
 #pragma unroll 4
         for (int idx = threadIdx.x; idx < hp * m; idx += kNT) {
-            const int j = idx & (m - 1), rp = idx >> lm;
+            int rp, j;
+            divlen(idx, lm, f3, rp, j);
             const int ya = y0 + 2 * rp;
             T a = 0, b = 0;
             if (j < nx) {
@@ -264,12 +285,14 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         }
         }
         __syncthreads();
-        fft_lines_x<V, false>(lines, yt, lm, twl);
+        fft_lines_x<V, false>(lines, yt, lm, f3, twl);
         __syncthreads();
         for (int idx = threadIdx.x; idx < (m + 1) * hp; idx += kNT) {
             const int rp = idx & (hp - 1), kx = idx >> lhp;
-            const int kr = (P2 - kx) & (P2 - 1);
-            const int iz = (2 * rp + (kx & 1)) * m + (kx >> 1), ir = (2 * rp + (kr & 1)) * m + (kr >> 1);
+            const int kr = kx ? P2 - kx : 0;
+            // the two halves (even, odd frequencies) are separate lines
+            const int iz = (2 * rp + (kx & 1)) * m + fpos(kx >> 1, lm, f3);
+            const int ir = (2 * rp + (kr & 1)) * m + fpos(kr >> 1, lm, f3);
             const V Z = lines[iz + (iz >> psh)];
             const V Zr = lines[ir + (ir >> psh)];
             const T hlf = T(0.5);
@@ -312,15 +335,17 @@ template <bool INV, typename V, int MZ>
 __device__ __forceinline__ V twz(V v, int zz, const V* __restrict__ tw)
 {
     if (MZ <= 8) return twc16<INV>(v, zz * (8 / MZ));
-    const V w = tw[zz << (kTwLog - 1 - 4)];
+    const V w = tw[zz * (kTwM / 32)];
     return INV ? cmulc(v, w) : cmul(v, w);
 }
 
-// y transform of the convolution: compile-time length when LMY > 0
+// y transform of the convolution: compile-time length when LMY > 0;
+// lengths 3 2^lmy (f3y) with the permuted order of fft_lines3
 template <typename V, bool INV, int LMY>
-__device__ __forceinline__ void conv_fft_y(V* lines, int nlines, int lmy, const V* twl)
+__device__ __forceinline__ void conv_fft_y(V* lines, int nlines, int lmy, int f3y, const V* twl)
 {
     if constexpr (LMY > 0) fft_lines_ct<V, INV, LMY, SSM_CONV_CT_RADIX_BITS>(lines, nlines, twl);
+    else if (f3y) fft_lines3<V, INV, SSM_CONV_RADIX_BITS>(lines, nlines, lmy, twl);
     else fft_lines<V, INV, SSM_CONV_RADIX_BITS>(lines, nlines, 1 << lmy, lmy, twl);
 }
 
@@ -428,11 +453,9 @@ __device__ __forceinline__ void conv_body_ct(const Prob& p, int s0, int G, cplx<
     constexpr int LNSL = fft_last_lns(LMY, MB);
     constexpr int BL = LMY - LNSL, RL = 1 << BL;
     static_assert(LNSL >= B0, "the y schedule needs at least two passes");
-    // pad layout and twiddle source (LDS copy of W_{2 m_y}, or the global
-    // W_{kTwM} table read at stride 2^TWS)
-    constexpr int PADL = conv_padl(MZ, LMY);
-    constexpr bool TWL = conv_tw_lds(MZ, LMY);
-    constexpr int TWS = TWL ? 0 : kTwLog - 1 - LMY;
+    // pad layout; twiddles W_{2 m_y} from an LDS copy
+    constexpr int PADL = conv_padl(MZ, LMY, 0);
+    constexpr int TWS = 0;
     // swizzled handoff between the two radix-16 passes of length 256
     constexpr bool SW = SSM_CONV_SWZ && PADL == 0 && LMY == 8 && MB == 4;
     using P0 = PassCT<V, R0, false, LMY, 0, PADL, TWS, false, SW>;
@@ -440,16 +463,9 @@ __device__ __forceinline__ void conv_body_ct(const Prob& p, int s0, int G, cplx<
     const int nsl_img = p.mx + 1;
     const int nz = p.nz, ny = p.ny, nhz = p.nhz;
     const int per = 3 * nz * ny, nlines = G * 3 * nz;
-    const V* twl;
-    V* lines;
-    if constexpr (TWL) {
-        load_twiddles(smem, LMY, tw);
-        twl = smem;
-        lines = smem + 2 * MY;
-    } else {
-        twl = tw;
-        lines = smem;
-    }
+    load_twiddles(smem, LMY, 0, tw);
+    const V* twl = smem;
+    V* lines = smem + 2 * MY;
     V* in = X + p.x_off + (long long)s0 * per;
     V* out = Xp + p.x_off + (long long)s0 * per;
     const int kx0 = s0 % nsl_img;
@@ -568,11 +584,12 @@ __device__ __forceinline__ void conv_body(const Prob& p, int s0, int G, cplx<T>*
     using V = cplx<T>;
     const int nsl_img = p.mx + 1;
     const int nz = p.nz, ny = p.ny, nhz = p.nhz;
-    const int lmy = LMY > 0 ? LMY : p.lmy, my = 1 << lmy;
+    const int lmy = LMY > 0 ? LMY : p.lmy, f3y = LMY > 0 ? 0 : p.f3y;
+    const int my = LMY > 0 ? 1 << LMY : p.my;
     const int per = 3 * nz * ny, nel = G * per, nlines = G * 3 * nz;
     V* twl = smem;
     V* lines = twl + 2 * my;
-    load_twiddles(twl, lmy, tw);
+    load_twiddles(twl, lmy, f3y, tw);
     V* in = X + p.x_off + (long long)s0 * per;
     V* out = Xp + p.x_off + (long long)s0 * per;
     const int dy = kNT % ny, dr = kNT / ny;
@@ -590,7 +607,7 @@ __device__ __forceinline__ void conv_body(const Prob& p, int s0, int G, cplx<T>*
             for (int e = threadIdx.x; e < nel; e += kNT) {
                 V v = in[e];
                 if (hy) v = cmul(v, twl[y]);
-                lines[lds_pad((r << lmy) + y)] = v;
+                lines[lds_pad(r * my + y)] = v;
                 y += dy;
                 r += dr;
                 if (y >= ny) { y -= ny; r += 1; }
@@ -600,20 +617,23 @@ __device__ __forceinline__ void conv_body(const Prob& p, int s0, int G, cplx<T>*
             const int tail = my - ny;
             for (int e = threadIdx.x; e < nlines * tail; e += kNT) {
                 const int r = e / tail, y = ny + e % tail;
-                lines[lds_pad((r << lmy) + y)] = mk<V>(0, 0);
+                lines[lds_pad(r * my + y)] = mk<V>(0, 0);
             }
         }
         __syncthreads();
-        conv_fft_y<V, false, LMY>(lines, nlines, lmy, twl);
+        conv_fft_y<V, false, LMY>(lines, nlines, lmy, f3y, twl);
         __syncthreads();
 
         int col0 = threadIdx.x;
         asm volatile("" : "+v"(col0));
-        for (int col = col0; col < (G << lmy); col += kNT) {
-            const int g = col >> lmy, qy = col & (my - 1);
+        for (int col = col0; col < G * my; col += kNT) {
+            // column at position py of slice g holds y frequency qy
+            int g, py;
+            divlen(col, lmy, f3y, g, py);
+            const int qy = f3y ? unperm3(py, lmy) : py;
             int kx = kx0 + g;
             while (kx >= nsl_img) kx -= nsl_img;
-            const int cbase = ((g * 3 * nz) << lmy) + qy;
+            const int cbase = g * 3 * nz * my + py;
             V b[3][MZ];
 #pragma unroll
             for (int c = 0; c < 3; ++c)
@@ -626,16 +646,16 @@ __device__ __forceinline__ void conv_body(const Prob& p, int s0, int G, cplx<T>*
                 for (int c = 0; c < 3; ++c)
 #pragma unroll
                     for (int zz = 0; zz < MZ; ++zz) {
-                        V v = (zz < nz) ? lines[lds_pad(cbase + ((c * nz + zz) << lmy))] : mk<V>(0, 0);
+                        V v = (zz < nz) ? lines[lds_pad(cbase + (c * nz + zz) * my)] : mk<V>(0, 0);
                         if (hz) v = twz<false, V, MZ>(v, zz, tw);
                         a[c][zz] = v;
                     }
 #pragma unroll
                 for (int c = 0; c < 3; ++c) dft_reg<V, MZ, false>(a[c]);
-                const T* nh = nhat + p.nh_off + (((((long long)kx * nhz + hz) * 2 + hy) * MZ) * 6 << lmy) + qy;
+                const T* nh = nhat + p.nh_off + ((((long long)kx * nhz + hz) * 2 + hy) * MZ) * 6 * my + qy;
 #pragma unroll
                 for (int r = 0; r < MZ; ++r) {
-                    const T* q6 = nh + ((long long)r * 6 << lmy);
+                    const T* q6 = nh + (long long)r * 6 * my;
                     if (SSM_CONV_NH_SERIAL) asm volatile("" : "+v"(q6));
                     const T nxx = q6[0], nxy = q6[my], nxz = q6[2 * my];
                     const T nyy = q6[3 * my], nyz = q6[4 * my], nzz = q6[5 * my];
@@ -659,10 +679,10 @@ __device__ __forceinline__ void conv_body(const Prob& p, int s0, int G, cplx<T>*
             for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int zz = 0; zz < MZ; ++zz)
-                    if (zz < nz) lines[lds_pad(cbase + ((c * nz + zz) << lmy))] = b[c][zz];
+                    if (zz < nz) lines[lds_pad(cbase + (c * nz + zz) * my)] = b[c][zz];
         }
         __syncthreads();
-        conv_fft_y<V, true, LMY>(lines, nlines, lmy, twl);
+        conv_fft_y<V, true, LMY>(lines, nlines, lmy, f3y, twl);
         __syncthreads();
         {
             // y half hy = 0 goes to the output slice, hy = 1 (un-twiddled)
@@ -672,7 +692,7 @@ __device__ __forceinline__ void conv_body(const Prob& p, int s0, int G, cplx<T>*
             V* dst = out;
 #pragma unroll 4
             for (int e = threadIdx.x; e < nel; e += kNT) {
-                V v = lines[lds_pad((r << lmy) + y)];
+                V v = lines[lds_pad(r * my + y)];
                 if (hy) v = cadd(cmulc(v, twl[y]), dst[e]);  // this thread stored half 0 at e
                 dst[e] = v;
                 y += dy;
@@ -696,7 +716,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     const int pi = find_problem(wstart, np, blockIdx.x);
     if (done && done[pi]) return;
     const Prob& p = P[pi];
-    if (conv_build(MZ, p.lmy) != BUILD) return;  // served by another build
+    if (conv_build(MZ, p.lmy, p.f3y) != BUILD) return;  // served by another build
     const int w = blockIdx.x - wstart[pi];
     const int nsl_img = p.mx + 1, nsl = p.K * nsl_img;
     int s0, G;
@@ -786,15 +806,15 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     const int z = SSM_XINV_ZFAST ? t % p.nz : (t / p.nty) % p.nz;
     const int ty = SSM_XINV_ZFAST ? (t / p.nz) % p.nty : t % p.nty;
     const int img = t / (p.nz * p.nty);
-    const int yt = p.yt, hp = yt >> 1, nx = p.nx, ny = p.ny, nz = p.nz, m = p.mx, lm = p.lmx;
+    const int yt = p.yt, hp = yt >> 1, nx = p.nx, ny = p.ny, nz = p.nz, m = p.mx, lm = p.lmx, f3 = p.f3x;
     const int lhp = __ffs(hp) - 1;  // tiles are powers of two
-    const int psh = x_padl(lm) ? x_padl(lm) : 31;  // pad layout of the lines
+    const int psh = x_padl(lm, f3) ? x_padl(lm, f3) : 31;  // pad layout of the lines
     const int y0 = ty * yt;
     const long long N = p.N;
     V* twl = reinterpret_cast<V*>(smem_);
     V* lines = twl + 2 * m;
-    T* hd = reinterpret_cast<T*>(lines + padded_len(yt * m, x_padl(lm)));
-    load_twiddles(twl, lm, tw);
+    T* hd = reinterpret_cast<T*>(lines + padded_len(yt * m, x_padl(lm, f3)));
+    load_twiddles(twl, lm, f3, tw);
     // the convolved x half-spectra of the image
     // (as a uniform base and 32-bit byte offsets: an image's spectra span
     // at most 1025 * 3 * 16 * 1024 complex values, under 2^32 bytes)
@@ -820,19 +840,21 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                 if (ya < ny) A = src[0];
                 if (ya + 1 < ny) B = *reinterpret_cast<const V*>(Xi + o + (unsigned)sizeof(V));
             }
-            const int i0 = (2 * rp + (kx & 1)) * m + (kx >> 1);
+            // the two halves (even, odd frequencies) are separate lines
+            const int i0 = (2 * rp + (kx & 1)) * m + fpos(kx >> 1, lm, f3);
             lines[i0 + (i0 >> psh)] = mk<V>(A.x - B.y, A.y + B.x);
             if (kx > 0 && kx < m) {
                 const int km = 2 * m - kx;
-                const int i1 = (2 * rp + (km & 1)) * m + (km >> 1);
+                const int i1 = (2 * rp + (km & 1)) * m + fpos(km >> 1, lm, f3);
                 lines[i1 + (i1 >> psh)] = mk<V>(A.x + B.y, B.x - A.y);
             }
         }
         __syncthreads();
-        fft_lines_x<V, true>(lines, yt, lm, twl);
+        fft_lines_x<V, true>(lines, yt, lm, f3, twl);
         __syncthreads();
-        for (int idx = threadIdx.x; idx < (hp << lm); idx += kNT) {
-            const int x = idx & (m - 1), rp = idx >> lm;
+        for (int idx = threadIdx.x; idx < hp * m; idx += kNT) {
+            int rp, x;
+            divlen(idx, lm, f3, rp, x);
             if (x >= nx) continue;
             const int ie = (2 * rp) * m + x, io = ie + m;
             const V e = lines[ie + (ie >> psh)];

@@ -9,14 +9,15 @@
 #include <cstdio>
 #include <cstdlib>
 #include <random>
+#include <type_traits>
 #include <vector>
 
 using namespace ssm;
 
-template <typename V, int R, bool INV>
+template <typename V, int R, bool INV, int TST = 1>
 static void emulate_pass(V* buf, int off0, int ls, int lm, int lns, int gl, const V* twl)
 {
-    using P = Pass<V, R, INV>;
+    using P = Pass<V, R, INV, TST>;
     std::vector<V> regs(64 * P::B * R);
     for (int lane = 0; lane < 64; ++lane)
         P::read(buf, off0, ls, lm, lns, gl, twl, lane, *reinterpret_cast<V(*)[P::B][R]>(&regs[lane * P::B * R]));
@@ -24,7 +25,7 @@ static void emulate_pass(V* buf, int off0, int ls, int lm, int lns, int gl, cons
         P::write(buf, off0, ls, lm, lns, gl, lane, *reinterpret_cast<V(*)[P::B][R]>(&regs[lane * P::B * R]));
 }
 
-template <typename V, bool INV>
+template <typename V, bool INV, int TST = 1>
 static void host_fft_lines(V* buf, int nl, int ls, int lm, const V* twl, int maxb)
 {
     if (lm == 0) return;
@@ -35,10 +36,10 @@ static void host_fft_lines(V* buf, int nl, int ls, int lm, const V* twl, int max
         for (int rem = lm; rem > 0;) {
             const int bits = fft_next_bits(rem, maxb);
             rem -= bits;
-            if (bits == 4) emulate_pass<V, 16, INV>(buf, g0 * ls, ls, lm, lns, gl, twl);
-            else if (bits == 3) emulate_pass<V, 8, INV>(buf, g0 * ls, ls, lm, lns, gl, twl);
-            else if (bits == 2) emulate_pass<V, 4, INV>(buf, g0 * ls, ls, lm, lns, gl, twl);
-            else emulate_pass<V, 2, INV>(buf, g0 * ls, ls, lm, lns, gl, twl);
+            if (bits == 4) emulate_pass<V, 16, INV, TST>(buf, g0 * ls, ls, lm, lns, gl, twl);
+            else if (bits == 3) emulate_pass<V, 8, INV, TST>(buf, g0 * ls, ls, lm, lns, gl, twl);
+            else if (bits == 2) emulate_pass<V, 4, INV, TST>(buf, g0 * ls, ls, lm, lns, gl, twl);
+            else emulate_pass<V, 2, INV, TST>(buf, g0 * ls, ls, lm, lns, gl, twl);
             lns += bits;
         }
     }
@@ -216,9 +217,95 @@ static double check(int lm, int nl, int pad, unsigned seed, int maxb)
     return worst / (nrm > 0 ? nrm : 1);
 }
 
+// Lines of length m = 3 2^lm (fft_lines3): the radix-3 step of every
+// (line, k) butterfly (independent, so any order), and the power-of-two
+// passes over the 3 nl sub-lines with the length-2m table at stride 3.
+// Forward: natural input, frequency q at position perm3(q); inverse: input
+// of frequency q at perm3(q), natural output.
+template <typename V, bool INV>
+static double check3(int lm, int nl, unsigned seed, int maxb)
+{
+    using S = decltype(V::x);
+    const int M = 1 << lm, m = 3 * M;
+    std::vector<V> twl(2 * m);
+    for (int e = 0; e < 2 * m; ++e) {
+        const long double th = 2.0L * 3.14159265358979323846264338327950288L * e / (2.0L * m);
+        twl[e] = mk<V>((S)cosl(th), (S)-sinl(th));
+    }
+    std::mt19937 rng(seed);
+    std::normal_distribution<double> nd;
+    std::vector<V> x((size_t)nl * m), buf((size_t)nl * m);
+    for (auto& v : x) v = mk<V>((S)nd(rng), (S)nd(rng));
+    // reference DFT of length m, natural order in and out
+    std::vector<V> ref((size_t)nl * m);
+    std::vector<long double> cs(m), sn(m);
+    for (int e = 0; e < m; ++e) {
+        const long double th = (INV ? 2.0L : -2.0L) * 3.14159265358979323846264338327950288L * e / m;
+        cs[e] = cosl(th);
+        sn[e] = sinl(th);
+    }
+    for (int l = 0; l < nl; ++l)
+        for (int k = 0; k < m; ++k) {
+            long double sr = 0, si = 0;
+            for (int j = 0; j < m; ++j) {
+                const int e = (int)((long long)j * k % m);
+                const V v = x[(size_t)l * m + j];
+                sr += v.x * cs[e] - v.y * sn[e];
+                si += v.x * sn[e] + v.y * cs[e];
+            }
+            ref[(size_t)l * m + k] = mk<V>((S)sr, (S)si);
+        }
+    for (int l = 0; l < nl; ++l)
+        for (int q = 0; q < m; ++q) buf[(size_t)l * m + (INV ? perm3(q, lm) : q)] = x[(size_t)l * m + q];
+    auto step = [&](auto inv) {
+        for (int i = 0; i < nl * M; ++i) {
+            const int line = i >> lm, k = i & (M - 1);
+            V* p = buf.data() + (size_t)line * m + k;
+            radix3_bfly<decltype(inv)::value>(p[0], p[M], p[2 * M], twl[2 * k], twl[4 * k]);
+        }
+    };
+    if (!INV) step(std::false_type{});
+    host_fft_lines<V, INV, 3>(buf.data(), 3 * nl, M, lm, twl.data(), maxb);
+    if (INV) step(std::true_type{});
+    double worst = 0, nrm = 0;
+    for (int l = 0; l < nl; ++l)
+        for (int q = 0; q < m; ++q) {
+            const V a = buf[(size_t)l * m + (INV ? q : perm3(q, lm))], b = ref[(size_t)l * m + q];
+            worst = fmax(worst, fabs((double)a.x - (double)b.x));
+            worst = fmax(worst, fabs((double)a.y - (double)b.y));
+            nrm = fmax(nrm, fabs((double)b.x) + fabs((double)b.y));
+        }
+    return worst / (nrm > 0 ? nrm : 1);
+}
+
 int main()
 {
     int bad = 0;
+    // the position map of the 3 2^lm order and its inverse
+    for (int lm = 0; lm <= 15; ++lm)
+        for (int q = 0; q < (3 << lm) && q < 98304; q += (lm > 10 ? 7 : 1)) {
+            const int pos = perm3(q, lm);
+            if (pos != (q % 3) * (1 << lm) + q / 3 || unperm3(pos, lm) != q) {
+                std::printf("perm3 wrong at lm=%d q=%d\n", lm, q);
+                bad = 1;
+                break;
+            }
+        }
+    for (int maxb = 2; maxb <= 4; ++maxb)
+        for (int lm = 0; lm <= 8; ++lm) {
+            const int nls[3] = {1, 2, 1024 / (3 << lm) + 2};
+            for (int t = 0; t < 3; ++t) {
+                const int nl = nls[t];
+                if ((long long)nl * (9LL << (2 * lm)) > (1LL << 22)) continue;
+                const double e64f = check3<double2, false>(lm, nl, 23 + lm, maxb);
+                const double e64i = check3<double2, true>(lm, nl, 29 + lm, maxb);
+                const double e32f = check3<float2, false>(lm, nl, 31 + lm, maxb);
+                const double e32i = check3<float2, true>(lm, nl, 37 + lm, maxb);
+                std::printf("radix3 maxb=%d m=%5d lines=%5d fp64 %.2e %.2e fp32 %.2e %.2e\n", maxb, 3 << lm, nl,
+                            e64f, e64i, e32f, e32i);
+                if (e64f > 1e-14 || e64i > 1e-14 || e32f > 2e-6 || e32i > 2e-6) bad = 1;
+            }
+        }
     for (int maxb = 2; maxb <= 4; ++maxb)
     for (int lm = 0; lm <= 10; ++lm) {
         // one line, an odd count, and a full group plus a partial one

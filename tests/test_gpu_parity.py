@@ -30,10 +30,13 @@ def rel_field(a, b):
 
 
 # ragged and power-of-two sizes; odd and even log2 transform lengths with full
-# line groups (32, 128, 512 along x); 1, 2, 3-4, 5-8 and 16 layers
+# line groups (32, 128, 512 along x); 1, 2, 3-4, 5-8 and 16 layers; half
+# padded lengths 3 2^a: 768 along x, 384 along y, 48 and 96 along y with
+# 9-16 layers
 SHAPES = [(1, 1, 1), (2, 2, 1), (5, 3, 1), (1, 6, 1), (9, 1, 1), (6, 5, 3), (7, 9, 2),
           (33, 17, 1), (16, 16, 4), (12, 10, 8), (20, 3, 5), (3, 4, 16), (32, 32, 1),
-          (100, 20, 1), (300, 5, 1), (2, 64, 1), (1000, 3, 1), (40, 128, 1)]
+          (100, 20, 1), (300, 5, 1), (2, 64, 1), (1000, 3, 1), (40, 128, 1),
+          (20, 40, 1), (70, 70, 1), (16, 150, 1), (600, 5, 1), (33, 300, 1), (5, 40, 12), (6, 70, 9)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -264,11 +267,13 @@ def test_full_size_tube_sampled_sites(oracle, precision, iters):
 @pytest.mark.parametrize("shape,precision", [
     ((1024, 1024, 1), ssm.SSM_FP64), ((1024, 1024, 1), ssm.SSM_FP32_MIXED),
     ((6, 1024, 2), ssm.SSM_FP64), ((5, 1000, 6), ssm.SSM_FP32_MIXED),
-    ((1024, 7, 16), ssm.SSM_FP64), ((1000, 9, 16), ssm.SSM_FP32_MIXED)])
+    ((1024, 7, 16), ssm.SSM_FP64), ((1000, 9, 16), ssm.SSM_FP32_MIXED),
+    ((700, 700, 1), ssm.SSM_FP64), ((700, 600, 3), ssm.SSM_FP32_MIXED)])
 def test_largest_shapes_sampled_sites(oracle, shape, precision):
     """The largest lattices the limits accept (1024 sites along x or y, the
-    most layers the LDS allows with a 1024-point y transform, 16 layers),
-    random spins: fields at sampled sites against the oracle's direct sum."""
+    most layers the LDS allows with a 1024-point y transform, 16 layers; the
+    longest 3 2^a half lengths, 768 along x and y), random spins: fields at
+    sampled sites against the oracle's direct sum."""
     nx, ny, nz = shape
     K = 3
     p = prob(nx, ny, nz, K, d=0.3, ku=0.1, D=0.02)
