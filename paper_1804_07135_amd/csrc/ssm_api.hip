@@ -83,6 +83,7 @@ struct Plan {
     int np = 0;
     int mz = 1;
     int conv_kinds = 0;               // convolution builds in use (launch_conv)
+    int x_kinds = 0;                  // x length kinds in use (launch_xfwd, launch_xinv)
     bool rk = false;                  // workspace of the adaptive integrator reserved
     size_t tsize = 8;                 // bytes of one spin component
     std::vector<Prob> P;
@@ -318,6 +319,7 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
         }
         pl.mz = p.mz;
         pl.conv_kinds |= 1 << conv_build(p.mz, p.lmy, p.f3y);
+        pl.x_kinds |= 1 << p.f3x;
         pl.lds_xf = std::max(pl.lds_xf, lds_xfwd(p, p.ytf, pl.tsize));
         pl.lds_xi = std::max(pl.lds_xi, lds_xinv(p, p.yt, pl.tsize));
         pl.lds_conv = std::max(pl.lds_conv, lds_convg(p, p.gconv, pl.tsize));
@@ -351,7 +353,7 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
     auto take = [&](size_t bytes) { size_t r = o; o = up(o + std::max<size_t>(bytes, 1)); return r; };
     pl.o_P = take(sizeof(Prob) * np);
     pl.o_wm = take(sizeof(int) * kNumMaps * (np + 1));
-    pl.o_tw = take(cs * kTwM);
+    pl.o_tw = take(cs * kTwCompact);
     pl.o_tw64 = take(16 * kTwM);
     pl.o_s = take(ts * spin);
     pl.o_ss = take(ts * spin);
@@ -522,7 +524,7 @@ struct Ops {
         const void* tw = c->at<void>(pl.o_tw);
         hipError_t e;
         e = timed(c, st, KK_XFWD, [&] {
-            return launch_xfwd<T>(c->P(), pl.np, c->wm_xf(), src, c->X(), tw, done, pl.lds_xf, st);
+            return launch_xfwd<T>(pl.x_kinds, c->P(), pl.np, c->wm_xf(), src, c->X(), tw, done, pl.lds_xf, st);
         });
         if (e != hipSuccess) return e;
         e = timed(c, st, KK_CONV, [&] {
@@ -531,7 +533,7 @@ struct Ops {
         });
         if (e != hipSuccess) return e;
         return timed(c, st, KK_XINV, [&] {
-            return launch_xinv<T>(c->P(), pl.np, c->wm_xi(), c->Xp(), src, s_star, hdst,
+            return launch_xinv<T>(pl.x_kinds, c->P(), pl.np, c->wm_xi(), c->Xp(), src, s_star, hdst,
                                   c->at<double>(pl.o_ep), tw, done, mode, tau, fcp, fcd, pl.lds_xi, st);
         });
     }
@@ -866,12 +868,12 @@ double time_kernel(ssm_ctx* c, int kind, int reps)
         if (hipEventRecord(a, c->stream) != hipSuccess) return 1e30;
         hipError_t e = hipSuccess;
         if (kind == KK_XFWD)
-            e = launch_xfwd<T>(c->P(), pl.np, c->wm_xf(), s, c->X(), tw, nullptr, pl.lds_xf, c->stream);
+            e = launch_xfwd<T>(pl.x_kinds, c->P(), pl.np, c->wm_xf(), s, c->X(), tw, nullptr, pl.lds_xf, c->stream);
         else if (kind == KK_CONV)
             e = launch_conv<T>(pl.mz, pl.conv_kinds, c->P(), pl.np, c->wm_conv(), c->X(), c->Xp(), c->at<T>(pl.o_nh), tw,
                                nullptr, pl.lds_conv, c->stream);
         else
-            e = launch_xinv<T>(c->P(), pl.np, c->wm_xi(), c->Xp(), s, nullptr, nullptr,
+            e = launch_xinv<T>(pl.x_kinds, c->P(), pl.np, c->wm_xi(), c->Xp(), s, nullptr, nullptr,
                                c->at<double>(pl.o_ep), tw, nullptr, EPI_TERMS, 0.0, 0.0, 1.0, pl.lds_xi,
                                c->stream);
         if (e != hipSuccess || hipEventRecord(b, c->stream) != hipSuccess) return 1e30;
@@ -1002,12 +1004,22 @@ static ssm_status setup_tables(ssm_ctx* c)
     const Plan& pl = c->pl;
     std::vector<double> tw64;
     twiddles(tw64);
-    std::vector<unsigned char> twt(2 * pl.tsize * kTwM);
+    // the compact table: W_{2m}^e = full-table entry e kTwM / (2m)
+    std::vector<double> cpt(2 * kTwCompact);
+    for (int f3 = 0; f3 < 2; ++f3)
+        for (int lg = 0; lg <= (f3 ? 8 : kMaxLogM); ++lg) {
+            const int n2 = (f3 ? 6 : 2) << lg, stride = kTwM / n2;
+            for (int e = 0; e < n2; ++e) {
+                cpt[2 * (tw_off(lg, f3) + e)] = tw64[2 * e * stride];
+                cpt[2 * (tw_off(lg, f3) + e) + 1] = tw64[2 * e * stride + 1];
+            }
+        }
+    std::vector<unsigned char> twt(2 * pl.tsize * kTwCompact);
     if (pl.tsize == 8) {
-        std::memcpy(twt.data(), tw64.data(), twt.size());
+        std::memcpy(twt.data(), cpt.data(), twt.size());
     } else {
         float* f = reinterpret_cast<float*>(twt.data());
-        for (int i = 0; i < 2 * kTwM; ++i) f[i] = (float)tw64[i];
+        for (int i = 0; i < 2 * kTwCompact; ++i) f[i] = (float)cpt[i];
     }
     hipError_t e = hipMemcpyAsync(c->ws + pl.o_tw, twt.data(), twt.size(), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
@@ -1067,7 +1079,7 @@ void carve_static(Plan& pl)
     pl.o_s2 = pl.o_kci = pl.o_splok = pl.o_cic = 0;
     pl.o_P = take(sizeof(Prob) * pl.np);
     pl.o_wm = take(sizeof(int) * kNumMaps * (pl.np + 1));
-    pl.o_tw = take(cs * kTwM);
+    pl.o_tw = take(cs * kTwCompact);
     pl.o_tw64 = take(16 * kTwM);
     pl.o_nh = take(ts * pl.n_nh);
     pl.o_big = take(std::max((size_t)(2 * cs * pl.n_x + cs * my_max), pl.scratch_bytes));

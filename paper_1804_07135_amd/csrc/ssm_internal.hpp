@@ -14,6 +14,14 @@ namespace ssm {
 // m = 3 2^a <= 768) and every sub-length divides kTwM = 3 * 2^11.
 constexpr int kTwM = 3 << 11;
 constexpr int kMaxLogM = 10;   // half padded length m <= 1024, padded P = 2m <= 2048
+// The FFT kernels read their twiddles from a compact table: for every half
+// length m = 2^lg (lg <= 10) and m = 3 2^lg (lg <= 8), the 2m values
+// W_{2m}^e, e < 2m, contiguous, starting at tw_off(lg, f3).
+__host__ __device__ constexpr int tw_off(int lg, int f3)
+{
+    return f3 ? (4 << kMaxLogM) - 2 + 6 * ((1 << lg) - 1) : (2 << lg) - 2;
+}
+constexpr int kTwCompact = tw_off(9, 1);  // entries of the compact table
 constexpr int kNT = 256;       // threads per workgroup for every kernel
 constexpr int kConvElems = 24 * kNT;  // complex values per convolution workgroup (slice batching cap)
 constexpr int kArcEPT = 8;     // flat elements per thread in the arc-length kernel
@@ -111,8 +119,10 @@ struct WorkMap {
 // ------------------------------------------------------------------------
 // launchers (ssm_kernels.hip); all enqueue on `st` and return the HIP error
 // ------------------------------------------------------------------------
+// kinds (x transforms): bit 0 set = some problem has a power-of-two x
+// length, bit 1 = some problem has an x length 3 2^a
 template <typename T>
-hipError_t launch_xfwd(const Prob* P, int np, const WorkMap& wm, const T* s, void* X,
+hipError_t launch_xfwd(int kinds, const Prob* P, int np, const WorkMap& wm, const T* s, void* X,
                        const void* tw, const int* done, size_t lds, hipStream_t st);
 // kinds: bit b set = some problem takes build b (conv_build)
 template <typename T>
@@ -128,7 +138,7 @@ hipError_t launch_conv(int mz, int kinds, const Prob* P, int np, const WorkMap& 
 enum { EPI_STEP = 1, EPI_FIELD = 2, EPI_TERMS = 4, EPI_FORCE = 8 };
 template <typename T>
 // fcp, fcd: coefficients of EPI_FORCE (precession, damping)
-hipError_t launch_xinv(const Prob* P, int np, const WorkMap& wm, const void* Xp, const T* s,
+hipError_t launch_xinv(int kinds, const Prob* P, int np, const WorkMap& wm, const void* Xp, const T* s,
                        T* s_star, T* h, double* epart, const void* tw, const int* done,
                        int mode, double tau, double fcp, double fcd, size_t lds, hipStream_t st);
 template <typename T>

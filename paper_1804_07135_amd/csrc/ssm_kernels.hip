@@ -105,22 +105,27 @@ __device__ __forceinline__ int find_problem(const int* __restrict__ start, int n
 // w: workgroup index within the problem, n8: item count padded to 8.
 __device__ __forceinline__ int xcd_item(int w, int n8) { return (w & 7) * (n8 >> 3) + (w >> 3); }
 
-// Load exp(-2 pi i e/(2m)), e < 2m, into LDS; m = 2^lm, or 3 2^lm when f3.
+// Load exp(-2 pi i e/(2m)), e < 2m, into LDS from the compact table;
+// m = 2^lm, or 3 2^lm when f3.
 template <typename V>
 __device__ __forceinline__ void load_twiddles(V* twl, int lm, int f3, const V* __restrict__ tw)
 {
     const int n = (f3 ? 6 : 2) << lm;
-    const int stride = (f3 ? 1 : 3) << (10 - lm);  // kTwM / (2m)
-    for (int e = threadIdx.x; e < n; e += blockDim.x) twl[e] = tw[e * stride];
+    const V* src = tw + tw_off(lm, f3);
+    for (int e = threadIdx.x; e < n; e += blockDim.x) twl[e] = src[e];
 }
 
 // q = i / L and r = i % L for a transform length L = 2^lg (f3 = 0) or
 // 3 2^lg (f3 = 1); i < 3 2^17
 __device__ __forceinline__ void divlen(int i, int lg, int f3, int& q, int& r)
 {
-    q = i >> lg;
-    if (f3) q = (q * 43691) >> 17;  // / 3
-    r = i - ((q * (f3 ? 3 : 1)) << lg);
+    if (f3) {
+        q = ((i >> lg) * 43691) >> 17;  // / 3
+        r = i - ((q * 3) << lg);
+    } else {
+        q = i >> lg;
+        r = i & ((1 << lg) - 1);
+    }
 }
 
 // position in a transformed line of length m of x frequency q (within a
@@ -211,7 +216,9 @@ __device__ __forceinline__ void load16(const T* p, bool ok, T (&v)[16 / sizeof(T
 // Output layout X[img][kx][c][z][y]: a tile writes ytf consecutive y values.
 // LDS: twiddles (2m) + ytf lines of m (padded layout).
 // ---------------------------------------------------------------------------
-template <typename T>
+// F3: x length 3 2^lmx (the kernel serves the problems of that length kind
+// only, so the length arithmetic is fixed at compile time)
+template <typename T, int F3>
 __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3, 8))) void k_xfwd(const Prob* __restrict__ P, int np,
                                               const int* __restrict__ wstart,
                                               const T* __restrict__ s, cplx<T>* __restrict__ X,
@@ -223,11 +230,13 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     const int pi = find_problem(wstart, np, blockIdx.x);
     if (done && done[pi]) return;
     const Prob& p = P[pi];
+    if (p.f3x != F3) return;  // served by the other length kind's launch
     const int t = xcd_item(blockIdx.x - wstart[pi], p.wgf);
     if (t >= p.K * p.tilesf) return;
     const int ty = t % p.ntyf, rest = t / p.ntyf;
     const int z = rest % p.nz, img = rest / p.nz;
-    const int yt = p.ytf, hp = yt >> 1, nx = p.nx, ny = p.ny, nz = p.nz, m = p.mx, lm = p.lmx, f3 = p.f3x;
+    const int yt = p.ytf, hp = yt >> 1, nx = p.nx, ny = p.ny, nz = p.nz, m = p.mx, lm = p.lmx;
+    constexpr int f3 = F3;
     const int lhp = __ffs(hp) - 1;  // tiles are powers of two
     const int psh = x_padl(lm, f3) ? x_padl(lm, f3) : 31;  // pad layout of the lines
     V* twl = reinterpret_cast<V*>(smem_);
@@ -335,7 +344,7 @@ template <bool INV, typename V, int MZ>
 __device__ __forceinline__ V twz(V v, int zz, const V* __restrict__ tw)
 {
     if (MZ <= 8) return twc16<INV>(v, zz * (8 / MZ));
-    const V w = tw[zz * (kTwM / 32)];
+    const V w = tw[tw_off(4, 0) + zz];  // W_32^zz
     return INV ? cmulc(v, w) : cmul(v, w);
 }
 
@@ -783,7 +792,7 @@ __device__ __forceinline__ T lane_prev(T v)
 // in the real part and row b in the imaginary part.
 // LDS: twiddles (2m) + yt lines of m + the tile's dipolar field (3 yt nx).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int F3>
 __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_xinv(const Prob* __restrict__ P, int np,
                                               const int* __restrict__ wstart,
                                               const cplx<T>* __restrict__ Xp,
@@ -799,6 +808,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     const int pi = find_problem(wstart, np, blockIdx.x);
     if (done && done[pi]) return;
     const Prob& p = P[pi];
+    if (p.f3x != F3) return;  // served by the other length kind's launch
     const int t = xcd_item(blockIdx.x - wstart[pi], p.wgi);
     if (t >= p.K * p.tiles) return;
     // z fastest: the tiles that read a plane's rows as z neighbours run
@@ -806,7 +816,8 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     const int z = SSM_XINV_ZFAST ? t % p.nz : (t / p.nty) % p.nz;
     const int ty = SSM_XINV_ZFAST ? (t / p.nz) % p.nty : t % p.nty;
     const int img = t / (p.nz * p.nty);
-    const int yt = p.yt, hp = yt >> 1, nx = p.nx, ny = p.ny, nz = p.nz, m = p.mx, lm = p.lmx, f3 = p.f3x;
+    const int yt = p.yt, hp = yt >> 1, nx = p.nx, ny = p.ny, nz = p.nz, m = p.mx, lm = p.lmx;
+    constexpr int f3 = F3;
     const int lhp = __ffs(hp) - 1;  // tiles are powers of two
     const int psh = x_padl(lm, f3) ? x_padl(lm, f3) : 31;  // pad layout of the lines
     const int y0 = ty * yt;
@@ -1673,12 +1684,16 @@ __global__ void k_spec3(Prob p, const double* __restrict__ F2, T* __restrict__ n
 // launchers
 // ---------------------------------------------------------------------------
 template <typename T>
-hipError_t launch_xfwd(const Prob* P, int np, const WorkMap& wm, const T* s, void* X,
+hipError_t launch_xfwd(int kinds, const Prob* P, int np, const WorkMap& wm, const T* s, void* X,
                        const void* tw, const int* done, size_t lds, hipStream_t st)
 {
     if (wm.total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_xfwd<T>, dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start, s,
-                       (cplx<T>*)X, (const cplx<T>*)tw, done);
+    if (kinds & 1)
+        hipLaunchKernelGGL((k_xfwd<T, 0>), dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start, s,
+                           (cplx<T>*)X, (const cplx<T>*)tw, done);
+    if (kinds & 2)
+        hipLaunchKernelGGL((k_xfwd<T, 1>), dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start, s,
+                           (cplx<T>*)X, (const cplx<T>*)tw, done);
     return hipGetLastError();
 }
 
@@ -1724,14 +1739,17 @@ hipError_t launch_conv(int mz, int kinds, const Prob* P, int np, const WorkMap& 
 }
 
 template <typename T>
-hipError_t launch_xinv(const Prob* P, int np, const WorkMap& wm, const void* Xp, const T* s,
+hipError_t launch_xinv(int kinds, const Prob* P, int np, const WorkMap& wm, const void* Xp, const T* s,
                        T* s_star, T* h, double* epart, const void* tw, const int* done, int mode,
                        double tau, double fcp, double fcd, size_t lds, hipStream_t st)
 {
     if (wm.total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_xinv<T>, dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start,
-                       (const cplx<T>*)Xp, s, s_star, h, epart, (const cplx<T>*)tw, done,
-                       mode, tau, fcp, fcd);
+    if (kinds & 1)
+        hipLaunchKernelGGL((k_xinv<T, 0>), dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start,
+                           (const cplx<T>*)Xp, s, s_star, h, epart, (const cplx<T>*)tw, done, mode, tau, fcp, fcd);
+    if (kinds & 2)
+        hipLaunchKernelGGL((k_xinv<T, 1>), dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start,
+                           (const cplx<T>*)Xp, s, s_star, h, epart, (const cplx<T>*)tw, done, mode, tau, fcp, fcd);
     return hipGetLastError();
 }
 
@@ -2399,11 +2417,11 @@ hipError_t launch_fill_double(double* p, int n, double v, hipStream_t st)
 
 // explicit instantiations
 #define SSM_INST(T)                                                                                \
-    template hipError_t launch_xfwd<T>(const Prob*, int, const WorkMap&, const T*, void*,         \
+    template hipError_t launch_xfwd<T>(int, const Prob*, int, const WorkMap&, const T*, void*,    \
                                        const void*, const int*, size_t, hipStream_t);             \
     template hipError_t launch_conv<T>(int, int, const Prob*, int, const WorkMap&, void*, void*,       \
                                        const T*, const void*, const int*, size_t, hipStream_t);   \
-    template hipError_t launch_xinv<T>(const Prob*, int, const WorkMap&, const void*,              \
+    template hipError_t launch_xinv<T>(int, const Prob*, int, const WorkMap&, const void*,         \
                                        const T*,                                                    \
                                        T*, T*, double*, const void*, const int*, int, double,     \
                                        double, double, size_t, hipStream_t);                       \
