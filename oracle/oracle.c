@@ -26,6 +26,13 @@
  *   - nearest-neighbour bonds <i,j> are counted once each; open boundaries,
  *     missing neighbours contribute nothing (Sec. II: free boundaries).
  *
+ * Parity unpinned by the paper: the adaptive step controller's constants
+ * (safety factor 0.9, step-factor bounds 0.2 and 5, exponent -1/5; the
+ * paper names Dormand-Prince with step control but no controller) and every
+ * barrier value (the paper prints none).  They are pinned only by behaviour
+ * (tableau order conditions, step response, single-spin closed forms) and
+ * through the pinned parts they are built from.
+ *
  * Every function below names the passage of the paper it follows.
  * Parity pins for each function live in tests/test_oracle_pins.py (field,
  * energy, step, reparametrisation, tangents), test_oracle_rk_pins.py and
