@@ -41,17 +41,14 @@ def kernel_source_hash():
 
 
 def half_len(n, axis="x", nz=1):
-    """The documented half padded length of the x or y axis: the power of
-    two >= n, or for n > 32 the length 3 2^a >= n (a >= 4, at most 768) when
-    that is smaller and the power of two exceeds 512 (x) or 256 (y; or the
-    padded layer count m_z exceeds 8 for y)."""
+    """The documented half padded length of the x or y axis (the same rule
+    for both, any layer count): the power of two >= n, or for n > 32 the
+    length 3 2^a >= n (a >= 4, at most 768) when that is smaller."""
     p2 = 1 << (n - 1).bit_length()
-    mz = 1 if nz == 1 else 1 << (nz - 1).bit_length()
-    slow = p2 > 512 if axis == "x" else (p2 > 256 or mz > 8)
     t = 48
     while t < n:
         t *= 2
-    return t if n > 32 and slow and t < p2 and t <= 768 else p2
+    return t if n > 32 and t < p2 and t <= 768 else p2
 
 
 def algorithmic_bytes(w, ts):

@@ -64,10 +64,9 @@
  * 2 m_y by (2 m_z, or 1 for nz = 1) sites; any padded length >= 2n - 1 per
  * axis gives the same field (Sec. II.A: circular sorting).  m_z is the
  * power of two >= nz; m_x and m_y are the power of two >= n or, for n > 32,
- * the length 3 * 2^a >= n (a >= 4, at most 768) when that is smaller and
- * the power of two exceeds 512 (x) or 256 (y; or m_z > 8 for y), e.g.
- * m_x = 768 for nx = 513..768 and m_y = 96 for ny = 65..96 with 9..16
- * layers.
+ * the length 3 * 2^a >= n (a >= 4, at most 768) when that is smaller, e.g.
+ * m = 48 for n = 33..48, 96 for 65..96, 192 for 129..192, 384 for
+ * 257..384 and 768 for 513..768.
  */
 #ifndef SSM_H
 #define SSM_H

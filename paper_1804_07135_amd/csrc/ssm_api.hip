@@ -50,24 +50,30 @@ size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 // Half padded transform length m >= n of an x or y axis.  Any padded
 // length 2m >= 2n - 1 gives the same zero-padded convolution, so this only
 // chooses the cheaper transform: the power of two >= n, or the length
-// 3 2^a >= n (a >= 4, m <= 768) when that is smaller and the power of two
-// would not take the compile-time-length transforms either (x: above 512;
-// y: above 256, or more than 8 padded layers), which run faster than the
-// runtime-length ones that 3 2^a takes.  lg = log2 of the power-of-two
-// factor, f3 = 1 for 3 2^a.
+// 3 2^a >= n (a >= 4, m <= 768) when that is smaller and not a slower kind
+// of transform: fast(lg, f3) says whether the length 2^lg (f3 = 0) or
+// 3 2^lg (f3 = 1) takes the compile-time-length transforms, which run faster
+// than the runtime-length ones.  lg = log2 of the power-of-two factor,
+// f3 = 1 for 3 2^a.
 #ifndef SSM_LEN3
 #define SSM_LEN3 1
 #endif
-void transform_len(int n, bool pow2_fast, int& m, int& lg, int& f3)
+#ifndef SSM_LEN3_CT_X
+#define SSM_LEN3_CT_X 3
+#endif
+#ifndef SSM_LEN3_CT_Y
+#define SSM_LEN3_CT_Y 3
+#endif
+template <typename Fast>
+void transform_len(int n, Fast fast, int& m, int& lg, int& f3)
 {
     m = pow2ceil(n);
     lg = ilog2(m);
     f3 = 0;
-    if (SSM_LEN3 && n > 32 && !pow2_fast) {
-        int t = 48, a = 4;
-        while (t < n) { t *= 2; ++a; }
-        if (t < m && t <= 768) { m = t; lg = a; f3 = 1; }
-    }
+    if (!SSM_LEN3 || n <= 32) return;
+    int t = 48, a = 4;
+    while (t < n) { t *= 2; ++a; }
+    if (t < m && t <= 768 && (fast(a, 1) || !fast(lg, 0))) { m = t; lg = a; f3 = 1; }
 }
 
 struct Tiles {
@@ -128,7 +134,7 @@ size_t lds_xinv(const Prob& p, int yt, size_t tsize)
 size_t lds_convg(const Prob& p, int G, size_t tsize)
 {
     const int n = G * 3 * p.nz * p.my;
-    if (conv_ct_shape(p.mz, p.lmy, p.f3y))
+    if (conv_ct_shape(p.mz, p.lmy, p.f3y) || conv_ct3_shape(p.mz, p.lmy, p.f3y))
         return (size_t)(2 * p.my + padded_len(n, conv_padl(p.mz, p.lmy, p.f3y))) * 2 * tsize;
     return (size_t)(2 * p.my + lds_padded_size(n)) * 2 * tsize;
 }
@@ -244,10 +250,17 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
     std::map<std::tuple<int, int, int>, int> shape_id;
     long long img = 0, spin = 0, xo = 0, ep = 0, ap = 0, fp = 0, fm = 0;
     long long batch_rows = 0, batch_slices = 0;
+    // SSM_LEN3_CT_X / _Y: precisions (bit 0 FP32-mixed, bit 1 FP64) in
+    // which a compile-time 3 2^a length is preferred to a compile-time power
+    // of two
+    const int pbit = pl.tsize == 8 ? 2 : 1;
+    const auto x_fast = [&](int lg, int f3) {
+        return f3 ? x_ct3_len(lg, f3) && (SSM_LEN3_CT_X & pbit) : x_ct_len(lg, f3);
+    };
     for (int i = 0; i < np; ++i) {
         batch_rows += (long long)pr[i].n_images * pr[i].nz * pr[i].ny;
         int mx, lg, f3;
-        transform_len(pr[i].nx, x_ct_len(ilog2(pow2ceil(pr[i].nx)), 0), mx, lg, f3);
+        transform_len(pr[i].nx, x_fast, mx, lg, f3);
         batch_slices += (long long)pr[i].n_images * (mx + 1);
     }
     for (int i = 0; i < np; ++i) {
@@ -257,8 +270,9 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
         p.nx = q.nx; p.ny = q.ny; p.nz = q.nz; p.K = q.n_images;
         p.mz = q.nz > 1 ? pow2ceil(q.nz) : 1;
         p.lmz = ilog2(p.mz);
-        transform_len(q.nx, x_ct_len(ilog2(pow2ceil(q.nx)), 0), p.mx, p.lmx, p.f3x);
-        transform_len(q.ny, conv_ct_shape(p.mz, ilog2(pow2ceil(q.ny)), 0), p.my, p.lmy, p.f3y);
+        transform_len(q.nx, x_fast, p.mx, p.lmx, p.f3x);
+        transform_len(q.ny, [&](int lg, int f3) { return conv_build(p.mz, lg, f3) > 0 && (!f3 || (SSM_LEN3_CT_Y & pbit)); },
+                      p.my, p.lmy, p.f3y);
         p.pz = q.nz > 1 ? 2 * p.mz : 1;
         p.nhz = q.nz > 1 ? 2 : 1;
         p.N = (long long)q.nx * q.ny * q.nz;

@@ -217,8 +217,10 @@ __host__ __device__ constexpr int pad_for(int padl, int lm) { return padl == 0 ?
 // both its strided side and its contiguous side hit distinct LDS banks.
 __host__ __device__ __forceinline__ int swz16(int i) { return i ^ ((i >> 4) & 15); }
 
+// TST: the lines are sub-lines of lines 3x as long whose twiddle table
+// (W_{6 * 2^LM}) serves them at stride 3 (lengths 3 2^a).
 template <typename V, int R, bool INV, int LM, int LNS, int PADL = 0, int TWS = 0, bool SWR = false,
-          bool SWW = false>
+          bool SWW = false, int TST = 1>
 struct PassCT {
     static constexpr int LR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
     static constexpr int B = 16 / R;
@@ -248,7 +250,7 @@ struct PassCT {
                 }
                 if (LNS > 0) {
 #pragma unroll
-                    for (int r = 1; r < R; ++r) v[b][r] = twm<INV>(v[b][r], twl[(r * k) << TSH]);
+                    for (int r = 1; r < R; ++r) v[b][r] = twm<INV>(v[b][r], twl[TST * ((r * k) << TSH)]);
                 }
                 dft_reg<V, R, INV>(v[b]);
             }
@@ -347,20 +349,40 @@ __device__ __forceinline__ void fft_lines(V* buf, int nl, int ls, int lm, const 
 // (so passes [LNS, LEND) of the schedule; LEND = LM runs all the rest).
 // SW: the swizzled handoff (swz16) between the passes starting at LNS = 0
 // and LNS = 4: the first pass writes swizzled, the second reads swizzled.
-template <typename V, bool INV, int LM, int MAXB, int LNS, int LEND, int PADL = 0, int TWS = 0, bool SW = false>
+template <typename V, bool INV, int LM, int MAXB, int LNS, int LEND, int PADL = 0, int TWS = 0, bool SW = false,
+          int TST = 1>
 __device__ __forceinline__ void fft_passes_ct_to(V* buf, int off0, int gl, const V* twl, int lane)
 {
     static_assert(!SW || fft_next_bits(LM, MAXB) == 4, "swizzled handoff needs a radix-16 first pass");
     if constexpr (LNS < LEND) {
         constexpr int bits = fft_next_bits(LM - LNS, MAXB);
         constexpr int R = 1 << bits;
-        using P = PassCT<V, R, INV, LM, LNS, PADL, TWS, SW && LNS == 4, SW && LNS == 0>;
+        using P = PassCT<V, R, INV, LM, LNS, PADL, TWS, SW && LNS == 4, SW && LNS == 0, TST>;
         V v[16 / R][R];
         P::read(buf, off0, gl, twl, lane, v);
         wave_sync();
         P::write(buf, off0, gl, lane, v);
         wave_sync();
-        fft_passes_ct_to<V, INV, LM, MAXB, LNS + bits, LEND, PADL, TWS, SW>(buf, off0, gl, twl, lane);
+        fft_passes_ct_to<V, INV, LM, MAXB, LNS + bits, LEND, PADL, TWS, SW, TST>(buf, off0, gl, twl, lane);
+    }
+}
+
+// Passes from sub-length 2^LNS to exactly 2^LEND, scheduled on the
+// LEND - LNS bits of that span (fft_next_bits), for a caller that runs the
+// passes beyond LEND itself.
+template <typename V, bool INV, int LM, int MAXB, int LNS, int LEND, int PADL = 0, int TST = 1>
+__device__ __forceinline__ void fft_passes_ct_span(V* buf, int off0, int gl, const V* twl, int lane)
+{
+    if constexpr (LNS < LEND) {
+        constexpr int bits = fft_next_bits(LEND - LNS, MAXB);
+        constexpr int R = 1 << bits;
+        using P = PassCT<V, R, INV, LM, LNS, PADL, 0, false, false, TST>;
+        V v[16 / R][R];
+        P::read(buf, off0, gl, twl, lane, v);
+        wave_sync();
+        P::write(buf, off0, gl, lane, v);
+        wave_sync();
+        fft_passes_ct_span<V, INV, LM, MAXB, LNS + bits, LEND, PADL, TST>(buf, off0, gl, twl, lane);
     }
 }
 
@@ -374,7 +396,7 @@ __host__ __device__ constexpr int fft_last_lns(int lm, int maxb)
 
 // fft_lines for a line length 2^LM known at compile time (line stride 2^LM
 // in the pad-PADL layout).  Same result as fft_lines up to rounding order.
-template <typename V, bool INV, int LM, int MAXB, int PADL = 0>
+template <typename V, bool INV, int LM, int MAXB, int PADL = 0, int TST = 1>
 __device__ __forceinline__ void fft_lines_ct(V* buf, int nl, const V* twl)
 {
     if constexpr (LM > 0) {
@@ -386,7 +408,7 @@ __device__ __forceinline__ void fft_lines_ct(V* buf, int nl, const V* twl)
         const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
         constexpr int LPG = fft_group_lines(LM);
         for (int g0 = wave * LPG; g0 < nl; g0 += nw * LPG)
-            fft_passes_ct_to<V, INV, LM, MAXB, 0, LM, PADL, 0>(buf, g0 << LM, min(LPG, nl - g0), twl, lane);
+            fft_passes_ct_to<V, INV, LM, MAXB, 0, LM, PADL, 0, false, TST>(buf, g0 << LM, min(LPG, nl - g0), twl, lane);
     }
 }
 

@@ -39,18 +39,23 @@ __host__ __device__ constexpr bool conv_ct_shape(int mz, int lmy, int f3y)
 {
     return SSM_CONV_CT && !f3y && mz <= 8 && lmy >= 5 && lmy <= 8;
 }
+// y lengths 3 2^lmy with compile-time sub-line passes (48, 96, 192)
+__host__ __device__ constexpr bool conv_ct3_shape(int mz, int lmy, int f3y)
+{
+    return SSM_CONV_CT && f3y && mz <= 8 && lmy >= 4 && lmy <= 6;
+}
 // build serving a problem: the y length's log2 (5..8) for the compile-time
-// builds, 0 for the runtime-length one (also every y length 3 2^a)
+// power-of-two builds, 16 + log2 of the power-of-two factor (20..22) for the
+// compile-time 3 2^a builds, 0 for the runtime-length one
 __host__ __device__ constexpr int conv_build(int mz, int lmy, int f3y)
 {
-    return conv_ct_shape(mz, lmy, f3y) ? lmy : 0;
+    return conv_ct_shape(mz, lmy, f3y) ? lmy : conv_ct3_shape(mz, lmy, f3y) ? 16 + lmy : 0;
 }
 
 // LDS layout of the line buffers (pad_for, padx in ssm_fft.hpp).  The
-// compile-time-length transforms store lines with one pad element per
-// 2^PADL, which spreads their strided accesses over the banks; the
-// runtime-length ones use the dense layout.  The compile-time convolution
-// can also read its twiddles from the global table instead of an LDS copy.
+// compile-time-length transforms can store lines with one pad element per
+// 2^PADL (PADL = 0: dense), which spreads their strided accesses over the
+// banks; the runtime-length ones use the dense layout.
 #ifndef SSM_X_CT
 #define SSM_X_CT 1
 #endif
@@ -60,13 +65,22 @@ __host__ __device__ constexpr int conv_build(int mz, int lmy, int f3y)
 #ifndef SSM_CONV_PADL
 #define SSM_CONV_PADL 0
 #endif
-// x lengths with compile-time passes: powers of two 32..512 (lm = log2 m;
-// lengths 3 2^lm take the runtime passes)
+#ifndef SSM_CONV3_PADL
+#define SSM_CONV3_PADL 4
+#endif
+// x lengths with compile-time passes: powers of two 32..512 (lm = log2 m)
+// and 3 2^lm for 48..384, both in the pad-SSM_X_PADL layout
 __host__ __device__ constexpr bool x_ct_len(int lm, int f3) { return SSM_X_CT && !f3 && lm >= 5 && lm <= 9; }
-__host__ __device__ constexpr int x_padl(int lm, int f3) { return x_ct_len(lm, f3) ? pad_for(SSM_X_PADL, lm) : 0; }
+__host__ __device__ constexpr bool x_ct3_len(int lm, int f3) { return SSM_X_CT && f3 && lm >= 4 && lm <= 7; }
+__host__ __device__ constexpr int x_padl(int lm, int f3)
+{
+    return (x_ct_len(lm, f3) || x_ct3_len(lm, f3)) ? pad_for(SSM_X_PADL, lm) : 0;
+}
 __host__ __device__ constexpr int conv_padl(int mz, int lmy, int f3y)
 {
-    return conv_ct_shape(mz, lmy, f3y) ? pad_for(SSM_CONV_PADL, lmy) : 0;
+    return conv_ct_shape(mz, lmy, f3y)    ? pad_for(SSM_CONV_PADL, lmy)
+           : conv_ct3_shape(mz, lmy, f3y) ? pad_for(SSM_CONV3_PADL, lmy)
+                                          : 0;
 }
 // elements of a buffer of n elements in the pad-padl layout
 __host__ __device__ constexpr int padded_len(int n, int padl) { return padl ? n + (n >> padl) + 1 : n; }

@@ -42,6 +42,13 @@ namespace ssm {
 #ifndef SSM_CONV_RADIX_BITS
 #define SSM_CONV_RADIX_BITS 2
 #endif
+// 1: the 3 2^a forward x loads read 16 bytes per load where rows allow
+#ifndef SSM_XFWD3_VEC
+#define SSM_XFWD3_VEC 0
+#endif
+#ifndef SSM_XINV_WAVES_F32
+#define SSM_XINV_WAVES_F32 3
+#endif
 #ifndef SSM_CONV_WAVES_F32
 #define SSM_CONV_WAVES_F32 3
 #endif
@@ -149,14 +156,23 @@ __device__ __forceinline__ T wave_max(T v)
     return v;
 }
 
-// Transform of nl lines of length 2^lm (stride 2^lm): compile-time-length
-// passes for lengths 32..512 (pad layout x_padl(lm)), runtime-length passes
-// (dense layout) otherwise.
+// Transform of nl lines of length 2^lm stored contiguously: compile-time-
+// length passes for 32..512 (pad layout x_padl), runtime-length passes
+// (dense layout) otherwise.  f3: lines of length 3 2^lm, of which this runs
+// only the power-of-two transforms of the 3 nl sub-lines (the x kernels do
+// the radix-3 step as they load or store the lines): compile-time passes for
+// 48..384.
 template <typename V, bool INV>
 __device__ __forceinline__ void fft_lines_x(V* lines, int nl, int lm, int f3, const V* twl)
 {
     if (f3) {
-        fft_lines3<V, INV, SSM_X_RADIX_BITS>(lines, nl, lm, twl);
+        switch (SSM_X_CT ? lm : 0) {
+        case 4: fft_lines_ct<V, INV, 4, SSM_X_CT_RADIX_BITS, pad_for(SSM_X_PADL, 4), 3>(lines, 3 * nl, twl); break;
+        case 5: fft_lines_ct<V, INV, 5, SSM_X_CT_RADIX_BITS, pad_for(SSM_X_PADL, 5), 3>(lines, 3 * nl, twl); break;
+        case 6: fft_lines_ct<V, INV, 6, SSM_X_CT_RADIX_BITS, pad_for(SSM_X_PADL, 6), 3>(lines, 3 * nl, twl); break;
+        case 7: fft_lines_ct<V, INV, 7, SSM_X_CT_RADIX_BITS, pad_for(SSM_X_PADL, 7), 3>(lines, 3 * nl, twl); break;
+        default: fft_lines<V, INV, SSM_X_RADIX_BITS, 3>(lines, 3 * nl, 1 << lm, lm, twl); break;
+        }
         return;
     }
     switch (SSM_X_CT ? lm : 0) {
@@ -208,6 +224,81 @@ __device__ __forceinline__ void load16(const T* p, bool ok, T (&v)[16 / sizeof(T
     }
 }
 
+// Loads of k_xfwd for x lengths m = 3 M (M = 2^lm) with the radix-3 step of
+// the forward transform (decimation in frequency, ssm_fft.hpp) applied on the
+// way: the thread of row pair rp and position k < M reads the sites k, k + M,
+// k + 2M of both rows, and writes the three butterfly outputs of the even
+// half line, and of the odd half line (input twiddled by W_{2m}^x first), to
+// positions k, k + M, k + 2M of those lines, where the sub-line transforms
+// take them.  vecw: rows are read VW sites per 16-byte load.
+template <typename T>
+__device__ __forceinline__ void xfwd_load3(const T* __restrict__ sc, cplx<T>* lines, const cplx<T>* twl, bool vecw,
+                                           int hp, int lm, int y0, int nx, int ny, int psh)
+{
+    using V = cplx<T>;
+    constexpr int VW = 16 / sizeof(T), LVW = VW == 4 ? 2 : 1;
+    const int M = 1 << lm, m = 3 * M;
+    auto put = [&](int rp, int k, V (&e)[3]) {
+        V o[3];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) o[t] = cmul(e[t], twl[k + t * M]);
+        const V w1 = twl[2 * k], w2 = twl[4 * k];
+        radix3_bfly<false>(e[0], e[1], e[2], w1, w2);
+        radix3_bfly<false>(o[0], o[1], o[2], w1, w2);
+        const int i0 = (2 * rp) * m + k, i1 = i0 + m;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const int a = i0 + t * M, b = i1 + t * M;
+            lines[a + (a >> psh)] = e[t];
+            lines[b + (b >> psh)] = o[t];
+        }
+    };
+    if (SSM_XFWD3_VEC && vecw) {
+        const int lmv = lm - LVW;  // a sub-line is M / VW chunks of VW sites
+#pragma unroll 1
+        for (int idx = threadIdx.x; idx < (hp << lmv); idx += kNT) {
+            const int rp = idx >> lmv, k0 = (idx & ((1 << lmv) - 1)) << LVW;
+            const int ya = y0 + 2 * rp;
+            T av[3][VW], bv[3][VW];
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                const int j = k0 + t * M;
+                load16<T>(sc + (long long)ya * nx + j, j < nx && ya < ny, av[t]);
+                load16<T>(sc + (long long)(ya + 1) * nx + j, j < nx && ya + 1 < ny, bv[t]);
+            }
+#pragma unroll
+            for (int q = 0; q < VW; ++q) {
+                V e[3];
+#pragma unroll
+                for (int t = 0; t < 3; ++t) e[t] = mk<V>(av[t][q], bv[t][q]);
+                put(rp, k0 + q, e);
+            }
+        }
+    } else {
+#pragma unroll 1
+        for (int idx = threadIdx.x; idx < (hp << lm); idx += kNT) {
+            const int rp = idx >> lm, k = idx & (M - 1);
+            const int ya = y0 + 2 * rp;
+            // rows and columns clamped into the lattice for the loads (all
+            // issued before any is used), zero outside it
+            const T* ra = sc + (long long)min(ya, ny - 1) * nx;
+            const T* rb = sc + (long long)min(ya + 1, ny - 1) * nx;
+            V e[3];
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                const int j = min(k + t * M, nx - 1);
+                e[t] = mk<V>(ra[j], rb[j]);
+            }
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                const bool in = k + t * M < nx;
+                e[t] = mk<V>(in && ya < ny ? e[t].x : T(0), in && ya + 1 < ny ? e[t].y : T(0));
+            }
+            put(rp, k, e);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // k_xfwd: rows of a tile (image, z, ytf rows) -> x half-spectra, one spin
 // component at a time.  Two real rows of one component form one complex
@@ -256,7 +347,9 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
 #pragma unroll 1
     for (int c = 0; c < 3; ++c) {
         const T* sc = si + (long long)c * N;
-        if (vecw) {
+        if constexpr (F3) {
+            xfwd_load3<T>(sc, lines, twl, vecw, hp, lm, y0, nx, ny, psh);
+        } else if (vecw) {
             const int lmv = lm - LVW;  // a line is m / VW chunks of VW sites
 #pragma unroll 1
             for (int idx = threadIdx.x; idx < hp * (m >> LVW); idx += kNT) {
@@ -348,36 +441,38 @@ __device__ __forceinline__ V twz(V v, int zz, const V* __restrict__ tw)
     return INV ? cmulc(v, w) : cmul(v, w);
 }
 
-// y transform of the convolution: compile-time length when LMY > 0;
-// lengths 3 2^lmy (f3y) with the permuted order of fft_lines3
-template <typename V, bool INV, int LMY>
+// y transform of the runtime-length convolution body; lengths 3 2^lmy
+// (f3y) in the permuted order of fft_lines3
+template <typename V, bool INV>
 __device__ __forceinline__ void conv_fft_y(V* lines, int nlines, int lmy, int f3y, const V* twl)
 {
-    if constexpr (LMY > 0) fft_lines_ct<V, INV, LMY, SSM_CONV_CT_RADIX_BITS>(lines, nlines, twl);
-    else if (f3y) fft_lines3<V, INV, SSM_CONV_RADIX_BITS>(lines, nlines, lmy, twl);
+    if (f3y) fft_lines3<V, INV, SSM_CONV_RADIX_BITS>(lines, nlines, lmy, twl);
     else fft_lines<V, INV, SSM_CONV_RADIX_BITS>(lines, nlines, 1 << lmy, lmy, twl);
 }
 
-// z-phase of the compile-time-length convolution body: for every column
-// (slice g, y frequency qy) of the G slices in LDS, both z halves of the
-// padded z transform (length-MZ DFTs), the 3x3 kernel-spectrum multiply,
-// the inverse and the sum of the halves.  NZ > 0 fixes nz at compile time.
-template <typename T, int MZ, int LMY, int NZ, int PADL>
+// z-phase of the compile-time-length convolution bodies: for every column
+// (slice g, position py, y frequency qy) of the G slices in LDS, both z
+// halves of the padded z transform (length-MZ DFTs), the 3x3 kernel-
+// spectrum multiply, the inverse and the sum of the halves.  NZ > 0 fixes
+// nz at compile time.  y length MY = 2^LMY, or 3 2^LMY (F3) with the
+// permuted frequency order of the 3 2^a transforms.
+template <typename T, int MZ, int LMY, int NZ, int PADL, int F3 = 0>
 __device__ __forceinline__ void conv_zphase(const Prob& p, int G, int kx0, int hy, cplx<T>* lines,
                                             const T* __restrict__ nhat, const cplx<T>* __restrict__ tw)
 {
     using V = cplx<T>;
-    constexpr int MY = 1 << LMY;
+    constexpr int MY = (F3 ? 3 : 1) << LMY;
     const int nz = NZ > 0 ? NZ : p.nz, nhz = p.nhz, nsl_img = p.mx + 1;
     int col0 = threadIdx.x;
     asm volatile("" : "+v"(col0));
-    for (int col = col0; col < (G << LMY); col += kNT) {
-        const int g = col >> LMY, qy = col & (MY - 1);
+    for (int col = col0; col < G * MY; col += kNT) {
+        const int g = col / MY, py = col - g * MY;
+        const int qy = F3 ? unperm3(py, LMY) : py;
         int kx = kx0 + g;
         while (kx >= nsl_img) kx -= nsl_img;
-        // padded offsets: cbase % 2^PADL = qy % 2^PADL and the line offsets
+        // padded offsets: cbase % 2^PADL = py % 2^PADL and the line offsets
         // are multiples of the line length, so padx distributes
-        const int cbase = padx<PADL>(((g * 3 * nz) << LMY) + qy);
+        const int cbase = padx<PADL>(g * 3 * nz * MY + py);
         V b[3][MZ];
         // the two z halves as separate bodies (hz a compile-time constant:
         // the even half has no twiddles, and no selects between the halves)
@@ -388,13 +483,13 @@ __device__ __forceinline__ void conv_zphase(const Prob& p, int G, int kx0, int h
             for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int zz = 0; zz < MZ; ++zz) {
-                    V v = (zz < nz) ? lines[cbase + padx<PADL>((c * nz + zz) << LMY)] : mk<V>(0, 0);
+                    V v = (zz < nz) ? lines[cbase + padx<PADL>((c * nz + zz) * MY)] : mk<V>(0, 0);
                     if constexpr (hz == 1) v = twz<false, V, MZ>(v, zz, tw);
                     a[c][zz] = v;
                 }
 #pragma unroll
             for (int c = 0; c < 3; ++c) dft_reg<V, MZ, false>(a[c]);
-            const T* nh = nhat + p.nh_off + (((((long long)kx * nhz + hz) * 2 + hy) * MZ) * 6 << LMY) + qy;
+            const T* nh = nhat + p.nh_off + (((((long long)kx * nhz + hz) * 2 + hy) * MZ) * 6 * MY) + qy;
 #pragma unroll
             for (int r = 0; r < MZ; ++r) {
                 // z frequency kz = 2r + hz and its mirror -kz (mod 2 MZ) hold
@@ -407,7 +502,7 @@ __device__ __forceinline__ void conv_zphase(const Prob& p, int G, int kx0, int h
                 constexpr bool kMir = SSM_CONV_NH_MIRROR && (MZ <= 4 || LMY >= 8);
                 const bool mir = kMir && (hz == 0 ? 2 * r > MZ : 2 * r >= MZ);
                 const int rs = mir ? (hz == 0 ? MZ - r : MZ - 1 - r) : r;
-                const T* q6 = nh + (rs * 6 << LMY);
+                const T* q6 = nh + rs * 6 * MY;
                 if (SSM_CONV_NH_SERIAL) asm volatile("" : "+v"(q6));
                 const T nxx = q6[0], nxy = q6[MY], nxz = mir ? -q6[2 * MY] : q6[2 * MY];
                 const T nyy = q6[3 * MY], nyz = mir ? -q6[4 * MY] : q6[4 * MY], nzz = q6[5 * MY];
@@ -437,7 +532,7 @@ __device__ __forceinline__ void conv_zphase(const Prob& p, int G, int kx0, int h
         for (int c = 0; c < 3; ++c)
 #pragma unroll
             for (int zz = 0; zz < MZ; ++zz)
-                if (zz < nz) lines[cbase + padx<PADL>((c * nz + zz) << LMY)] = b[c][zz];
+                if (zz < nz) lines[cbase + padx<PADL>((c * nz + zz) * MY)] = b[c][zz];
     }
 }
 
@@ -504,11 +599,12 @@ __device__ __forceinline__ void conv_body_ct(const Prob& p, int s0, int G, cplx<
 #pragma unroll
                             for (int r = 0; r < R0; ++r) v[b][r] = src[j + r * P0::Q];
                         } else {
+                            // loads from inside the line first, then zeros
 #pragma unroll
-                            for (int r = 0; r < R0; ++r) {
-                                const int y = j + r * P0::Q;
-                                v[b][r] = (y < ny) ? src[y] : mk<V>(0, 0);
-                            }
+                            for (int r = 0; r < R0; ++r) v[b][r] = src[min(j + r * P0::Q, ny - 1)];
+#pragma unroll
+                            for (int r = 0; r < R0; ++r)
+                                if (j + r * P0::Q >= ny) v[b][r] = mk<V>(0, 0);
                         }
                         if (hy) {
 #pragma unroll
@@ -582,10 +678,9 @@ __device__ __forceinline__ void conv_body_ct(const Prob& p, int s0, int G, cplx<
     }
 }
 
-// The convolution of G slices starting at s0.  LMY > 0 fixes the y length
-// m_y = 2^LMY at compile time (all FFT indexing constant-folds); LMY = 0
-// takes it from the problem.
-template <typename T, int MZ, int LMY>
+// The convolution of G slices starting at s0, y length from the problem
+// (the runtime-length body).
+template <typename T, int MZ>
 __device__ __forceinline__ void conv_body(const Prob& p, int s0, int G, cplx<T>* __restrict__ X,
                                           cplx<T>* __restrict__ Xp, const T* __restrict__ nhat,
                                           const cplx<T>* __restrict__ tw, cplx<T>* smem)
@@ -593,8 +688,7 @@ __device__ __forceinline__ void conv_body(const Prob& p, int s0, int G, cplx<T>*
     using V = cplx<T>;
     const int nsl_img = p.mx + 1;
     const int nz = p.nz, ny = p.ny, nhz = p.nhz;
-    const int lmy = LMY > 0 ? LMY : p.lmy, f3y = LMY > 0 ? 0 : p.f3y;
-    const int my = LMY > 0 ? 1 << LMY : p.my;
+    const int lmy = p.lmy, f3y = p.f3y, my = p.my;
     const int per = 3 * nz * ny, nel = G * per, nlines = G * 3 * nz;
     V* twl = smem;
     V* lines = twl + 2 * my;
@@ -630,7 +724,7 @@ __device__ __forceinline__ void conv_body(const Prob& p, int s0, int G, cplx<T>*
             }
         }
         __syncthreads();
-        conv_fft_y<V, false, LMY>(lines, nlines, lmy, f3y, twl);
+        conv_fft_y<V, false>(lines, nlines, lmy, f3y, twl);
         __syncthreads();
 
         int col0 = threadIdx.x;
@@ -691,7 +785,7 @@ __device__ __forceinline__ void conv_body(const Prob& p, int s0, int G, cplx<T>*
                     if (zz < nz) lines[lds_pad(cbase + (c * nz + zz) * my)] = b[c][zz];
         }
         __syncthreads();
-        conv_fft_y<V, true, LMY>(lines, nlines, lmy, f3y, twl);
+        conv_fft_y<V, true>(lines, nlines, lmy, f3y, twl);
         __syncthreads();
         {
             // y half hy = 0 goes to the output slice, hy = 1 (un-twiddled)
@@ -710,6 +804,155 @@ __device__ __forceinline__ void conv_body(const Prob& p, int s0, int G, cplx<T>*
             }
         }
         __syncthreads();
+    }
+}
+
+// Compile-time-length body for y lengths m_y = 3 M, M = 2^LMY (48, 96,
+// 192).  As conv_body_ct, with the radix-3 steps of the y transform
+// (ssm_fft.hpp) fused into the global-memory side: the forward one reads
+// the slice (zero beyond ny, the odd-half twiddle applied), does the radix-3
+// butterflies and the first, radix-4 pass of the three sub-lines, and
+// writes to LDS; the inverse one does the last, radix-4 pass of the three
+// sub-lines and the inverse radix-3 butterflies, and writes the slice.  A
+// wavefront owns whole lines (PLG of them, 3 PLG sub-lines), so only the
+// z-phase needs workgroup barriers.
+template <typename T, int MZ, int LMY>
+__device__ __forceinline__ void conv_body_ct3(const Prob& p, int s0, int G, cplx<T>* __restrict__ X,
+                                              cplx<T>* __restrict__ Xp, const T* __restrict__ nhat,
+                                              const cplx<T>* __restrict__ tw, cplx<T>* smem)
+{
+    using V = cplx<T>;
+    constexpr int MB = SSM_CONV_CT_RADIX_BITS;
+    constexpr int M = 1 << LMY, MY = 3 * M;
+    constexpr int PLG = 1024 / MY;      // lines per wavefront group
+    constexpr int BF = 2, RF = 1 << BF;  // fused sub-line passes: radix 4
+    constexpr int QF = M / RF;           // their butterflies per sub-line
+    constexpr int LQF = LMY - BF;
+    constexpr int PADL = conv_padl(MZ, LMY, 1);
+    static_assert(PLG >= 1 && LMY - BF >= 2, "length outside the compile-time 3 2^a set");
+    const int nsl_img = p.mx + 1;
+    const int nz = p.nz, ny = p.ny;
+    const int per = 3 * nz * ny, nlines = G * 3 * nz;
+    load_twiddles(smem, LMY, 1, tw);
+    const V* twl = smem;
+    V* lines = smem + 2 * MY;
+    V* in = X + p.x_off + (long long)s0 * per;
+    V* out = Xp + p.x_off + (long long)s0 * per;
+    const int kx0 = s0 % nsl_img;
+    const int wave = threadIdx.x >> 6;
+    constexpr int NW = kNT / 64;
+    __syncthreads();
+
+#pragma unroll 1
+    for (int hy = 0; hy < 2; ++hy) {
+        int lane = threadIdx.x;
+        asm volatile("" : "+v"(lane));
+        lane &= 63;
+        for (int g0 = wave * PLG; g0 < nlines; g0 += NW * PLG) {
+            const int gl = min(PLG, nlines - g0);
+            // item (line, j): inputs y = j + r QF + t M (r < 4, t < 3), all
+            // loaded (from inside the line) before any is used, then zeroed
+            // beyond ny
+            for (int it = lane; it < (gl << LQF); it += 64) {
+                const int line = it >> LQF, j = it & (QF - 1);
+                const V* src = in + (long long)(g0 + line) * ny;
+                V v[3][RF];
+#pragma unroll
+                for (int t = 0; t < 3; ++t)
+#pragma unroll
+                    for (int r = 0; r < RF; ++r) v[t][r] = src[min(j + r * QF + t * M, ny - 1)];
+                if (hy) {
+#pragma unroll
+                    for (int t = 0; t < 3; ++t)
+#pragma unroll
+                        for (int r = 0; r < RF; ++r) v[t][r] = cmul(v[t][r], twl[j + r * QF + t * M]);
+                }
+#pragma unroll
+                for (int t = 0; t < 3; ++t)
+#pragma unroll
+                    for (int r = 0; r < RF; ++r)
+                        if (j + r * QF + t * M >= ny) v[t][r] = mk<V>(0, 0);
+#pragma unroll
+                for (int r = 0; r < RF; ++r) {
+                    const int k = j + r * QF;
+                    radix3_bfly<false>(v[0][r], v[1][r], v[2][r], twl[2 * k], twl[4 * k]);
+                }
+                // first pass (sub-length 1) of sub-line t: outputs at j RF + r
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    dft_reg<V, RF, false>(v[t]);
+                    const int b = (((g0 + line) * 3 + t) << LMY) + j * RF;
+#pragma unroll
+                    for (int r = 0; r < RF; ++r) lines[padx<PADL>(b + r)] = v[t][r];
+                }
+            }
+            wave_sync();
+            fft_passes_ct_to<V, false, LMY, MB, BF, LMY, PADL, 0, false, 3>(lines, (3 * g0) << LMY, 3 * gl, twl,
+                                                                           lane);
+        }
+        __syncthreads();
+
+        conv_zphase<T, MZ, LMY, 0, PADL, 1>(p, G, kx0, hy, lines, nhat, tw);
+        __syncthreads();
+
+        lane = threadIdx.x;
+        asm volatile("" : "+v"(lane));
+        lane &= 63;
+        for (int g0 = wave * PLG; g0 < nlines; g0 += NW * PLG) {
+            const int gl = min(PLG, nlines - g0);
+            fft_passes_ct_span<V, true, LMY, MB, 0, LMY - BF, PADL, 3>(lines, (3 * g0) << LMY, 3 * gl, twl, lane);
+            // item (line, j): the last pass (sub-length M / 4) of the three
+            // sub-lines gives their values at k = j + r QF, the inverse
+            // radix-3 butterflies turn them into y = k + t M
+            for (int it = lane; it < (gl << LQF); it += 64) {
+                const int line = it >> LQF, j = it & (QF - 1);
+                V v[3][RF];
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    const int b = (((g0 + line) * 3 + t) << LMY) + j;
+#pragma unroll
+                    for (int r = 0; r < RF; ++r) {
+                        V a = lines[padx<PADL>(b + r * QF)];
+                        // twiddle W_{4 QF}^{r j} = twl[3 (2 r j)] of the 3 M table
+                        if (r > 0) a = cmulc(a, twl[6 * r * j]);
+                        v[t][r] = a;
+                    }
+                    dft_reg<V, RF, true>(v[t]);
+                }
+                V* dst = out + (long long)(g0 + line) * ny;
+#pragma unroll
+                for (int r = 0; r < RF; ++r) {
+                    const int k = j + r * QF;
+                    radix3_bfly<true>(v[0][r], v[1][r], v[2][r], twl[2 * k], twl[4 * k]);
+                }
+                // y half hy = 0 to the output slice; hy = 1 (un-twiddled) added
+                // onto it (this thread stored those half-0 values itself; all
+                // are loaded, from inside the line, before any is stored)
+                if (hy) {
+                    V h0[3][RF];
+#pragma unroll
+                    for (int t = 0; t < 3; ++t)
+#pragma unroll
+                        for (int r = 0; r < RF; ++r) h0[t][r] = dst[min(j + r * QF + t * M, ny - 1)];
+#pragma unroll
+                    for (int t = 0; t < 3; ++t)
+#pragma unroll
+                        for (int r = 0; r < RF; ++r) {
+                            const int y = j + r * QF + t * M;
+                            v[t][r] = cadd(cmulc(v[t][r], twl[y]), h0[t][r]);
+                        }
+                }
+#pragma unroll
+                for (int t = 0; t < 3; ++t)
+#pragma unroll
+                    for (int r = 0; r < RF; ++r) {
+                        const int y = j + r * QF + t * M;
+                        if (y < ny) dst[y] = v[t][r];
+                    }
+            }
+            // the next forward pass of this group rewrites these lines
+            wave_sync();
+        }
     }
 }
 
@@ -748,8 +991,9 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         G = min(p.gconv, nsl - s0);
     }
     cplx<T>* sm = reinterpret_cast<cplx<T>*>(smem_);
-    if constexpr (BUILD > 0) conv_body_ct<T, MZ, BUILD>(p, s0, G, X, Xp, nhat, tw, sm);
-    else conv_body<T, MZ, 0>(p, s0, G, X, Xp, nhat, tw, sm);
+    if constexpr (BUILD >= 16) conv_body_ct3<T, MZ, BUILD - 16>(p, s0, G, X, Xp, nhat, tw, sm);
+    else if constexpr (BUILD > 0) conv_body_ct<T, MZ, BUILD>(p, s0, G, X, Xp, nhat, tw, sm);
+    else conv_body<T, MZ>(p, s0, G, X, Xp, nhat, tw, sm);
 }
 
 // The value of the next (previous) lane of the wavefront: DPP wavefront
@@ -793,7 +1037,7 @@ __device__ __forceinline__ T lane_prev(T v)
 // LDS: twiddles (2m) + yt lines of m + the tile's dipolar field (3 yt nx).
 // ---------------------------------------------------------------------------
 template <typename T, int F3>
-__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_xinv(const Prob* __restrict__ P, int np,
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? SSM_XINV_WAVES_F32 : 3, 8))) void k_xinv(const Prob* __restrict__ P, int np,
                                               const int* __restrict__ wstart,
                                               const cplx<T>* __restrict__ Xp,
                                               const T* __restrict__ s, T* __restrict__ ss,
@@ -863,15 +1107,44 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         __syncthreads();
         fft_lines_x<V, true>(lines, yt, lm, f3, twl);
         __syncthreads();
-        for (int idx = threadIdx.x; idx < hp * m; idx += kNT) {
-            int rp, x;
-            divlen(idx, lm, f3, rp, x);
-            if (x >= nx) continue;
-            const int ie = (2 * rp) * m + x, io = ie + m;
-            const V e = lines[ie + (ie >> psh)];
-            const V o = cmulc(lines[io + (io >> psh)], twl[x]);
-            hd[(c * yt + 2 * rp) * nx + x] = e.x + o.x;
-            hd[(c * yt + 2 * rp + 1) * nx + x] = e.y + o.y;
+        if constexpr (F3) {
+            // the inverse radix-3 step (decimation in time) on the way out:
+            // sub-line positions k of both half lines give x = k + t 2^lm
+            const int M = 1 << lm;
+            for (int idx = threadIdx.x; idx < (hp << lm); idx += kNT) {
+                const int rp = idx >> lm, k = idx & (M - 1);
+                if (k >= nx) continue;
+                const int ie = (2 * rp) * m + k, io = ie + m;
+                V e[3], o[3];
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    const int a = ie + t * M, b = io + t * M;
+                    e[t] = lines[a + (a >> psh)];
+                    o[t] = lines[b + (b >> psh)];
+                }
+                const V w1 = twl[2 * k], w2 = twl[4 * k];
+                radix3_bfly<true>(e[0], e[1], e[2], w1, w2);
+                radix3_bfly<true>(o[0], o[1], o[2], w1, w2);
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    const int x = k + t * M;
+                    if (x < nx) {
+                        const V ot = cmulc(o[t], twl[x]);
+                        hd[(c * yt + 2 * rp) * nx + x] = e[t].x + ot.x;
+                        hd[(c * yt + 2 * rp + 1) * nx + x] = e[t].y + ot.y;
+                    }
+                }
+            }
+        } else {
+            for (int idx = threadIdx.x; idx < hp * m; idx += kNT) {
+                const int rp = idx >> lm, x = idx & (m - 1);
+                if (x >= nx) continue;
+                const int ie = (2 * rp) * m + x, io = ie + m;
+                const V e = lines[ie + (ie >> psh)];
+                const V o = cmulc(lines[io + (io >> psh)], twl[x]);
+                hd[(c * yt + 2 * rp) * nx + x] = e.x + o.x;
+                hd[(c * yt + 2 * rp + 1) * nx + x] = e.y + o.y;
+            }
         }
         __syncthreads();
     }
@@ -1716,6 +1989,9 @@ static hipError_t launch_conv_mz(int kinds, const Prob* P, int np, const WorkMap
         if (kinds & (1 << 6)) launch_conv_b<T, MZ, 6>(P, np, wm, x, xp, nhat, t, done, lds, st);
         if (kinds & (1 << 7)) launch_conv_b<T, MZ, 7>(P, np, wm, x, xp, nhat, t, done, lds, st);
         if (kinds & (1 << 8)) launch_conv_b<T, MZ, 8>(P, np, wm, x, xp, nhat, t, done, lds, st);
+        if (kinds & (1 << 20)) launch_conv_b<T, MZ, 20>(P, np, wm, x, xp, nhat, t, done, lds, st);
+        if (kinds & (1 << 21)) launch_conv_b<T, MZ, 21>(P, np, wm, x, xp, nhat, t, done, lds, st);
+        if (kinds & (1 << 22)) launch_conv_b<T, MZ, 22>(P, np, wm, x, xp, nhat, t, done, lds, st);
     }
     return hipGetLastError();
 }

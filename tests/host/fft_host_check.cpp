@@ -46,19 +46,19 @@ static void host_fft_lines(V* buf, int nl, int ls, int lm, const V* twl, int max
 }
 
 // the compile-time passes (PassCT), same lockstep emulation
-template <typename V, bool INV, int LM, int MAXB, int LNS, int PADL, int TWS, bool SW = false>
+template <typename V, bool INV, int LM, int MAXB, int LNS, int PADL, int TWS, bool SW = false, int TST = 1>
 static void host_passes_ct(V* buf, int off0, int gl, const V* twl)
 {
     if constexpr (LNS < LM) {
         constexpr int bits = fft_next_bits(LM - LNS, MAXB);
         constexpr int R = 1 << bits;
-        using P = PassCT<V, R, INV, LM, LNS, PADL, TWS, SW && LNS == 4, SW && LNS == 0>;
+        using P = PassCT<V, R, INV, LM, LNS, PADL, TWS, SW && LNS == 4, SW && LNS == 0, TST>;
         std::vector<V> regs(64 * P::B * R);
         for (int lane = 0; lane < 64; ++lane)
             P::read(buf, off0, gl, twl, lane, *reinterpret_cast<V(*)[P::B][R]>(&regs[lane * P::B * R]));
         for (int lane = 0; lane < 64; ++lane)
             P::write(buf, off0, gl, lane, *reinterpret_cast<V(*)[P::B][R]>(&regs[lane * P::B * R]));
-        host_passes_ct<V, INV, LM, MAXB, LNS + bits, PADL, TWS, SW>(buf, off0, gl, twl);
+        host_passes_ct<V, INV, LM, MAXB, LNS + bits, PADL, TWS, SW, TST>(buf, off0, gl, twl);
     }
 }
 
@@ -217,13 +217,46 @@ static double check(int lm, int nl, int pad, unsigned seed, int maxb)
     return worst / (nrm > 0 ? nrm : 1);
 }
 
+// the compile-time passes over the 3 nl sub-lines of length 2^LM with the
+// parent lines' table at stride 3 (the x kernels and the compile-time
+// 3 2^a convolution body), groups as on the device,
+// lines in the pad-PADL layout
+template <typename V, bool INV, int LM, int MAXB, int PADL>
+static void host_lines3_ct(V* buf, int nsub, const V* twl)
+{
+    constexpr int LPG = fft_group_lines(LM);
+    for (int g0 = 0; g0 < nsub; g0 += LPG)
+        host_passes_ct<V, INV, LM, MAXB, 0, PADL, 0, false, 3>(buf, g0 << LM, std::min(LPG, nsub - g0), twl);
+}
+
+template <typename V, bool INV, int MAXB, int PADL>
+static bool host_lines3_ct_lm(V* buf, int nsub, int lm, const V* twl)
+{
+    switch (lm) {
+    case 4: host_lines3_ct<V, INV, 4, MAXB, PADL>(buf, nsub, twl); return true;
+    case 5: host_lines3_ct<V, INV, 5, MAXB, PADL>(buf, nsub, twl); return true;
+    case 6: host_lines3_ct<V, INV, 6, MAXB, PADL>(buf, nsub, twl); return true;
+    case 7: host_lines3_ct<V, INV, 7, MAXB, PADL>(buf, nsub, twl); return true;
+    default: return false;
+    }
+}
+
+template <typename V, bool INV, int MAXB>
+static bool host_lines3_ct_any(V* buf, int nsub, int lm, int padl, const V* twl)
+{
+    return padl ? host_lines3_ct_lm<V, INV, MAXB, 4>(buf, nsub, lm, twl)
+                : host_lines3_ct_lm<V, INV, MAXB, 0>(buf, nsub, lm, twl);
+}
+
 // Lines of length m = 3 2^lm (fft_lines3): the radix-3 step of every
 // (line, k) butterfly (independent, so any order), and the power-of-two
-// passes over the 3 nl sub-lines with the length-2m table at stride 3.
+// passes over the 3 nl sub-lines with the length-2m table at stride 3
+// (runtime passes, or with ct the compile-time ones, in the dense layout or
+// with padl = 4 the pad-4 layout).
 // Forward: natural input, frequency q at position perm3(q); inverse: input
 // of frequency q at perm3(q), natural output.
 template <typename V, bool INV>
-static double check3(int lm, int nl, unsigned seed, int maxb)
+static double check3(int lm, int nl, unsigned seed, int maxb, bool ct = false, int padl = 0)
 {
     using S = decltype(V::x);
     const int M = 1 << lm, m = 3 * M;
@@ -255,22 +288,29 @@ static double check3(int lm, int nl, unsigned seed, int maxb)
             }
             ref[(size_t)l * m + k] = mk<V>((S)sr, (S)si);
         }
+    // physical position of element i of the lines
+    auto P = [&](size_t i) { return padl ? i + (i >> padl) : i; };
+    buf.assign(P((size_t)nl * m) + 1, mk<V>((S)0, (S)0));
     for (int l = 0; l < nl; ++l)
-        for (int q = 0; q < m; ++q) buf[(size_t)l * m + (INV ? perm3(q, lm) : q)] = x[(size_t)l * m + q];
+        for (int q = 0; q < m; ++q) buf[P((size_t)l * m + (INV ? perm3(q, lm) : q))] = x[(size_t)l * m + q];
     auto step = [&](auto inv) {
         for (int i = 0; i < nl * M; ++i) {
             const int line = i >> lm, k = i & (M - 1);
-            V* p = buf.data() + (size_t)line * m + k;
-            radix3_bfly<decltype(inv)::value>(p[0], p[M], p[2 * M], twl[2 * k], twl[4 * k]);
+            const size_t i0 = (size_t)line * m + k;
+            radix3_bfly<decltype(inv)::value>(buf[P(i0)], buf[P(i0 + M)], buf[P(i0 + 2 * M)], twl[2 * k],
+                                              twl[4 * k]);
         }
     };
     if (!INV) step(std::false_type{});
-    host_fft_lines<V, INV, 3>(buf.data(), 3 * nl, M, lm, twl.data(), maxb);
+    if (!ct) host_fft_lines<V, INV, 3>(buf.data(), 3 * nl, M, lm, twl.data(), maxb);
+    else if (maxb == 2) host_lines3_ct_any<V, INV, 2>(buf.data(), 3 * nl, lm, padl, twl.data());
+    else if (maxb == 3) host_lines3_ct_any<V, INV, 3>(buf.data(), 3 * nl, lm, padl, twl.data());
+    else host_lines3_ct_any<V, INV, 4>(buf.data(), 3 * nl, lm, padl, twl.data());
     if (INV) step(std::true_type{});
     double worst = 0, nrm = 0;
     for (int l = 0; l < nl; ++l)
         for (int q = 0; q < m; ++q) {
-            const V a = buf[(size_t)l * m + (INV ? q : perm3(q, lm))], b = ref[(size_t)l * m + q];
+            const V a = buf[P((size_t)l * m + (INV ? q : perm3(q, lm)))], b = ref[(size_t)l * m + q];
             worst = fmax(worst, fabs((double)a.x - (double)b.x));
             worst = fmax(worst, fabs((double)a.y - (double)b.y));
             nrm = fmax(nrm, fabs((double)b.x) + fabs((double)b.y));
@@ -303,6 +343,22 @@ int main()
                 const double e32i = check3<float2, true>(lm, nl, 37 + lm, maxb);
                 std::printf("radix3 maxb=%d m=%5d lines=%5d fp64 %.2e %.2e fp32 %.2e %.2e\n", maxb, 3 << lm, nl,
                             e64f, e64i, e32f, e32i);
+                if (e64f > 1e-14 || e64i > 1e-14 || e32f > 2e-6 || e32i > 2e-6) bad = 1;
+            }
+        }
+    // the same with the compile-time sub-line passes (lengths 48 .. 384),
+    // dense and pad-4 layouts
+    for (int maxb = 2; maxb <= 4; ++maxb)
+        for (int lm = 4; lm <= 7; ++lm) {
+            const int nls[2] = {1, 1024 / (1 << lm) + 1};
+            for (int t = 0; t < 4; ++t) {
+                const int nl = nls[t & 1], padl = t < 2 ? 0 : 4;
+                const double e64f = check3<double2, false>(lm, nl, 41 + lm, maxb, true, padl);
+                const double e64i = check3<double2, true>(lm, nl, 43 + lm, maxb, true, padl);
+                const double e32f = check3<float2, false>(lm, nl, 47 + lm, maxb, true, padl);
+                const double e32i = check3<float2, true>(lm, nl, 53 + lm, maxb, true, padl);
+                std::printf("radix3 ct maxb=%d m=%5d lines=%5d pad %d fp64 %.2e %.2e fp32 %.2e %.2e\n", maxb,
+                            3 << lm, nl, padl, e64f, e64i, e32f, e32i);
                 if (e64f > 1e-14 || e64i > 1e-14 || e32f > 2e-6 || e32i > 2e-6) bad = 1;
             }
         }

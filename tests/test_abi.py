@@ -69,27 +69,22 @@ def test_workspace_size_rejects(bad, status):
 
 
 def half_len(n, axis="x", nz=1):
-    """The documented half padded length of the x or y axis: the power of
-    two >= n, or for n > 32 the length 3 2^a >= n (a >= 4, at most 768) when
-    that is smaller and the power of two exceeds 512 (x) or 256 (y; or the
-    padded layer count m_z exceeds 8 for y)."""
+    """The documented half padded length of the x or y axis (the same rule
+    for both, any layer count): the power of two >= n, or for n > 32 the
+    length 3 2^a >= n (a >= 4, at most 768) when that is smaller."""
     p2 = 1 << (n - 1).bit_length()
-    mz = 1 if nz == 1 else 1 << (nz - 1).bit_length()
-    slow = p2 > 512 if axis == "x" else (p2 > 256 or mz > 8)
     t = 48
     while t < n:
         t *= 2
-    return t if n > 32 and slow and t < p2 and t <= 768 else p2
+    return t if n > 32 and t < p2 and t <= 768 else p2
 
 
 def test_half_lengths():
     ns = (1, 3, 32, 33, 48, 49, 64, 65, 96, 97, 100, 129, 192, 200, 257, 300, 500, 513, 700, 769, 1024)
-    assert [half_len(n, "x") for n in ns] == \
-        [1, 4, 32, 64, 64, 64, 64, 128, 128, 128, 128, 256, 256, 256, 512, 512, 512, 768, 768, 1024, 1024]
-    assert [half_len(n, "y") for n in ns] == \
-        [1, 4, 32, 64, 64, 64, 64, 128, 128, 128, 128, 256, 256, 256, 384, 384, 512, 768, 768, 1024, 1024]
-    assert [half_len(n, "y", nz=12) for n in ns] == \
-        [1, 4, 32, 48, 48, 64, 64, 96, 96, 128, 128, 192, 192, 256, 384, 384, 512, 768, 768, 1024, 1024]
+    want = [1, 4, 32, 48, 48, 64, 64, 96, 96, 128, 128, 192, 192, 256, 384, 384, 512, 768, 768, 1024, 1024]
+    assert [half_len(n, "x") for n in ns] == want
+    assert [half_len(n, "y") for n in ns] == want
+    assert [half_len(n, "y", nz=12) for n in ns] == want
 
 
 @pytest.mark.parametrize("precision,cap", [(ssm.SSM_FP64, 10240), (ssm.SSM_FP32_MIXED, 20480)])

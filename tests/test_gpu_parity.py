@@ -31,12 +31,14 @@ def rel_field(a, b):
 
 # ragged and power-of-two sizes; odd and even log2 transform lengths with full
 # line groups (32, 128, 512 along x); 1, 2, 3-4, 5-8 and 16 layers; half
-# padded lengths 3 2^a: 768 along x, 384 along y, 48 and 96 along y with
-# 9-16 layers
+# padded lengths 3 2^a: runtime-length 768 along x, 384 along y, 48 and 96
+# along y with 9-16 layers; compile-time-length 48, 96, 192 and 384 along x
+# and 48, 96 and 192 along y with 1, 4 and 8 padded layers
 SHAPES = [(1, 1, 1), (2, 2, 1), (5, 3, 1), (1, 6, 1), (9, 1, 1), (6, 5, 3), (7, 9, 2),
           (33, 17, 1), (16, 16, 4), (12, 10, 8), (20, 3, 5), (3, 4, 16), (32, 32, 1),
           (100, 20, 1), (300, 5, 1), (2, 64, 1), (1000, 3, 1), (40, 128, 1),
-          (20, 40, 1), (70, 70, 1), (16, 150, 1), (600, 5, 1), (33, 300, 1), (5, 40, 12), (6, 70, 9)]
+          (20, 40, 1), (70, 70, 1), (16, 150, 1), (600, 5, 1), (33, 300, 1), (5, 40, 12), (6, 70, 9),
+          (150, 20, 1), (50, 90, 3), (12, 140, 5)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
