@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 import torch
 
-from paper_1804_07135_amd import inputs, ssm
+from paper_1804_07135_amd import inputs, ssm, sweep
 
 pytestmark = pytest.mark.gpu
 
@@ -123,6 +123,31 @@ def test_iterate_workload_32x32_fp64(oracle):
     assert abs(bar[0] - B) <= TOL64 * abs(B)
     assert int(bar[1]) == km
     assert np.abs(sm.get_string().cpu().numpy() - r["s"]).max() < TOL64
+
+
+@pytest.mark.parametrize("L", [65, 72, 96])
+def test_iterate_sweep_lattices_vs_oracle(oracle, L):
+    """L x L x 1 lattices of the (k_u, d) sweep that take the 96-point
+    transforms (padded length 192 for 2L - 1 = 129..191): the sweep's
+    Bloch-point string of 6 images, 5 iterations.  FP64: string, energies,
+    barrier and argmax against the oracle at 1e-10; FP32-mixed: barrier at
+    1e-4."""
+    p = prob(L, L, 1, 6, J=1.0, d=0.3, ku=0.1, D=0.01)
+    pt = dict(nx=L, ny=L, nz=1, K=6, R=5.0, seed=4000 + L)
+    s0 = sweep.initial_strings([pt])[0]
+    sm, r, n = run_both(oracle, p, s0, 5)
+    assert n == 5
+    assert np.abs(sm.get_string().cpu().numpy() - r["s"]).max() < TOL64
+    E = sm.energies().cpu().numpy()
+    np.testing.assert_allclose(E, r["E"], rtol=0, atol=TOL64 * np.abs(r["E"]).max())
+    B, km = oracle.barrier(r["E"])
+    bar = sm.barrier().cpu().numpy()[0]
+    assert abs(bar[0] - B) <= TOL64 * abs(B)
+    assert int(bar[1]) == km
+    s32 = ssm.StringMethod(p, ssm.SSM_FP32_MIXED)
+    s32.set_string(s0)
+    s32.iterate(5, 0.1)
+    assert abs(s32.barrier().cpu().numpy()[0, 0] - B) <= TOL32_BARRIER * abs(B)
 
 
 def test_iterate_workload_32x32_fp32_barrier(oracle):
