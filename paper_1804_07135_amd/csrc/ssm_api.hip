@@ -58,6 +58,10 @@ size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 #ifndef SSM_LEN3
 #define SSM_LEN3 1
 #endif
+// 1: the spline step in one pass where the image counts allow
+#ifndef SSM_SPLW
+#define SSM_SPLW 1
+#endif
 #ifndef SSM_LEN3_CT_X
 #define SSM_LEN3_CT_X 3
 #endif
@@ -91,6 +95,7 @@ struct Plan {
     int conv_kinds = 0;               // convolution builds in use (launch_conv)
     int x_kinds = 0;                  // x length kinds in use (launch_xfwd, launch_xinv)
     bool rk = false;                  // workspace of the adaptive integrator reserved
+    int kmax = 0;                     // largest image count of the batch
     size_t tsize = 8;                 // bytes of one spin component
     std::vector<Prob> P;
     std::vector<Tiles> tiles;         // tile shapes in use, per problem
@@ -347,6 +352,7 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
     }
     for (int i = 0; i < np; ++i) pl.P[i].nh_off = nh_off[pl.geo[i]];
     pl.n_img = img; pl.n_spin = spin; pl.n_x = xo; pl.n_nh = nh;
+    for (const Prob& q : pl.P) pl.kmax = std::max(pl.kmax, q.K);
     pl.n_ep = ep; pl.n_ap = ap; pl.n_fp = fp; pl.n_fm = fm;
     // work maps
     auto prefix = [&](std::vector<int>& v, auto count) {
@@ -576,7 +582,13 @@ struct Ops {
                                  flags, 1, st, o);
         });
         if (e != hipSuccess) return e;
-        if (o.opts & 1) {
+        if ((o.opts & 1) && SSM_SPLW && pl.kmax <= kSplwMax<T>) {
+            e = timed(c, st, KK_INTERP, [&] {
+                return launch_interp_splw<T>(c->P(), pl.np, c->wm_sitep(), pl.kmax, ss, s, c->at<int>(pl.o_j),
+                                             c->at<double>(pl.o_w), o, done, flags, st);
+            });
+            if (e != hipSuccess) return e;
+        } else if (o.opts & 1) {
             T* M = c->at<T>(pl.o_h);
             e = timed(c, st, KK_INTERP, [&] {
                 return launch_spline_m<T>(c->P(), pl.np, c->wm_sitep(), ss, M, o, done, st);

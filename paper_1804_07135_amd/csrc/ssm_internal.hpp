@@ -197,6 +197,14 @@ template <typename T>
 hipError_t launch_interp_spline(const Prob* P, int np, const WorkMap& wm, const T* ss, const T* M, T* s,
                                 const int* jidx, const double* wgt, Step2 s2, const int* done, int* flags,
                                 hipStream_t st);
+// the spline step in one pass (K <= 16, or <= 32 in FP32; one thread per
+// site, wm_sitep); kmax: the largest image count of the batch
+template <typename T>
+constexpr int kSplwMax = sizeof(T) == 4 ? 32 : 16;
+template <typename T>
+hipError_t launch_interp_splw(const Prob* P, int np, const WorkMap& wm_sitep, int kmax, const T* ss, T* s,
+                              const int* jidx, const double* wgt, Step2 s2, const int* done, int* flags,
+                              hipStream_t st);
 // climbing image: partial sums (|t~|^2, F.t~) over image kci, their
 // per-problem reduction to c = F.t~ / |t~|^2, and the step
 // normalise(s + tau (F - 2 c t~)) into ss

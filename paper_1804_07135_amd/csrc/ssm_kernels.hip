@@ -2486,6 +2486,101 @@ __global__ __launch_bounds__(kNT) void k_interp_spline(const Prob* __restrict__ 
     }
 }
 
+// The same spline step in one pass for K <= KMAX: the interpolated value at
+// a target is linear in the K images of its site, s(t_k) = sum_i W_ki f_i,
+// so each workgroup first forms the problem's K x K operator W in LDS (the
+// columns of the second-derivative map by the Thomas recurrences of
+// k_spline_m applied to unit right-hand sides, then the spline formula of
+// k_interp_spline), and each thread then reads its site's K images once and
+// writes the K targets.  Endpoints and the climbing image are copied.
+template <typename T, int KMAX>
+__global__ __launch_bounds__(kNT) void k_interp_splw(const Prob* __restrict__ P, int np,
+                                                     const int* __restrict__ wstart, const T* __restrict__ ss,
+                                                     T* __restrict__ s, const int* __restrict__ jidx,
+                                                     const double* __restrict__ wgt, Step2 s2,
+                                                     const int* __restrict__ done, int* flags)
+{
+    __shared__ double Z[KMAX][KMAX];
+    __shared__ double W[KMAX][KMAX];
+    const int pi = find_problem(wstart, np, blockIdx.x);
+    if ((done && done[pi]) || !s2.spl_ok[pi]) return;
+    const Prob& p = P[pi];
+    const int K = p.K, g0 = p.img0, kci = s2.kci ? s2.kci[pi] : -1;
+    if (threadIdx.x < K) {
+        // column i: M as a function of the unit image e_i (M_0 = M_{K-1} = 0)
+        const int i = threadIdx.x;
+        double dpp = 0.0;
+        Z[0][i] = 0.0;
+        Z[K - 1][i] = 0.0;
+        for (int k = 1; k <= K - 2; ++k) {
+            const double r = ((i == k + 1 ? 1.0 : 0.0) - (i == k ? 1.0 : 0.0)) / s2.hh[g0 + k] -
+                             ((i == k ? 1.0 : 0.0) - (i == k - 1 ? 1.0 : 0.0)) / s2.hh[g0 + k - 1];
+            const double dp = (r - (k > 1 ? s2.sa[g0 + k] * dpp : 0.0)) / s2.den[g0 + k];
+            Z[k][i] = dp;
+            dpp = dp;
+        }
+        if (K >= 3) {
+            double mn = Z[K - 2][i];
+            for (int k = K - 3; k >= 1; --k) {
+                const double mk = Z[k][i] - s2.cp[g0 + k] * mn;
+                Z[k][i] = mk;
+                mn = mk;
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < KMAX * KMAX; e += kNT) {
+        const int k = e / KMAX, i = e % KMAX;
+        double w = 0.0;
+        if (k < K && i < K && k > 0 && k < K - 1 && k != kci) {
+            const int g = g0 + k, j = jidx[g];
+            const double A = s2.A[g], B = s2.B[g], h = s2.H[g];
+            w = (i == j ? A : 0.0) + (i == j + 1 ? B : 0.0) +
+                ((A * A * A - A) * Z[j][i] + (B * B * B - B) * Z[j + 1][i]) * h * h / 6.0;
+        }
+        W[k][i] = w;
+    }
+    __syncthreads();
+    const long long N = p.N, Ms = 3 * N;
+    const long long i = (long long)(blockIdx.x - wstart[pi]) * kNT + threadIdx.x;
+    if (i >= N) return;
+    const T* src = ss + p.s_off + i;
+    T* dst = s + p.s_off + i;
+    T f[3][KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) f[c][k] = (k < K) ? src[k * Ms + c * N] : T(0);
+#pragma unroll 1
+    for (int k = 0; k < K; ++k) {
+        if (k == 0 || k == K - 1 || k == kci) {
+            // copied like the endpoints (the same bits)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dst[k * Ms + c * N] = src[k * Ms + c * N];
+            continue;
+        }
+        double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q) {
+            const double w = W[k][q];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[c] += w * (double)f[c][q];
+        }
+        const double nrm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        if (!isfinite(nrm)) atomicOr(flags, 4);
+        if (nrm < 1e-12) {
+            atomicOr(flags, 2);
+            const int g = g0 + k, j = jidx[g];
+            const int jn = (wgt[g] < 0.5) ? j : j + 1;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dst[k * Ms + c * N] = src[jn * Ms + c * N];
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dst[k * Ms + c * N] = (T)(v[c] / nrm);
+        }
+    }
+}
+
 // one workgroup per (problem, site chunk): the image of highest energy
 // (every workgroup finds the same one) and, when interior, partial sums of
 // |t~|^2 and F.t~ over the chunk
@@ -2639,6 +2734,23 @@ hipError_t launch_interp_spline(const Prob* P, int np, const WorkMap& wm, const 
 }
 
 template <typename T>
+hipError_t launch_interp_splw(const Prob* P, int np, const WorkMap& wm_sitep, int kmax, const T* ss, T* s,
+                              const int* jidx, const double* wgt, Step2 s2, const int* done, int* flags,
+                              hipStream_t st)
+{
+    if (wm_sitep.total == 0) return hipSuccess;
+    if (kmax > kSplwMax<T>) return hipErrorInvalidValue;
+    if (kmax <= 16) {
+        hipLaunchKernelGGL((k_interp_splw<T, 16>), dim3(wm_sitep.total), dim3(kNT), 0, st, P, np, wm_sitep.start,
+                           ss, s, jidx, wgt, s2, done, flags);
+    } else if constexpr (kSplwMax<T> >= 32) {
+        hipLaunchKernelGGL((k_interp_splw<T, 32>), dim3(wm_sitep.total), dim3(kNT), 0, st, P, np, wm_sitep.start,
+                           ss, s, jidx, wgt, s2, done, flags);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_ci_part(const Prob* P, int np, const WorkMap& wm, const T* s, const T* h, const double* E,
                           double* part, int* kci, const int* done, hipStream_t st)
 {
@@ -2708,6 +2820,9 @@ hipError_t launch_fill_double(double* p, int n, double v, hipStream_t st)
                                          hipStream_t, const int*, const int*);                     \
     template hipError_t launch_spline_m<T>(const Prob*, int, const WorkMap&, const T*, T*, Step2,  \
                                            const int*, hipStream_t);                               \
+    template hipError_t launch_interp_splw<T>(const Prob*, int, const WorkMap&, int, const T*, T*, \
+                                              const int*, const double*, Step2, const int*, int*,  \
+                                              hipStream_t);                                        \
     template hipError_t launch_interp_spline<T>(const Prob*, int, const WorkMap&, const T*,        \
                                                 const T*, T*, const int*, const double*, Step2,    \
                                                 const int*, int*, hipStream_t);                    \

@@ -22,8 +22,11 @@ def params(p):
 
 
 @pytest.mark.parametrize("spline,climb", [(True, False), (False, True), (True, True)])
-@pytest.mark.parametrize("shape,K", [((12, 10, 1), 6), ((9, 8, 3), 5)])
+@pytest.mark.parametrize("shape,K", [((12, 10, 1), 6), ((9, 8, 3), 5), ((8, 7, 2), 16), ((12, 10, 1), 20)])
 def test_options_match_oracle(oracle, spline, climb, shape, K):
+    """FP64, 6 iterations, against the oracle at 1e-10.  K = 16 is the
+    largest image count of the one-pass spline step in FP64; K = 20 takes the
+    two-kernel one (second derivatives, then evaluation)."""
     nx, ny, nz = shape
     p = prob(nx, ny, nz, K, d=0.33, ku=0.12, D=0.05)
     s0 = inputs.perturb(inputs.bloch_point_string(nx, ny, nz, K, 2.5), 11)
@@ -34,6 +37,24 @@ def test_options_match_oracle(oracle, spline, climb, shape, K):
     r = oracle.iterate_opts(s0, *params(p), 6, 0.1, spline=spline, climb=climb)
     np.testing.assert_allclose(sm.get_string().cpu().numpy(), r["s"], rtol=0, atol=TOL64)
     np.testing.assert_allclose(sm.energies().cpu().numpy(), r["E"], rtol=0, atol=TOL64 * np.abs(r["E"]).max())
+
+
+@pytest.mark.parametrize("K", [24, 40])
+def test_fp32_spline_paths_vs_oracle(oracle, K):
+    """FP32-mixed form with the spline and the climbing image: K = 24 takes
+    the one-pass spline step (up to 32 images in FP32), K = 40 the two-kernel
+    one; both against the oracle run from the same FP32 string, 6 iterations
+    (spins 2e-5, energies 1e-5 relative)."""
+    p = prob(12, 10, 1, K, d=0.33, ku=0.12, D=0.05)
+    s0 = inputs.perturb(inputs.bloch_point_string(12, 10, 1, K, 2.5), 13).astype(np.float32)
+    sm = ssm.StringMethod(p, ssm.SSM_FP32_MIXED)
+    sm.set_reparam(ssm.SSM_INTERP_SPLINE, True)
+    sm.set_string(s0)
+    sm.iterate(6, 0.1)
+    assert sm.check() == 0
+    r = oracle.iterate_opts(s0.astype(np.float64), *params(p), 6, 0.1, spline=True, climb=True)
+    np.testing.assert_allclose(sm.get_string().cpu().numpy(), r["s"], rtol=0, atol=2e-5)
+    np.testing.assert_allclose(sm.energies().cpu().numpy(), r["E"], rtol=0, atol=1e-5 * np.abs(r["E"]).max())
 
 
 def test_bloch_32x32_climbing_spline_200(oracle):
