@@ -224,6 +224,79 @@ __device__ __forceinline__ void load16(const T* p, bool ok, T (&v)[16 / sizeof(T
     }
 }
 
+// Loads of k_xfwd for power-of-two x lengths m = 2^lm: row pair rp, site j
+// goes to position j of the even half line 2 rp and, twiddled by W_{2m}^j,
+// of the odd half line 2 rp + 1; zero beyond the lattice.  kXfwdU items
+// per thread per round: their loads, from positions clamped into the
+// lattice, are issued together (no load sits under a branch), then the
+// zeros are selected and the LDS writes done.  vecw: rows are read VW
+// sites per 16-byte load.
+#ifndef SSM_XFWD_U
+#define SSM_XFWD_U 4
+#endif
+constexpr int kXfwdU = SSM_XFWD_U;
+template <typename T>
+__device__ __forceinline__ void xfwd_load_lines(const T* __restrict__ sc, cplx<T>* lines, const cplx<T>* twl,
+                                                bool vecw, int hp, int m, int lm, int y0, int nx, int ny, int psh)
+{
+    using V = cplx<T>;
+    constexpr int VW = 16 / sizeof(T), LVW = VW == 4 ? 2 : 1;
+    auto put = [&](int rp, int j, V v) {
+        const int i0 = (2 * rp) * m + j, i1 = i0 + m;
+        lines[i0 + (i0 >> psh)] = v;
+        lines[i1 + (i1 >> psh)] = cmul(v, twl[j]);
+    };
+    if (vecw) {
+        const int lmv = lm - LVW;  // a line is m / VW chunks of VW sites
+        const int total = hp << lmv;
+#pragma unroll 1
+        for (int idx0 = threadIdx.x; idx0 < total; idx0 += kXfwdU * kNT) {
+            T av[kXfwdU][VW], bv[kXfwdU][VW];
+#pragma unroll
+            for (int u = 0; u < kXfwdU; ++u) {
+                const int idx = min(idx0 + u * kNT, total - 1);
+                const int rp = idx >> lmv, j = min((idx & ((1 << lmv) - 1)) << LVW, nx - VW);
+                const int ya = y0 + 2 * rp;
+                load16<T>(sc + (long long)min(ya, ny - 1) * nx + j, true, av[u]);
+                load16<T>(sc + (long long)min(ya + 1, ny - 1) * nx + j, true, bv[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < kXfwdU; ++u) {
+                const int idx = idx0 + u * kNT;
+                if (idx >= total) break;
+                const int rp = idx >> lmv, j = (idx & ((1 << lmv) - 1)) << LVW;
+                const int ya = y0 + 2 * rp;
+                const bool oka = j < nx && ya < ny, okb = j < nx && ya + 1 < ny;
+#pragma unroll
+                for (int k = 0; k < VW; ++k) put(rp, j + k, mk<V>(oka ? av[u][k] : T(0), okb ? bv[u][k] : T(0)));
+            }
+        }
+    } else {
+        const int total = hp << lm;
+#pragma unroll 1
+        for (int idx0 = threadIdx.x; idx0 < total; idx0 += kXfwdU * kNT) {
+            T a[kXfwdU], b[kXfwdU];
+#pragma unroll
+            for (int u = 0; u < kXfwdU; ++u) {
+                const int idx = min(idx0 + u * kNT, total - 1);
+                const int rp = idx >> lm, j = min(idx & (m - 1), nx - 1);
+                const int ya = y0 + 2 * rp;
+                a[u] = sc[(long long)min(ya, ny - 1) * nx + j];
+                b[u] = sc[(long long)min(ya + 1, ny - 1) * nx + j];
+            }
+#pragma unroll
+            for (int u = 0; u < kXfwdU; ++u) {
+                const int idx = idx0 + u * kNT;
+                if (idx >= total) break;
+                const int rp = idx >> lm, j = idx & (m - 1);
+                const int ya = y0 + 2 * rp;
+                const bool in = j < nx;
+                put(rp, j, mk<V>(in && ya < ny ? a[u] : T(0), in && ya + 1 < ny ? b[u] : T(0)));
+            }
+        }
+    }
+}
+
 // Loads of k_xfwd for x lengths m = 3 M (M = 2^lm) with the radix-3 step of
 // the forward transform (decimation in frequency, ssm_fft.hpp) applied on the
 // way: the thread of row pair rp and position k < M reads the sites k, k + M,
@@ -349,42 +422,8 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         const T* sc = si + (long long)c * N;
         if constexpr (F3) {
             xfwd_load3<T>(sc, lines, twl, vecw, hp, lm, y0, nx, ny, psh);
-        } else if (vecw) {
-            const int lmv = lm - LVW;  // a line is m / VW chunks of VW sites
-#pragma unroll 1
-            for (int idx = threadIdx.x; idx < hp * (m >> LVW); idx += kNT) {
-                int rp, jc;
-                divlen(idx, lmv, f3, rp, jc);
-                const int j = jc << LVW;
-                const int ya = y0 + 2 * rp;
-                T av[VW], bv[VW];
-                load16<T>(sc + (long long)ya * nx + j, j < nx && ya < ny, av);
-                load16<T>(sc + (long long)(ya + 1) * nx + j, j < nx && ya + 1 < ny, bv);
-#pragma unroll
-                for (int k = 0; k < VW; ++k) {
-                    const V v = mk<V>(av[k], bv[k]);
-                    const int i0 = (2 * rp) * m + j + k, i1 = i0 + m;
-                    lines[i0 + (i0 >> psh)] = v;
-                    lines[i1 + (i1 >> psh)] = cmul(v, twl[j + k]);
-                }
-            }
         } else {
-        // unrolled so that several loads are in flight per thread
-#pragma unroll 4
-        for (int idx = threadIdx.x; idx < hp * m; idx += kNT) {
-            int rp, j;
-            divlen(idx, lm, f3, rp, j);
-            const int ya = y0 + 2 * rp;
-            T a = 0, b = 0;
-            if (j < nx) {
-                if (ya < ny) a = sc[(long long)ya * nx + j];
-                if (ya + 1 < ny) b = sc[(long long)(ya + 1) * nx + j];
-            }
-            const V v = mk<V>(a, b);
-            const int i0 = (2 * rp) * m + j, i1 = i0 + m;
-            lines[i0 + (i0 >> psh)] = v;
-            lines[i1 + (i1 >> psh)] = cmul(v, twl[j]);
-        }
+            xfwd_load_lines<T>(sc, lines, twl, vecw, hp, m, lm, y0, nx, ny, psh);
         }
         __syncthreads();
         fft_lines_x<V, false>(lines, yt, lm, f3, twl);
@@ -680,6 +719,7 @@ __device__ __forceinline__ void conv_body_ct(const Prob& p, int s0, int G, cplx<
 
 // The convolution of G slices starting at s0, y length from the problem
 // (the runtime-length body).
+constexpr int kConvU = 4;
 template <typename T, int MZ>
 __device__ __forceinline__ void conv_body(const Prob& p, int s0, int G, cplx<T>* __restrict__ X,
                                           cplx<T>* __restrict__ Xp, const T* __restrict__ nhat,
@@ -704,16 +744,22 @@ __device__ __forceinline__ void conv_body(const Prob& p, int s0, int G, cplx<T>*
 #pragma unroll 1
     for (int hy = 0; hy < 2; ++hy) {
         {
+            // kConvU elements per thread per round, their loads issued
+            // together (an element past the end loads the last one)
             int y = yb, r = rb;
             asm volatile("" : "+v"(y), "+v"(r));
-#pragma unroll 4
-            for (int e = threadIdx.x; e < nel; e += kNT) {
-                V v = in[e];
-                if (hy) v = cmul(v, twl[y]);
-                lines[lds_pad(r * my + y)] = v;
-                y += dy;
-                r += dr;
-                if (y >= ny) { y -= ny; r += 1; }
+#pragma unroll 1
+            for (int e0 = threadIdx.x; e0 < nel; e0 += kConvU * kNT) {
+                V v[kConvU];
+#pragma unroll
+                for (int u = 0; u < kConvU; ++u) v[u] = in[min(e0 + u * kNT, nel - 1)];
+#pragma unroll
+                for (int u = 0; u < kConvU; ++u) {
+                    if (e0 + u * kNT < nel) lines[lds_pad(r * my + y)] = hy ? cmul(v[u], twl[y]) : v[u];
+                    y += dy;
+                    r += dr;
+                    if (y >= ny) { y -= ny; r += 1; }
+                }
             }
         }
         if (my > ny) {
@@ -790,17 +836,30 @@ __device__ __forceinline__ void conv_body(const Prob& p, int s0, int G, cplx<T>*
         {
             // y half hy = 0 goes to the output slice, hy = 1 (un-twiddled)
             // over this workgroup's input slice, which is no longer read
+            // (half 1: the half-0 values of a round's elements, which this
+            // thread stored itself, are loaded together first)
             int y = yb, r = rb;
             asm volatile("" : "+v"(y), "+v"(r));
             V* dst = out;
-#pragma unroll 4
-            for (int e = threadIdx.x; e < nel; e += kNT) {
-                V v = lines[lds_pad(r * my + y)];
-                if (hy) v = cadd(cmulc(v, twl[y]), dst[e]);  // this thread stored half 0 at e
-                dst[e] = v;
-                y += dy;
-                r += dr;
-                if (y >= ny) { y -= ny; r += 1; }
+#pragma unroll 1
+            for (int e0 = threadIdx.x; e0 < nel; e0 += kConvU * kNT) {
+                V h0[kConvU];
+                if (hy) {
+#pragma unroll
+                    for (int u = 0; u < kConvU; ++u) h0[u] = dst[min(e0 + u * kNT, nel - 1)];
+                }
+#pragma unroll
+                for (int u = 0; u < kConvU; ++u) {
+                    const int e = e0 + u * kNT;
+                    if (e < nel) {
+                        V v = lines[lds_pad(r * my + y)];
+                        if (hy) v = cadd(cmulc(v, twl[y]), h0[u]);
+                        dst[e] = v;
+                    }
+                    y += dy;
+                    r += dr;
+                    if (y >= ny) { y -= ny; r += 1; }
+                }
             }
         }
         __syncthreads();
@@ -1028,6 +1087,69 @@ __device__ __forceinline__ T lane_prev(T v)
     }
 }
 
+// The convolved x half-spectra of component c of a k_xinv tile into its
+// LDS lines: item (kx, row pair rp) reads rows ya, ya + 1 of frequency kx
+// and writes Z(kx) = A + iB and, for 0 < kx < m, Z(2m - kx) = conj(A) +
+// i conj(B), each into the line of its half (even, odd frequencies).  A row
+// past the lattice reads a row inside it instead (rows transform
+// independently, and no field of a row past the lattice is used); even ny
+// reads the pair as one 16-byte load.
+#ifndef SSM_XINV_U
+#define SSM_XINV_U 8
+#endif
+constexpr int kXinvU = SSM_XINV_U;
+template <typename T, int F3>
+__device__ __forceinline__ void xinv_load_lines(const char* __restrict__ Xi, cplx<T>* lines, int c, int z, int y0,
+                                                int hp, int lhp, int m, int lm, int nz, int ny, int psh)
+{
+    using V = cplx<T>;
+    constexpr int f3 = F3;
+    const int total = (m + 1) * hp;
+    auto rounds = [&](auto oddc) {
+        constexpr bool ODD = decltype(oddc)::value;
+#pragma unroll 1
+        for (int idx0 = threadIdx.x; idx0 < total; idx0 += kXinvU * kNT) {
+            V A[kXinvU], B[kXinvU];
+#pragma unroll
+            for (int u = 0; u < kXinvU; ++u) {
+                const int idx = min(idx0 + u * kNT, total - 1);
+                const int rp = idx & (hp - 1), kx = idx >> lhp;
+                const int ya = y0 + 2 * rp;
+                const unsigned cb = (unsigned)(((kx * 3 + c) * nz + z) * ny) * (unsigned)sizeof(V);
+                if constexpr (!ODD) {
+                    load2(reinterpret_cast<const V*>(Xi + cb + (unsigned)min(ya, ny - 2) * (unsigned)sizeof(V)), A[u],
+                          B[u]);
+                } else {
+                    A[u] = *reinterpret_cast<const V*>(Xi + cb + (unsigned)min(ya, ny - 1) * (unsigned)sizeof(V));
+                    B[u] = *reinterpret_cast<const V*>(Xi + cb + (unsigned)min(ya + 1, ny - 1) * (unsigned)sizeof(V));
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kXinvU; ++u) {
+                const int idx = idx0 + u * kNT;
+                if (idx >= total) break;
+                const int rp = idx & (hp - 1), kx = idx >> lhp;
+                V a = A[u], b = B[u];
+                if constexpr (ODD) {
+                    const int ya = y0 + 2 * rp;
+                    if (ya >= ny) a = mk<V>(0, 0);
+                    if (ya + 1 >= ny) b = mk<V>(0, 0);
+                }
+                // the two halves (even, odd frequencies) are separate lines
+                const int i0 = (2 * rp + (kx & 1)) * m + fpos(kx >> 1, lm, f3);
+                lines[i0 + (i0 >> psh)] = mk<V>(a.x - b.y, a.y + b.x);
+                if (kx > 0 && kx < m) {
+                    const int km = 2 * m - kx;
+                    const int i1 = (2 * rp + (km & 1)) * m + fpos(km >> 1, lm, f3);
+                    lines[i1 + (i1 >> psh)] = mk<V>(a.x + b.y, b.x - a.y);
+                }
+            }
+        }
+    };
+    if (ny & 1) rounds(std::true_type{});
+    else rounds(std::false_type{});
+}
+
 // ---------------------------------------------------------------------------
 // k_xinv: x half-spectra of the convolved field -> unit-strength dipolar
 // field of a tile (one component at a time), then the per-site epilogue.
@@ -1077,33 +1199,10 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     __syncthreads();
 #pragma unroll 1
     for (int c = 0; c < 3; ++c) {
-        // unrolled so that several loads are in flight per thread
-#pragma unroll 4
-        for (int idx = threadIdx.x; idx < (m + 1) * hp; idx += kNT) {
-            const int rp = idx & (hp - 1), kx = idx >> lhp;
-            const int ya = y0 + 2 * rp;
-            // even ny: a row pair past the lattice reads the last pair
-            // instead (rows transform independently, and no field of a row
-            // past the lattice is used), so the load needs no predicate
-            const int yl = (ny & 1) ? ya : min(ya, ny - 2);
-            const unsigned o = (unsigned)(((kx * 3 + c) * nz + z) * ny + yl) * (unsigned)sizeof(V);
-            const V* src = reinterpret_cast<const V*>(Xi + o);  // row yl
-            V A = mk<V>(0, 0), B = mk<V>(0, 0);
-            if (!(ny & 1)) {
-                load2(src, A, B);
-            } else {
-                if (ya < ny) A = src[0];
-                if (ya + 1 < ny) B = *reinterpret_cast<const V*>(Xi + o + (unsigned)sizeof(V));
-            }
-            // the two halves (even, odd frequencies) are separate lines
-            const int i0 = (2 * rp + (kx & 1)) * m + fpos(kx >> 1, lm, f3);
-            lines[i0 + (i0 >> psh)] = mk<V>(A.x - B.y, A.y + B.x);
-            if (kx > 0 && kx < m) {
-                const int km = 2 * m - kx;
-                const int i1 = (2 * rp + (km & 1)) * m + fpos(km >> 1, lm, f3);
-                lines[i1 + (i1 >> psh)] = mk<V>(A.x + B.y, B.x - A.y);
-            }
-        }
+        // kXinvU items per thread per round: their loads are issued
+        // together (no load sits under a branch; an item past the end loads
+        // the last item's values and stores nothing), then their LDS writes
+        xinv_load_lines<T, F3>(Xi, lines, c, z, y0, hp, lhp, m, lm, nz, ny, psh);
         __syncthreads();
         fft_lines_x<V, true>(lines, yt, lm, f3, twl);
         __syncthreads();
@@ -2161,12 +2260,13 @@ __global__ void k_rk_init(const Prob* __restrict__ P, int np, int nimg, const in
     rs.dtu[g] = cap ? Tint : rs.dtp[g];
 }
 
-// stage input y = s + dtu * sum_{j < stage} a[stage][j] k_j (FP64 sums);
-// images that are not integrating get y = s
-template <typename T>
+// stage input y = s + dtu * sum_{j < STAGE} a[STAGE][j] k_j (FP64 sums);
+// images that are not integrating get y = s.  STAGE at compile time: the
+// slope loads of a site are all in flight together.
+template <typename T, int STAGE>
 __global__ __launch_bounds__(kNT) void k_rk_stage(const Prob* __restrict__ P, int np,
                                                   const int* __restrict__ wstart, const T* __restrict__ s,
-                                                  RkSlopes<T> ks, int stage, RkState rs, T* __restrict__ y,
+                                                  RkSlopes<T> ks, RkState rs, T* __restrict__ y,
                                                   const int* __restrict__ done)
 {
     const int pi = find_problem(wstart, np, blockIdx.x);
@@ -2184,7 +2284,8 @@ __global__ __launch_bounds__(kNT) void k_rk_stage(const Prob* __restrict__ P, in
     for (int c = 0; c < 3; ++c) {
         const long long o = base + c * N;
         double acc = 0.0;
-        for (int j = 0; j < stage; ++j) acc += kDopriA[stage][j] * (double)ks.k[j][o];
+#pragma unroll
+        for (int j = 0; j < STAGE; ++j) acc += kDopriA[STAGE][j] * (double)ks.k[j][o];
         y[o] = (T)((double)s[o] + h * acc);
     }
 }
@@ -2350,9 +2451,21 @@ hipError_t launch_rk_stage(const Prob* P, int np, const WorkMap& wm, const T* s,
                            RkState rs, T* y, const int* done, hipStream_t st)
 {
     if (wm.total == 0) return hipSuccess;
-    if (stage < 1 || stage > 6) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_rk_stage<T>, dim3(wm.total), dim3(kNT), 0, st, P, np, wm.start, s, ks, stage, rs, y,
-                       done);
+    switch (stage) {
+#define SSM_RK_STAGE(S)                                                                                     \
+    case S:                                                                                                 \
+        hipLaunchKernelGGL((k_rk_stage<T, S>), dim3(wm.total), dim3(kNT), 0, st, P, np, wm.start, s, ks, rs, y, \
+                           done);                                                                           \
+        break;
+        SSM_RK_STAGE(1)
+        SSM_RK_STAGE(2)
+        SSM_RK_STAGE(3)
+        SSM_RK_STAGE(4)
+        SSM_RK_STAGE(5)
+        SSM_RK_STAGE(6)
+#undef SSM_RK_STAGE
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
