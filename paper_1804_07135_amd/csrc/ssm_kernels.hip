@@ -415,7 +415,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     __syncthreads();
     // rows of a length divisible by VW = 16 / sizeof(T) from a 16-byte
     // aligned image are read VW sites per 16-byte load
-    constexpr int VW = 16 / sizeof(T), LVW = VW == 4 ? 2 : 1;
+    constexpr int VW = 16 / sizeof(T);
     const bool vecw = !(nx & (VW - 1)) && !(reinterpret_cast<size_t>(si) & 15);
 #pragma unroll 1
     for (int c = 0; c < 3; ++c) {
@@ -604,7 +604,7 @@ __device__ __forceinline__ void conv_body_ct(const Prob& p, int s0, int G, cplx<
     using P0 = PassCT<V, R0, false, LMY, 0, PADL, TWS, false, SW>;
     using PL = PassCT<V, RL, true, LMY, LNSL, PADL, TWS, SW, false>;
     const int nsl_img = p.mx + 1;
-    const int nz = p.nz, ny = p.ny, nhz = p.nhz;
+    const int nz = p.nz, ny = p.ny;
     const int per = 3 * nz * ny, nlines = G * 3 * nz;
     load_twiddles(smem, LMY, 0, tw);
     const V* twl = smem;
@@ -1394,7 +1394,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         if (lane == 0) red[wave][j] = v;
     }
     __syncthreads();
-    if (threadIdx.x < nterm) {
+    if ((int)threadIdx.x < nterm) {
         double v = 0;
         for (int wv = 0; wv < kNT / 64; ++wv) v += red[wv][threadIdx.x];
         epart[p.ep_off + ((long long)img * p.tiles + (z * p.nty + ty)) * kNTerm + threadIdx.x] = v;
@@ -2619,7 +2619,7 @@ __global__ __launch_bounds__(kNT) void k_interp_splw(const Prob* __restrict__ P,
     if ((done && done[pi]) || !s2.spl_ok[pi]) return;
     const Prob& p = P[pi];
     const int K = p.K, g0 = p.img0, kci = s2.kci ? s2.kci[pi] : -1;
-    if (threadIdx.x < K) {
+    if ((int)threadIdx.x < K) {
         // column i: M as a function of the unit image e_i (M_0 = M_{K-1} = 0)
         const int i = threadIdx.x;
         double dpp = 0.0;
