@@ -295,13 +295,15 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
         p.ep_off = ep;
         p.ap_off = ap;
         p.arc_chunks = (int)((3 * p.N + kNT * kArcEPT - 1) / (kNT * kArcEPT));
-        // image groups so that a launch has about 2048 workgroups in FP32
-        // and 512 in FP64 (measured: FP64 chunks carry twice the bytes and
-        // stream best ungrouped on large lattices): small lattices get
-        // parallelism over images (each group reads the image before it
-        // once more)
-        const int arc_target = pl.tsize == 4 ? 2048 : 512;
-        p.arc_ng = std::max(1, std::min(p.K - 1, (arc_target + p.arc_chunks - 1) / p.arc_chunks));
+        // image groups: in FP32 at most 12288 workgroups (six per resident
+        // slot on 256 CUs; short groups of about three images balance
+        // better than one long round, and the image each group re-reads is
+        // mostly an L2 hit: the same chunk of neighbouring groups lands on
+        // the same XCD), in FP64 at least 512 (FP64 chunks carry twice the
+        // bytes and stream best ungrouped on large lattices); small
+        // lattices get parallelism over images
+        const int arc_ng = pl.tsize == 4 ? 12288 / p.arc_chunks : (512 + p.arc_chunks - 1) / p.arc_chunks;
+        p.arc_ng = std::max(1, std::min(p.K - 1, arc_ng));
         p.arc_g = (p.K - 1 + p.arc_ng - 1) / p.arc_ng;
         p.arc_ng = (p.K - 1 + p.arc_g - 1) / p.arc_g;
         p.ichunks = (int)((p.N + kNT - 1) / kNT);

@@ -1493,11 +1493,35 @@ __global__ __launch_bounds__(kNT) void k_reduce(const Prob* __restrict__ P, int 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double v[kNTerm + 1] = {0, 0, 0, 0, 0, 0};
     const double* ep = epart + p.ep_off + (long long)k * p.tiles * kNTerm;
-    for (int t = threadIdx.x; t < p.tiles; t += kNT)
-        for (int j = 0; j < kNTerm; ++j) v[j] += ep[(long long)t * kNTerm + j];
+    // partials in rounds: a round's loads (past the end: the last partial)
+    // are issued together, then added in the same order as one at a time
+    constexpr int RE = 4, RA = 8;
+    const int nt = p.tiles;
+    for (int t0 = threadIdx.x; t0 < nt; t0 += RE * kNT) {
+        double q[RE][kNTerm];
+#pragma unroll
+        for (int u = 0; u < RE; ++u) {
+            const long long t = min(t0 + u * kNT, nt - 1);
+#pragma unroll
+            for (int j = 0; j < kNTerm; ++j) q[u][j] = ep[t * kNTerm + j];
+        }
+#pragma unroll
+        for (int u = 0; u < RE; ++u)
+            if (t0 + u * kNT < nt)
+#pragma unroll
+                for (int j = 0; j < kNTerm; ++j) v[j] += q[u][j];
+    }
     if (with_arc && k > 0) {
         const double* ap = apart + p.ap_off + (long long)k * p.arc_chunks * 4;
-        for (int t = threadIdx.x; t < p.arc_chunks * 4; t += kNT) v[kNTerm] += ap[t];
+        const int na = p.arc_chunks * 4;
+        for (int t0 = threadIdx.x; t0 < na; t0 += RA * kNT) {
+            double q[RA];
+#pragma unroll
+            for (int u = 0; u < RA; ++u) q[u] = ap[min(t0 + u * kNT, na - 1)];
+#pragma unroll
+            for (int u = 0; u < RA; ++u)
+                if (t0 + u * kNT < na) v[kNTerm] += q[u];
+        }
     }
     for (int j = 0; j <= kNTerm; ++j) {
         const double s = wave_sum(v[j]);
