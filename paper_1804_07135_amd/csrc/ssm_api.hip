@@ -94,6 +94,7 @@ struct Plan {
     int mz = 1;
     int conv_kinds = 0;               // convolution builds in use (launch_conv)
     int x_kinds = 0;                  // x length kinds in use (launch_xfwd, launch_xinv)
+    int red_kinds = 0;                // reduction kernels in use (launch_reduce)
     bool rk = false;                  // workspace of the adaptive integrator reserved
     int kmax = 0;                     // largest image count of the batch
     size_t tsize = 8;                 // bytes of one spin component
@@ -306,6 +307,9 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
         p.arc_ng = std::max(1, std::min(p.K - 1, arc_ng));
         p.arc_g = (p.K - 1 + p.arc_ng - 1) / p.arc_ng;
         p.arc_ng = (p.K - 1 + p.arc_g - 1) / p.arc_g;
+        // few images with few partials each: the whole reduction in one
+        // workgroup (no hand-off between workgroups)
+        p.red1 = (p.K <= kRed1MaxK && p.tiles * kNTerm + 4 * p.arc_chunks <= kRed1MaxPart) ? 1 : 0;
         p.ichunks = (int)((p.N + kNT - 1) / kNT);
         // spin buffers are 256-byte aligned, so an image is 16-byte aligned
         // when its element offset is a multiple of 4
@@ -341,6 +345,7 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
         pl.mz = p.mz;
         pl.conv_kinds |= 1 << conv_build(p.mz, p.lmy, p.f3y);
         pl.x_kinds |= 1 << p.f3x;
+        pl.red_kinds |= p.red1 ? 2 : 1;
         pl.lds_xf = std::max(pl.lds_xf, lds_xfwd(p, p.ytf, pl.tsize));
         pl.lds_xi = std::max(pl.lds_xi, lds_xinv(p, p.yt, pl.tsize));
         pl.lds_conv = std::max(pl.lds_conv, lds_convg(p, p.gconv, pl.tsize));
@@ -575,7 +580,7 @@ struct Ops {
         });
         if (e != hipSuccess) return e;
         e = timed(c, st, KK_REDUCE, [&] {
-            return launch_reduce(c->P(), pl.np, (int)pl.n_img, c->wm_img().start,
+            return launch_reduce(c->P(), pl.np, (int)pl.n_img, pl.red_kinds, c->wm_img().start,
                                  c->at<double>(pl.o_ep), c->at<double>(pl.o_ap),
                                  write_E ? c->at<double>(pl.o_E) : nullptr, nullptr, nullptr, nullptr,
                                  c->at<double>(pl.o_seg), c->at<double>(pl.o_alpha),
@@ -623,7 +628,7 @@ struct Ops {
             // energies of the current string, then the climbing image's step
             const Step2 o = c->step2();
             e = timed(c, st, KK_REDUCE, [&] {
-                return launch_reduce(c->P(), pl.np, (int)pl.n_img, c->wm_img().start, c->at<double>(pl.o_ep),
+                return launch_reduce(c->P(), pl.np, (int)pl.n_img, pl.red_kinds, c->wm_img().start, c->at<double>(pl.o_ep),
                                      nullptr, c->at<double>(pl.o_E), nullptr, nullptr, nullptr, nullptr, nullptr,
                                      nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c->at<int>(pl.o_flags), 0,
                                      st);
@@ -674,7 +679,7 @@ struct Ops {
         HIPCHK(c, field(c, st, s, nullptr, ks.k[0], EPI_FORCE, 0.0, done, fcp, fcd), "integrator");
         if (energies)
             HIPCHK(c, timed(c, st, KK_REDUCE, [&] {
-                       return launch_reduce(c->P(), pl.np, nimg, istart, c->at<double>(pl.o_ep), nullptr,
+                       return launch_reduce(c->P(), pl.np, nimg, pl.red_kinds, istart, c->at<double>(pl.o_ep), nullptr,
                                             c->at<double>(pl.o_E), nullptr, nullptr, nullptr, nullptr, nullptr,
                                             nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, flags, 0, st);
                    }), "integrator");
@@ -756,7 +761,7 @@ struct Ops {
         hipError_t e = field(c, st, src, nullptr, hdst, mode, 0.0, nullptr);
         if (e != hipSuccess) return e;
         return timed(c, st, KK_REDUCE, [&] {
-            return launch_reduce(c->P(), pl.np, (int)pl.n_img, c->wm_img().start,
+            return launch_reduce(c->P(), pl.np, (int)pl.n_img, pl.red_kinds, c->wm_img().start,
                                  c->at<double>(pl.o_ep), nullptr,
                                  store ? c->at<double>(pl.o_E) : nullptr,
                                  store ? c->at<double>(pl.o_T) : nullptr, E_out, T_out, nullptr,

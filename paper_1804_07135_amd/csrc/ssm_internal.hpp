@@ -26,6 +26,11 @@ constexpr int kNT = 256;       // threads per workgroup for every kernel
 constexpr int kConvElems = 24 * kNT;  // complex values per convolution workgroup (slice batching cap)
 constexpr int kArcEPT = 8;     // flat elements per thread in the arc-length kernel
 constexpr int kNTerm = 5;      // energy partial slots: E, T_J, T_d, T_ku, T_dip
+constexpr int kMaxImages = 1024;  // images per problem (the ABI's limit)
+// Reduction in one workgroup per problem (k_reduce1) for problems of at
+// most kRed1MaxK images with at most kRed1MaxPart energy and arc partials
+// per image; kRedLanes lanes sum one image's partials there.
+constexpr int kRed1MaxK = 64, kRed1MaxPart = 256, kRedLanes = 16;
 
 // The convolution kernel comes in two builds: one with compile-time-length
 // bodies for y lengths 32..256 and up to 8 layers, one with a runtime-length
@@ -121,6 +126,7 @@ struct Prob {
     int ichunks4;          // interpolation workgroups per image (ichunks / 4 with vec4)
     int arc_g;             // images per arc-length workgroup (image groups of arc_g)
     int arc_ng;            // image groups: arc-length workgroups = arc_chunks * arc_ng
+    int red1;              // 1: reduced by one workgroup (k_reduce1), else one per image (k_reduce)
     double J, d, ku, D;    // eq. (1) parameters
 };
 
@@ -176,7 +182,9 @@ struct Step2 {
     double* B = nullptr;
     double* H = nullptr;
 };
-hipError_t launch_reduce(const Prob* P, int np, int nimg, const int* istart, const double* epart,
+// kinds: bit 0 problems reduced per image, bit 1 problems reduced by one
+// workgroup (Prob::red1)
+hipError_t launch_reduce(const Prob* P, int np, int nimg, int kinds, const int* istart, const double* epart,
                          const double* apart, double* E, double* Tm, double* E_out, double* T_out,
                          double* seg, double* alpha, int* jidx, double* wgt, int* skip, int* done,
                          int* iters, int* count, int* flags, int with_arc, hipStream_t st,

@@ -1464,12 +1464,131 @@ __global__ __launch_bounds__(kNT) void k_arc(const Prob* __restrict__ P, int np,
 }
 
 // ---------------------------------------------------------------------------
-// k_reduce: one workgroup per image.  Fixed-order sums of the image's energy
-// partials (E and the four unit-parameter terms) and, with_arc, of its arc
-// partials (segment length |phi*_k - phi*_{k-1}|).  With with_arc the last
-// workgroup of a problem to finish (atomic counter) forms S_k,
-// alpha*_k = S_k/S_{K-1} and, for every interior image, the interval
-// j = max{j <= K-2 : alpha*_j <= k/(K-1)} and its weight.  Every sum has a
+// The end of step 2 for problem pi, by one workgroup.  al[0..K) (LDS) holds
+// the segment lengths |phi*_k - phi*_{k-1}| (al[0] = 0); el is LDS for K
+// energies.  Scans them in a fixed order into S_k, alpha*_k = S_k/S_{K-1}
+// and, for every interior image, the interval
+// j = max{j <= K-2 : alpha*_j <= target} and its weight; with the options,
+// the climbing image and the spline factors.
+// ---------------------------------------------------------------------------
+__device__ void reduce_final(const Prob& p, int pi, double* al, double* el, double* bc, int* s_kci,
+                             double* alpha, int* jidx, double* wgt, int* skip, int* iters, const Step2& s2)
+{
+    const int K = p.K, g0 = p.img0;
+    if (threadIdx.x == 0) {
+        double S = 0;
+        for (int kk = 1; kk < K; ++kk) {
+            S += al[kk];
+            al[kk] = S;
+        }
+        *bc = S;
+        skip[pi] = (S > 0.0) ? 0 : 1;
+        atomicAdd(&iters[pi], 1);  // the problem's only writer in this launch
+    }
+    __syncthreads();
+    const double L = *bc;
+    if (!(L > 0.0)) {
+        for (int kk = threadIdx.x; kk < K; kk += kNT) {
+            alpha[g0 + kk] = 0;
+            jidx[g0 + kk] = kk;
+            wgt[g0 + kk] = 0;
+        }
+        if (threadIdx.x == 0) {
+            if (s2.kci) s2.kci[pi] = -1;
+            if (s2.spl_ok) s2.spl_ok[pi] = 0;
+        }
+        return;
+    }
+    for (int kk = 1 + threadIdx.x; kk < K; kk += kNT) al[kk] = al[kk] / L;
+    if (s2.opts & 2) {
+        const volatile double* Ev = s2.E;
+        for (int kk = threadIdx.x; kk < K; kk += kNT) el[kk] = Ev[g0 + kk];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // climbing image: the image of highest energy (smallest index on
+        // ties) when it is interior
+        int kci = -1;
+        if (s2.opts & 2) {
+            int km = 0;
+            double em = el[0];
+            for (int kk = 1; kk < K; ++kk) {
+                const double e = el[kk];
+                if (e > em) { em = e; km = kk; }
+            }
+            if (km > 0 && km < K - 1) kci = km;
+        }
+        *s_kci = kci;
+        if (s2.kci) s2.kci[pi] = kci;
+    }
+    __syncthreads();
+    const int kci = *s_kci;
+    // target of image kk: k/(K-1), or equal spacing within 0..kci and
+    // within kci..K-1 around a climbing image
+    auto target = [&](int kk) {
+        if (kci < 0) return (double)kk / (double)(K - 1);
+        if (kk <= kci) return al[kci] * (double)kk / (double)kci;
+        return al[kci] + (1.0 - al[kci]) * (double)(kk - kci) / (double)(K - 1 - kci);
+    };
+    for (int kk = threadIdx.x; kk < K; kk += kNT) {
+        alpha[g0 + kk] = al[kk];
+        if (kk == 0 || kk == K - 1 || kk == kci) {
+            jidx[g0 + kk] = kk;
+            wgt[g0 + kk] = 0;
+            continue;
+        }
+        const double tk = target(kk);
+        int j = 0;
+        for (int jj = 0; jj <= K - 2; ++jj)
+            if (al[jj] <= tk) j = jj;
+        const double width = al[j + 1] - al[j];
+        jidx[g0 + kk] = j;
+        wgt[g0 + kk] = (width > 0.0) ? (tk - al[j]) / width : 0.0;
+    }
+    if (!(s2.opts & 1)) return;
+    // natural cubic spline in alpha: interval widths and the Thomas factors
+    // of the tridiagonal system for the interior second derivatives
+    if (threadIdx.x == 0) {
+        int ok = K > 2;
+        for (int j = 0; j + 1 < K; ++j) {
+            const double hw = al[j + 1] - al[j];
+            s2.hh[g0 + j] = hw;
+            if (!(hw > 0.0)) ok = 0;
+        }
+        if (ok) {
+            double cpp = 0.0;
+            for (int i = 1; i <= K - 2; ++i) {
+                const double hl = al[i] - al[i - 1], hr = al[i + 1] - al[i];
+                const double a = hl / 6.0, b = (hl + hr) / 3.0, c = hr / 6.0;
+                const double den = b - (i > 1 ? a * cpp : 0.0);
+                cpp = c / den;
+                s2.sa[g0 + i] = a;
+                s2.den[g0 + i] = den;
+                s2.cp[g0 + i] = cpp;
+            }
+        }
+        s2.spl_ok[pi] = ok;
+    }
+    for (int kk = threadIdx.x; kk < K; kk += kNT) {
+        if (kk == 0 || kk == K - 1 || kk == kci) continue;
+        const double tk = target(kk);
+        int j = 0;
+        for (int jj = 0; jj <= K - 2; ++jj)
+            if (al[jj] <= tk) j = jj;
+        const double h = al[j + 1] - al[j];
+        const double A = (al[j + 1] - tk) / h;
+        s2.A[g0 + kk] = A;
+        s2.B[g0 + kk] = 1.0 - A;
+        s2.H[g0 + kk] = h;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_reduce: one workgroup per image of the problems without red1.
+// Fixed-order sums of the image's energy partials (E and the four
+// unit-parameter terms) and, with_arc, of its arc partials (segment length
+// |phi*_k - phi*_{k-1}|).  With with_arc the last workgroup of a problem to
+// finish (atomic counter) ends step 2 (reduce_final).  Every sum has a
 // fixed order, so results do not depend on which workgroup finishes last.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kNT) void k_reduce(const Prob* __restrict__ P, int np,
@@ -1483,12 +1602,14 @@ __global__ __launch_bounds__(kNT) void k_reduce(const Prob* __restrict__ P, int 
                                                 Step2 s2)
 {
     __shared__ double red[kNT / 64][kNTerm + 1];
-    __shared__ double red_alpha[1024];
+    __shared__ double al[kMaxImages], el[kMaxImages];
+    __shared__ double bc;
     __shared__ int last, s_kci;
     const int gimg = blockIdx.x;
     const int pi = find_problem(istart, np, gimg);
     if (with_arc && done && done[pi]) return;
     const Prob& p = P[pi];
+    if (p.red1) return;  // reduced by k_reduce1
     const int k = gimg - p.img0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double v[kNTerm + 1] = {0, 0, 0, 0, 0, 0};
@@ -1552,117 +1673,97 @@ __global__ __launch_bounds__(kNT) void k_reduce(const Prob* __restrict__ P, int 
     if (!last) return;
     // last workgroup of the problem: every image's segment length is
     // visible (written before the counter increment); fetch them in
-    // parallel, scan in a fixed order on one thread, then search the
-    // interval of every target image in parallel
+    // parallel, then end step 2
     __threadfence();
     const int K = p.K, g0 = p.img0;
-    double* al = red_alpha;
     const volatile double* sg = seg;
     for (int kk = threadIdx.x; kk < K; kk += kNT) al[kk] = (kk == 0) ? 0.0 : sg[g0 + kk];
+    if (threadIdx.x == 0) count[pi] = 0;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        count[pi] = 0;
-        double S = 0;
-        for (int kk = 1; kk < K; ++kk) {
-            S += al[kk];
-            al[kk] = S;
-        }
-        red[0][0] = S;
-        skip[pi] = (S > 0.0) ? 0 : 1;
-        iters[pi] += 1;
-    }
-    __syncthreads();
-    const double L = red[0][0];
-    if (!(L > 0.0)) {
-        for (int kk = threadIdx.x; kk < K; kk += kNT) {
-            alpha[g0 + kk] = 0;
-            jidx[g0 + kk] = kk;
-            wgt[g0 + kk] = 0;
-        }
-        if (threadIdx.x == 0) {
-            if (s2.kci) s2.kci[pi] = -1;
-            if (s2.spl_ok) s2.spl_ok[pi] = 0;
-        }
-        return;
-    }
-    for (int kk = 1 + threadIdx.x; kk < K; kk += kNT) al[kk] = al[kk] / L;
-    if (threadIdx.x == 0) {
-        // climbing image: the image of highest energy (smallest index on
-        // ties) when it is interior
-        int kci = -1;
-        if (s2.opts & 2) {
-            const volatile double* Ev = s2.E;
-            int km = 0;
-            double em = Ev[g0];
-            for (int kk = 1; kk < K; ++kk) {
-                const double e = Ev[g0 + kk];
-                if (e > em) { em = e; km = kk; }
+    reduce_final(p, pi, al, el, &bc, &s_kci, alpha, jidx, wgt, skip, iters, s2);
+}
+
+// ---------------------------------------------------------------------------
+// k_reduce1: the whole reduction of one problem with red1 (few images and
+// few partials per image) in one workgroup, so that no result passes
+// between workgroups: the device-scope fences of that hand-off cost more
+// than these sums.  kRedLanes lanes per image sum its partials in rounds,
+// then combine them in a fixed butterfly order; with_arc, reduce_final ends
+// step 2 from the segment lengths kept in LDS.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kNT) void k_reduce1(const Prob* __restrict__ P, int np,
+                                                 const double* __restrict__ epart,
+                                                 const double* __restrict__ apart,
+                                                 double* E, double* Tm, double* E_out,
+                                                 double* T_out, double* seg, double* alpha,
+                                                 int* jidx, double* wgt, int* skip, int* done,
+                                                 int* iters, int* flags, int with_arc, Step2 s2)
+{
+    __shared__ double al[kMaxImages], el[kMaxImages];
+    __shared__ double bc;
+    __shared__ int s_kci;
+    const int pi = blockIdx.x;
+    if (pi >= np) return;
+    if (with_arc && done && done[pi]) return;
+    const Prob& p = P[pi];
+    if (!p.red1) return;  // reduced by k_reduce
+    const int K = p.K, g0 = p.img0, nt = p.tiles, na = p.arc_chunks * 4;
+    constexpr int IPP = kNT / kRedLanes;  // images per pass
+    constexpr int RE = 4, RA = 8;
+    const int sub = threadIdx.x & (kRedLanes - 1);
+    for (int k0 = 0; k0 < K; k0 += IPP) {
+        const int k = k0 + (int)threadIdx.x / kRedLanes;
+        const int kc = min(k, K - 1);  // lanes past the last image repeat it and store nothing
+        double v[kNTerm + 1] = {0, 0, 0, 0, 0, 0};
+        const double* ep = epart + p.ep_off + (long long)kc * nt * kNTerm;
+        for (int t0 = sub; t0 < nt; t0 += RE * kRedLanes) {
+            double q[RE][kNTerm];
+#pragma unroll
+            for (int u = 0; u < RE; ++u) {
+                const long long t = min(t0 + u * kRedLanes, nt - 1);
+#pragma unroll
+                for (int j = 0; j < kNTerm; ++j) q[u][j] = ep[t * kNTerm + j];
             }
-            if (km > 0 && km < K - 1) kci = km;
+#pragma unroll
+            for (int u = 0; u < RE; ++u)
+                if (t0 + u * kRedLanes < nt)
+#pragma unroll
+                    for (int j = 0; j < kNTerm; ++j) v[j] += q[u][j];
         }
-        s_kci = kci;
-        if (s2.kci) s2.kci[pi] = kci;
-    }
-    __syncthreads();
-    const int kci = s_kci;
-    // target of image kk: k/(K-1), or equal spacing within 0..kci and
-    // within kci..K-1 around a climbing image
-    auto target = [&](int kk) {
-        if (kci < 0) return (double)kk / (double)(K - 1);
-        if (kk <= kci) return al[kci] * (double)kk / (double)kci;
-        return al[kci] + (1.0 - al[kci]) * (double)(kk - kci) / (double)(K - 1 - kci);
-    };
-    for (int kk = threadIdx.x; kk < K; kk += kNT) {
-        alpha[g0 + kk] = al[kk];
-        if (kk == 0 || kk == K - 1 || kk == kci) {
-            jidx[g0 + kk] = kk;
-            wgt[g0 + kk] = 0;
-            continue;
-        }
-        const double tk = target(kk);
-        int j = 0;
-        for (int jj = 0; jj <= K - 2; ++jj)
-            if (al[jj] <= tk) j = jj;
-        const double width = al[j + 1] - al[j];
-        jidx[g0 + kk] = j;
-        wgt[g0 + kk] = (width > 0.0) ? (tk - al[j]) / width : 0.0;
-    }
-    if (!(s2.opts & 1)) return;
-    // natural cubic spline in alpha: interval widths and the Thomas factors
-    // of the tridiagonal system for the interior second derivatives
-    if (threadIdx.x == 0) {
-        int ok = K > 2;
-        for (int j = 0; j + 1 < K; ++j) {
-            const double hw = al[j + 1] - al[j];
-            s2.hh[g0 + j] = hw;
-            if (!(hw > 0.0)) ok = 0;
-        }
-        if (ok) {
-            double cpp = 0.0;
-            for (int i = 1; i <= K - 2; ++i) {
-                const double hl = al[i] - al[i - 1], hr = al[i + 1] - al[i];
-                const double a = hl / 6.0, b = (hl + hr) / 3.0, c = hr / 6.0;
-                const double den = b - (i > 1 ? a * cpp : 0.0);
-                cpp = c / den;
-                s2.sa[g0 + i] = a;
-                s2.den[g0 + i] = den;
-                s2.cp[g0 + i] = cpp;
+        if (with_arc && kc > 0) {
+            const double* ap = apart + p.ap_off + (long long)kc * na;
+            for (int t0 = sub; t0 < na; t0 += RA * kRedLanes) {
+                double q[RA];
+#pragma unroll
+                for (int u = 0; u < RA; ++u) q[u] = ap[min(t0 + u * kRedLanes, na - 1)];
+#pragma unroll
+                for (int u = 0; u < RA; ++u)
+                    if (t0 + u * kRedLanes < na) v[kNTerm] += q[u];
             }
         }
-        s2.spl_ok[pi] = ok;
+#pragma unroll
+        for (int off = kRedLanes / 2; off > 0; off >>= 1)
+#pragma unroll
+            for (int j = 0; j <= kNTerm; ++j) v[j] += __shfl_xor(v[j], off, kRedLanes);
+        if (sub == 0 && k < K) {
+            const int g = g0 + k;
+            if (E) E[g] = v[0];
+            if (E_out) E_out[g] = v[0];
+            for (int j = 0; j < 4; ++j) {
+                if (Tm) Tm[(long long)g * 4 + j] = v[j + 1];
+                if (T_out) T_out[(long long)g * 4 + j] = v[j + 1];
+            }
+            if (!isfinite(v[0])) atomicOr(flags, 1);
+            if (with_arc) {
+                const double sl = sqrt(v[kNTerm]);
+                seg[g] = sl;
+                al[k] = (k == 0) ? 0.0 : sl;
+            }
+        }
     }
-    for (int kk = threadIdx.x; kk < K; kk += kNT) {
-        if (kk == 0 || kk == K - 1 || kk == kci) continue;
-        const double tk = target(kk);
-        int j = 0;
-        for (int jj = 0; jj <= K - 2; ++jj)
-            if (al[jj] <= tk) j = jj;
-        const double h = al[j + 1] - al[j];
-        const double A = (al[j + 1] - tk) / h;
-        s2.A[g0 + kk] = A;
-        s2.B[g0 + kk] = 1.0 - A;
-        s2.H[g0 + kk] = h;
-    }
+    if (!with_arc) return;
+    __syncthreads();
+    reduce_final(p, pi, al, el, &bc, &s_kci, alpha, jidx, wgt, skip, iters, s2);
 }
 
 // ---------------------------------------------------------------------------
@@ -2161,13 +2262,17 @@ hipError_t launch_arc(const Prob* P, int np, const WorkMap& wm, const T* ss, dou
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(const Prob* P, int np, int nimg, const int* istart, const double* epart,
+hipError_t launch_reduce(const Prob* P, int np, int nimg, int kinds, const int* istart, const double* epart,
                          const double* apart, double* E, double* Tm, double* E_out, double* T_out,
                          double* seg, double* alpha, int* jidx, double* wgt, int* skip, int* done,
                          int* iters, int* count, int* flags, int with_arc, hipStream_t st, Step2 s2)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(nimg), dim3(kNT), 0, st, P, np, istart, epart, apart, E, Tm,
-                       E_out, T_out, seg, alpha, jidx, wgt, skip, done, iters, count, flags, with_arc, s2);
+    if (kinds & 1)
+        hipLaunchKernelGGL(k_reduce, dim3(nimg), dim3(kNT), 0, st, P, np, istart, epart, apart, E, Tm,
+                           E_out, T_out, seg, alpha, jidx, wgt, skip, done, iters, count, flags, with_arc, s2);
+    if (kinds & 2)
+        hipLaunchKernelGGL(k_reduce1, dim3(np), dim3(kNT), 0, st, P, np, epart, apart, E, Tm, E_out, T_out,
+                           seg, alpha, jidx, wgt, skip, done, iters, flags, with_arc, s2);
     return hipGetLastError();
 }
 
