@@ -23,7 +23,9 @@ namespace {
 constexpr int kVersion = 1;
 constexpr size_t kAlign = 256;
 constexpr size_t kLdsMax = 160 * 1024;
-constexpr int kNumMaps = 8;
+// work maps: forward / inverse x per length kind (2 + 2), convolution per
+// build slot, arc, site, image, per-problem site, 4-site
+constexpr int kNumMaps = 4 + kConvSlots + 5;
 
 thread_local std::string g_create_error;
 
@@ -92,8 +94,6 @@ struct Plan {
     int prec = 0;
     int np = 0;
     int mz = 1;
-    int conv_kinds = 0;               // convolution builds in use (launch_conv)
-    int x_kinds = 0;                  // x length kinds in use (launch_xfwd, launch_xinv)
     int red_kinds = 0;                // reduction kernels in use (launch_reduce)
     bool rk = false;                  // workspace of the adaptive integrator reserved
     int kmax = 0;                     // largest image count of the batch
@@ -103,7 +103,8 @@ struct Plan {
     std::vector<int> geo;             // problem -> distinct-shape index
     std::vector<std::tuple<int, int, int>> shapes;
     std::vector<long long> nh_size;   // elements per distinct shape
-    std::vector<int> wm_xf, wm_xi, wm_conv, wm_arc, wm_site, wm_img, wm_sitep, wm_site4;
+    std::vector<int> wm_xf[2], wm_xi[2], wm_conv[kConvSlots];  // per kind
+    std::vector<int> wm_arc, wm_site, wm_img, wm_sitep, wm_site4;
     long long n_img = 0, n_spin = 0, n_x = 0, n_nh = 0, n_ep = 0, n_ap = 0, n_fp = 0, n_fm = 0;
     size_t lds_xf = 0, lds_xi = 0, lds_conv = 0;
     size_t scratch_bytes = 0;
@@ -343,8 +344,6 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
             pl.geo[i] = it->second;
         }
         pl.mz = p.mz;
-        pl.conv_kinds |= 1 << conv_build(p.mz, p.lmy, p.f3y);
-        pl.x_kinds |= 1 << p.f3x;
         pl.red_kinds |= p.red1 ? 2 : 1;
         pl.lds_xf = std::max(pl.lds_xf, lds_xfwd(p, p.ytf, pl.tsize));
         pl.lds_xi = std::max(pl.lds_xi, lds_xinv(p, p.yt, pl.tsize));
@@ -366,9 +365,15 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
         v.assign(np + 1, 0);
         for (int i = 0; i < np; ++i) v[i + 1] = v[i] + count(pl.P[i]);
     };
-    prefix(pl.wm_xf, [](const Prob& p) { return p.wgf; });
-    prefix(pl.wm_xi, [](const Prob& p) { return p.wgi; });
-    prefix(pl.wm_conv, [](const Prob& p) { return conv_wgs(p); });
+    // the FFT kernels per kind: other kinds' problems get no workgroups
+    for (int k = 0; k < 2; ++k) {
+        prefix(pl.wm_xf[k], [k](const Prob& p) { return p.f3x == k ? p.wgf : 0; });
+        prefix(pl.wm_xi[k], [k](const Prob& p) { return p.f3x == k ? p.wgi : 0; });
+    }
+    for (int j = 0; j < kConvSlots; ++j)
+        prefix(pl.wm_conv[j], [j](const Prob& p) {
+            return conv_slot(conv_build(p.mz, p.lmy, p.f3y)) == j ? (int)conv_wgs(p) : 0;
+        });
     prefix(pl.wm_arc, [](const Prob& p) { return p.arc_chunks * p.arc_ng; });
     prefix(pl.wm_site, [](const Prob& p) { return p.K * p.ichunks; });
     prefix(pl.wm_img, [](const Prob& p) { return p.K; });
@@ -469,14 +474,21 @@ struct ssm_ctx {
         w.total = v.back();
         return w;
     }
-    WorkMap wm_xf() const { return wm(0, pl.wm_xf); }
-    WorkMap wm_xi() const { return wm(1, pl.wm_xi); }
-    WorkMap wm_conv() const { return wm(2, pl.wm_conv); }
-    WorkMap wm_arc() const { return wm(3, pl.wm_arc); }
-    WorkMap wm_site() const { return wm(4, pl.wm_site); }
-    WorkMap wm_img() const { return wm(5, pl.wm_img); }
-    WorkMap wm_sitep() const { return wm(6, pl.wm_sitep); }
-    WorkMap wm_site4() const { return wm(7, pl.wm_site4); }
+    struct XMaps { WorkMap m[2]; };
+    struct ConvMaps { WorkMap m[kConvSlots]; };
+    XMaps wm_xf() const { return {{wm(0, pl.wm_xf[0]), wm(1, pl.wm_xf[1])}}; }
+    XMaps wm_xi() const { return {{wm(2, pl.wm_xi[0]), wm(3, pl.wm_xi[1])}}; }
+    ConvMaps wm_conv() const
+    {
+        ConvMaps r;
+        for (int j = 0; j < kConvSlots; ++j) r.m[j] = wm(4 + j, pl.wm_conv[j]);
+        return r;
+    }
+    WorkMap wm_arc() const { return wm(4 + kConvSlots, pl.wm_arc); }
+    WorkMap wm_site() const { return wm(5 + kConvSlots, pl.wm_site); }
+    WorkMap wm_img() const { return wm(6 + kConvSlots, pl.wm_img); }
+    WorkMap wm_sitep() const { return wm(7 + kConvSlots, pl.wm_sitep); }
+    WorkMap wm_site4() const { return wm(8 + kConvSlots, pl.wm_site4); }
     Step2 step2() const
     {
         Step2 r;
@@ -551,16 +563,16 @@ struct Ops {
         const void* tw = c->at<void>(pl.o_tw);
         hipError_t e;
         e = timed(c, st, KK_XFWD, [&] {
-            return launch_xfwd<T>(pl.x_kinds, c->P(), pl.np, c->wm_xf(), src, c->X(), tw, done, pl.lds_xf, st);
+            return launch_xfwd<T>(c->P(), pl.np, c->wm_xf().m, src, c->X(), tw, done, pl.lds_xf, st);
         });
         if (e != hipSuccess) return e;
         e = timed(c, st, KK_CONV, [&] {
-            return launch_conv<T>(pl.mz, pl.conv_kinds, c->P(), pl.np, c->wm_conv(), c->X(), c->Xp(),
+            return launch_conv<T>(pl.mz, c->P(), pl.np, c->wm_conv().m, c->X(), c->Xp(),
                                   c->at<T>(pl.o_nh), tw, done, pl.lds_conv, st);
         });
         if (e != hipSuccess) return e;
         return timed(c, st, KK_XINV, [&] {
-            return launch_xinv<T>(pl.x_kinds, c->P(), pl.np, c->wm_xi(), c->Xp(), src, s_star, hdst,
+            return launch_xinv<T>(c->P(), pl.np, c->wm_xi().m, c->Xp(), src, s_star, hdst,
                                   c->at<double>(pl.o_ep), tw, done, mode, tau, fcp, fcd, pl.lds_xi, st);
         });
     }
@@ -854,8 +866,10 @@ static ssm_status upload_plan(ssm_ctx* c)
     HIPCHK(c, hipMemcpyAsync(c->ws + pl.o_P, pl.P.data(), sizeof(Prob) * pl.np,
                              hipMemcpyHostToDevice, c->stream), "upload descriptors");
     std::vector<int> wm;
-    for (const auto* v : {&pl.wm_xf, &pl.wm_xi, &pl.wm_conv, &pl.wm_arc, &pl.wm_site, &pl.wm_img, &pl.wm_sitep, &pl.wm_site4})
-        wm.insert(wm.end(), v->begin(), v->end());
+    std::vector<const std::vector<int>*> maps = {&pl.wm_xf[0], &pl.wm_xf[1], &pl.wm_xi[0], &pl.wm_xi[1]};
+    for (int j = 0; j < kConvSlots; ++j) maps.push_back(&pl.wm_conv[j]);
+    for (const auto* v : {&pl.wm_arc, &pl.wm_site, &pl.wm_img, &pl.wm_sitep, &pl.wm_site4}) maps.push_back(v);
+    for (const auto* v : maps) wm.insert(wm.end(), v->begin(), v->end());
     HIPCHK(c, hipMemcpyAsync(c->ws + pl.o_wm, wm.data(), sizeof(int) * wm.size(),
                              hipMemcpyHostToDevice, c->stream), "upload work maps");
     HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
@@ -901,12 +915,12 @@ double time_kernel(ssm_ctx* c, int kind, int reps)
         if (hipEventRecord(a, c->stream) != hipSuccess) return 1e30;
         hipError_t e = hipSuccess;
         if (kind == KK_XFWD)
-            e = launch_xfwd<T>(pl.x_kinds, c->P(), pl.np, c->wm_xf(), s, c->X(), tw, nullptr, pl.lds_xf, c->stream);
+            e = launch_xfwd<T>(c->P(), pl.np, c->wm_xf().m, s, c->X(), tw, nullptr, pl.lds_xf, c->stream);
         else if (kind == KK_CONV)
-            e = launch_conv<T>(pl.mz, pl.conv_kinds, c->P(), pl.np, c->wm_conv(), c->X(), c->Xp(), c->at<T>(pl.o_nh), tw,
+            e = launch_conv<T>(pl.mz, c->P(), pl.np, c->wm_conv().m, c->X(), c->Xp(), c->at<T>(pl.o_nh), tw,
                                nullptr, pl.lds_conv, c->stream);
         else
-            e = launch_xinv<T>(pl.x_kinds, c->P(), pl.np, c->wm_xi(), c->Xp(), s, nullptr, nullptr,
+            e = launch_xinv<T>(c->P(), pl.np, c->wm_xi().m, c->Xp(), s, nullptr, nullptr,
                                c->at<double>(pl.o_ep), tw, nullptr, EPI_TERMS, 0.0, 0.0, 1.0, pl.lds_xi,
                                c->stream);
         if (e != hipSuccess || hipEventRecord(b, c->stream) != hipSuccess) return 1e30;

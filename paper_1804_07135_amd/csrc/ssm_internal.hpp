@@ -139,17 +139,19 @@ struct WorkMap {
 // ------------------------------------------------------------------------
 // launchers (ssm_kernels.hip); all enqueue on `st` and return the HIP error
 // ------------------------------------------------------------------------
-// kinds (x transforms): bit 0 set = some problem has a power-of-two x
-// length, bit 1 = some problem has an x length 3 2^a
+// The FFT kernels come in kinds (x: power-of-two or 3 2^a length;
+// convolution: one build per conv_build value) and each kind has a work map
+// of its own, in which the problems of other kinds have no workgroups; a
+// kind whose map is empty is not launched.  wm[0..1]: x length kinds
+// (f3x); wm[conv_slot(b)]: convolution build b.
+constexpr int kConvSlots = 8;
+__host__ __device__ constexpr int conv_slot(int b) { return b == 0 ? 0 : (b <= 8 ? b - 4 : b - 15); }
 template <typename T>
-hipError_t launch_xfwd(int kinds, const Prob* P, int np, const WorkMap& wm, const T* s, void* X,
+hipError_t launch_xfwd(const Prob* P, int np, const WorkMap* wm, const T* s, void* X,
                        const void* tw, const int* done, size_t lds, hipStream_t st);
-// kinds: bit b set = some problem takes build b (conv_build)
+// X' receives the convolved x half-spectra (X keeps the inputs)
 template <typename T>
-// The convolution leaves the convolved spectrum as two parts: the even-y
-// half's contribution in Xp and the odd-y half's over its input X; the
-// inverse-x kernel reads both and sums them.
-hipError_t launch_conv(int mz, int kinds, const Prob* P, int np, const WorkMap& wm, void* X,
+hipError_t launch_conv(int mz, const Prob* P, int np, const WorkMap* wm, void* X,
                        void* Xp, const T* nhat, const void* tw, const int* done, size_t lds,
                        hipStream_t st);
 // mode bits for the inverse/epilogue kernel: EPI_STEP writes the stepped
@@ -158,7 +160,7 @@ hipError_t launch_conv(int mz, int kinds, const Prob* P, int np, const WorkMap& 
 enum { EPI_STEP = 1, EPI_FIELD = 2, EPI_TERMS = 4, EPI_FORCE = 8 };
 template <typename T>
 // fcp, fcd: coefficients of EPI_FORCE (precession, damping)
-hipError_t launch_xinv(int kinds, const Prob* P, int np, const WorkMap& wm, const void* Xp, const T* s,
+hipError_t launch_xinv(const Prob* P, int np, const WorkMap* wm, const void* Xp, const T* s,
                        T* s_star, T* h, double* epart, const void* tw, const int* done,
                        int mode, double tau, double fcp, double fcd, size_t lds, hipStream_t st);
 template <typename T>

@@ -2181,74 +2181,73 @@ __global__ void k_spec3(Prob p, const double* __restrict__ F2, T* __restrict__ n
 // launchers
 // ---------------------------------------------------------------------------
 template <typename T>
-hipError_t launch_xfwd(int kinds, const Prob* P, int np, const WorkMap& wm, const T* s, void* X,
+hipError_t launch_xfwd(const Prob* P, int np, const WorkMap* wm, const T* s, void* X,
                        const void* tw, const int* done, size_t lds, hipStream_t st)
 {
-    if (wm.total == 0) return hipSuccess;
-    if (kinds & 1)
-        hipLaunchKernelGGL((k_xfwd<T, 0>), dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start, s,
+    if (wm[0].total)
+        hipLaunchKernelGGL((k_xfwd<T, 0>), dim3(wm[0].total), dim3(kNT), lds, st, P, np, wm[0].start, s,
                            (cplx<T>*)X, (const cplx<T>*)tw, done);
-    if (kinds & 2)
-        hipLaunchKernelGGL((k_xfwd<T, 1>), dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start, s,
+    if (wm[1].total)
+        hipLaunchKernelGGL((k_xfwd<T, 1>), dim3(wm[1].total), dim3(kNT), lds, st, P, np, wm[1].start, s,
                            (cplx<T>*)X, (const cplx<T>*)tw, done);
     return hipGetLastError();
 }
 
 template <typename T, int MZ, int BUILD>
-static void launch_conv_b(const Prob* P, int np, const WorkMap& wm, cplx<T>* x, cplx<T>* xp,
+static void launch_conv_b(const Prob* P, int np, const WorkMap* wm, cplx<T>* x, cplx<T>* xp,
                           const T* nhat, const cplx<T>* t, const int* done, size_t lds, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_conv<T, MZ, BUILD>), dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start, x, xp,
-                       nhat, t, done);
+    const WorkMap& w = wm[conv_slot(BUILD)];
+    if (w.total)
+        hipLaunchKernelGGL((k_conv<T, MZ, BUILD>), dim3(w.total), dim3(kNT), lds, st, P, np, w.start, x, xp,
+                           nhat, t, done);
 }
 
 template <typename T, int MZ>
-static hipError_t launch_conv_mz(int kinds, const Prob* P, int np, const WorkMap& wm, cplx<T>* x,
+static hipError_t launch_conv_mz(const Prob* P, int np, const WorkMap* wm, cplx<T>* x,
                                  cplx<T>* xp, const T* nhat, const cplx<T>* t, const int* done, size_t lds,
                                  hipStream_t st)
 {
-    if (kinds & 1) launch_conv_b<T, MZ, 0>(P, np, wm, x, xp, nhat, t, done, lds, st);
+    launch_conv_b<T, MZ, 0>(P, np, wm, x, xp, nhat, t, done, lds, st);
     if constexpr (MZ <= 8 && SSM_CONV_CT) {
-        if (kinds & (1 << 5)) launch_conv_b<T, MZ, 5>(P, np, wm, x, xp, nhat, t, done, lds, st);
-        if (kinds & (1 << 6)) launch_conv_b<T, MZ, 6>(P, np, wm, x, xp, nhat, t, done, lds, st);
-        if (kinds & (1 << 7)) launch_conv_b<T, MZ, 7>(P, np, wm, x, xp, nhat, t, done, lds, st);
-        if (kinds & (1 << 8)) launch_conv_b<T, MZ, 8>(P, np, wm, x, xp, nhat, t, done, lds, st);
-        if (kinds & (1 << 20)) launch_conv_b<T, MZ, 20>(P, np, wm, x, xp, nhat, t, done, lds, st);
-        if (kinds & (1 << 21)) launch_conv_b<T, MZ, 21>(P, np, wm, x, xp, nhat, t, done, lds, st);
-        if (kinds & (1 << 22)) launch_conv_b<T, MZ, 22>(P, np, wm, x, xp, nhat, t, done, lds, st);
+        launch_conv_b<T, MZ, 5>(P, np, wm, x, xp, nhat, t, done, lds, st);
+        launch_conv_b<T, MZ, 6>(P, np, wm, x, xp, nhat, t, done, lds, st);
+        launch_conv_b<T, MZ, 7>(P, np, wm, x, xp, nhat, t, done, lds, st);
+        launch_conv_b<T, MZ, 8>(P, np, wm, x, xp, nhat, t, done, lds, st);
+        launch_conv_b<T, MZ, 20>(P, np, wm, x, xp, nhat, t, done, lds, st);
+        launch_conv_b<T, MZ, 21>(P, np, wm, x, xp, nhat, t, done, lds, st);
+        launch_conv_b<T, MZ, 22>(P, np, wm, x, xp, nhat, t, done, lds, st);
     }
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_conv(int mz, int kinds, const Prob* P, int np, const WorkMap& wm, void* X, void* Xp,
+hipError_t launch_conv(int mz, const Prob* P, int np, const WorkMap* wm, void* X, void* Xp,
                        const T* nhat, const void* tw, const int* done, size_t lds, hipStream_t st)
 {
-    if (wm.total == 0) return hipSuccess;
     cplx<T>* x = (cplx<T>*)X;
     cplx<T>* xp = (cplx<T>*)Xp;
     const cplx<T>* t = (const cplx<T>*)tw;
     switch (mz) {
-    case 1: return launch_conv_mz<T, 1>(kinds, P, np, wm, x, xp, nhat, t, done, lds, st);
-    case 2: return launch_conv_mz<T, 2>(kinds, P, np, wm, x, xp, nhat, t, done, lds, st);
-    case 4: return launch_conv_mz<T, 4>(kinds, P, np, wm, x, xp, nhat, t, done, lds, st);
-    case 8: return launch_conv_mz<T, 8>(kinds, P, np, wm, x, xp, nhat, t, done, lds, st);
-    case 16: return launch_conv_mz<T, 16>(kinds, P, np, wm, x, xp, nhat, t, done, lds, st);
+    case 1: return launch_conv_mz<T, 1>(P, np, wm, x, xp, nhat, t, done, lds, st);
+    case 2: return launch_conv_mz<T, 2>(P, np, wm, x, xp, nhat, t, done, lds, st);
+    case 4: return launch_conv_mz<T, 4>(P, np, wm, x, xp, nhat, t, done, lds, st);
+    case 8: return launch_conv_mz<T, 8>(P, np, wm, x, xp, nhat, t, done, lds, st);
+    case 16: return launch_conv_mz<T, 16>(P, np, wm, x, xp, nhat, t, done, lds, st);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T>
-hipError_t launch_xinv(int kinds, const Prob* P, int np, const WorkMap& wm, const void* Xp, const T* s,
+hipError_t launch_xinv(const Prob* P, int np, const WorkMap* wm, const void* Xp, const T* s,
                        T* s_star, T* h, double* epart, const void* tw, const int* done, int mode,
                        double tau, double fcp, double fcd, size_t lds, hipStream_t st)
 {
-    if (wm.total == 0) return hipSuccess;
-    if (kinds & 1)
-        hipLaunchKernelGGL((k_xinv<T, 0>), dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start,
+    if (wm[0].total)
+        hipLaunchKernelGGL((k_xinv<T, 0>), dim3(wm[0].total), dim3(kNT), lds, st, P, np, wm[0].start,
                            (const cplx<T>*)Xp, s, s_star, h, epart, (const cplx<T>*)tw, done, mode, tau, fcp, fcd);
-    if (kinds & 2)
-        hipLaunchKernelGGL((k_xinv<T, 1>), dim3(wm.total), dim3(kNT), lds, st, P, np, wm.start,
+    if (wm[1].total)
+        hipLaunchKernelGGL((k_xinv<T, 1>), dim3(wm[1].total), dim3(kNT), lds, st, P, np, wm[1].start,
                            (const cplx<T>*)Xp, s, s_star, h, epart, (const cplx<T>*)tw, done, mode, tau, fcp, fcd);
     return hipGetLastError();
 }
@@ -3047,11 +3046,11 @@ hipError_t launch_fill_double(double* p, int n, double v, hipStream_t st)
 
 // explicit instantiations
 #define SSM_INST(T)                                                                                \
-    template hipError_t launch_xfwd<T>(int, const Prob*, int, const WorkMap&, const T*, void*,    \
+    template hipError_t launch_xfwd<T>(const Prob*, int, const WorkMap*, const T*, void*,         \
                                        const void*, const int*, size_t, hipStream_t);             \
-    template hipError_t launch_conv<T>(int, int, const Prob*, int, const WorkMap&, void*, void*,       \
+    template hipError_t launch_conv<T>(int, const Prob*, int, const WorkMap*, void*, void*,            \
                                        const T*, const void*, const int*, size_t, hipStream_t);   \
-    template hipError_t launch_xinv<T>(int, const Prob*, int, const WorkMap&, const void*,         \
+    template hipError_t launch_xinv<T>(const Prob*, int, const WorkMap*, const void*,              \
                                        const T*,                                                    \
                                        T*, T*, double*, const void*, const int*, int, double,     \
                                        double, double, size_t, hipStream_t);                       \
