@@ -97,6 +97,7 @@ struct Plan {
     int red_kinds = 0;                // reduction kernels in use (launch_reduce)
     bool rk = false;                  // workspace of the adaptive integrator reserved
     int kmax = 0;                     // largest image count of the batch
+    int kmax_le16 = 0, kmax_le32 = 0; // largest image counts <= 16 and <= 32 (0: none)
     size_t tsize = 8;                 // bytes of one spin component
     std::vector<Prob> P;
     std::vector<Tiles> tiles;         // tile shapes in use, per problem
@@ -358,7 +359,11 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
     }
     for (int i = 0; i < np; ++i) pl.P[i].nh_off = nh_off[pl.geo[i]];
     pl.n_img = img; pl.n_spin = spin; pl.n_x = xo; pl.n_nh = nh;
-    for (const Prob& q : pl.P) pl.kmax = std::max(pl.kmax, q.K);
+    for (const Prob& q : pl.P) {
+        pl.kmax = std::max(pl.kmax, q.K);
+        if (q.K <= 16) pl.kmax_le16 = std::max(pl.kmax_le16, q.K);
+        if (q.K <= 32) pl.kmax_le32 = std::max(pl.kmax_le32, q.K);
+    }
     pl.n_ep = ep; pl.n_ap = ap; pl.n_fp = fp; pl.n_fm = fm;
     // work maps
     auto prefix = [&](std::vector<int>& v, auto count) {
@@ -601,21 +606,27 @@ struct Ops {
                                  flags, 1, st, o);
         });
         if (e != hipSuccess) return e;
-        if ((o.opts & 1) && SSM_SPLW && pl.kmax <= kSplwMax<T>) {
+        // the spline: problems of at most kSplwMax images in one pass, the
+        // others by second derivatives then evaluation (per problem, so a
+        // problem's path does not depend on the rest of the batch)
+        const int kw = SSM_SPLW ? (kSplwMax<T> >= 32 ? pl.kmax_le32 : pl.kmax_le16) : 0;
+        const int kskip = SSM_SPLW ? kSplwMax<T> : 0;
+        if ((o.opts & 1) && kw > 0) {
             e = timed(c, st, KK_INTERP, [&] {
-                return launch_interp_splw<T>(c->P(), pl.np, c->wm_sitep(), pl.kmax, ss, s, c->at<int>(pl.o_j),
+                return launch_interp_splw<T>(c->P(), pl.np, c->wm_sitep(), kw, ss, s, c->at<int>(pl.o_j),
                                              c->at<double>(pl.o_w), o, done, flags, st);
             });
             if (e != hipSuccess) return e;
-        } else if (o.opts & 1) {
+        }
+        if ((o.opts & 1) && pl.kmax > kskip) {
             T* M = c->at<T>(pl.o_h);
             e = timed(c, st, KK_INTERP, [&] {
-                return launch_spline_m<T>(c->P(), pl.np, c->wm_sitep(), ss, M, o, done, st);
+                return launch_spline_m<T>(c->P(), pl.np, c->wm_sitep(), ss, M, o, done, kskip, st);
             });
             if (e != hipSuccess) return e;
             e = timed(c, st, KK_INTERP, [&] {
                 return launch_interp_spline<T>(c->P(), pl.np, c->wm_site(), ss, M, s, c->at<int>(pl.o_j),
-                                               c->at<double>(pl.o_w), o, done, flags, st);
+                                               c->at<double>(pl.o_w), o, done, flags, kskip, st);
             });
             if (e != hipSuccess) return e;
         }

@@ -199,16 +199,19 @@ hipError_t launch_interp(const Prob* P, int np, const WorkMap& wm, const T* ss, 
                          int* flags, hipStream_t st, const int* kci = nullptr,
                          const int* skip_if = nullptr);
 // natural cubic spline: second derivatives M of every site and component
-// (M buffer in the spin layout), then the interpolation at the targets
+// (M buffer in the spin layout), then the interpolation at the targets;
+// problems of at most kskip images are left to launch_interp_splw
 template <typename T>
 hipError_t launch_spline_m(const Prob* P, int np, const WorkMap& wm_sitep, const T* ss, T* M, Step2 s2,
-                           const int* done, hipStream_t st);
+                           const int* done, int kskip, hipStream_t st);
 template <typename T>
 hipError_t launch_interp_spline(const Prob* P, int np, const WorkMap& wm, const T* ss, const T* M, T* s,
                                 const int* jidx, const double* wgt, Step2 s2, const int* done, int* flags,
-                                hipStream_t st);
-// the spline step in one pass (K <= 16, or <= 32 in FP32; one thread per
-// site, wm_sitep); kmax: the largest image count of the batch
+                                int kskip, hipStream_t st);
+// the spline step in one pass for the problems of at most kSplwMax images
+// (one thread per site, wm_sitep); kmax: the largest of their image
+// counts; problems with more images are left to the two kernels above, so
+// each problem takes the same path whatever else is in the batch
 template <typename T>
 constexpr int kSplwMax = sizeof(T) == 4 ? 32 : 16;
 template <typename T>

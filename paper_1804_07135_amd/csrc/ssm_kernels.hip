@@ -96,7 +96,10 @@ template <> struct CT<float> { using type = float2; };
 template <> struct CT<double> { using type = double2; };
 template <typename T> using cplx = typename CT<T>::type;
 
-__device__ __forceinline__ int find_problem(const int* __restrict__ start, int np, int b)
+// The problem of item b: the last one whose first item (start, prefix
+// sums) is <= b.  find_problem_lane takes any b per lane; find_problem a b
+// that is the same on every lane of a full wavefront.
+__device__ __forceinline__ int find_problem_lane(const int* __restrict__ start, int np, int b)
 {
     int lo = 0, hi = np - 1;
     while (lo < hi) {
@@ -104,6 +107,17 @@ __device__ __forceinline__ int find_problem(const int* __restrict__ start, int n
         if (start[mid] <= b) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+__device__ __forceinline__ int find_problem(const int* __restrict__ start, int np, int b)
+{
+    if (np > 1 && np <= 64) {
+        // one load per lane and a ballot instead of a chain of dependent loads
+        const int lane = threadIdx.x & 63;
+        const int v = start[lane < np ? lane : 0];
+        return __popcll(__ballot(lane < np && v <= b)) - 1;
+    }
+    return find_problem_lane(start, np, b);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
@@ -2378,7 +2392,7 @@ __global__ void k_rk_init(const Prob* __restrict__ P, int np, int nimg, const in
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= nimg) return;
-    const int pi = find_problem(istart, np, g);
+    const int pi = find_problem_lane(istart, np, g);
     rs.t[g] = 0.0;
     rs.acc[g] = 0;
     const bool on = !(done && done[pi]);
@@ -2646,11 +2660,13 @@ hipError_t launch_rk_norm(const Prob* P, int np, const WorkMap& wm, const T* s, 
 template <typename T>
 __global__ __launch_bounds__(kNT) void k_spline_m(const Prob* __restrict__ P, int np,
                                                   const int* __restrict__ wstart, const T* __restrict__ ss,
-                                                  T* __restrict__ M, Step2 s2, const int* __restrict__ done)
+                                                  T* __restrict__ M, Step2 s2, const int* __restrict__ done,
+                                                  int kskip)
 {
     const int pi = find_problem(wstart, np, blockIdx.x);
     if ((done && done[pi]) || !s2.spl_ok[pi]) return;
     const Prob& p = P[pi];
+    if (p.K <= kskip) return;  // served by k_interp_splw
     const long long N = p.N, Ms = 3 * N;
     const long long i = (long long)(blockIdx.x - wstart[pi]) * kNT + threadIdx.x;
     if (i >= N) return;
@@ -2685,11 +2701,12 @@ __global__ __launch_bounds__(kNT) void k_interp_spline(const Prob* __restrict__ 
                                                        const T* __restrict__ M, T* __restrict__ s,
                                                        const int* __restrict__ jidx,
                                                        const double* __restrict__ wgt, Step2 s2,
-                                                       const int* __restrict__ done, int* flags)
+                                                       const int* __restrict__ done, int* flags, int kskip)
 {
     const int pi = find_problem(wstart, np, blockIdx.x);
     if ((done && done[pi]) || !s2.spl_ok[pi]) return;
     const Prob& p = P[pi];
+    if (p.K <= kskip) return;  // served by k_interp_splw
     const int w = blockIdx.x - wstart[pi];
     const int k = w / p.ichunks, chunk = w - k * p.ichunks;
     const long long N = p.N, Ms = 3 * N;
@@ -2746,6 +2763,7 @@ __global__ __launch_bounds__(kNT) void k_interp_splw(const Prob* __restrict__ P,
     const int pi = find_problem(wstart, np, blockIdx.x);
     if ((done && done[pi]) || !s2.spl_ok[pi]) return;
     const Prob& p = P[pi];
+    if (p.K > KMAX) return;  // served by k_spline_m and k_interp_spline
     const int K = p.K, g0 = p.img0, kci = s2.kci ? s2.kci[pi] : -1;
     if ((int)threadIdx.x < K) {
         // column i: M as a function of the unit image e_i (M_0 = M_{K-1} = 0)
@@ -2955,22 +2973,22 @@ __global__ __launch_bounds__(kNT) void k_ci_step(const Prob* __restrict__ P, int
 
 template <typename T>
 hipError_t launch_spline_m(const Prob* P, int np, const WorkMap& wm_sitep, const T* ss, T* M, Step2 s2,
-                           const int* done, hipStream_t st)
+                           const int* done, int kskip, hipStream_t st)
 {
     if (wm_sitep.total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_spline_m<T>, dim3(wm_sitep.total), dim3(kNT), 0, st, P, np, wm_sitep.start, ss, M, s2,
-                       done);
+                       done, kskip);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_interp_spline(const Prob* P, int np, const WorkMap& wm, const T* ss, const T* M, T* s,
                                 const int* jidx, const double* wgt, Step2 s2, const int* done, int* flags,
-                                hipStream_t st)
+                                int kskip, hipStream_t st)
 {
     if (wm.total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_interp_spline<T>, dim3(wm.total), dim3(kNT), 0, st, P, np, wm.start, ss, M, s, jidx, wgt,
-                       s2, done, flags);
+                       s2, done, flags, kskip);
     return hipGetLastError();
 }
 
@@ -3060,13 +3078,13 @@ hipError_t launch_fill_double(double* p, int n, double v, hipStream_t st)
                                          const int*, const double*, const int*, const int*, int*, \
                                          hipStream_t, const int*, const int*);                     \
     template hipError_t launch_spline_m<T>(const Prob*, int, const WorkMap&, const T*, T*, Step2,  \
-                                           const int*, hipStream_t);                               \
+                                           const int*, int, hipStream_t);                          \
     template hipError_t launch_interp_splw<T>(const Prob*, int, const WorkMap&, int, const T*, T*, \
                                               const int*, const double*, Step2, const int*, int*,  \
                                               hipStream_t);                                        \
     template hipError_t launch_interp_spline<T>(const Prob*, int, const WorkMap&, const T*,        \
                                                 const T*, T*, const int*, const double*, Step2,    \
-                                                const int*, int*, hipStream_t);                    \
+                                                const int*, int*, int, hipStream_t);               \
     template hipError_t launch_ci_part<T>(const Prob*, int, const WorkMap&, const T*, const T*,   \
                                           const double*, double*, int*, const int*, hipStream_t);  \
     template hipError_t launch_ci_step<T>(const Prob*, int, const WorkMap&, const T*, const T*,   \

@@ -39,6 +39,42 @@ def test_options_match_oracle(oracle, spline, climb, shape, K):
     np.testing.assert_allclose(sm.energies().cpu().numpy(), r["E"], rtol=0, atol=TOL64 * np.abs(r["E"]).max())
 
 
+@pytest.mark.parametrize("spline,climb", [(False, False), (True, True)])
+def test_both_reduction_paths_in_one_batch_vs_oracle(oracle, spline, climb):
+    """A problem of 70 images (more than the one-workgroup reduction takes:
+    one workgroup per image, the last one ends step 2) batched with one of 6
+    images (reduced in one workgroup), FP64, 5 iterations: each problem's
+    string and energies against the oracle at 1e-10, and bitwise equal to
+    its run alone."""
+    specs = [((8, 7, 1), 70, 3), ((9, 8, 1), 6, 4)]
+    probs, strings = [], []
+    for (nx, ny, nz), K, seed in specs:
+        probs.append(prob(nx, ny, nz, K, d=0.33, ku=0.12, D=0.05))
+        strings.append(inputs.perturb(inputs.bloch_point_string(nx, ny, nz, K, 2.0), seed))
+    mode = ssm.SSM_INTERP_SPLINE if spline else ssm.SSM_INTERP_LINEAR
+    sm = ssm.StringMethod(probs, ssm.SSM_FP64)
+    sm.set_reparam(mode, climb)
+    sm.set_string(strings)
+    sm.iterate(5, 0.1)
+    assert sm.check() == 0
+    flat = sm.get_string().cpu().numpy()
+    E = sm.energies().cpu().numpy()
+    off = e0 = 0
+    for p, s0 in zip(probs, strings):
+        r = oracle.iterate_opts(s0, *params(p), 5, 0.1, spline=spline, climb=climb)
+        n = r["s"].size
+        np.testing.assert_allclose(flat[off:off + n].reshape(r["s"].shape), r["s"], rtol=0, atol=TOL64)
+        np.testing.assert_allclose(E[e0:e0 + p["K"]], r["E"], rtol=0, atol=TOL64 * np.abs(r["E"]).max())
+        one = ssm.StringMethod(p, ssm.SSM_FP64)
+        one.set_reparam(mode, climb)
+        one.set_string(s0)
+        one.iterate(5, 0.1)
+        assert np.array_equal(flat[off:off + n], one.get_string().cpu().numpy().ravel())
+        assert np.array_equal(E[e0:e0 + p["K"]], one.energies().cpu().numpy())
+        off += n
+        e0 += p["K"]
+
+
 @pytest.mark.parametrize("K", [24, 40])
 def test_fp32_spline_paths_vs_oracle(oracle, K):
     """FP32-mixed form with the spline and the climbing image: K = 24 takes
