@@ -13,6 +13,7 @@ already resident in HBM when timing starts.  Prints one JSON line.
 """
 import argparse
 import hashlib
+import re
 import json
 import math
 import os
@@ -29,14 +30,19 @@ HBM_PEAK_GBS = 8000.0
 # packed FP32, which the build leaves off)
 FP32_VECTOR_NONPACKED_TFLOPS = 78.6
 KERNEL_SOURCES = ["paper_1804_07135_amd/csrc/ssm_kernels.hip", "paper_1804_07135_amd/csrc/ssm_internal.hpp",
-                  "paper_1804_07135_amd/csrc/ssm_fft.hpp"]
+                  "paper_1804_07135_amd/csrc/ssm_fft.hpp", "paper_1804_07135_amd/csrc/ssm_api.hip"]
+_CODE_TOKENS = re.compile(r'//[^\n]*|/\*.*?\*/|("(?:\\.|[^"\\])*")', re.S)
 
 
 def kernel_source_hash():
+    """Hash of the code of the kernels and of their launch configuration
+    (comments and layout ignored): a profile is reused only while this is
+    unchanged."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f)) as fh:
+            code = _CODE_TOKENS.sub(lambda m: m.group(1) or " ", fh.read())
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()[:16]
 
 

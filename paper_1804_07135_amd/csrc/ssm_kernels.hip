@@ -13,18 +13,22 @@
 //            renormalisation (eq. (10), Appendix force);
 //   k_arc    FP64 partial sums of |phi*_k - phi*_{k-1}|^2 (eq. (11));
 //   k_reduce per problem: energies, arc lengths, alpha* (eq. (12)) and the
-//            interpolation interval/weight of every image;
-//   k_interp linear interpolation onto alpha_k = k/(K-1) + renormalisation.
+//            interpolation interval/weight of every image (one workgroup
+//            per image, or k_reduce1: one per small problem);
+//   k_interp linear interpolation onto alpha_k = k/(K-1) + renormalisation
+//            (or the spline step of the options).
 //
-// Padded lengths are P = 2m with m a power of two >= n.  A zero-padded
-// length-P transform of n <= m inputs is two length-m transforms: the even
-// outputs are the FFT of the inputs, the odd outputs the FFT of the inputs
-// times W_P^j.  The inverse restricted to the first n outputs is the sum of
-// the two inverse length-m transforms, the odd one times W_P^{-j}.  So no
-// transform ever runs on a buffer of zeros, and only the x-spectra (m+1
-// complex values per row of n reals) travel through HBM.
+// Padded lengths are P = 2m with m >= n a power of two, or 3 2^a where that
+// is smaller.  A zero-padded length-P transform of n <= m inputs is two
+// length-m transforms: the even outputs are the FFT of the inputs, the odd
+// outputs the FFT of the inputs times W_P^j.  The inverse restricted to the
+// first n outputs is the sum of the two inverse length-m transforms, the
+// odd one times W_P^{-j}.  So no transform ever runs on a buffer of zeros,
+// and only the x-spectra (m+1 complex values per row of n reals) travel
+// through HBM.
 //
-// Length-m transforms run in LDS as Stockham radix-4 (+ one radix-2) passes;
+// Length-m transforms run in LDS as Stockham passes (radix 16 first at the
+// compile-time lengths, radix 4 and 2 otherwise; a radix-3 step for 3 2^a);
 // every line belongs to one wavefront, which needs no workgroup barrier
 // between passes.
 #include "ssm_fft.hpp"

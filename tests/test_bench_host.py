@@ -58,3 +58,23 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
             "    print('raised', e)\n")
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120, cwd=ROOT)
     assert "raised" in r.stdout and "missing" in r.stdout
+
+
+def test_profile_hash_follows_code_not_comments(tmp_path, monkeypatch):
+    """A stored profile is reused while the kernels' and launchers' code is
+    unchanged: editing a comment or the layout keeps the hash, editing code
+    (here one launch constant of the host plan) changes it."""
+    for f in bench.KERNEL_SOURCES:
+        d = tmp_path / os.path.dirname(f)
+        d.mkdir(parents=True, exist_ok=True)
+        (tmp_path / f).write_text(open(os.path.join(bench.ROOT, f)).read())
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h0 = bench.kernel_source_hash()
+    k = tmp_path / bench.KERNEL_SOURCES[0]
+    k.write_text("// a new comment line\n" + k.read_text().replace("\n{", "\n  {", 3))
+    assert bench.kernel_source_hash() == h0
+    a = tmp_path / "paper_1804_07135_amd/csrc/ssm_api.hip"
+    src = a.read_text()
+    assert "12288 / p.arc_chunks" in src
+    a.write_text(src.replace("12288 / p.arc_chunks", "6144 / p.arc_chunks"))
+    assert bench.kernel_source_hash() != h0
