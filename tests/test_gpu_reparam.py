@@ -40,13 +40,14 @@ def test_options_match_oracle(oracle, spline, climb, shape, K):
 
 
 @pytest.mark.parametrize("spline,climb", [(False, False), (True, True)])
-def test_both_reduction_paths_in_one_batch_vs_oracle(oracle, spline, climb):
-    """A problem of 70 images (more than the one-workgroup reduction takes:
-    one workgroup per image, the last one ends step 2) batched with one of 6
-    images (reduced in one workgroup), FP64, 5 iterations: each problem's
-    string and energies against the oracle at 1e-10, and bitwise equal to
-    its run alone."""
-    specs = [((8, 7, 1), 70, 3), ((9, 8, 1), 6, 4)]
+@pytest.mark.parametrize("K1", [64, 65, 70])
+def test_both_reduction_paths_in_one_batch_vs_oracle(oracle, spline, climb, K1):
+    """A problem of K1 images (64: the most the one-workgroup reduction
+    takes; 65, 70: one workgroup per image, the last one ends step 2)
+    batched with one of 6 images (reduced in one workgroup, one-pass
+    spline), FP64, 5 iterations: each problem's string and energies against
+    the oracle at 1e-10, and bitwise equal to its run alone."""
+    specs = [((8, 7, 1), K1, 3), ((9, 8, 1), 6, 4)]
     probs, strings = [], []
     for (nx, ny, nz), K, seed in specs:
         probs.append(prob(nx, ny, nz, K, d=0.33, ku=0.12, D=0.05))
