@@ -421,6 +421,8 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     constexpr int f3 = F3;
     const int lhp = __ffs(hp) - 1;  // tiles are powers of two
     const int psh = x_padl(lm, f3) ? x_padl(lm, f3) : 31;  // pad layout of the lines
+    // line index of position q (< m) of line l: l m + q, m = 2^lm or 3 2^lm
+    auto lidx = [&](int l, int q) { return (F3 ? (l + (l << 1)) << lm : l << lm) + q; };
     V* twl = reinterpret_cast<V*>(smem_);
     V* lines = twl + 2 * m;
     load_twiddles(twl, lm, f3, tw);
@@ -450,8 +452,8 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
             const int rp = idx & (hp - 1), kx = idx >> lhp;
             const int kr = kx ? P2 - kx : 0;
             // the two halves (even, odd frequencies) are separate lines
-            const int iz = (2 * rp + (kx & 1)) * m + fpos(kx >> 1, lm, f3);
-            const int ir = (2 * rp + (kr & 1)) * m + fpos(kr >> 1, lm, f3);
+            const int iz = lidx(2 * rp + (kx & 1), fpos(kx >> 1, lm, f3));
+            const int ir = lidx(2 * rp + (kr & 1), fpos(kr >> 1, lm, f3));
             const V Z = lines[iz + (iz >> psh)];
             const V Zr = lines[ir + (ir >> psh)];
             const T hlf = T(0.5);
@@ -1123,42 +1125,53 @@ __device__ __forceinline__ void xinv_load_lines(const char* __restrict__ Xi, cpl
     using V = cplx<T>;
     constexpr int f3 = F3;
     const int total = (m + 1) * hp;
+    // line index of position q (< m) of line l: l m + q, m = 2^lm or 3 2^lm
+    auto lidx = [&](int l, int q) { return (F3 ? (l + (l << 1)) << lm : l << lm) + q; };
     auto rounds = [&](auto oddc) {
         constexpr bool ODD = decltype(oddc)::value;
+        // the items of a thread share rp (kNT is a multiple of hp) and step
+        // kx by dk = kNT / hp, so their offsets step by a uniform stride;
+        // items past the end read kx = m
+        const int dk = kNT >> lhp;
+        const unsigned kstr = (unsigned)(dk * 3 * nz * ny) * (unsigned)sizeof(V);
+        const unsigned cbm = (unsigned)(((m * 3 + c) * nz + z) * ny) * (unsigned)sizeof(V);
 #pragma unroll 1
         for (int idx0 = threadIdx.x; idx0 < total; idx0 += kXinvU * kNT) {
+            const int rp = idx0 & (hp - 1), kx0 = idx0 >> lhp;
+            const int ya = y0 + 2 * rp;
+            const unsigned cb0 = (unsigned)(((kx0 * 3 + c) * nz + z) * ny) * (unsigned)sizeof(V);
+            const unsigned ya0 = (unsigned)min(ya, ny - (ODD ? 1 : 2)) * (unsigned)sizeof(V);
+            const unsigned ya1 = (unsigned)min(ya + 1, ny - 1) * (unsigned)sizeof(V);
             V A[kXinvU], B[kXinvU];
 #pragma unroll
             for (int u = 0; u < kXinvU; ++u) {
-                const int idx = min(idx0 + u * kNT, total - 1);
-                const int rp = idx & (hp - 1), kx = idx >> lhp;
-                const int ya = y0 + 2 * rp;
-                const unsigned cb = (unsigned)(((kx * 3 + c) * nz + z) * ny) * (unsigned)sizeof(V);
+                const unsigned cb = min(cb0 + (unsigned)u * kstr, cbm);
                 if constexpr (!ODD) {
-                    load2(reinterpret_cast<const V*>(Xi + cb + (unsigned)min(ya, ny - 2) * (unsigned)sizeof(V)), A[u],
-                          B[u]);
+                    load2(reinterpret_cast<const V*>(Xi + cb + ya0), A[u], B[u]);
                 } else {
-                    A[u] = *reinterpret_cast<const V*>(Xi + cb + (unsigned)min(ya, ny - 1) * (unsigned)sizeof(V));
-                    B[u] = *reinterpret_cast<const V*>(Xi + cb + (unsigned)min(ya + 1, ny - 1) * (unsigned)sizeof(V));
+                    A[u] = *reinterpret_cast<const V*>(Xi + cb + ya0);
+                    B[u] = *reinterpret_cast<const V*>(Xi + cb + ya1);
                 }
+            }
+            if constexpr (ODD) {
+                if (ya >= ny)
+#pragma unroll
+                    for (int u = 0; u < kXinvU; ++u) A[u] = mk<V>(0, 0);
+                if (ya + 1 >= ny)
+#pragma unroll
+                    for (int u = 0; u < kXinvU; ++u) B[u] = mk<V>(0, 0);
             }
 #pragma unroll
             for (int u = 0; u < kXinvU; ++u) {
-                const int idx = idx0 + u * kNT;
-                if (idx >= total) break;
-                const int rp = idx & (hp - 1), kx = idx >> lhp;
-                V a = A[u], b = B[u];
-                if constexpr (ODD) {
-                    const int ya = y0 + 2 * rp;
-                    if (ya >= ny) a = mk<V>(0, 0);
-                    if (ya + 1 >= ny) b = mk<V>(0, 0);
-                }
+                if (idx0 + u * kNT >= total) break;
+                const int kx = kx0 + u * dk;
+                const V a = A[u], b = B[u];
                 // the two halves (even, odd frequencies) are separate lines
-                const int i0 = (2 * rp + (kx & 1)) * m + fpos(kx >> 1, lm, f3);
+                const int i0 = lidx(2 * rp + (kx & 1), fpos(kx >> 1, lm, f3));
                 lines[i0 + (i0 >> psh)] = mk<V>(a.x - b.y, a.y + b.x);
                 if (kx > 0 && kx < m) {
                     const int km = 2 * m - kx;
-                    const int i1 = (2 * rp + (km & 1)) * m + fpos(km >> 1, lm, f3);
+                    const int i1 = lidx(2 * rp + (km & 1), fpos(km >> 1, lm, f3));
                     lines[i1 + (i1 >> psh)] = mk<V>(a.x + b.y, b.x - a.y);
                 }
             }
@@ -1219,7 +1232,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     for (int c = 0; c < 3; ++c) {
         // kXinvU items per thread per round: their loads are issued
         // together (no load sits under a branch; an item past the end loads
-        // the last item's values and stores nothing), then their LDS writes
+        // the values at kx = m and stores nothing), then their LDS writes
         xinv_load_lines<T, F3>(Xi, lines, c, z, y0, hp, lhp, m, lm, nz, ny, psh);
         __syncthreads();
         fft_lines_x<V, true>(lines, yt, lm, f3, twl);
