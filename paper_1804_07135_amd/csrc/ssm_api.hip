@@ -419,7 +419,7 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
     pl.o_flags = take(4);
     pl.o_seg = take(8 * img);
     pl.o_cnt = take(4 * np);
-    pl.o_s2 = take(8 * 7 * img);   // spline: hh, sa, den, cp, A, B, H per image
+    pl.o_s2 = take(8 * (7 + kWRow) * img);  // spline: hh, sa, den, cp, A, B, H, operator row per image
     pl.o_kci = take(4 * np);
     pl.o_splok = take(4 * np);
     pl.o_cic = take(8 * np);
@@ -505,6 +505,8 @@ struct ssm_ctx {
         const long long n = pl.n_img;
         r.hh = b; r.sa = b + n; r.den = b + 2 * n; r.cp = b + 3 * n;
         r.A = b + 4 * n; r.B = b + 5 * n; r.H = b + 6 * n;
+        r.Wm = b + 7 * n;
+        r.wmax = SSM_SPLW ? (pl.tsize == 4 ? kSplwMax<float> : kSplwMax<double>) : 0;
         return r;
     }
     void* X() const { return ws + pl.o_big; }

@@ -183,7 +183,13 @@ struct Step2 {
     double* A = nullptr;
     double* B = nullptr;
     double* H = nullptr;
+    // the one-pass spline step's K x K operator of every problem of at most
+    // wmax images (row k of problem pi at Wm + (img0 + k) kWRow), formed by
+    // the end of step 2; wmax = 0: not formed
+    double* Wm = nullptr;
+    int wmax = 0;
 };
+constexpr int kWRow = 32;  // row stride of Step2::Wm (the largest one-pass image count)
 // kinds: bit 0 problems reduced per image, bit 1 problems reduced by one
 // workgroup (Prob::red1)
 hipError_t launch_reduce(const Prob* P, int np, int nimg, int kinds, const int* istart, const double* epart,
@@ -214,6 +220,7 @@ hipError_t launch_interp_spline(const Prob* P, int np, const WorkMap& wm, const 
 // each problem takes the same path whatever else is in the batch
 template <typename T>
 constexpr int kSplwMax = sizeof(T) == 4 ? 32 : 16;
+static_assert(kSplwMax<float> <= kWRow && kSplwMax<double> <= kWRow, "operator rows");
 template <typename T>
 hipError_t launch_interp_splw(const Prob* P, int np, const WorkMap& wm_sitep, int kmax, const T* ss, T* s,
                               const int* jidx, const double* wgt, Step2 s2, const int* done, int* flags,

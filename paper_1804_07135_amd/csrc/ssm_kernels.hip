@@ -1577,6 +1577,12 @@ __device__ void reduce_final(const Prob& p, int pi, double* al, double* el, doub
         wgt[g0 + kk] = (width > 0.0) ? (tk - al[j]) / width : 0.0;
     }
     if (!(s2.opts & 1)) return;
+    // the one-pass spline step's operator is formed here for K <= wmax
+    // (copies of the factors and targets kept in LDS for it)
+    const bool wop = K <= s2.wmax;
+    __shared__ double fsa[kWRow], fden[kWRow], fcp[kWRow], tA[kWRow], tB[kWRow], tH[kWRow];
+    __shared__ double Zs[kWRow][kWRow + 1];
+    __shared__ int tj[kWRow], s_ok;
     // natural cubic spline in alpha: interval widths and the Thomas factors
     // of the tridiagonal system for the interior second derivatives
     if (threadIdx.x == 0) {
@@ -1596,9 +1602,11 @@ __device__ void reduce_final(const Prob& p, int pi, double* al, double* el, doub
                 s2.sa[g0 + i] = a;
                 s2.den[g0 + i] = den;
                 s2.cp[g0 + i] = cpp;
+                if (wop) { fsa[i] = a; fden[i] = den; fcp[i] = cpp; }
             }
         }
         s2.spl_ok[pi] = ok;
+        s_ok = ok;
     }
     for (int kk = threadIdx.x; kk < K; kk += kNT) {
         if (kk == 0 || kk == K - 1 || kk == kci) continue;
@@ -1611,6 +1619,46 @@ __device__ void reduce_final(const Prob& p, int pi, double* al, double* el, doub
         s2.A[g0 + kk] = A;
         s2.B[g0 + kk] = 1.0 - A;
         s2.H[g0 + kk] = h;
+        if (wop) { tA[kk] = A; tB[kk] = 1.0 - A; tH[kk] = h; tj[kk] = j; }
+    }
+    if (!wop) return;
+    __syncthreads();
+    if (!s_ok) return;
+    // the interpolated value at target k is linear in the K images of a
+    // site, s(t_k) = sum_i W_ki f_i: column i of the second-derivative map
+    // by the Thomas recurrences on the unit image e_i (M_0 = M_{K-1} = 0),
+    // then the spline formula; rows of the endpoints and of the climbing
+    // image are zero (they are copied)
+    if ((int)threadIdx.x < K) {
+        const int i = threadIdx.x;
+        double dpp = 0.0;
+        Zs[0][i] = 0.0;
+        Zs[K - 1][i] = 0.0;
+        for (int k = 1; k <= K - 2; ++k) {
+            const double r = ((i == k + 1 ? 1.0 : 0.0) - (i == k ? 1.0 : 0.0)) / (al[k + 1] - al[k]) -
+                             ((i == k ? 1.0 : 0.0) - (i == k - 1 ? 1.0 : 0.0)) / (al[k] - al[k - 1]);
+            const double dp = (r - (k > 1 ? fsa[k] * dpp : 0.0)) / fden[k];
+            Zs[k][i] = dp;
+            dpp = dp;
+        }
+        double mn = Zs[K - 2][i];
+        for (int k = K - 3; k >= 1; --k) {
+            const double mk = Zs[k][i] - fcp[k] * mn;
+            Zs[k][i] = mk;
+            mn = mk;
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < K * K; e += kNT) {
+        const int k = e / K, i = e - k * K;
+        double w = 0.0;
+        if (k > 0 && k < K - 1 && k != kci) {
+            const int j = tj[k];
+            const double A = tA[k], B = tB[k], h = tH[k];
+            w = (i == j ? A : 0.0) + (i == j + 1 ? B : 0.0) +
+                ((A * A * A - A) * Zs[j][i] + (B * B * B - B) * Zs[j + 1][i]) * h * h / 6.0;
+        }
+        s2.Wm[(long long)(g0 + k) * kWRow + i] = w;
     }
 }
 
@@ -2762,12 +2810,13 @@ __global__ __launch_bounds__(kNT) void k_interp_spline(const Prob* __restrict__ 
 }
 
 // The same spline step in one pass for K <= KMAX: the interpolated value at
-// a target is linear in the K images of its site, s(t_k) = sum_i W_ki f_i,
-// so each workgroup first forms the problem's K x K operator W in LDS (the
-// columns of the second-derivative map by the Thomas recurrences of
-// k_spline_m applied to unit right-hand sides, then the spline formula of
-// k_interp_spline), and each thread then reads its site's K images once and
-// writes the K targets.  Endpoints and the climbing image are copied.
+// a target is linear in the K images of its site, s(t_k) = sum_i W_ki f_i.
+// The problem's K x K operator W (the columns of the second-derivative map
+// by the Thomas recurrences of k_spline_m applied to unit right-hand sides,
+// then the spline formula of k_interp_spline) is formed once by the end of
+// step 2 (reduce_final); each workgroup loads it into LDS, and each thread
+// then reads its site's K images once and writes the K targets.  Endpoints
+// and the climbing image are copied.
 template <typename T, int KMAX>
 __global__ __launch_bounds__(kNT) void k_interp_splw(const Prob* __restrict__ P, int np,
                                                      const int* __restrict__ wstart, const T* __restrict__ ss,
@@ -2775,46 +2824,16 @@ __global__ __launch_bounds__(kNT) void k_interp_splw(const Prob* __restrict__ P,
                                                      const double* __restrict__ wgt, Step2 s2,
                                                      const int* __restrict__ done, int* flags)
 {
-    __shared__ double Z[KMAX][KMAX];
     __shared__ double W[KMAX][KMAX];
     const int pi = find_problem(wstart, np, blockIdx.x);
     if ((done && done[pi]) || !s2.spl_ok[pi]) return;
     const Prob& p = P[pi];
     if (p.K > KMAX) return;  // served by k_spline_m and k_interp_spline
     const int K = p.K, g0 = p.img0, kci = s2.kci ? s2.kci[pi] : -1;
-    if ((int)threadIdx.x < K) {
-        // column i: M as a function of the unit image e_i (M_0 = M_{K-1} = 0)
-        const int i = threadIdx.x;
-        double dpp = 0.0;
-        Z[0][i] = 0.0;
-        Z[K - 1][i] = 0.0;
-        for (int k = 1; k <= K - 2; ++k) {
-            const double r = ((i == k + 1 ? 1.0 : 0.0) - (i == k ? 1.0 : 0.0)) / s2.hh[g0 + k] -
-                             ((i == k ? 1.0 : 0.0) - (i == k - 1 ? 1.0 : 0.0)) / s2.hh[g0 + k - 1];
-            const double dp = (r - (k > 1 ? s2.sa[g0 + k] * dpp : 0.0)) / s2.den[g0 + k];
-            Z[k][i] = dp;
-            dpp = dp;
-        }
-        if (K >= 3) {
-            double mn = Z[K - 2][i];
-            for (int k = K - 3; k >= 1; --k) {
-                const double mk = Z[k][i] - s2.cp[g0 + k] * mn;
-                Z[k][i] = mk;
-                mn = mk;
-            }
-        }
-    }
-    __syncthreads();
+    // the problem's operator, formed by the end of step 2
     for (int e = threadIdx.x; e < KMAX * KMAX; e += kNT) {
         const int k = e / KMAX, i = e % KMAX;
-        double w = 0.0;
-        if (k < K && i < K && k > 0 && k < K - 1 && k != kci) {
-            const int g = g0 + k, j = jidx[g];
-            const double A = s2.A[g], B = s2.B[g], h = s2.H[g];
-            w = (i == j ? A : 0.0) + (i == j + 1 ? B : 0.0) +
-                ((A * A * A - A) * Z[j][i] + (B * B * B - B) * Z[j + 1][i]) * h * h / 6.0;
-        }
-        W[k][i] = w;
+        W[k][i] = (k < K && i < K) ? s2.Wm[(long long)(g0 + k) * kWRow + i] : 0.0;
     }
     __syncthreads();
     const long long N = p.N, Ms = 3 * N;
@@ -2842,17 +2861,21 @@ __global__ __launch_bounds__(kNT) void k_interp_splw(const Prob* __restrict__ P,
 #pragma unroll
             for (int c = 0; c < 3; ++c) v[c] += w * (double)f[c][q];
         }
-        const double nrm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-        if (!isfinite(nrm)) atomicOr(flags, 4);
-        if (nrm < 1e-12) {
+        // renormalised by the device library's FP64 reciprocal square root
+        // (within an ulp or two of sqrt and division); the norm below 1e-12
+        // takes the nearer source's spin
+        const double n2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        if (!isfinite(n2)) atomicOr(flags, 4);
+        if (n2 < 1e-24) {
             atomicOr(flags, 2);
             const int g = g0 + k, j = jidx[g];
             const int jn = (wgt[g] < 0.5) ? j : j + 1;
 #pragma unroll
             for (int c = 0; c < 3; ++c) dst[k * Ms + c * N] = src[jn * Ms + c * N];
         } else {
+            const double inv = rsqrt(n2);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) dst[k * Ms + c * N] = (T)(v[c] / nrm);
+            for (int c = 0; c < 3; ++c) dst[k * Ms + c * N] = (T)(v[c] * inv);
         }
     }
 }
