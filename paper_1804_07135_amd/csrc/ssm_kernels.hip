@@ -1900,14 +1900,14 @@ __global__ __launch_bounds__(kNT) void k_interp(const Prob* __restrict__ P, int 
                 double v[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) v[c] = (1.0 - wt) * (double)av[c][q] + wt * (double)bv[c][q];
-                const double nrm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-                if (!isfinite(nrm)) atomicOr(flags, 4);
-                if (nrm < 1e-12) {
+                const double n2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+                if (!isfinite(n2)) atomicOr(flags, 4);
+                if (n2 < 1e-24) {
                     atomicOr(flags, 2);
 #pragma unroll
                     for (int c = 0; c < 3; ++c) o[c][q] = (wt < 0.5) ? av[c][q] : bv[c][q];
                 } else {
-                    const double inv = 1.0 / nrm;
+                    const double inv = rsqrt(n2);
 #pragma unroll
                     for (int c = 0; c < 3; ++c) o[c][q] = (float)(v[c] * inv);
                 }
@@ -1932,9 +1932,12 @@ __global__ __launch_bounds__(kNT) void k_interp(const Prob* __restrict__ P, int 
     double v[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) v[c] = (1.0 - wt) * (double)a[c * N + i] + wt * (double)b[c * N + i];
-    const double nrm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-    if (!isfinite(nrm)) atomicOr(flags, 4);
-    if (nrm < 1e-12) {
+    // renormalised by the device library's FP64 reciprocal square root
+    // (within an ulp or two of sqrt and division); a norm below 1e-12 takes
+    // the nearer source's spin
+    const double n2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    if (!isfinite(n2)) atomicOr(flags, 4);
+    if (n2 < 1e-24) {
         atomicOr(flags, 2);
         const T* n = (wt < 0.5) ? a : b;
 #pragma unroll
@@ -1942,7 +1945,7 @@ __global__ __launch_bounds__(kNT) void k_interp(const Prob* __restrict__ P, int 
     } else {
         // the same arithmetic as the four-site path, so a problem's result
         // does not depend on which path its place in a batch selects
-        const double inv = 1.0 / nrm;
+        const double inv = rsqrt(n2);
 #pragma unroll
         for (int c = 0; c < 3; ++c) dst[c * N + i] = (T)(v[c] * inv);
     }
