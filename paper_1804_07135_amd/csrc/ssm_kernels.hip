@@ -537,6 +537,30 @@ __device__ __forceinline__ void conv_zphase(const Prob& p, int G, int kx0, int h
         // the even half has no twiddles, and no selects between the halves)
         auto zhalf = [&](auto hzc) {
             constexpr int hz = decltype(hzc)::value;
+            const T* nh = nhat + p.nh_off + (((((long long)kx * nhz + hz) * 2 + hy) * MZ) * 6 * MY) + qy;
+            // the column's kernel-spectrum rows, loaded before its LDS reads
+            // and z transforms so that their latency overlaps that work.
+            // z frequency kz = 2r + hz and its mirror -kz (mod 2 MZ) hold
+            // the same spectrum up to the sign of the z-odd components xz
+            // and yz (the tensor is even in z except for those), so each
+            // column reads only the rows r <= mirror (9 of 16 for MZ = 8)
+            // and the unrolled loop folds the repeated loads (not for 8
+            // layers with y lengths below 256, where keeping the shared rows
+            // live costs more registers than it saves)
+            constexpr bool kMir = SSM_CONV_NH_MIRROR && (MZ <= 4 || LMY >= 8);
+            T nv[MZ][6];
+#pragma unroll
+            for (int r = 0; r < MZ; ++r) {
+                const bool mir = kMir && (hz == 0 ? 2 * r > MZ : 2 * r >= MZ);
+                const int rs = mir ? (hz == 0 ? MZ - r : MZ - 1 - r) : r;
+                const T* q6 = nh + rs * 6 * MY;
+                nv[r][0] = q6[0];
+                nv[r][1] = q6[MY];
+                nv[r][2] = mir ? -q6[2 * MY] : q6[2 * MY];
+                nv[r][3] = q6[3 * MY];
+                nv[r][4] = mir ? -q6[4 * MY] : q6[4 * MY];
+                nv[r][5] = q6[5 * MY];
+            }
             V a[3][MZ];
 #pragma unroll
             for (int c = 0; c < 3; ++c)
@@ -548,23 +572,10 @@ __device__ __forceinline__ void conv_zphase(const Prob& p, int G, int kx0, int h
                 }
 #pragma unroll
             for (int c = 0; c < 3; ++c) dft_reg<V, MZ, false>(a[c]);
-            const T* nh = nhat + p.nh_off + (((((long long)kx * nhz + hz) * 2 + hy) * MZ) * 6 * MY) + qy;
 #pragma unroll
             for (int r = 0; r < MZ; ++r) {
-                // z frequency kz = 2r + hz and its mirror -kz (mod 2 MZ) hold
-                // the same spectrum up to the sign of the z-odd components
-                // xz and yz (the tensor is even in z except for those), so
-                // each column reads only the rows r <= mirror (9 of 16 for
-                // MZ = 8) and the unrolled loop folds the repeated loads
-                // (not for 8 layers with y lengths below 256, where keeping
-                // the shared rows live costs more registers than it saves)
-                constexpr bool kMir = SSM_CONV_NH_MIRROR && (MZ <= 4 || LMY >= 8);
-                const bool mir = kMir && (hz == 0 ? 2 * r > MZ : 2 * r >= MZ);
-                const int rs = mir ? (hz == 0 ? MZ - r : MZ - 1 - r) : r;
-                const T* q6 = nh + rs * 6 * MY;
-                if (SSM_CONV_NH_SERIAL) asm volatile("" : "+v"(q6));
-                const T nxx = q6[0], nxy = q6[MY], nxz = mir ? -q6[2 * MY] : q6[2 * MY];
-                const T nyy = q6[3 * MY], nyz = mir ? -q6[4 * MY] : q6[4 * MY], nzz = q6[5 * MY];
+                const T nxx = nv[r][0], nxy = nv[r][1], nxz = nv[r][2];
+                const T nyy = nv[r][3], nyz = nv[r][4], nzz = nv[r][5];
                 const V sx = a[0][r], sy = a[1][r], sz = a[2][r];
                 a[0][r] = mk<V>(nxx * sx.x + nxy * sy.x + nxz * sz.x, nxx * sx.y + nxy * sy.y + nxz * sz.y);
                 a[1][r] = mk<V>(nxy * sx.x + nyy * sy.x + nyz * sz.x, nxy * sx.y + nyy * sy.y + nyz * sz.y);
