@@ -1306,8 +1306,11 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     auto at = [&](unsigned o) -> T { return *reinterpret_cast<const T*>(sb + o); };
     int nxp = 1;
     while (nxp < nx && nxp < kNT) nxp <<= 1;
+    // row groups of nxp lanes: the power of two >= nx, or nx itself where
+    // that gives each thread fewer rows (lanes past the last group idle)
+    if (nx < nxp && (yt + kNT / nx - 1) / (kNT / nx) < (yt + kNT / nxp - 1) / (kNT / nxp)) nxp = nx;
     const int rgs = kNT / nxp;                    // row groups
-    const int rg = threadIdx.x / nxp, xl = threadIdx.x & (nxp - 1);
+    const int rg = threadIdx.x / nxp, xl = threadIdx.x - rg * nxp;
     const int rper = (yt + rgs - 1) / rgs;
     const int ra = rg * rper, rb = min(yt, ra + rper);
     const int lane = threadIdx.x & 63;
@@ -1317,9 +1320,12 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         const int x = xc + xl;
         const bool xin = x < nx;
         // a lane at the edge of its wavefront or row group loads its one
-        // neighbour outside it (the last lane the right one, the first lane
-        // the left one; a lane at both edges has nx = 1 and no neighbours)
-        const bool egok = redge ? x + 1 < nx : (ledge && x > 0);
+        // neighbour outside it that lies in the lattice: the right one at a
+        // right edge, else the left one at a left edge (with row groups of
+        // nx lanes a lane can end a row group and start a wavefront; it is
+        // then at the lattice's right end and needs only the left one)
+        const bool needR = redge && x + 1 < nx, needL = ledge && x > 0;
+        const bool egok = needR || needL;
         const int xcl = min(x, nx - 1);
         // spin component c at (x, y0 + rr), zero outside the lattice in y
         // (loaded from the site clamped into the lattice, then selected: the
@@ -1342,7 +1348,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
                 const unsigned oc = o + c * cb;
                 zu[c] = (z + 1 < nz) ? at(oc + plb) : T(0);
                 zd[c] = (z > 0) ? at(oc - plb) : T(0);
-                eg[c] = (a && egok) ? at(redge ? oc + xb : oc - xb) : T(0);
+                eg[c] = (a && egok) ? at(needR ? oc + xb : oc - xb) : T(0);
             }
         };
         T cm[3], cc[3], cp[3], zu[3], zd[3], eg[3];
@@ -1368,7 +1374,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
                 T right = lane_next(cc[c]);
                 T left = lane_prev(cc[c]);
                 if (redge) right = eg[c];
-                if (ledge) left = eg[c];
+                if (ledge) left = needL ? eg[c] : T(0);
                 if (x + 1 >= nx) right = T(0);
                 sv[c] = (double)cc[c];
                 xp[c] = (double)right;
