@@ -298,14 +298,16 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
         p.ep_off = ep;
         p.ap_off = ap;
         p.arc_chunks = (int)((3 * p.N + kNT * kArcEPT - 1) / (kNT * kArcEPT));
-        // image groups: in FP32 at most 12288 workgroups (six per resident
-        // slot on 256 CUs; short groups of about three images balance
-        // better than one long round, and the image each group re-reads is
-        // mostly an L2 hit: the same chunk of neighbouring groups lands on
-        // the same XCD), in FP64 at least 512 (FP64 chunks carry twice the
-        // bytes and stream best ungrouped on large lattices); small
-        // lattices get parallelism over images
-        const int arc_ng = pl.tsize == 4 ? 12288 / p.arc_chunks : (512 + p.arc_chunks - 1) / p.arc_chunks;
+        // image groups: in FP32 groups of about three images (short groups
+        // balance better than one long round, and the image each group
+        // re-reads is mostly an L2 hit: the same chunk of neighbouring
+        // groups lands on the same XCD; single images leave small lattices
+        // with workgroups too short to pay for their start), at most 12288
+        // workgroups per problem; in FP64 at least 512 workgroups (FP64
+        // chunks carry twice the bytes and stream best ungrouped on large
+        // lattices)
+        const int arc_ng = pl.tsize == 4 ? std::min(12288 / p.arc_chunks, (p.K - 1 + 2) / 3)
+                                         : (512 + p.arc_chunks - 1) / p.arc_chunks;
         p.arc_ng = std::max(1, std::min(p.K - 1, arc_ng));
         p.arc_g = (p.K - 1 + p.arc_ng - 1) / p.arc_ng;
         p.arc_ng = (p.K - 1 + p.arc_g - 1) / p.arc_g;
