@@ -2917,13 +2917,30 @@ __global__ __launch_bounds__(kNT) void k_ci_part(const Prob* __restrict__ P, int
     const Prob& p = P[pi];
     const int chunk = blockIdx.x - wstart[pi];
     const int K = p.K, g0 = p.img0;
-    if (threadIdx.x == 0) {
-        int km = 0;
-        double em = E[g0];
-        for (int kk = 1; kk < K; ++kk)
-            if (E[g0 + kk] > em) { em = E[g0 + kk]; km = kk; }
-        s_km = km;
-        if (chunk == 0) kci[pi] = (km > 0 && km < K - 1) ? km : -1;
+    if (threadIdx.x < 64) {
+        // the first index of the largest energy (NaN energies never count;
+        // a NaN first energy gives 0), by the first wavefront in parallel:
+        // each lane scans its own images in order, then the lanes combine
+        // (larger value, else smaller index)
+        const int lane = threadIdx.x;
+        double bv = 0.0;
+        int bi = -1;
+        for (int kk = lane; kk < K; kk += 64) {
+            const double e = E[g0 + kk];
+            if (e == e && (bi < 0 || e > bv)) { bv = e; bi = kk; }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(bv, o);
+            const int oi = __shfl_xor(bi, o);
+            if (oi >= 0 && (bi < 0 || ov > bv || (ov == bv && oi < bi))) { bv = ov; bi = oi; }
+        }
+        if (lane == 0) {
+            const double e0 = E[g0];
+            const int km = (e0 == e0) ? bi : 0;
+            s_km = km;
+            if (chunk == 0) kci[pi] = (km > 0 && km < K - 1) ? km : -1;
+        }
     }
     __syncthreads();
     const int km = s_km;
