@@ -236,6 +236,40 @@ def test_two_images(oracle):
     assert np.abs(sm.get_string().cpu().numpy() - r["s"]).max() < TOL64
 
 
+def test_batch_of_70_problems_equals_separate_runs(oracle):
+    """More problems than one wavefront's lookup covers (70 > 64: the
+    workgroups find their problem by binary search), of both x length kinds
+    (8, 16 and 48-point half lengths) and several image counts: every
+    seventh problem's string and energies bitwise equal to its run alone
+    after 3 iterations, and the first and last against the oracle at
+    1e-10."""
+    rng = np.random.default_rng(70)
+    shapes = [(int(rng.choice([5, 9, 12, 40, 45])), int(rng.integers(3, 9)), int(rng.integers(2, 5)))
+              for _ in range(70)]
+    probs = [prob(nx, ny, 1, K, d=0.2 + 0.002 * i) for i, (nx, ny, K) in enumerate(shapes)]
+    strings = [inputs.perturb(inputs.bloch_point_string(nx, ny, 1, K, 1.5), i)
+               for i, (nx, ny, K) in enumerate(shapes)]
+    sm = ssm.StringMethod(probs, ssm.SSM_FP64)
+    sm.set_string(strings)
+    sm.iterate(3, 0.1)
+    flat = sm.get_string().cpu().numpy()
+    E = sm.energies().cpu().numpy()
+    off = e0 = 0
+    for i, (p, s0) in enumerate(zip(probs, strings)):
+        n = s0.size
+        if i in (0, 69):
+            r = oracle.iterate(s0, p["J"], p["d"], p["ku"], p["D"], 3, 0.1)
+            assert np.abs(flat[off:off + n] - r["s"].ravel()).max() < TOL64
+        if i % 7 == 0 or i == 69:
+            one = ssm.StringMethod(p, ssm.SSM_FP64)
+            one.set_string(s0)
+            one.iterate(3, 0.1)
+            assert np.array_equal(flat[off:off + n], one.get_string().cpu().numpy().ravel())
+            assert np.array_equal(E[e0:e0 + p["K"]], one.energies().cpu().numpy())
+        off += n
+        e0 += p["K"]
+
+
 def test_batch_equals_separate_runs():
     shapes = [(10, 9, 1, 4, 0.2), (17, 5, 1, 3, 0.3), (8, 8, 1, 5, 0.4)]
     probs = [prob(nx, ny, nz, K, d=d) for nx, ny, nz, K, d in shapes]
