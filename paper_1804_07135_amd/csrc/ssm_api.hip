@@ -126,7 +126,7 @@ struct Plan {
 size_t lds_xfwd(const Prob& p, int yt, size_t tsize)
 {
     const int n = yt * p.mx;
-    const int pl = x_padl(p.lmx, p.f3x);
+    const int pl = x_padl(p.lmx, p.f3x, (int)tsize);
     const int lines = pl ? padded_len(n, pl) : lds_padded_size(n);
     return (size_t)(2 * p.mx + lines) * 2 * tsize;
 }
@@ -134,7 +134,7 @@ size_t lds_xfwd(const Prob& p, int yt, size_t tsize)
 size_t lds_xinv(const Prob& p, int yt, size_t tsize)
 {
     const int n = yt * p.mx;
-    const int pl = x_padl(p.lmx, p.f3x);
+    const int pl = x_padl(p.lmx, p.f3x, (int)tsize);
     const int lines = pl ? padded_len(n, pl) : lds_padded_size(n);
     return (size_t)(2 * p.mx + lines) * 2 * tsize + (size_t)3 * yt * p.nx * tsize;
 }
@@ -143,7 +143,7 @@ size_t lds_convg(const Prob& p, int G, size_t tsize)
 {
     const int n = G * 3 * p.nz * p.my;
     if (conv_ct_shape(p.mz, p.lmy, p.f3y) || conv_ct3_shape(p.mz, p.lmy, p.f3y))
-        return (size_t)(2 * p.my + padded_len(n, conv_padl(p.mz, p.lmy, p.f3y))) * 2 * tsize;
+        return (size_t)(2 * p.my + padded_len(n, conv_padl(p.mz, p.lmy, p.f3y, (int)tsize))) * 2 * tsize;
     return (size_t)(2 * p.my + lds_padded_size(n)) * 2 * tsize;
 }
 

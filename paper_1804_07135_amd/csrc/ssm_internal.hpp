@@ -73,18 +73,29 @@ __host__ __device__ constexpr int conv_build(int mz, int lmy, int f3y)
 #ifndef SSM_CONV3_PADL
 #define SSM_CONV3_PADL 4
 #endif
+// the 3 2^a layouts of the FP32 form: one pad per 8 elements (fewer bank
+// conflicts on its 8-byte elements; FP64 keeps one per 16)
+#ifndef SSM_X3_PADL_F32
+#define SSM_X3_PADL_F32 3
+#endif
+#ifndef SSM_CONV3_PADL_F32
+#define SSM_CONV3_PADL_F32 3
+#endif
 // x lengths with compile-time passes: powers of two 32..512 (lm = log2 m)
-// and 3 2^lm for 48..384, both in the pad-SSM_X_PADL layout
+// and 3 2^lm for 48..384, in the pad-SSM_X_PADL layout (3 2^lm in FP32:
+// pad-SSM_X3_PADL_F32); tsize: bytes per real value
 __host__ __device__ constexpr bool x_ct_len(int lm, int f3) { return SSM_X_CT && !f3 && lm >= 5 && lm <= 9; }
 __host__ __device__ constexpr bool x_ct3_len(int lm, int f3) { return SSM_X_CT && f3 && lm >= 4 && lm <= 7; }
-__host__ __device__ constexpr int x_padl(int lm, int f3)
+__host__ __device__ constexpr int x_padl(int lm, int f3, int tsize)
 {
-    return (x_ct_len(lm, f3) || x_ct3_len(lm, f3)) ? pad_for(SSM_X_PADL, lm) : 0;
+    return x_ct_len(lm, f3)    ? pad_for(SSM_X_PADL, lm)
+           : x_ct3_len(lm, f3) ? pad_for(tsize == 4 ? SSM_X3_PADL_F32 : SSM_X_PADL, lm)
+                               : 0;
 }
-__host__ __device__ constexpr int conv_padl(int mz, int lmy, int f3y)
+__host__ __device__ constexpr int conv_padl(int mz, int lmy, int f3y, int tsize)
 {
     return conv_ct_shape(mz, lmy, f3y)    ? pad_for(SSM_CONV_PADL, lmy)
-           : conv_ct3_shape(mz, lmy, f3y) ? pad_for(SSM_CONV3_PADL, lmy)
+           : conv_ct3_shape(mz, lmy, f3y) ? pad_for(tsize == 4 ? SSM_CONV3_PADL_F32 : SSM_CONV3_PADL, lmy)
                                           : 0;
 }
 // elements of a buffer of n elements in the pad-padl layout

@@ -185,10 +185,10 @@ __device__ __forceinline__ void fft_lines_x(V* lines, int nl, int lm, int f3, co
 {
     if (f3) {
         switch (SSM_X_CT ? lm : 0) {
-        case 4: fft_lines_ct<V, INV, 4, SSM_X_CT_RADIX_BITS, pad_for(SSM_X_PADL, 4), 3>(lines, 3 * nl, twl); break;
-        case 5: fft_lines_ct<V, INV, 5, SSM_X_CT_RADIX_BITS, pad_for(SSM_X_PADL, 5), 3>(lines, 3 * nl, twl); break;
-        case 6: fft_lines_ct<V, INV, 6, SSM_X_CT_RADIX_BITS, pad_for(SSM_X_PADL, 6), 3>(lines, 3 * nl, twl); break;
-        case 7: fft_lines_ct<V, INV, 7, SSM_X_CT_RADIX_BITS, pad_for(SSM_X_PADL, 7), 3>(lines, 3 * nl, twl); break;
+        case 4: fft_lines_ct<V, INV, 4, SSM_X_CT_RADIX_BITS, x_padl(4, 1, sizeof(V) / 2), 3>(lines, 3 * nl, twl); break;
+        case 5: fft_lines_ct<V, INV, 5, SSM_X_CT_RADIX_BITS, x_padl(5, 1, sizeof(V) / 2), 3>(lines, 3 * nl, twl); break;
+        case 6: fft_lines_ct<V, INV, 6, SSM_X_CT_RADIX_BITS, x_padl(6, 1, sizeof(V) / 2), 3>(lines, 3 * nl, twl); break;
+        case 7: fft_lines_ct<V, INV, 7, SSM_X_CT_RADIX_BITS, x_padl(7, 1, sizeof(V) / 2), 3>(lines, 3 * nl, twl); break;
         default: fft_lines<V, INV, SSM_X_RADIX_BITS, 3>(lines, 3 * nl, 1 << lm, lm, twl); break;
         }
         return;
@@ -420,7 +420,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     const int yt = p.ytf, hp = yt >> 1, nx = p.nx, ny = p.ny, nz = p.nz, m = p.mx, lm = p.lmx;
     constexpr int f3 = F3;
     const int lhp = __ffs(hp) - 1;  // tiles are powers of two
-    const int psh = x_padl(lm, f3) ? x_padl(lm, f3) : 31;  // pad layout of the lines
+    const int psh = x_padl(lm, f3, sizeof(T)) ? x_padl(lm, f3, sizeof(T)) : 31;  // pad layout of the lines
     // line index of position q (< m) of line l: l m + q, m = 2^lm or 3 2^lm
     auto lidx = [&](int l, int q) { return (F3 ? (l + (l << 1)) << lm : l << lm) + q; };
     V* twl = reinterpret_cast<V*>(smem_);
@@ -628,7 +628,7 @@ __device__ __forceinline__ void conv_body_ct(const Prob& p, int s0, int G, cplx<
     constexpr int BL = LMY - LNSL, RL = 1 << BL;
     static_assert(LNSL >= B0, "the y schedule needs at least two passes");
     // pad layout; twiddles W_{2 m_y} from an LDS copy
-    constexpr int PADL = conv_padl(MZ, LMY, 0);
+    constexpr int PADL = conv_padl(MZ, LMY, 0, sizeof(T));
     constexpr int TWS = 0;
     // swizzled handoff between the two radix-16 passes of length 256
     constexpr bool SW = SSM_CONV_SWZ && PADL == 0 && LMY == 8 && MB == 4;
@@ -918,7 +918,7 @@ __device__ __forceinline__ void conv_body_ct3(const Prob& p, int s0, int G, cplx
     constexpr int BF = 2, RF = 1 << BF;  // fused sub-line passes: radix 4
     constexpr int QF = M / RF;           // their butterflies per sub-line
     constexpr int LQF = LMY - BF;
-    constexpr int PADL = conv_padl(MZ, LMY, 1);
+    constexpr int PADL = conv_padl(MZ, LMY, 1, sizeof(T));
     static_assert(PLG >= 1 && LMY - BF >= 2, "length outside the compile-time 3 2^a set");
     const int nsl_img = p.mx + 1;
     const int nz = p.nz, ny = p.ny;
@@ -1227,12 +1227,12 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     const int yt = p.yt, hp = yt >> 1, nx = p.nx, ny = p.ny, nz = p.nz, m = p.mx, lm = p.lmx;
     constexpr int f3 = F3;
     const int lhp = __ffs(hp) - 1;  // tiles are powers of two
-    const int psh = x_padl(lm, f3) ? x_padl(lm, f3) : 31;  // pad layout of the lines
+    const int psh = x_padl(lm, f3, sizeof(T)) ? x_padl(lm, f3, sizeof(T)) : 31;  // pad layout of the lines
     const int y0 = ty * yt;
     const long long N = p.N;
     V* twl = reinterpret_cast<V*>(smem_);
     V* lines = twl + 2 * m;
-    T* hd = reinterpret_cast<T*>(lines + padded_len(yt * m, x_padl(lm, f3)));
+    T* hd = reinterpret_cast<T*>(lines + padded_len(yt * m, x_padl(lm, f3, sizeof(T))));
     load_twiddles(twl, lm, f3, tw);
     // the convolved x half-spectra of the image
     // (as a uniform base and 32-bit byte offsets: an image's spectra span
