@@ -77,6 +77,14 @@ def algorithmic_bytes(w, ts):
     }
 
 
+def replay_chunk(warmup, graph_chunk):
+    """Iterations per replayed HIP graph for a run with `warmup` untimed
+    steps: graph capture and instantiation happen in the warm-up, never in
+    the timed steps, so the chunk is at most the warm-up's length (no
+    warm-up: 0, direct launches)."""
+    return graph_chunk if warmup >= graph_chunk else max(warmup, 0)
+
+
 def time_iterations(sm, steps, tau):
     import torch
     torch.cuda.synchronize()
@@ -528,10 +536,7 @@ def main():
     steps, warm = args.steps, args.warmup
 
     # --- FP32-mixed form, graph replay -------------------------------------
-    # graph capture and instantiation happen in the warm-up, never in the
-    # timed steps: the replayed chunk is at most the warm-up's length (no
-    # warm-up: direct launches)
-    gchunk = args.graph_chunk if warm >= args.graph_chunk else warm
+    gchunk = replay_chunk(warm, args.graph_chunk)
     sm = ssm.StringMethod(prob, ssm.SSM_FP32_MIXED)
     sm.set_options(check_every=10, graph_chunk=gchunk)
     sm.set_string(s0)

@@ -78,3 +78,13 @@ def test_profile_hash_follows_code_not_comments(tmp_path, monkeypatch):
     assert "12288 / p.arc_chunks" in src
     a.write_text(src.replace("12288 / p.arc_chunks", "6144 / p.arc_chunks"))
     assert bench.kernel_source_hash() != h0
+
+
+def test_replay_chunk_keeps_capture_out_of_the_timed_steps():
+    """The warm-up builds the graph the timed steps replay: the chunk never
+    exceeds the warm-up, and no warm-up means direct launches."""
+    assert bench.replay_chunk(10, 10) == 10
+    assert bench.replay_chunk(100, 10) == 10
+    assert bench.replay_chunk(5, 10) == 5
+    assert bench.replay_chunk(0, 10) == 0
+    assert bench.replay_chunk(3, 0) == 0
