@@ -25,9 +25,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "site-field evals/s + string iters/s; FP32-batched vs FP64 plain at 1e-4 barrier"
 HBM_PEAK_GBS = 8000.0
-# FP32 vector ceiling of the instructions this build issues: 256 CUs x 4 SIMDs
+# FP32 vector ceiling of the instructions these kernels issue: 256 CUs x 4 SIMDs
 # x 16 lanes x 2 flops per FMA x 2.4 GHz (the published 157.3 TFLOP/s counts
-# packed FP32, which the build leaves off)
+# packed FP32, which these kernels are compiled without)
 FP32_VECTOR_NONPACKED_TFLOPS = 78.6
 KERNEL_SOURCES = ["paper_1804_07135_amd/csrc/ssm_kernels.hip", "paper_1804_07135_amd/csrc/ssm_internal.hpp",
                   "paper_1804_07135_amd/csrc/ssm_fft.hpp", "paper_1804_07135_amd/csrc/ssm_api.hip"]

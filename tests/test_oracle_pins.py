@@ -51,7 +51,7 @@ def test_two_spins(oracle, axis):
         assert oracle.energy(s, J, d, k, D) == pytest.approx(expect, abs=1e-14)
 
 
-def test_two_spins_survey_values(oracle):
+def test_two_spins_closed_form_values(oracle):
     # two +z spins at distance 1 along x: -J - 2k + D; two +x: -J - 2D
     s = np.zeros((3, 1, 1, 2)); s[2] = 1
     assert oracle.energy(s, 1, 0.3, 0.1, 0.01) == pytest.approx(-1 - 0.2 + 0.01, abs=1e-15)
