@@ -236,16 +236,17 @@ def test_two_images(oracle):
     assert np.abs(sm.get_string().cpu().numpy() - r["s"]).max() < TOL64
 
 
-def test_batch_of_70_problems_equals_separate_runs(oracle):
-    """More problems than one wavefront's lookup covers (70 > 64: the
-    workgroups find their problem by binary search), of both x length kinds
-    (8, 16 and 48-point half lengths) and several image counts: every
-    seventh problem's string and energies bitwise equal to its run alone
-    after 3 iterations, and the first and last against the oracle at
-    1e-10."""
+@pytest.mark.parametrize("nprob", [64, 70])
+def test_batch_of_many_problems_equals_separate_runs(oracle, nprob):
+    """64 problems (the most one wavefront's ballot lookup serves) and 70
+    (more: the workgroups find their problem by binary search), of both x
+    length kinds (8, 16 and 48-point half lengths) and several image counts:
+    every seventh problem's string and energies, and the last one's, bitwise
+    equal to its run alone after 3 iterations, and the first and last
+    against the oracle at 1e-10."""
     rng = np.random.default_rng(70)
     shapes = [(int(rng.choice([5, 9, 12, 40, 45])), int(rng.integers(3, 9)), int(rng.integers(2, 5)))
-              for _ in range(70)]
+              for _ in range(nprob)]
     probs = [prob(nx, ny, 1, K, d=0.2 + 0.002 * i) for i, (nx, ny, K) in enumerate(shapes)]
     strings = [inputs.perturb(inputs.bloch_point_string(nx, ny, 1, K, 1.5), i)
                for i, (nx, ny, K) in enumerate(shapes)]
@@ -257,10 +258,10 @@ def test_batch_of_70_problems_equals_separate_runs(oracle):
     off = e0 = 0
     for i, (p, s0) in enumerate(zip(probs, strings)):
         n = s0.size
-        if i in (0, 69):
+        if i in (0, nprob - 1):
             r = oracle.iterate(s0, p["J"], p["d"], p["ku"], p["D"], 3, 0.1)
             assert np.abs(flat[off:off + n] - r["s"].ravel()).max() < TOL64
-        if i % 7 == 0 or i == 69:
+        if i % 7 == 0 or i == nprob - 1:
             one = ssm.StringMethod(p, ssm.SSM_FP64)
             one.set_string(s0)
             one.iterate(3, 0.1)
