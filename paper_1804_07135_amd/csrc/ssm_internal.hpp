@@ -30,7 +30,10 @@ constexpr int kMaxImages = 1024;  // images per problem (the ABI's limit)
 // Reduction in one workgroup per problem (k_reduce1) for problems of at
 // most kRed1MaxK images with at most kRed1MaxPart energy and arc partials
 // per image; kRedLanes lanes sum one image's partials there.
-constexpr int kRed1MaxK = 64, kRed1MaxPart = 256, kRedLanes = 16;
+#ifndef SSM_RED_LANES
+#define SSM_RED_LANES 4
+#endif
+constexpr int kRed1MaxK = 64, kRed1MaxPart = 256, kRedLanes = SSM_RED_LANES;
 
 // The convolution kernel comes in two builds: one with compile-time-length
 // bodies for y lengths 32..256 and up to 8 layers, one with a runtime-length

@@ -1523,15 +1523,30 @@ __device__ void reduce_final(const Prob& p, int pi, double* al, double* el, doub
                              double* alpha, int* jidx, double* wgt, int* skip, int* iters, const Step2& s2)
 {
     const int K = p.K, g0 = p.img0;
-    if (threadIdx.x == 0) {
-        double S = 0;
-        for (int kk = 1; kk < K; ++kk) {
-            S += al[kk];
-            al[kk] = S;
+    // S_k = al[1] + ... + al[k]: an inclusive scan by the first wavefront,
+    // 64 images at a time with the running total carried over (a fixed
+    // order, so reruns are bitwise identical)
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        double carry = 0.0;
+        for (int base = 0; base < K; base += 64) {
+            const int kk = base + lane;
+            const bool in = kk >= 1 && kk < K;
+            double v = in ? al[kk] : 0.0;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const double u = __shfl_up(v, o);
+                if (lane >= o) v += u;
+            }
+            v += carry;
+            if (in) al[kk] = v;
+            carry = __shfl(v, 63);
         }
-        *bc = S;
-        skip[pi] = (S > 0.0) ? 0 : 1;
-        atomicAdd(&iters[pi], 1);  // the problem's only writer in this launch
+        if (lane == 0) {
+            *bc = carry;
+            skip[pi] = (carry > 0.0) ? 0 : 1;
+            atomicAdd(&iters[pi], 1);  // the problem's only writer in this launch
+        }
     }
     __syncthreads();
     const double L = *bc;
@@ -1578,6 +1593,18 @@ __device__ void reduce_final(const Prob& p, int pi, double* al, double* el, doub
         if (kk <= kci) return al[kci] * (double)kk / (double)kci;
         return al[kci] + (1.0 - al[kci]) * (double)(kk - kci) / (double)(K - 1 - kci);
     };
+    // interval of target t >= 0: the largest j <= K-2 with al[j] <= t, by
+    // bisection (al is non-decreasing from al[0] = 0; with non-finite
+    // lengths j still lies in 0..K-2)
+    auto interval = [&](double t) {
+        int lo = 0, hi = K - 2;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (al[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    };
     for (int kk = threadIdx.x; kk < K; kk += kNT) {
         alpha[g0 + kk] = al[kk];
         if (kk == 0 || kk == K - 1 || kk == kci) {
@@ -1586,9 +1613,7 @@ __device__ void reduce_final(const Prob& p, int pi, double* al, double* el, doub
             continue;
         }
         const double tk = target(kk);
-        int j = 0;
-        for (int jj = 0; jj <= K - 2; ++jj)
-            if (al[jj] <= tk) j = jj;
+        const int j = interval(tk);
         const double width = al[j + 1] - al[j];
         jidx[g0 + kk] = j;
         wgt[g0 + kk] = (width > 0.0) ? (tk - al[j]) / width : 0.0;
@@ -1628,9 +1653,7 @@ __device__ void reduce_final(const Prob& p, int pi, double* al, double* el, doub
     for (int kk = threadIdx.x; kk < K; kk += kNT) {
         if (kk == 0 || kk == K - 1 || kk == kci) continue;
         const double tk = target(kk);
-        int j = 0;
-        for (int jj = 0; jj <= K - 2; ++jj)
-            if (al[jj] <= tk) j = jj;
+        const int j = interval(tk);
         const double h = al[j + 1] - al[j];
         const double A = (al[j + 1] - tk) / h;
         s2.A[g0 + kk] = A;
@@ -1784,8 +1807,10 @@ __global__ __launch_bounds__(kNT) void k_reduce(const Prob* __restrict__ P, int 
 // few partials per image) in one workgroup, so that no result passes
 // between workgroups: the device-scope fences of that hand-off cost more
 // than these sums.  kRedLanes lanes per image sum its partials in rounds,
-// then combine them in a fixed butterfly order; with_arc, reduce_final ends
-// step 2 from the segment lengths kept in LDS.
+// then combine them in a fixed butterfly order (4 lanes: the 64 images of
+// the largest such problem in one pass, so the partials' loads wait on
+// memory once); with_arc, reduce_final ends step 2 from the segment
+// lengths kept in LDS.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kNT) void k_reduce1(const Prob* __restrict__ P, int np,
                                                  const double* __restrict__ epart,
