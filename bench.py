@@ -328,10 +328,12 @@ def sweep_leg(ssm, torch, inputs, args):
 def paper_shape_leg(ssm, torch, args):
     """The paper's production shape: a 112x112x1 monolayer, 60 images, with
     its material in SI units (d = 5.30 meV, k = 0.5 meV), FP32-mixed form,
-    graph replay: one problem alone, then args.paper_batch (d, k) points in
-    one context (the batched phase-diagram form).  Explicit steps of 0.1
+    graph replay, tiles from the autotuner: one problem alone, then
+    args.paper_batch (d, k) points in one context (the batched
+    phase-diagram form).  Explicit steps of 0.1
     (the paper's interval of 5e-14 s is 1.74 in these units at damping 1,
     for the adaptive integrator, whose cost the integrator leg gives)."""
+    import tempfile
     from paper_1804_07135_amd import si
     res = {}
     tau = 0.1
@@ -341,6 +343,9 @@ def paper_shape_leg(ssm, torch, args):
         strings = [si.initial_string("bloch", 112, 60, 10.0, seed=i) for i in range(n_points)]
         sm = ssm.StringMethod(probs, ssm.SSM_FP32_MIXED)
         sm.set_options(check_every=10, graph_chunk=10)
+        sm.set_string(strings)
+        with tempfile.TemporaryDirectory() as td:
+            sm.autotune(os.path.join(td, "tiles.txt"))
         sm.set_string(strings)
         sm.iterate(10, tau)
         steps = args.paper_steps
