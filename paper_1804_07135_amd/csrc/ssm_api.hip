@@ -318,7 +318,9 @@ ssm_status build_plan(const ssm_problem* pr, int np, int prec_flags, const std::
         // spin buffers are 256-byte aligned, so an image is 16-byte aligned
         // when its element offset is a multiple of 4
         p.vec4 = (pl.tsize == 4 && p.N % 4 == 0 && spin % 4 == 0) ? 1 : 0;
-        p.ichunks4 = p.vec4 ? (int)((p.N + 4 * kNT - 1) / (4 * kNT)) : p.ichunks;
+        p.vec2 = (pl.tsize == 8 && p.N % 2 == 0 && spin % 2 == 0) ? 1 : 0;
+        p.ichunks4 = p.vec4 ? (int)((p.N + 4 * kNT - 1) / (4 * kNT))
+                            : p.vec2 ? (int)((p.N + 2 * kNT - 1) / (2 * kNT)) : p.ichunks;
         p.fp_off = fp;
         p.fm_off = fm;
         p.J = q.J; p.d = q.d; p.ku = q.ku; p.D = q.dip;

@@ -137,7 +137,8 @@ struct Prob {
     long long fm_off;      // offset (doubles) of per-workgroup force maxima: [K][ichunks]
     int ichunks;           // per-site workgroups per image (interp / tangents)
     int vec4;              // FP32 images of N divisible by 4, 16-byte aligned: 4 sites per thread
-    int ichunks4;          // interpolation workgroups per image (ichunks / 4 with vec4)
+    int vec2;              // FP64 images of even N, 16-byte aligned: 2 sites per thread
+    int ichunks4;          // interpolation workgroups per image (ichunks / 4 with vec4, / 2 with vec2)
     int arc_g;             // images per arc-length workgroup (image groups of arc_g)
     int arc_ng;            // image groups: arc-length workgroups = arc_chunks * arc_ng
     int red1;              // 1: reduced by one workgroup (k_reduce1), else one per image (k_reduce)

@@ -1887,6 +1887,31 @@ __global__ __launch_bounds__(kNT) void k_reduce1(const Prob* __restrict__ P, int
     reduce_final(p, pi, al, el, &bc, &s_kci, alpha, jidx, wgt, skip, iters, s2);
 }
 
+// One site of the linear interpolation: (1 - w) a + w b renormalised in
+// FP64 by the device library's reciprocal square root (within an ulp or two
+// of sqrt and division); a norm below 1e-12 takes the nearer source's spin.
+// Flags: 4 a non-finite norm, 2 a degenerate one.  Every path of k_interp
+// calls it, so a problem's result does not depend on which path its place
+// in a batch selects.
+template <typename T>
+__device__ __forceinline__ void interp_site(const T (&a)[3], const T (&b)[3], double wt, T (&o)[3], int* flags)
+{
+    double v[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = (1.0 - wt) * (double)a[c] + wt * (double)b[c];
+    const double n2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    if (!isfinite(n2)) atomicOr(flags, 4);
+    if (n2 < 1e-24) {
+        atomicOr(flags, 2);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) o[c] = (wt < 0.5) ? a[c] : b[c];
+    } else {
+        const double inv = rsqrt(n2);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) o[c] = (T)(v[c] * inv);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // k_interp: s_k = normalise((1-w) s*_j + w s*_{j+1}); endpoints (and every
 // image when the reparametrisation is skipped) are copied.
@@ -1939,24 +1964,51 @@ __global__ __launch_bounds__(kNT) void k_interp(const Prob* __restrict__ P, int 
             float o[3][4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                double v[3];
+                float ta[3] = {av[0][q], av[1][q], av[2][q]}, tb[3] = {bv[0][q], bv[1][q], bv[2][q]}, to[3];
+                interp_site<float>(ta, tb, wt, to, flags);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) v[c] = (1.0 - wt) * (double)av[c][q] + wt * (double)bv[c][q];
-                const double n2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-                if (!isfinite(n2)) atomicOr(flags, 4);
-                if (n2 < 1e-24) {
-                    atomicOr(flags, 2);
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) o[c][q] = (wt < 0.5) ? av[c][q] : bv[c][q];
-                } else {
-                    const double inv = rsqrt(n2);
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) o[c][q] = (float)(v[c] * inv);
-                }
+                for (int c = 0; c < 3; ++c) o[c][q] = to[c];
             }
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 *reinterpret_cast<float4*>(dst + c * N + i) = make_float4(o[c][0], o[c][1], o[c][2], o[c][3]);
+            return;
+        }
+    } else {
+        if (p.vec2) {
+            // two consecutive sites per thread, 16-byte accesses
+            const long long i = ((long long)chunk * kNT + threadIdx.x) * 2;
+            if (i >= N) return;
+            if (copy) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    *reinterpret_cast<double2*>(dst + c * N + i) =
+                        *reinterpret_cast<const double2*>(src + (long long)k * M + c * N + i);
+                return;
+            }
+            const int j = jidx[p.img0 + k];
+            const double wt = wgt[p.img0 + k];
+            const T* a = src + (long long)j * M;
+            const T* b = a + M;
+            double av[3][2], bv[3][2];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double2 x = *reinterpret_cast<const double2*>(a + c * N + i);
+                const double2 y = *reinterpret_cast<const double2*>(b + c * N + i);
+                av[c][0] = x.x; av[c][1] = x.y;
+                bv[c][0] = y.x; bv[c][1] = y.y;
+            }
+            double o[3][2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                double ta[3] = {av[0][q], av[1][q], av[2][q]}, tb[3] = {bv[0][q], bv[1][q], bv[2][q]}, to[3];
+                interp_site<double>(ta, tb, wt, to, flags);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) o[c][q] = to[c];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                *reinterpret_cast<double2*>(dst + c * N + i) = make_double2(o[c][0], o[c][1]);
             return;
         }
     }
@@ -1971,26 +2023,15 @@ __global__ __launch_bounds__(kNT) void k_interp(const Prob* __restrict__ P, int 
     const double wt = wgt[p.img0 + k];
     const T* a = src + (long long)j * M;
     const T* b = a + M;
-    double v[3];
+    T ta[3], tb[3], to[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) v[c] = (1.0 - wt) * (double)a[c * N + i] + wt * (double)b[c * N + i];
-    // renormalised by the device library's FP64 reciprocal square root
-    // (within an ulp or two of sqrt and division); a norm below 1e-12 takes
-    // the nearer source's spin
-    const double n2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-    if (!isfinite(n2)) atomicOr(flags, 4);
-    if (n2 < 1e-24) {
-        atomicOr(flags, 2);
-        const T* n = (wt < 0.5) ? a : b;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) dst[c * N + i] = n[c * N + i];
-    } else {
-        // the same arithmetic as the four-site path, so a problem's result
-        // does not depend on which path its place in a batch selects
-        const double inv = rsqrt(n2);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) dst[c * N + i] = (T)(v[c] * inv);
+    for (int c = 0; c < 3; ++c) {
+        ta[c] = a[c * N + i];
+        tb[c] = b[c * N + i];
     }
+    interp_site<T>(ta, tb, wt, to, flags);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dst[c * N + i] = to[c];
 }
 
 // ---------------------------------------------------------------------------
