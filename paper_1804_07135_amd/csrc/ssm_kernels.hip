@@ -1125,10 +1125,16 @@ __device__ __forceinline__ T lane_prev(T v)
 // past the lattice reads a row inside it instead (rows transform
 // independently, and no field of a row past the lattice is used); even ny
 // reads the pair as one 16-byte load.
+// items per thread per round: 8 in FP32; 4 in FP64, whose 16-byte
+// complex values hold twice the registers per item
 #ifndef SSM_XINV_U
 #define SSM_XINV_U 8
 #endif
-constexpr int kXinvU = SSM_XINV_U;
+#ifndef SSM_XINV_U_F64
+#define SSM_XINV_U_F64 4
+#endif
+template <typename T>
+constexpr int kXinvU = sizeof(T) == 4 ? SSM_XINV_U : SSM_XINV_U_F64;
 template <typename T, int F3>
 __device__ __forceinline__ void xinv_load_lines(const char* __restrict__ Xi, cplx<T>* lines, int c, int z, int y0,
                                                 int hp, int lhp, int m, int lm, int nz, int ny, int psh)
@@ -1147,15 +1153,15 @@ __device__ __forceinline__ void xinv_load_lines(const char* __restrict__ Xi, cpl
         const unsigned kstr = (unsigned)(dk * 3 * nz * ny) * (unsigned)sizeof(V);
         const unsigned cbm = (unsigned)(((m * 3 + c) * nz + z) * ny) * (unsigned)sizeof(V);
 #pragma unroll 1
-        for (int idx0 = threadIdx.x; idx0 < total; idx0 += kXinvU * kNT) {
+        for (int idx0 = threadIdx.x; idx0 < total; idx0 += kXinvU<T> * kNT) {
             const int rp = idx0 & (hp - 1), kx0 = idx0 >> lhp;
             const int ya = y0 + 2 * rp;
             const unsigned cb0 = (unsigned)(((kx0 * 3 + c) * nz + z) * ny) * (unsigned)sizeof(V);
             const unsigned ya0 = (unsigned)min(ya, ny - (ODD ? 1 : 2)) * (unsigned)sizeof(V);
             const unsigned ya1 = (unsigned)min(ya + 1, ny - 1) * (unsigned)sizeof(V);
-            V A[kXinvU], B[kXinvU];
+            V A[kXinvU<T>], B[kXinvU<T>];
 #pragma unroll
-            for (int u = 0; u < kXinvU; ++u) {
+            for (int u = 0; u < kXinvU<T>; ++u) {
                 const unsigned cb = min(cb0 + (unsigned)u * kstr, cbm);
                 if constexpr (!ODD) {
                     load2(reinterpret_cast<const V*>(Xi + cb + ya0), A[u], B[u]);
@@ -1167,13 +1173,13 @@ __device__ __forceinline__ void xinv_load_lines(const char* __restrict__ Xi, cpl
             if constexpr (ODD) {
                 if (ya >= ny)
 #pragma unroll
-                    for (int u = 0; u < kXinvU; ++u) A[u] = mk<V>(0, 0);
+                    for (int u = 0; u < kXinvU<T>; ++u) A[u] = mk<V>(0, 0);
                 if (ya + 1 >= ny)
 #pragma unroll
-                    for (int u = 0; u < kXinvU; ++u) B[u] = mk<V>(0, 0);
+                    for (int u = 0; u < kXinvU<T>; ++u) B[u] = mk<V>(0, 0);
             }
 #pragma unroll
-            for (int u = 0; u < kXinvU; ++u) {
+            for (int u = 0; u < kXinvU<T>; ++u) {
                 if (idx0 + u * kNT >= total) break;
                 const int kx = kx0 + u * dk;
                 const V a = A[u], b = B[u];
