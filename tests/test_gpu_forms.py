@@ -172,16 +172,17 @@ def test_autograd_tube_128x128x4(oracle):
     np.testing.assert_allclose(th.grad.numpy(), (g.cpu().numpy()[:, None] * To).sum(0), rtol=1e-10)
 
 
-def test_fp32_batch_position_does_not_change_results():
-    """FP32 images of N divisible by 4 take 16-byte paths when they start
-    16-byte aligned; placed after a problem of odd size in a batch they take
-    the one-site paths.  Both give bitwise the same string, energies and
-    barrier as the problem run alone."""
+@pytest.mark.parametrize("precision", [ssm.SSM_FP32_MIXED, ssm.SSM_FP64])
+def test_batch_position_does_not_change_results(precision):
+    """Images of N divisible by 4 (FP32) or 2 (FP64) take 16-byte paths when
+    they start 16-byte aligned; placed after a problem of odd size in a
+    batch they take the one-site paths.  Both give bitwise the same string,
+    energies and barrier as the problem run alone."""
     shapes = [(5, 3, 1, 3, 0.2), (8, 8, 1, 5, 0.3), (16, 12, 1, 4, 0.35)]
     probs = [prob(nx, ny, nz, K, d=d) for nx, ny, nz, K, d in shapes]
     strings = [inputs.perturb(inputs.bloch_point_string(nx, ny, nz, K, 2.0), 7 + i)
                for i, (nx, ny, nz, K, _) in enumerate(shapes)]
-    sm = ssm.StringMethod(probs, ssm.SSM_FP32_MIXED)
+    sm = ssm.StringMethod(probs, precision)
     sm.set_string(strings)
     sm.iterate(8, 0.1)
     flat = sm.get_string().cpu().numpy()
@@ -189,7 +190,7 @@ def test_fp32_batch_position_does_not_change_results():
     bar = sm.barrier().cpu().numpy()
     off = e0 = 0
     for i, (p, s0) in enumerate(zip(probs, strings)):
-        one = ssm.StringMethod(p, ssm.SSM_FP32_MIXED)
+        one = ssm.StringMethod(p, precision)
         one.set_string(s0)
         one.iterate(8, 0.1)
         a = one.get_string().cpu().numpy().ravel()
