@@ -1125,16 +1125,20 @@ __device__ __forceinline__ T lane_prev(T v)
 // past the lattice reads a row inside it instead (rows transform
 // independently, and no field of a row past the lattice is used); even ny
 // reads the pair as one 16-byte load.
-// items per thread per round: 8 in FP32; 4 in FP64, whose 16-byte
-// complex values hold twice the registers per item
+// items per thread per round: 8 in FP32 at power-of-two lengths; 4 at
+// lengths 3 2^a, whose radix-3 step holds more registers, and in FP64,
+// whose 16-byte complex values hold twice the registers per item
 #ifndef SSM_XINV_U
 #define SSM_XINV_U 8
+#endif
+#ifndef SSM_XINV_U_F3
+#define SSM_XINV_U_F3 4
 #endif
 #ifndef SSM_XINV_U_F64
 #define SSM_XINV_U_F64 4
 #endif
-template <typename T>
-constexpr int kXinvU = sizeof(T) == 4 ? SSM_XINV_U : SSM_XINV_U_F64;
+template <typename T, int F3>
+constexpr int kXinvU = sizeof(T) == 4 ? (F3 ? SSM_XINV_U_F3 : SSM_XINV_U) : SSM_XINV_U_F64;
 template <typename T, int F3>
 __device__ __forceinline__ void xinv_load_lines(const char* __restrict__ Xi, cplx<T>* lines, int c, int z, int y0,
                                                 int hp, int lhp, int m, int lm, int nz, int ny, int psh)
@@ -1153,15 +1157,15 @@ __device__ __forceinline__ void xinv_load_lines(const char* __restrict__ Xi, cpl
         const unsigned kstr = (unsigned)(dk * 3 * nz * ny) * (unsigned)sizeof(V);
         const unsigned cbm = (unsigned)(((m * 3 + c) * nz + z) * ny) * (unsigned)sizeof(V);
 #pragma unroll 1
-        for (int idx0 = threadIdx.x; idx0 < total; idx0 += kXinvU<T> * kNT) {
+        for (int idx0 = threadIdx.x; idx0 < total; idx0 += kXinvU<T, F3> * kNT) {
             const int rp = idx0 & (hp - 1), kx0 = idx0 >> lhp;
             const int ya = y0 + 2 * rp;
             const unsigned cb0 = (unsigned)(((kx0 * 3 + c) * nz + z) * ny) * (unsigned)sizeof(V);
             const unsigned ya0 = (unsigned)min(ya, ny - (ODD ? 1 : 2)) * (unsigned)sizeof(V);
             const unsigned ya1 = (unsigned)min(ya + 1, ny - 1) * (unsigned)sizeof(V);
-            V A[kXinvU<T>], B[kXinvU<T>];
+            V A[kXinvU<T, F3>], B[kXinvU<T, F3>];
 #pragma unroll
-            for (int u = 0; u < kXinvU<T>; ++u) {
+            for (int u = 0; u < kXinvU<T, F3>; ++u) {
                 const unsigned cb = min(cb0 + (unsigned)u * kstr, cbm);
                 if constexpr (!ODD) {
                     load2(reinterpret_cast<const V*>(Xi + cb + ya0), A[u], B[u]);
@@ -1173,13 +1177,13 @@ __device__ __forceinline__ void xinv_load_lines(const char* __restrict__ Xi, cpl
             if constexpr (ODD) {
                 if (ya >= ny)
 #pragma unroll
-                    for (int u = 0; u < kXinvU<T>; ++u) A[u] = mk<V>(0, 0);
+                    for (int u = 0; u < kXinvU<T, F3>; ++u) A[u] = mk<V>(0, 0);
                 if (ya + 1 >= ny)
 #pragma unroll
-                    for (int u = 0; u < kXinvU<T>; ++u) B[u] = mk<V>(0, 0);
+                    for (int u = 0; u < kXinvU<T, F3>; ++u) B[u] = mk<V>(0, 0);
             }
 #pragma unroll
-            for (int u = 0; u < kXinvU<T>; ++u) {
+            for (int u = 0; u < kXinvU<T, F3>; ++u) {
                 if (idx0 + u * kNT >= total) break;
                 const int kx = kx0 + u * dk;
                 const V a = A[u], b = B[u];
